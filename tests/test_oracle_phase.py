@@ -1,0 +1,151 @@
+"""Pins of the oracle's phase recovery (Section 2), CPU only."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.metrics import eps_K
+from oracle.phase import (mround, partition2, randomized_svd, recovery_path_general,
+                          recovery_path_lattice, recovery_vector2, recovery_vector2_prefix,
+                          low_rank_factorization, wrapped_phase)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_fig5():
+    path, subs, cut = [], {}, None
+    for line in open(os.path.join(GOLD, "partition_fig5.txt")):
+        p = line.split()
+        if not p or p[0].startswith("#"):
+            continue
+        if p[0] == "path":
+            path.append((int(p[1]), int(p[2])))
+        elif p[0] == "cut":
+            cut = int(p[1])
+        elif p[0] == "sub":
+            subs.setdefault(int(p[1]), []).append((int(p[2]), int(p[3])))
+    return np.array(path), cut, subs
+
+
+def test_partition2_worked_example():
+    P, cut, subs = _load_fig5()
+    parts = partition2(P, 1, [1, cut])
+    assert [r for r, _ in parts] == [1, 4]
+    for r, sub in parts:
+        assert [tuple(x) for x in sub.tolist()] == subs[r]
+
+
+def _check_def23(P, N, root, adjacency):
+    # Definition 2.3: P(:,2) a permutation of all nodes but the root, non-decreasing
+    # depth, P(i,1) the predecessor of P(i,2)
+    assert sorted(P[:, 1].tolist()) == sorted(set(range(N)) - {root})
+    depth = {root: 0}
+    for bg, ed in P:
+        assert bg in depth, "predecessor must precede its child"
+        depth[ed] = depth[bg] + 1
+        assert adjacency(bg, ed)
+    ds = [depth[e] for e in P[:, 1]]
+    assert ds == sorted(ds)
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 5)])
+def test_lattice_comb_tree_is_a_valid_path(d, n):
+    q = (n // 2,) * d
+    P = recovery_path_lattice(d, n, q)
+    root = int(np.ravel_multi_index(q, (n,) * d))
+    coords = np.array(np.unravel_index(np.arange(n ** d), (n,) * d)).T
+    _check_def23(P, n ** d, root, lambda a, b: np.abs(coords[a] - coords[b]).sum() == 1)
+    # depth equals the Manhattan distance: every edge is a unit axis edge (minimum spanning weight)
+    assert len(P) == n ** d - 1
+
+
+def test_general_path_is_mst_bfs():
+    rng = W.rng(21, 0)
+    X = rng.random((60, 2))
+    P = recovery_path_general(X, root=0)
+    _check_def23(P, 60, 0, lambda a, b: True)
+    # weight equals the MST of the complete graph (the DT contains an MST); brute-force Prim
+    w = np.linalg.norm(X[P[:, 0]] - X[P[:, 1]], axis=1).sum()
+    D = np.linalg.norm(X[:, None] - X[None], axis=2)
+    inT = np.zeros(60, bool)
+    inT[0] = True
+    best = D[0].copy()
+    tot = 0.0
+    for _ in range(59):
+        best[inT] = np.inf
+        j = int(np.argmin(best))
+        tot += best[j]
+        inT[j] = True
+        best = np.minimum(best, D[j])
+    assert abs(w - tot) < 1e-12
+
+
+def test_round_half_away_from_zero():
+    assert mround(np.array([0.5, -0.5, 1.5, -1.49, 2.5]) ).tolist() == [1.0, -1.0, 2.0, -1.0, 3.0]
+
+
+def test_recovery_vector2_unwraps_smooth_phase_exactly():
+    n = 16
+    P = recovery_path_lattice(2, n, (0, 0))
+    a = np.array(np.unravel_index(np.arange(n * n), (n, n))).T / n
+    phi = 3.1 * a[:, 0] - 2.3 * a[:, 1] + 1.7 * a[:, 0] * a[:, 1] + 5.2
+    u = wrapped_phase(np.exp(2j * np.pi * phi))
+    v, D = recovery_vector2(u, 0.25, P, 0)
+    shift = v - phi
+    assert np.allclose(shift, np.round(shift[0]), atol=1e-12)   # v = phi + integer constant
+    assert D == [0]
+
+
+def test_recovery_vector2_flags_jump():
+    n = 16
+    P = recovery_path_lattice(2, n, (0, 0))
+    a = np.array(np.unravel_index(np.arange(n * n), (n, n))).T / n
+    phi = 0.5 * a[:, 0] + np.where(a[:, 1] >= 0.5, 0.35, 0.0)
+    u = wrapped_phase(np.exp(2j * np.pi * phi))
+    _, D = recovery_vector2(u, 0.25, P, 0)
+    flagged = np.array(D[1:])
+    assert len(flagged) == n and (a[flagged, 1] == 0.5).all()
+
+
+def test_loop_equals_prefix_sum():
+    rng = W.rng(22, 0)
+    X = rng.random((80, 3))
+    P = recovery_path_general(X, root=5)
+    u = rng.random(80) - 0.5
+    v, _ = recovery_vector2(u, 1.0, P, 5)
+    assert np.allclose(recovery_vector2_prefix(u, P, 5, u[5]), v, atol=1e-12)
+
+
+def test_randomized_svd_exact_on_low_rank():
+    rng = W.rng(23, 0)
+    A = rng.standard_normal((200, 5)) @ rng.standard_normal((5, 150))
+    R = rng.choice(200, 10, replace=False)
+    C = rng.choice(150, 10, replace=False)
+    U, s, V = randomized_svd(lambda i: A[i], lambda j: A[:, j], 200, 150, R, C, 5, rng)
+    assert np.linalg.norm(U @ np.diag(s) @ V.T - A) / np.linalg.norm(A) < 1e-10
+
+
+@pytest.mark.parametrize("r", [5, 6])
+def test_low_rank_factorization_lemma22_regime(r):
+    # Phi = x^T xi on [0,1)^3 x [0,1)^3 (Example 2's phase on lattices): increments
+    # along the paths stay below 1/4, so Lemma 2.2 applies and the recovery is exact
+    n, d = 8, 3
+    pts = np.array(np.unravel_index(np.arange(n ** d), (n,) * d)).T / n
+    X1, X2 = pts, pts * 0.9
+    Phi = lambda I, J: X1[I] @ X2[J].T
+    kr = lambda i: np.exp(2j * np.pi * Phi([i], np.arange(n ** d))[0])
+    kc = lambda j: np.exp(2j * np.pi * Phi(np.arange(n ** d), [j])[:, 0])
+    q = (0,) * d
+    P1 = recovery_path_lattice(d, n, q)
+    P2 = recovery_path_lattice(d, n, q)
+    U, V, H = low_rank_factorization(kr, kc, n ** d, P1, P2, r, 2, W.rng(23, r))
+    assert len(H.Dr) == 1 and len(H.Dc) == 1
+    S = W.index_sample(n ** d, 128, 23, 2)
+    Kt = np.exp(2j * np.pi * Phi(S, S))
+    assert eps_K(Kt, U, V, S) < 1e-12
+    # recovered rows and columns agree at every intersection (Lemma 2.2)
+    i, j = 17, 301
+    assert abs(H.row(i)[j] - H.col(j)[i]) < 1e-12
+    # e^{2 pi i Psi} = K on recovered entries
+    assert np.allclose(np.exp(2j * np.pi * H.row(i)), kr(i), atol=1e-12)
