@@ -1,0 +1,180 @@
+/*
+ * midbf.h -- C interface of the MI355X MIDBF library (libmidbf.so).
+ *
+ * The library evaluates the oscillatory transform
+ *     g(x) = sum_{xi in Omega} exp(2 pi i Phi(x, xi)) f(xi),   x in X      (Section 1, eq. 1)
+ * with the multidimensional interpolative decomposition butterfly
+ * factorization (MIDBF, Section 3): K ~ U^L ... U^h S V^h ... V^L.
+ *
+ * Point sets.  X = {0..n-1}^d / n and Omega = {0..n-1}^d - n/2 (integers),
+ * d = 2 or 3.  Points are numbered in C order (last coordinate fastest);
+ * vectors f and g are indexed by these numbers.
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device pointers (hipMalloc'ed or torch CUDA
+ *     tensors); all other pointers are host pointers.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *     Applies are asynchronous on `stream`; build and phase_recover may
+ *     synchronize it.
+ *   - Complex vectors are interleaved (re, im): complex128 for MIDBF_FP64,
+ *     complex64 for MIDBF_FP32 and MIDBF_SPLIT_BF16.  A block of nrhs vectors
+ *     is column-major: element (point p, rhs r) at [r * ld + p], ld >= N.
+ *   - No call throws; each returns a midbf_status and, on failure, leaves a
+ *     message for midbf_last_error() (per thread).
+ *   - The handle owns its device factors; the caller owns every buffer it
+ *     passes.  Calls on one handle must not overlap on different streams.
+ */
+#ifndef MIDBF_H
+#define MIDBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct midbf_plan* midbf_handle;
+
+typedef enum {
+    MIDBF_OK = 0,
+    MIDBF_ERR_ARG = -1,             /* invalid argument or null pointer            */
+    MIDBF_ERR_SHAPE = -2,           /* sizes inconsistent (n not leaf * 2^L, ...)  */
+    MIDBF_ERR_OOM = -3,             /* device allocation failed                    */
+    MIDBF_ERR_RANK_SATURATED = -4,  /* an ID kept as many pivots as samples        */
+    MIDBF_ERR_RECOVERY = -5,        /* phase recovery failed (tau schedule ran out) */
+    MIDBF_ERR_HIP = -6,             /* a HIP runtime call failed                   */
+    MIDBF_ERR_UNIMPLEMENTED = -7
+} midbf_status;
+
+/* Phase functions (Scenario 1 of Table 1: O(1) entry access). */
+typedef enum {
+    MIDBF_PHASE_LINEAR = 0,        /* Phi = x . xi                                          */
+    MIDBF_PHASE_FIO_ELLIPSE = 1,   /* Section 4, Example 1: x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),
+                                      c1 = (2 + sin 2pi x1 sin 2pi x2)/16,
+                                      c2 = (2 + cos 2pi x1 cos 2pi x2)/16  (d = 2)          */
+    MIDBF_PHASE_FIO_PIECEWISE = 2, /* x.xi + c(x)|xi|, c = (2 + sin 2pi x1)/16 if x1 < 1/2,
+                                      else (3 + cos 2pi x2)/16  (d = 2)                    */
+    MIDBF_PHASE_ISO3D = 3,         /* x.xi + c(x)|xi|, c = (3 + prod_q sin 2pi x_q)/100 (d = 3) */
+    MIDBF_PHASE_LOWRANK = 4        /* Phi = U V^T from phase_recover (Section 2.3.5, Alg. 7) */
+} midbf_phase_kind;
+
+typedef enum {
+    MIDBF_FP64 = 0,          /* FP64 factors and arithmetic                              */
+    MIDBF_FP32 = 1,          /* FP32 factors, FP32 accumulation                          */
+    MIDBF_SPLIT_BF16 = 2     /* factors and inputs split into bf16 hi + lo, three bf16
+                                products per real product, FP32 accumulation (MFMA)      */
+} midbf_precision;
+
+/* Bits of midbf_params.precisions: which factor copies the build keeps. */
+#define MIDBF_KEEP_FP64 1u
+#define MIDBF_KEEP_FP32 2u
+#define MIDBF_KEEP_BF16 4u
+
+typedef struct {
+    int d;               /* 2 or 3                                                     */
+    int n;               /* points per dimension; n = leaf_box * 2^L with L >= 1        */
+    double tol;          /* ID tolerance epsilon of the rank rule (Sec. 3.5), e.g. 1e-6 */
+    int leaf_box;        /* leaf side in points, n0 = leaf_box^d (paper: 8)            */
+    int oversample_t;    /* t of the linear-scaling ID: t*k samples (Sec. 3.2; paper 5) */
+    int k_cap;           /* rank cap per ID; 0 = no cap beyond min(samples, candidates) */
+    midbf_phase_kind phase;
+    const double* U_dev; /* MIDBF_PHASE_LOWRANK: N x r row-major FP64 (x side)          */
+    const double* V_dev; /* MIDBF_PHASE_LOWRANK: N x r row-major FP64 (xi side)         */
+    int r;               /* rank of U V^T                                               */
+    unsigned precisions; /* MIDBF_KEEP_* bits; 0 = all three                            */
+    size_t build_workspace_bytes; /* cap on transient build memory; 0 = 16 GiB          */
+} midbf_params;
+
+typedef struct {
+    int L, b, hstar;            /* tree depth, MSCS steps, level of the last IDs        */
+    long long ids;              /* interpolative decompositions performed              */
+    long long entries;          /* complex entries stored (T blocks plus middle)       */
+    long long bytes_fp64, bytes_fp32, bytes_bf16;  /* bytes of each factor copy        */
+    long long index_bytes;      /* permutation and offset tables read by an apply      */
+    int k_min, k_max;           /* ranks over all IDs                                  */
+    double build_seconds;       /* wall time of midbf_build                            */
+} midbf_stats;
+
+/*
+ * midbf_build -- factor K = (exp(2 pi i Phi(x, xi))) on the lattices
+ * (Sections 3.1-3.5): Z-ordered trees, then for steps s = 0..b-1 (b = ceil(L/2))
+ * batched interpolative decompositions of every block (row node at level L-s,
+ * column node at level s+1) and its transpose, from Mock-Chebyshev samples
+ * with FP64 column-pivoted QR and the adaptive rank rule
+ * k = #{j : |R_jj| > tol |R_11|}; then the middle factor from the last skeletons.
+ * Runs on the GPU of the current device; synchronizes `stream`.
+ * Errors: MIDBF_ERR_ARG / _SHAPE for bad params, _OOM, _RANK_SATURATED if
+ * doubling the samples could not lift a saturated ID, _HIP.
+ */
+midbf_status midbf_build(const midbf_params* p, void* stream, midbf_handle* out);
+
+/*
+ * midbf_apply -- g = K~ f for nrhs right-hand sides (the factor product of
+ * Sec. 3.5 applied right to left).  f_dev, g_dev: N x nrhs column-major with
+ * leading dimension ld (complex128 for MIDBF_FP64, complex64 otherwise).
+ * The precision's factor copy must have been kept.  Workspace for nrhs is
+ * allocated on the first call with that many right-hand sides.
+ */
+midbf_status midbf_apply(midbf_handle h, const void* f_dev, void* g_dev, int nrhs, long long ld,
+                         midbf_precision prec, void* stream);
+
+/*
+ * midbf_apply_adjoint -- f = K~^H g: conjugate-transposed factors in reverse
+ * order (the transposed butterfly).  Same layouts as midbf_apply.
+ */
+midbf_status midbf_apply_adjoint(midbf_handle h, const void* g_dev, void* f_dev, int nrhs, long long ld,
+                                 midbf_precision prec, void* stream);
+
+/*
+ * midbf_apply_batched -- count independent transforms (different handles,
+ * possibly different N) applied in one stream-ordered sequence of launches:
+ * g_j = K~_j f_j.  hs, f_devs, g_devs, nrhs are host arrays of length count;
+ * each f/g block is column-major with ld = N_j.
+ */
+midbf_status midbf_apply_batched(int count, const midbf_handle* hs, const void* const* f_devs,
+                                 void* const* g_devs, const int* nrhs, midbf_precision prec,
+                                 void* stream);
+
+/* Sizes and ranks of a built factorization. */
+midbf_status midbf_factor_stats(midbf_handle h, midbf_stats* out);
+
+/*
+ * midbf_ranks -- copy the ranks of step `step` (0..b-1) of side `side`
+ * (0 = row IDs / U factors, 1 = column IDs / V factors) into out[0..count).
+ * IDs are numbered node * P^(step+1) + partner.
+ */
+midbf_status midbf_ranks(midbf_handle h, int side, int step, int* out, long long count);
+
+/*
+ * midbf_kernel_entries -- out_dev[i * ncols + j] = K(x_rows[i], xi_cols[j])
+ * (complex128) for point numbers rows_dev[0..nrows) and cols_dev[0..ncols),
+ * with the phase of p (Sec. 3 preamble: entry evaluation from Phi in FP64,
+ * reduced mod 1 before the exponential).
+ */
+midbf_status midbf_kernel_entries(const midbf_params* p, const int* rows_dev, int nrows,
+                                  const int* cols_dev, int ncols, void* out_dev, void* stream);
+
+/*
+ * midbf_id_batch -- the batched FP64 interpolative decomposition on caller
+ * matrices (Sec. 3.2 with the rank rule of Sec. 3.5): for b = 0..batch-1,
+ * X_b = X_dev + b*m*n (m x n, row-major complex128, overwritten) is
+ * factored as X_b[:, perm] ~ X_b[:, perm[:k]] [I T].  Outputs: k_dev[b],
+ * perm_dev[b*n + j] (0-based column numbers, skeleton first) and
+ * T_dev + b*m*n holding T (k x (n-k), row-major, leading dimension n-k).
+ * Constraint: m <= 4096, n <= 2048.
+ */
+midbf_status midbf_id_batch(void* X_dev, int batch, int m, int n, double tol, int k_cap,
+                            int* k_dev, int* perm_dev, void* T_dev, void* stream);
+
+/* Release the factorization and its workspaces. */
+void midbf_destroy(midbf_handle h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* midbf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIDBF_H */

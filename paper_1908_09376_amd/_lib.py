@@ -1,0 +1,79 @@
+"""ctypes binding of libmidbf.so (include/midbf.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; PyTorch supplies device
+memory and the stream.  Importing this module fails loudly if the library
+has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmidbf.so")
+
+MIDBF_OK = 0
+STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_OOM", -4: "ERR_RANK_SATURATED",
+          -5: "ERR_RECOVERY", -6: "ERR_HIP", -7: "ERR_UNIMPLEMENTED"}
+
+PHASES = {"linear": 0, "fio_ellipse": 1, "fio_piecewise": 2, "iso3d": 3, "lowrank": 4}
+FP64, FP32, SPLIT_BF16 = 0, 1, 2
+KEEP_FP64, KEEP_FP32, KEEP_BF16 = 1, 2, 4
+
+
+class Params(C.Structure):
+    _fields_ = [("d", C.c_int), ("n", C.c_int), ("tol", C.c_double), ("leaf_box", C.c_int),
+                ("oversample_t", C.c_int), ("k_cap", C.c_int), ("phase", C.c_int),
+                ("U_dev", C.c_void_p), ("V_dev", C.c_void_p), ("r", C.c_int),
+                ("precisions", C.c_uint), ("build_workspace_bytes", C.c_size_t)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("L", C.c_int), ("b", C.c_int), ("hstar", C.c_int), ("ids", C.c_longlong),
+                ("entries", C.c_longlong), ("bytes_fp64", C.c_longlong), ("bytes_fp32", C.c_longlong),
+                ("bytes_bf16", C.c_longlong), ("index_bytes", C.c_longlong), ("k_min", C.c_int),
+                ("k_max", C.c_int), ("build_seconds", C.c_double)]
+
+
+class MidbfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1908_09376_amd.build_lib` (no CPU fallback exists)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, ll = C.c_void_p, C.c_int, C.c_longlong
+    sig = {
+        "midbf_build": (i, [C.POINTER(Params), vp, C.POINTER(vp)]),
+        "midbf_apply": (i, [vp, vp, vp, i, ll, i, vp]),
+        "midbf_apply_adjoint": (i, [vp, vp, vp, i, ll, i, vp]),
+        "midbf_apply_batched": (i, [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(i), i, vp]),
+        "midbf_factor_stats": (i, [vp, C.POINTER(Stats)]),
+        "midbf_ranks": (i, [vp, i, i, C.POINTER(i), ll]),
+        "midbf_kernel_entries": (i, [C.POINTER(Params), vp, i, vp, i, vp, vp]),
+        "midbf_id_batch": (i, [vp, i, i, i, C.c_double, i, vp, vp, vp, vp]),
+        "midbf_destroy": (None, [vp]),
+        "midbf_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(status: int) -> None:
+    if status != MIDBF_OK:
+        raise MidbfError(status, lib.midbf_last_error().decode())
+
+
+EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_batched",
+            "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",
+            "midbf_destroy", "midbf_last_error"]

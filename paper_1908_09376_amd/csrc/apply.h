@@ -1,0 +1,74 @@
+// Level kernels of the apply: argument blocks and launch entry.
+#pragma once
+
+#include "plan.h"
+
+namespace midbf {
+
+constexpr int APPLY_RT = 8;     // right-hand sides per workgroup, multi-RHS FP32 VALU path
+constexpr int APPLY_RT64 = 4;   // the same for FP64
+
+struct ApplyGeom {
+    int d, n, P, L, leaf, n0;
+};
+
+// Tables of one level (one step, one side) as seen by a kernel.
+struct LevelArgs {
+    const int* k;
+    const int* n;
+    const long long* perm_off;
+    const int* perm;
+    const long long* y_off;
+    const void* const* T;    // per-ID factor block of the precision in use
+};
+
+struct UpArgs {
+    ApplyGeom G;
+    LevelArgs lev;
+    int s;
+    long long Ps;            // P^s
+    const void* ext;         // s == 0: external input block (column-major, ld)
+    long long ld;
+    const void* in;          // s >= 1: previous level buffer
+    const int* k_prev;
+    const long long* yoff_prev;
+    void* out;               // this level's buffer
+    int nrhs;
+};
+
+struct DownArgs {
+    ApplyGeom G;
+    LevelArgs lev;
+    int s;
+    long long Ps;
+    const void* in;          // this level's buffer
+    void* ext;               // s == 0: external output block
+    long long ld;
+    void* out;               // s >= 1: previous level buffer
+    const int* k_prev;
+    const long long* yoff_prev;
+    int nrhs;
+    int ncand_max;
+};
+
+struct MidArgs {
+    const int* nr;
+    const int* nc;
+    const long long* off;
+    const void* S;
+    int pieces;
+    const long long* in_off;
+    const int* in_len;
+    const long long* out_off;
+    const int* out_len;
+    const void* in;
+    void* out;
+    int nrhs;
+};
+
+enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown };
+
+void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
+                         hipStream_t s);
+
+}  // namespace midbf

@@ -1,0 +1,449 @@
+// Apply of the MIDBF factor product g = U^L...U^h S V^h...V^L f and of its
+// adjoint (Sec. 3.3-3.5), level by level, FP64 or FP32 with accumulation in
+// the same precision.
+//
+// Vectors between levels: the level buffer of step s holds, for each
+// decomposition id (in id order), k_id rows of nrhs values; row-major
+// (right-hand side fastest), starting at row y_off[id].
+//
+// Workgroup = the 2^d decompositions that share one candidate vector:
+//   going up (V side), (B, A_t) for the children A_t of one row node share
+//   the concatenation of y[child(B), parent(A_t)];
+//   going down (U side), (A, B_t) for the children B_t of one column node
+//   share the candidate set of A, and their outputs are summed into it.
+// The 2^d-way butterfly permutations are index math on the Z-order numbers,
+// so each workgroup gathers its inputs and scatters its outputs directly and
+// no atomics are needed.
+#include "apply.h"
+
+namespace midbf {
+
+namespace {
+
+constexpr int AT = 256;   // threads per workgroup
+constexpr int AW = AT / 64;
+
+template <class C> __device__ inline C czero() { return cplx_traits<C>::zero(); }
+__device__ inline double2 ld_c(const double2* p) { return *p; }
+__device__ inline float2 ld_c(const float2* p) { return *p; }
+
+__device__ inline double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 sub2(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+template <class C> __device__ inline C wave_sum_c(C v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
+// Gather the candidate vector of group (a, partner) into LDS: either the
+// leaf's points from an external column-major block or the P child pieces
+// of the previous level buffer.
+template <class C, int RT>
+__device__ int gather_candidates(C* s_x, const ApplyGeom& G, int s, long long a, long long partner, long long Ps,
+                                 const C* ext, long long ld, const C* prev_buf, const int* k_prev,
+                                 const long long* yoff_prev, int nrhs, int r0, int nr) {
+    const int tid = threadIdx.x;
+    if (s == 0) {
+        int origin[3];
+        node_origin(a, G.L, G.d, G.n, origin);
+        for (int e = tid; e < G.n0 * RT; e += AT) {
+            const int c = e / RT, r = e - c * RT;
+            C v = czero<C>();
+            if (r < nr) v = ext[(long long)(r0 + r) * ld + box_point(origin, G.leaf, c, G.d, G.n)];
+            s_x[e] = v;
+        }
+        return G.n0;
+    }
+    int start = 0;
+    for (int t = 0; t < G.P; ++t) {
+        const long long idp = ((long long)G.P * a + t) * Ps + partner;
+        const int len = k_prev[idp];
+        const long long off = yoff_prev[idp];
+        for (int e = tid; e < len * RT; e += AT) {
+            const int c = e / RT, r = e - c * RT;
+            s_x[(start + c) * RT + r] = (r < nr) ? prev_buf[(off + c) * nrhs + r0 + r] : czero<C>();
+        }
+        start += len;
+    }
+    return start;
+}
+
+// Scatter a candidate vector (LDS) of group (a, partner) back to the leaf's
+// points of an external block or to the P child pieces of the previous level.
+template <class C, int RT>
+__device__ void scatter_candidates(const C* s_w, const ApplyGeom& G, int s, long long a, long long partner,
+                                   long long Ps, C* ext, long long ld, C* prev_buf, const int* k_prev,
+                                   const long long* yoff_prev, int nrhs, int r0, int nr) {
+    const int tid = threadIdx.x;
+    if (s == 0) {
+        int origin[3];
+        node_origin(a, G.L, G.d, G.n, origin);
+        for (int e = tid; e < G.n0 * RT; e += AT) {
+            const int c = e / RT, r = e - c * RT;
+            if (r < nr) ext[(long long)(r0 + r) * ld + box_point(origin, G.leaf, c, G.d, G.n)] = s_w[e];
+        }
+        return;
+    }
+    int start = 0;
+    for (int t = 0; t < G.P; ++t) {
+        const long long idp = ((long long)G.P * a + t) * Ps + partner;
+        const int len = k_prev[idp];
+        const long long off = yoff_prev[idp];
+        for (int e = tid; e < len * RT; e += AT) {
+            const int c = e / RT, r = e - c * RT;
+            if (r < nr) prev_buf[(off + c) * nrhs + r0 + r] = s_w[(start + c) * RT + r];
+        }
+        start += len;
+    }
+}
+
+// ---- forward, going up: y[id] = x[skel] + T x[red]  (T column-major k x (n-k)) ----
+template <class C, int RT, int OPL>
+__global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
+    extern __shared__ unsigned char smem_raw[];
+    C* s_x = reinterpret_cast<C*>(smem_raw);
+    const long long g = blockIdx.x;
+    const int r0 = blockIdx.y * RT;
+    const int nr = min(RT, A.nrhs - r0);
+    const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
+    gather_candidates<C, RT>(s_x, A.G, A.s, a, ap, A.Ps, (const C*)A.ext, A.ld, (const C*)A.in, A.k_prev,
+                             A.yoff_prev, A.nrhs, r0, nr);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    C* out = (C*)A.out;
+    for (int t = wave; t < A.G.P; t += AW) {
+        const long long id = g * A.G.P + t;
+        const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+        const int* perm = A.lev.perm + A.lev.perm_off[id];
+        const C* T = (const C*)A.lev.T[id];
+        const long long yo = A.lev.y_off[id];
+        for (int o0 = 0; o0 < k; o0 += 64 * OPL) {
+            C acc[OPL][RT];
+#pragma unroll
+            for (int u = 0; u < OPL; ++u)
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[u][r] = czero<C>();
+            int o[OPL];
+#pragma unroll
+            for (int u = 0; u < OPL; ++u) o[u] = o0 + lane + 64 * u;
+#pragma unroll 4
+            for (int j = 0; j < nred; ++j) {
+                const int pj = perm[k + j];
+                C xv[RT];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) xv[r] = s_x[pj * RT + r];
+#pragma unroll
+                for (int u = 0; u < OPL; ++u) {
+                    if (o[u] < k) {
+                        const C tv = T[(long long)j * k + o[u]];
+#pragma unroll
+                        for (int r = 0; r < RT; ++r) cfma(acc[u][r], tv, xv[r]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < OPL; ++u) {
+                if (o[u] < k) {
+                    const int ps = perm[o[u]];
+#pragma unroll
+                    for (int r = 0; r < RT; ++r)
+                        if (r < nr) out[(yo + o[u]) * A.nrhs + r0 + r] = cadd(acc[u][r], s_x[ps * RT + r]);
+                }
+            }
+        }
+    }
+}
+
+// ---- forward, going down: w(cand) = sum_t Pi_t [z_t ; T_t^T z_t]  (T row-major k x (n-k)) ----
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void down_kernel(DownArgs A) {
+    extern __shared__ unsigned char smem_raw[];
+    const long long g = blockIdx.x;
+    const int r0 = blockIdx.y * RT;
+    const int nr = min(RT, A.nrhs - r0);
+    const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
+    const int ncand = A.lev.n[g * A.G.P];
+    C* s_w = reinterpret_cast<C*>(smem_raw);
+    C* s_z = s_w + (size_t)A.ncand_max * RT;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < ncand * RT; e += AT) s_w[e] = czero<C>();
+    const C* zin = (const C*)A.in;
+    for (int t = 0; t < A.G.P; ++t) {
+        const long long id = g * A.G.P + t;
+        const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+        const int* perm = A.lev.perm + A.lev.perm_off[id];
+        const C* T = (const C*)A.lev.T[id];
+        const long long yo = A.lev.y_off[id];
+        __syncthreads();
+        for (int e = tid; e < k * RT; e += AT) {
+            const int i = e / RT, r = e - i * RT;
+            s_z[e] = (r < nr) ? zin[(yo + i) * A.nrhs + r0 + r] : czero<C>();
+        }
+        __syncthreads();
+        for (int e = tid; e < k * RT; e += AT) {
+            const int i = e / RT, r = e - i * RT;
+            const int ps = perm[i];
+            s_w[ps * RT + r] = cadd(s_w[ps * RT + r], s_z[e]);
+        }
+        for (int j = tid; j < nred; j += AT) {
+            C acc[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+#pragma unroll 4
+            for (int i = 0; i < k; ++i) {
+                const C tv = T[(long long)i * nred + j];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) cfma(acc[r], tv, s_z[i * RT + r]);
+            }
+            const int pr = perm[k + j];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) s_w[pr * RT + r] = cadd(s_w[pr * RT + r], acc[r]);
+        }
+    }
+    __syncthreads();
+    scatter_candidates<C, RT>(s_w, A.G, A.s, a, bp, A.Ps, (C*)A.ext, A.ld, (C*)A.out, A.k_prev, A.yoff_prev,
+                              A.nrhs, r0, nr);
+}
+
+// ---- middle: z(rows) = S x(cols), S column-major nr x nc ----
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void middle_kernel(MidArgs A) {
+    extern __shared__ unsigned char smem_raw[];
+    C* s_x = reinterpret_cast<C*>(smem_raw);
+    const long long bi = blockIdx.x;
+    const int r0 = blockIdx.y * RT;
+    const int nrr = min(RT, A.nrhs - r0);
+    const int nr = A.nr[bi], nc = A.nc[bi];
+    const int tid = threadIdx.x;
+    const C* xin = (const C*)A.in;
+    C* zout = (C*)A.out;
+    // input pieces (columns of S)
+    int start = 0;
+    for (int t = 0; t < A.pieces; ++t) {
+        const long long off = A.in_off[bi * A.pieces + t];
+        const int len = A.in_len[bi * A.pieces + t];
+        for (int e = tid; e < len * RT; e += AT) {
+            const int c = e / RT, r = e - c * RT;
+            s_x[(start + c) * RT + r] = (r < nrr) ? xin[(off + c) * A.nrhs + r0 + r] : czero<C>();
+        }
+        start += len;
+    }
+    __syncthreads();
+    const C* S = (const C*)A.S + A.off[bi];
+    for (int row = tid; row < nr; row += AT) {
+        C acc[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+#pragma unroll 4
+        for (int c = 0; c < nc; ++c) {
+            const C sv = S[(long long)c * nr + row];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) cfma(acc[r], sv, s_x[c * RT + r]);
+        }
+        // output piece of this row
+        int t = 0, base = 0;
+        while (t + 1 < A.pieces && row >= base + A.out_len[bi * A.pieces + t]) {
+            base += A.out_len[bi * A.pieces + t];
+            ++t;
+        }
+        const long long off = A.out_off[bi * A.pieces + t] + (row - base);
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+            if (r < nrr) zout[off * A.nrhs + r0 + r] = acc[r];
+    }
+}
+
+// ---- adjoint going up (row side): out_i = x[skel_i] + sum_j conj(T_ij) x[red_j], T row-major ----
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void adj_up_kernel(UpArgs A) {
+    extern __shared__ unsigned char smem_raw[];
+    C* s_x = reinterpret_cast<C*>(smem_raw);
+    const long long g = blockIdx.x;
+    const int r0 = blockIdx.y * RT;
+    const int nr = min(RT, A.nrhs - r0);
+    const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
+    gather_candidates<C, RT>(s_x, A.G, A.s, a, bp, A.Ps, (const C*)A.ext, A.ld, (const C*)A.in, A.k_prev,
+                             A.yoff_prev, A.nrhs, r0, nr);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    C* out = (C*)A.out;
+    for (int t = 0; t < A.G.P; ++t) {
+        const long long id = g * A.G.P + t;
+        const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+        const int* perm = A.lev.perm + A.lev.perm_off[id];
+        const C* T = (const C*)A.lev.T[id];
+        const long long yo = A.lev.y_off[id];
+        for (int i = wave; i < k; i += AW) {
+            C acc[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+            const C* Ti = T + (long long)i * nred;
+            for (int j = lane; j < nred; j += 64) {
+                const C tv = Ti[j];
+                const int pj = perm[k + j];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) cfmac(acc[r], tv, s_x[pj * RT + r]);
+            }
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = wave_sum_c(acc[r]);
+            if (lane == 0) {
+                const int ps = perm[i];
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+                    if (r < nr) out[(yo + i) * A.nrhs + r0 + r] = cadd(acc[r], s_x[ps * RT + r]);
+            }
+        }
+    }
+}
+
+// ---- adjoint middle: x(cols) = S^H z(rows) ----
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void adj_middle_kernel(MidArgs A) {
+    extern __shared__ unsigned char smem_raw[];
+    C* s_z = reinterpret_cast<C*>(smem_raw);
+    const long long bi = blockIdx.x;
+    const int r0 = blockIdx.y * RT;
+    const int nrr = min(RT, A.nrhs - r0);
+    const int nr = A.nr[bi], nc = A.nc[bi];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const C* zin = (const C*)A.in;
+    C* xout = (C*)A.out;
+    int start = 0;
+    for (int t = 0; t < A.pieces; ++t) {          // input: row pieces
+        const long long off = A.out_off[bi * A.pieces + t];
+        const int len = A.out_len[bi * A.pieces + t];
+        for (int e = tid; e < len * RT; e += AT) {
+            const int c = e / RT, r = e - c * RT;
+            s_z[(start + c) * RT + r] = (r < nrr) ? zin[(off + c) * A.nrhs + r0 + r] : czero<C>();
+        }
+        start += len;
+    }
+    __syncthreads();
+    const C* S = (const C*)A.S + A.off[bi];
+    for (int col = wave; col < nc; col += AW) {
+        C acc[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+        const C* Sc = S + (long long)col * nr;
+        for (int row = lane; row < nr; row += 64) {
+            const C sv = Sc[row];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) cfmac(acc[r], sv, s_z[row * RT + r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[r] = wave_sum_c(acc[r]);
+        if (lane == 0) {
+            int t = 0, base = 0;
+            while (t + 1 < A.pieces && col >= base + A.in_len[bi * A.pieces + t]) {
+                base += A.in_len[bi * A.pieces + t];
+                ++t;
+            }
+            const long long off = A.in_off[bi * A.pieces + t] + (col - base);
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                if (r < nrr) xout[off * A.nrhs + r0 + r] = acc[r];
+        }
+    }
+}
+
+// ---- adjoint going down (column side): w(cand) = sum_t Pi_t [z_t ; T_t^H z_t], T column-major ----
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void adj_down_kernel(DownArgs A) {
+    extern __shared__ unsigned char smem_raw[];
+    const long long g = blockIdx.x;
+    const int r0 = blockIdx.y * RT;
+    const int nr = min(RT, A.nrhs - r0);
+    const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
+    const int ncand = A.lev.n[g * A.G.P];
+    C* s_w = reinterpret_cast<C*>(smem_raw);
+    C* s_z = s_w + (size_t)A.ncand_max * RT;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int e = tid; e < ncand * RT; e += AT) s_w[e] = czero<C>();
+    const C* zin = (const C*)A.in;
+    for (int t = 0; t < A.G.P; ++t) {
+        const long long id = g * A.G.P + t;
+        const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+        const int* perm = A.lev.perm + A.lev.perm_off[id];
+        const C* T = (const C*)A.lev.T[id];
+        const long long yo = A.lev.y_off[id];
+        __syncthreads();
+        for (int e = tid; e < k * RT; e += AT) {
+            const int i = e / RT, r = e - i * RT;
+            s_z[e] = (r < nr) ? zin[(yo + i) * A.nrhs + r0 + r] : czero<C>();
+        }
+        __syncthreads();
+        for (int e = tid; e < k * RT; e += AT) {
+            const int i = e / RT, r = e - i * RT;
+            const int ps = perm[i];
+            s_w[ps * RT + r] = cadd(s_w[ps * RT + r], s_z[e]);
+        }
+        for (int j = wave; j < nred; j += AW) {
+            C acc[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+            const C* Tj = T + (long long)j * k;
+            for (int i = lane; i < k; i += 64) {
+                const C tv = Tj[i];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) cfmac(acc[r], tv, s_z[i * RT + r]);
+            }
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = wave_sum_c(acc[r]);
+            if (lane == 0) {
+                const int pr = perm[k + j];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) s_w[pr * RT + r] = cadd(s_w[pr * RT + r], acc[r]);
+            }
+        }
+    }
+    __syncthreads();
+    scatter_candidates<C, RT>(s_w, A.G, A.s, a, ap, A.Ps, (C*)A.ext, A.ld, (C*)A.out, A.k_prev, A.yoff_prev,
+                              A.nrhs, r0, nr);
+}
+
+template <class C, int RT>
+void launch_level(LevelKernel which, const void* args, dim3 grid, size_t smem, hipStream_t s) {
+    switch (which) {
+        case LevelKernel::Up:
+            if (RT == 1)
+                hipLaunchKernelGGL((up_kernel<C, RT, 2>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
+            else
+                hipLaunchKernelGGL((up_kernel<C, RT, 1>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
+            break;
+        case LevelKernel::Down:
+            hipLaunchKernelGGL((down_kernel<C, RT>), grid, dim3(AT), smem, s, *(const DownArgs*)args);
+            break;
+        case LevelKernel::Middle:
+            hipLaunchKernelGGL((middle_kernel<C, RT>), grid, dim3(AT), smem, s, *(const MidArgs*)args);
+            break;
+        case LevelKernel::AdjUp:
+            hipLaunchKernelGGL((adj_up_kernel<C, RT>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
+            break;
+        case LevelKernel::AdjMiddle:
+            hipLaunchKernelGGL((adj_middle_kernel<C, RT>), grid, dim3(AT), smem, s, *(const MidArgs*)args);
+            break;
+        case LevelKernel::AdjDown:
+            hipLaunchKernelGGL((adj_down_kernel<C, RT>), grid, dim3(AT), smem, s, *(const DownArgs*)args);
+            break;
+    }
+    MIDBF_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
+                         hipStream_t s) {
+    if (prec == PREC_FP64) {
+        if (rt == 1) launch_level<double2, 1>(which, args, grid, smem, s);
+        else launch_level<double2, APPLY_RT64>(which, args, grid, smem, s);
+    } else {
+        if (rt == 1) launch_level<float2, 1>(which, args, grid, smem, s);
+        else launch_level<float2, APPLY_RT>(which, args, grid, smem, s);
+    }
+}
+
+}  // namespace midbf

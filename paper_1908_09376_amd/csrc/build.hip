@@ -1,0 +1,605 @@
+// Factor construction (Sec. 3.1-3.5): trees, Mock-Chebyshev samples, batched
+// interpolative decompositions per unrolled MSCS step, factor packing and
+// the middle blocks.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "build.h"
+#include "id.h"
+
+namespace midbf {
+
+namespace {
+
+constexpr int BT = 256;
+
+// ---- kernels ------------------------------------------------------------
+
+struct CandArgs {
+    int s, P, d, n, L, leaf, la, lb;
+    long long id0, Ps;          // first ID of the wave; P^s
+    long long nB;               // partners per node, P^lb
+    const int* n_arr;           // per wave ID
+    const int* k_prev;
+    const long long* yoff_prev;
+    const int* skel_prev;
+    int* cand;                  // wave x nmax
+    int nmax;
+};
+
+// Candidate lattice points of each decomposition: the points of the leaf
+// (s = 0) or the children's skeletons against the partner's parent.
+__global__ void cand_kernel(CandArgs A) {
+    const int w = blockIdx.x;
+    const long long id = A.id0 + w;
+    const long long a = id / A.nB, bb = id - (id / A.nB) * A.nB;
+    const int ncand = A.n_arr[w];
+    int* out = A.cand + (long long)w * A.nmax;
+    if (A.s == 0) {
+        int origin[3];
+        node_origin(a, A.L, A.d, A.n, origin);
+        for (int c = threadIdx.x; c < ncand; c += BT) out[c] = (int)box_point(origin, A.leaf, c, A.d, A.n);
+        return;
+    }
+    const long long pb = bb / A.P;
+    int start = 0;
+    for (int t = 0; t < A.P; ++t) {
+        const long long idp = ((long long)A.P * a + t) * A.Ps + pb;
+        const int len = A.k_prev[idp];
+        const long long off = A.yoff_prev[idp];
+        for (int c = threadIdx.x; c < len; c += BT) out[start + c] = A.skel_prev[off + c];
+        start += len;
+    }
+}
+
+struct GenArgs {
+    PhaseDesc ph;
+    int side, lb;
+    long long id0, nB;
+    int m;
+    const int* samples;         // local indices within the partner box (m)
+    int box_side;
+    const int* n_arr;
+    const int* cand;
+    int nmax;
+    double2* X;
+    long long x_stride;
+};
+
+// Sample matrix of decomposition w, row-major m x n:
+//   row side:    X[i][c] = K(x = cand_c, xi = sample_i)   (X = K(cand, samples)^T)
+//   column side: X[i][c] = K(x = sample_i, xi = cand_c)   (X = K(samples, cand))
+__global__ void gen_kernel(GenArgs A) {
+    const int w = blockIdx.y;
+    const long long id = A.id0 + w;
+    const long long bb = id - (id / A.nB) * A.nB;
+    const int n = A.n_arr[w];
+    int origin[3];
+    node_origin(bb, A.lb, A.ph.d, A.ph.n, origin);
+    const int* cand = A.cand + (long long)w * A.nmax;
+    double2* X = A.X + (long long)w * A.x_stride;
+    const long long total = (long long)A.m * n;
+    for (long long e = (long long)blockIdx.x * BT + threadIdx.x; e < total; e += (long long)gridDim.x * BT) {
+        const int i = (int)(e / n), c = (int)(e - (e / n) * n);
+        const long long sp = box_point(origin, A.box_side, A.samples[i], A.ph.d, A.ph.n);
+        const long long cp = cand[c];
+        X[e] = (A.side == SIDE_ROW) ? kernel_entry(A.ph, cp, sp) : kernel_entry(A.ph, sp, cp);
+    }
+}
+
+struct PackArgs {
+    int side;
+    long long id0;
+    const int* k_w;
+    const int* n_w;
+    const double2* X;
+    long long x_stride;
+    const int* perm_w;
+    long long p_stride;
+    const int* cand;
+    int nmax;
+    const long long* toff_w;    // per wave ID: element offset of T in the wave's chunk
+    double2* T64;
+    float2* T32;
+    const long long* perm_off;  // level tables (global ID)
+    const long long* y_off;
+    int* perm;
+    int* skel;
+};
+
+// Copy T of each decomposition into the factor store (column-major k x (n-k)
+// for the column side, row-major for the row side), its candidate
+// permutation, and its skeleton lattice points.
+__global__ void pack_kernel(PackArgs A) {
+    const int w = blockIdx.x;
+    const long long id = A.id0 + w;
+    const int k = A.k_w[w], n = A.n_w[w], nred = n - k;
+    const double2* X = A.X + (long long)w * A.x_stride;
+    const int* pw = A.perm_w + (long long)w * A.p_stride;
+    const int* cand = A.cand + (long long)w * A.nmax;
+    int* pd = A.perm + A.perm_off[id];
+    for (int j = threadIdx.x; j < n; j += BT) pd[j] = pw[j];
+    int* sk = A.skel + A.y_off[id];
+    for (int i = threadIdx.x; i < k; i += BT) sk[i] = cand[pw[i]];
+    const long long to = A.toff_w[w];
+    const long long tot = (long long)k * nred;
+    for (long long e = threadIdx.x; e < tot; e += BT) {
+        int i, j;
+        if (A.side == SIDE_COL) { j = (int)(e / k); i = (int)(e - (long long)j * k); }
+        else { i = (int)(e / nred); j = (int)(e - (long long)i * nred); }
+        const double2 v = X[(long long)i * n + k + j];
+        if (A.T64) A.T64[to + e] = v;
+        if (A.T32) A.T32[to + e] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+struct MidGenArgs {
+    PhaseDesc ph;
+    const int* nr;
+    const int* nc;
+    const long long* off;       // element offset of block bi
+    const long long* pts_off;   // offset of block bi's row points, then column points
+    const int* pts;
+    double2* S64;
+    float2* S32;
+};
+
+// Middle block bi, column-major nr x nc: S = K(row skeletons, column skeletons).
+__global__ void midgen_kernel(MidGenArgs A) {
+    const long long bi = blockIdx.y;
+    const int nr = A.nr[bi], nc = A.nc[bi];
+    const int* rp = A.pts + A.pts_off[bi];
+    const int* cp = rp + nr;
+    const long long base = A.off[bi];
+    const long long tot = (long long)nr * nc;
+    for (long long e = (long long)blockIdx.x * BT + threadIdx.x; e < tot; e += (long long)gridDim.x * BT) {
+        const int c = (int)(e / nr), r = (int)(e - (long long)c * nr);
+        const double2 v = kernel_entry(A.ph, rp[r], cp[c]);
+        if (A.S64) A.S64[base + e] = v;
+        if (A.S32) A.S32[base + e] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void entries_kernel(PhaseDesc ph, const int* rows, int nrows, const int* cols, int ncols, double2* out) {
+    const long long tot = (long long)nrows * ncols;
+    for (long long e = (long long)blockIdx.x * BT + threadIdx.x; e < tot; e += (long long)gridDim.x * BT) {
+        const int i = (int)(e / ncols), j = (int)(e - (long long)i * ncols);
+        out[e] = kernel_entry(ph, rows[i], cols[j]);
+    }
+}
+
+__global__ void copy_T_kernel(const double2* X, long long x_stride, const int* k_arr, int m, int n, double2* T) {
+    const int b = blockIdx.x;
+    const int k = k_arr[b], nred = n - k;
+    const double2* src = X + (long long)b * x_stride;
+    double2* dst = T + (long long)b * m * n;
+    for (long long e = threadIdx.x; e < (long long)k * nred; e += BT) {
+        const int i = (int)(e / nred), j = (int)(e - (long long)i * nred);
+        dst[e] = src[(long long)i * n + k + j];
+    }
+}
+
+// ---- host helpers -------------------------------------------------------
+
+template <class T> T* dalloc(size_t count) {
+    T* p = nullptr;
+    if (count == 0) count = 1;
+    MIDBF_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    return p;
+}
+
+template <class T> void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+    if (!src.empty()) MIDBF_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// Local indices (C order inside a box of the given side) of the Mock-
+// Chebyshev samples: per dimension q = ceil(count^(1/d)) Chebyshev-Lobatto
+// nodes over [0, side-1] rounded to the nearest index (duplicates removed);
+// the whole box when q >= side (Sec. 3.2).
+std::vector<int> mock_chebyshev_local(int d, int side, long long count) {
+    int q = 1;
+    while (ipow(q, d) < count) ++q;
+    std::vector<int> loc;
+    if (q >= side) {
+        for (int i = 0; i < side; ++i) loc.push_back(i);
+    } else {
+        for (int j = 0; j < q; ++j) {
+            double node = 0.5 * (side - 1) * (1.0 - std::cos(M_PI * j / (q - 1)));
+            int v = (int)std::floor(node + 0.5);
+            if (loc.empty() || loc.back() != v) loc.push_back(v);
+        }
+    }
+    std::vector<int> out;
+    const int l = (int)loc.size();
+    long long tot = ipow(l, d);
+    out.reserve(tot);
+    for (long long e = 0; e < tot; ++e) {
+        long long r = e;
+        int idx = 0;
+        int mul = 1;
+        int digits[3];
+        for (int qd = d - 1; qd >= 0; --qd) { digits[qd] = loc[r % l]; r /= l; }
+        idx = 0;
+        for (int qd = 0; qd < d; ++qd) idx = idx * side + digits[qd];
+        (void)mul;
+        out.push_back(idx);
+    }
+    return out;
+}
+
+void free_level(LevelSide& lv) {
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(lv.d_k); f(lv.d_n); f(lv.d_perm_off); f(lv.d_y_off); f(lv.d_perm); f(lv.d_skel);
+    for (int q = 0; q < NPREC; ++q) f(lv.d_T[q]);
+    for (void* c : lv.chunks) f(c);
+    lv.d_k = lv.d_n = nullptr; lv.d_perm_off = lv.d_y_off = nullptr; lv.d_perm = lv.d_skel = nullptr;
+    for (int q = 0; q < NPREC; ++q) lv.d_T[q] = nullptr;
+    lv.chunks.clear();
+}
+
+struct Scratch {
+    double2* X = nullptr; double2* V = nullptr; double2* Y = nullptr;
+    int* perm = nullptr; int* cand = nullptr; int* k = nullptr; int* n = nullptr; long long* toff = nullptr;
+    int* samples = nullptr;
+    long long wave = 0, xs = 0, vs = 0, ys = 0, nmax = 0;
+    void release() {
+        auto f = [](void* p) { if (p) (void)hipFree(p); };
+        f(X); f(V); f(Y); f(perm); f(cand); f(k); f(n); f(toff); f(samples);
+        *this = Scratch();
+    }
+};
+
+// Decompositions of one step and side.  Returns false if some ID kept as
+// many pivots as it had samples while more samples were available.
+bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long want, hipStream_t st) {
+    const int P = h->P, d = h->d;
+    const int side_len = h->n >> lv.lb;
+    std::vector<int> samples = mock_chebyshev_local(d, side_len, want);
+    lv.m = (int)samples.size();
+    MIDBF_CHECK(lv.m <= ID_MMAX, MIDBF_ERR_SHAPE, "too many samples per decomposition");
+    const long long nid = lv.nid;
+    const long long nB = ipow(P, lv.lb);
+    const long long Ps = ipow(P, lv.s);
+    // candidate counts
+    lv.n.assign(nid, 0);
+    for (long long id = 0; id < nid; ++id) {
+        if (lv.s == 0) { lv.n[id] = h->n0; continue; }
+        const long long a = id / nB, pb = (id % nB) / P;
+        int c = 0;
+        for (int t = 0; t < P; ++t) c += prev->k[((long long)P * a + t) * Ps + pb];
+        lv.n[id] = c;
+    }
+    lv.nmax = *std::max_element(lv.n.begin(), lv.n.end());
+    MIDBF_CHECK(lv.nmax <= ID_NMAX, MIDBF_ERR_SHAPE, "too many candidates per decomposition (rank too large)");
+    lv.perm_off.assign(nid + 1, 0);
+    for (long long id = 0; id < nid; ++id) lv.perm_off[id + 1] = lv.perm_off[id] + lv.n[id];
+    lv.total_n = lv.perm_off[nid];
+    lv.perm_off.resize(nid);
+    lv.k.assign(nid, 0);
+    lv.y_off.assign(nid, 0);
+
+    lv.d_k = dalloc<int>(nid);
+    lv.d_n = dalloc<int>(nid);
+    lv.d_perm_off = dalloc<long long>(nid);
+    lv.d_y_off = dalloc<long long>(nid);
+    lv.d_perm = dalloc<int>(lv.total_n);
+    lv.d_skel = dalloc<int>(lv.total_n);
+    upload(lv.d_n, lv.n, st);
+    upload(lv.d_perm_off, lv.perm_off, st);
+    for (int q = 0; q < NPREC; ++q)
+        if (h->keep & (1u << q)) lv.d_T[q] = (void**)dalloc<void*>(nid);
+
+    // wave size from the workspace budget
+    const long long nmax = lv.nmax, m = lv.m;
+    const long long per = (m * nmax + m * ID_NB + (long long)ID_ELL * nmax) * 16 + nmax * 8 + 64;
+    long long wave = (long long)(h->p.build_workspace_bytes / per);
+    wave = std::max<long long>(1, std::min<long long>(wave, nid));
+    wave = std::min<long long>(wave, 65535);
+    Scratch sc;
+    sc.wave = wave; sc.nmax = nmax;
+    sc.xs = m * nmax; sc.vs = m * ID_NB; sc.ys = (long long)ID_ELL * nmax;
+    sc.X = dalloc<double2>(wave * sc.xs);
+    sc.V = dalloc<double2>(wave * sc.vs);
+    sc.Y = dalloc<double2>(wave * sc.ys);
+    sc.perm = dalloc<int>(wave * nmax);
+    sc.cand = dalloc<int>(wave * nmax);
+    sc.k = dalloc<int>(wave);
+    sc.toff = dalloc<long long>(wave);
+    sc.samples = dalloc<int>(m);
+    upload(sc.samples, samples, st);
+
+    bool saturated = false;
+    long long yrun = 0;
+    const long long box_pts = ipow(side_len, d);
+    try {
+        for (long long id0 = 0; id0 < nid; id0 += wave) {
+            const int cnt = (int)std::min<long long>(wave, nid - id0);
+            CandArgs ca{lv.s, P, d, h->n, h->L, h->leaf, lv.la, lv.lb, id0, Ps, nB, lv.d_n + id0,
+                        prev ? prev->d_k : nullptr, prev ? prev->d_y_off : nullptr, prev ? prev->d_skel : nullptr,
+                        sc.cand, (int)nmax};
+            hipLaunchKernelGGL(cand_kernel, dim3(cnt), dim3(BT), 0, st, ca);
+            MIDBF_HIP(hipGetLastError());
+            GenArgs ga{h->ph, lv.side, lv.lb, id0, nB, (int)m, sc.samples, side_len, lv.d_n + id0, sc.cand,
+                       (int)nmax, sc.X, sc.xs};
+            const int gx = (int)std::min<long long>((m * nmax + BT - 1) / BT, 64);
+            hipLaunchKernelGGL(gen_kernel, dim3(gx, cnt), dim3(BT), 0, st, ga);
+            MIDBF_HIP(hipGetLastError());
+            IdBatch ib{sc.X, sc.xs, sc.V, sc.vs, sc.Y, sc.ys, sc.perm, nmax, sc.k, lv.d_n + id0, 0, (int)m,
+                       h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side)};
+            launch_id_batch(ib, cnt, st);
+            std::vector<int> kw(cnt);
+            MIDBF_HIP(hipMemcpyAsync(kw.data(), sc.k, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+            MIDBF_HIP(hipStreamSynchronize(st));
+            std::vector<long long> toff(cnt);
+            long long tw = 0;
+            for (int w = 0; w < cnt; ++w) {
+                const long long id = id0 + w;
+                const int k = kw[w], nn = lv.n[id];
+                if (k >= m && m < box_pts && m < nn) saturated = true;
+                lv.k[id] = k;
+                lv.y_off[id] = yrun;
+                yrun += k;
+                toff[w] = tw;
+                tw += (long long)k * (nn - k);
+            }
+            if (saturated) break;
+            const std::vector<long long> yw(lv.y_off.begin() + id0, lv.y_off.begin() + id0 + cnt);
+            upload(lv.d_y_off + id0, yw, st);
+            upload(sc.toff, toff, st);
+            double2* c64 = nullptr;
+            float2* c32 = nullptr;
+            if (h->keep & MIDBF_KEEP_FP64) { c64 = dalloc<double2>(tw); lv.chunks.push_back(c64); }
+            if (h->keep & (MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16)) { c32 = dalloc<float2>(tw); lv.chunks.push_back(c32); }
+            PackArgs pa{lv.side, id0, sc.k, lv.d_n + id0, sc.X, sc.xs, sc.perm, nmax, sc.cand, (int)nmax, sc.toff,
+                        c64, c32, lv.d_perm_off, lv.d_y_off, lv.d_perm, lv.d_skel};
+            hipLaunchKernelGGL(pack_kernel, dim3(cnt), dim3(BT), 0, st, pa);
+            MIDBF_HIP(hipGetLastError());
+            // per-ID block pointers
+            std::vector<void*> p64(cnt), p32(cnt);
+            for (int w = 0; w < cnt; ++w) {
+                p64[w] = c64 ? (void*)(c64 + toff[w]) : nullptr;
+                p32[w] = c32 ? (void*)(c32 + toff[w]) : nullptr;
+            }
+            if (lv.d_T[PREC_FP64]) upload((void**)lv.d_T[PREC_FP64] + id0, p64, st);
+            if (lv.d_T[PREC_FP32]) upload((void**)lv.d_T[PREC_FP32] + id0, p32, st);
+            if (lv.d_T[PREC_BF16]) upload((void**)lv.d_T[PREC_BF16] + id0, p32, st);
+            MIDBF_HIP(hipStreamSynchronize(st));
+        }
+    } catch (...) {
+        sc.release();
+        throw;
+    }
+    sc.release();
+    if (saturated) return false;
+    upload(lv.d_k, lv.k, st);
+    lv.total_k = yrun;
+    lv.kmin = *std::min_element(lv.k.begin(), lv.k.end());
+    lv.kmax = *std::max_element(lv.k.begin(), lv.k.end());
+    lv.entries = 0;
+    for (long long id = 0; id < nid; ++id) lv.entries += (long long)lv.k[id] * (lv.n[id] - lv.k[id]);
+    MIDBF_HIP(hipStreamSynchronize(st));
+    return true;
+}
+
+void build_middle(midbf_plan* h, hipStream_t st) {
+    Middle& M = h->mid;
+    const int P = h->P;
+    const LevelSide& R = h->rows.back();
+    const LevelSide& C = h->cols.back();
+    const long long nb = ipow(P, h->b);
+    const bool odd = (h->L % 2) == 1;
+    M.pieces = odd ? 1 : P;
+    M.nblk = nb * nb;
+    std::vector<int> skR(R.total_k), skC(C.total_k);
+    MIDBF_HIP(hipMemcpyAsync(skR.data(), R.d_skel, R.total_k * sizeof(int), hipMemcpyDeviceToHost, st));
+    MIDBF_HIP(hipMemcpyAsync(skC.data(), C.d_skel, C.total_k * sizeof(int), hipMemcpyDeviceToHost, st));
+    MIDBF_HIP(hipStreamSynchronize(st));
+    M.nr.assign(M.nblk, 0);
+    M.nc.assign(M.nblk, 0);
+    M.off.assign(M.nblk, 0);
+    std::vector<long long> in_off(M.nblk * M.pieces), out_off(M.nblk * M.pieces), pts_off(M.nblk);
+    std::vector<int> in_len(M.nblk * M.pieces), out_len(M.nblk * M.pieces);
+    std::vector<int> pts;
+    long long tot = 0;
+    const long long Pb = ipow(P, h->b);
+    for (long long a = 0; a < nb; ++a) {
+        for (long long bb = 0; bb < nb; ++bb) {
+            const long long bi = a * nb + bb;
+            pts_off[bi] = (long long)pts.size();
+            int nr = 0, nc = 0;
+            for (int t = 0; t < M.pieces; ++t) {
+                const long long rid = odd ? bi : ((long long)P * a + t) * Pb + bb;
+                const long long cid = odd ? bb * Pb + a : ((long long)P * bb + t) * Pb + a;
+                out_off[bi * M.pieces + t] = R.y_off[rid];
+                out_len[bi * M.pieces + t] = R.k[rid];
+                in_off[bi * M.pieces + t] = C.y_off[cid];
+                in_len[bi * M.pieces + t] = C.k[cid];
+                nr += R.k[rid];
+                nc += C.k[cid];
+            }
+            for (int t = 0; t < M.pieces; ++t) {
+                const long long rid = odd ? bi : ((long long)P * a + t) * Pb + bb;
+                for (int i = 0; i < R.k[rid]; ++i) pts.push_back(skR[R.y_off[rid] + i]);
+            }
+            for (int t = 0; t < M.pieces; ++t) {
+                const long long cid = odd ? bb * Pb + a : ((long long)P * bb + t) * Pb + a;
+                for (int i = 0; i < C.k[cid]; ++i) pts.push_back(skC[C.y_off[cid] + i]);
+            }
+            M.nr[bi] = nr;
+            M.nc[bi] = nc;
+            M.off[bi] = tot;
+            tot += (long long)nr * nc;
+        }
+    }
+    M.total = tot;
+    M.nr_max = *std::max_element(M.nr.begin(), M.nr.end());
+    M.nc_max = *std::max_element(M.nc.begin(), M.nc.end());
+    M.d_nr = dalloc<int>(M.nblk);
+    M.d_nc = dalloc<int>(M.nblk);
+    M.d_off = dalloc<long long>(M.nblk);
+    M.d_in_off = dalloc<long long>(in_off.size());
+    M.d_out_off = dalloc<long long>(out_off.size());
+    M.d_in_len = dalloc<int>(in_len.size());
+    M.d_out_len = dalloc<int>(out_len.size());
+    upload(M.d_nr, M.nr, st);
+    upload(M.d_nc, M.nc, st);
+    upload(M.d_off, M.off, st);
+    upload(M.d_in_off, in_off, st);
+    upload(M.d_out_off, out_off, st);
+    upload(M.d_in_len, in_len, st);
+    upload(M.d_out_len, out_len, st);
+    int* d_pts = dalloc<int>(pts.size());
+    long long* d_pts_off = dalloc<long long>(M.nblk);
+    upload(d_pts, pts, st);
+    upload(d_pts_off, pts_off, st);
+    double2* S64 = nullptr;
+    float2* S32 = nullptr;
+    if (h->keep & MIDBF_KEEP_FP64) S64 = dalloc<double2>(tot);
+    if (h->keep & (MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16)) S32 = dalloc<float2>(tot);
+    M.S[PREC_FP64] = S64;
+    M.S[PREC_FP32] = S32;
+    MidGenArgs ma{h->ph, M.d_nr, M.d_nc, M.d_off, d_pts_off, d_pts, S64, S32};
+    const long long per = (long long)M.nr_max * M.nc_max;
+    const int gx = (int)std::max<long long>(1, std::min<long long>((per + BT - 1) / BT, 256));
+    for (long long b0 = 0; b0 < M.nblk; b0 += 65535) {
+        const long long cnt = std::min<long long>(65535, M.nblk - b0);
+        MidGenArgs mb = ma;
+        mb.nr += b0; mb.nc += b0; mb.off += b0; mb.pts_off += b0;
+        hipLaunchKernelGGL(midgen_kernel, dim3(gx, (unsigned)cnt), dim3(BT), 0, st, mb);
+        MIDBF_HIP(hipGetLastError());
+    }
+    MIDBF_HIP(hipStreamSynchronize(st));
+    (void)hipFree(d_pts);
+    (void)hipFree(d_pts_off);
+}
+
+}  // namespace
+
+void destroy_plan(midbf_plan* h) {
+    if (!h) return;
+    for (auto& lv : h->rows) free_level(lv);
+    for (auto& lv : h->cols) free_level(lv);
+    Middle& M = h->mid;
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(M.d_nr); f(M.d_nc); f(M.d_off); f(M.d_in_off); f(M.d_in_len); f(M.d_out_off); f(M.d_out_len);
+    for (int q = 0; q < NPREC; ++q) f(M.S[q]);
+    for (int q = 0; q < NPREC; ++q) { f(h->ws[q].buf[0]); f(h->ws[q].buf[1]); }
+    delete h;
+}
+
+midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    MIDBF_CHECK(p.d == 2 || p.d == 3, MIDBF_ERR_ARG, "d must be 2 or 3");
+    MIDBF_CHECK(p.leaf_box >= 1 && p.n >= 2 * p.leaf_box && p.n % p.leaf_box == 0, MIDBF_ERR_SHAPE,
+                "n must be a multiple of leaf_box and at least 2*leaf_box");
+    int L = 0;
+    while ((p.leaf_box << L) < p.n) ++L;
+    MIDBF_CHECK((p.leaf_box << L) == p.n, MIDBF_ERR_SHAPE, "n / leaf_box must be a power of two");
+    MIDBF_CHECK(p.n % 2 == 0, MIDBF_ERR_SHAPE, "n must be even");
+    MIDBF_CHECK(p.tol > 0.0 && p.tol < 1.0, MIDBF_ERR_ARG, "tol must be in (0, 1)");
+    MIDBF_CHECK(p.oversample_t >= 1, MIDBF_ERR_ARG, "oversample_t must be >= 1");
+    if (p.phase == MIDBF_PHASE_LOWRANK)
+        MIDBF_CHECK(p.U_dev && p.V_dev && p.r >= 1, MIDBF_ERR_ARG, "low-rank phase needs U, V and r");
+    if (p.phase == MIDBF_PHASE_FIO_ELLIPSE || p.phase == MIDBF_PHASE_FIO_PIECEWISE)
+        MIDBF_CHECK(p.d == 2, MIDBF_ERR_ARG, "this phase is two-dimensional");
+    if (p.phase == MIDBF_PHASE_ISO3D) MIDBF_CHECK(p.d == 3, MIDBF_ERR_ARG, "this phase is three-dimensional");
+    MIDBF_CHECK(p.phase >= MIDBF_PHASE_LINEAR && p.phase <= MIDBF_PHASE_LOWRANK, MIDBF_ERR_ARG, "unknown phase");
+
+    midbf_plan* h = new midbf_plan();
+    try {
+        h->p = p;
+        if (h->p.build_workspace_bytes == 0) h->p.build_workspace_bytes = (size_t)16 << 30;
+        h->keep = p.precisions ? p.precisions : (MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16);
+        h->d = p.d; h->n = p.n; h->P = 1 << p.d; h->L = L; h->leaf = p.leaf_box;
+        h->n0 = (int)ipow(p.leaf_box, p.d);
+        h->N = ipow(p.n, p.d);
+        h->b = (L + 1) / 2;
+        h->hstar = L - h->b + 1;
+        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r};
+        h->rows.resize(h->b);
+        h->cols.resize(h->b);
+        long long khat[2] = {h->n0, h->n0};
+        for (int s = 0; s < h->b; ++s) {
+            for (int side = 0; side < 2; ++side) {
+                LevelSide& lv = side == SIDE_ROW ? h->rows[s] : h->cols[s];
+                const LevelSide* prev = s == 0 ? nullptr : (side == SIDE_ROW ? &h->rows[s - 1] : &h->cols[s - 1]);
+                long long want = (long long)p.oversample_t * khat[side];
+                for (int attempt = 0;; ++attempt) {
+                    lv = LevelSide();
+                    lv.s = s; lv.side = side; lv.la = L - s; lv.lb = s + 1;
+                    lv.nid = ipow(h->P, L + 1);
+                    if (build_level(h, lv, prev, want, st)) break;
+                    free_level(lv);
+                    MIDBF_CHECK(attempt < 4, MIDBF_ERR_RANK_SATURATED, "rank saturated the samples");
+                    want *= 2;    // the sample set was too small: enlarge it (Sec. 3.2)
+                }
+                khat[side] = lv.kmax;
+            }
+        }
+        build_middle(h, st);
+        // statistics
+        midbf_stats& S = h->stats;
+        S.L = h->L; S.b = h->b; S.hstar = h->hstar;
+        S.k_min = 1 << 30; S.k_max = 0;
+        long long ent = h->mid.total, idx = 0;
+        for (auto* side : {&h->rows, &h->cols})
+            for (auto& lv : *side) {
+                S.ids += lv.nid;
+                ent += lv.entries;
+                idx += lv.total_n * 4 + lv.nid * (4 * 2 + 8 * 3);
+                S.k_min = std::min(S.k_min, lv.kmin);
+                S.k_max = std::max(S.k_max, lv.kmax);
+                h->max_total_k = std::max(h->max_total_k, lv.total_k);
+                h->max_n = std::max(h->max_n, lv.nmax);
+                h->max_k = std::max(h->max_k, lv.kmax);
+            }
+        S.entries = ent;
+        S.bytes_fp64 = (h->keep & MIDBF_KEEP_FP64) ? ent * 16 : 0;
+        S.bytes_fp32 = (h->keep & MIDBF_KEEP_FP32) ? ent * 8 : 0;
+        S.bytes_bf16 = (h->keep & MIDBF_KEEP_BF16) ? ent * 8 : 0;
+        S.index_bytes = idx;
+        S.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    } catch (...) {
+        destroy_plan(h);
+        throw;
+    }
+    return h;
+}
+
+void kernel_entries(const midbf_params& p, const int* rows, int nrows, const int* cols, int ncols, void* out,
+                    hipStream_t st) {
+    PhaseDesc ph{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r};
+    const long long tot = (long long)nrows * ncols;
+    if (tot == 0) return;
+    const int gx = (int)std::min<long long>((tot + BT - 1) / BT, 4096);
+    hipLaunchKernelGGL(entries_kernel, dim3(gx), dim3(BT), 0, st, ph, rows, nrows, cols, ncols, (double2*)out);
+    MIDBF_HIP(hipGetLastError());
+}
+
+void id_batch(void* X, int batch, int m, int n, double tol, int kcap, int* k_out, int* perm_out, void* T_out,
+              hipStream_t st) {
+    MIDBF_CHECK(batch >= 0 && m >= 1 && n >= 1, MIDBF_ERR_ARG, "bad batch sizes");
+    MIDBF_CHECK(m <= ID_MMAX && n <= ID_NMAX, MIDBF_ERR_SHAPE, "m or n too large");
+    if (batch == 0) return;
+    double2* V = dalloc<double2>((size_t)batch * m * ID_NB);
+    double2* Y = dalloc<double2>((size_t)batch * ID_ELL * n);
+    try {
+        IdBatch ib{(double2*)X, (long long)m * n, V, (long long)m * ID_NB, Y, (long long)ID_ELL * n, perm_out, n,
+                   k_out, nullptr, n, m, tol, kcap, 0x5eedu};
+        launch_id_batch(ib, batch, st);
+        hipLaunchKernelGGL(copy_T_kernel, dim3(batch), dim3(BT), 0, st, (const double2*)X, (long long)m * n, k_out, m,
+                           n, (double2*)T_out);
+        MIDBF_HIP(hipGetLastError());
+        MIDBF_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+        (void)hipFree(V);
+        (void)hipFree(Y);
+        throw;
+    }
+    (void)hipFree(V);
+    (void)hipFree(Y);
+}
+
+}  // namespace midbf

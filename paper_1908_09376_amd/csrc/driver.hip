@@ -1,0 +1,226 @@
+// Apply orchestration and the C interface (include/midbf.h).
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "apply.h"
+#include "build.h"
+
+namespace midbf {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+midbf_status fail(midbf_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F> midbf_status guarded(F&& f) {
+    try {
+        f();
+        return MIDBF_OK;
+    } catch (const Error& e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(MIDBF_ERR_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(MIDBF_ERR_HIP, e.what());
+    }
+}
+
+int prec_index(midbf_precision p) {
+    switch (p) {
+        case MIDBF_FP64: return PREC_FP64;
+        case MIDBF_FP32: return PREC_FP32;
+        case MIDBF_SPLIT_BF16: return PREC_BF16;
+    }
+    throw Error(MIDBF_ERR_ARG, "unknown precision");
+}
+
+LevelArgs level_args(const LevelSide& lv, int prec) {
+    return LevelArgs{lv.d_k, lv.d_n, lv.d_perm_off, lv.d_perm, lv.d_y_off, (const void* const*)lv.d_T[prec]};
+}
+
+size_t csize(int prec) { return prec == PREC_FP64 ? 16 : 8; }
+
+constexpr size_t LDS_LIMIT = 64 * 1024;
+
+void launch_checked(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem, hipStream_t st) {
+    MIDBF_CHECK(smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
+                "candidate vectors of this factorization exceed the apply kernels' LDS budget");
+    launch_level_kernel(which, prec, rt, args, grid, smem, st);
+}
+
+void ensure_workspace(midbf_plan* h, int prec, int nrhs) {
+    Workspace& w = h->ws[prec];
+    const size_t need = (size_t)std::max<long long>(h->max_total_k, 1) * nrhs * csize(prec);
+    if (w.bytes >= need) return;
+    if (w.buf[0]) MIDBF_HIP(hipFree(w.buf[0]));
+    if (w.buf[1]) MIDBF_HIP(hipFree(w.buf[1]));
+    w.buf[0] = w.buf[1] = nullptr;
+    w.bytes = 0;
+    MIDBF_HIP(hipMalloc(&w.buf[0], need));
+    MIDBF_HIP(hipMalloc(&w.buf[1], need));
+    w.bytes = need;
+}
+
+// One application of the factor product (adjoint = false) or of its
+// conjugate transpose (adjoint = true).
+void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
+               hipStream_t st, bool adjoint) {
+    MIDBF_CHECK(nrhs >= 1, MIDBF_ERR_ARG, "nrhs must be >= 1");
+    MIDBF_CHECK(ld >= h->N, MIDBF_ERR_ARG, "ld must be >= N");
+    MIDBF_CHECK(in_ext && out_ext, MIDBF_ERR_ARG, "null vector pointer");
+    MIDBF_CHECK(prec != PREC_BF16, MIDBF_ERR_UNIMPLEMENTED, "split-bf16 apply is served by the MFMA path only");
+    const unsigned bit = 1u << prec;
+    MIDBF_CHECK(h->keep & bit, MIDBF_ERR_ARG, "this precision's factors were not kept by the build");
+    ensure_workspace(h, prec, nrhs);
+    const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
+    const int tiles = (nrhs + rt - 1) / rt;
+    const size_t cs = csize(prec);
+    const ApplyGeom G{h->d, h->n, h->P, h->L, h->leaf, h->n0};
+    const auto& up = adjoint ? h->rows : h->cols;
+    const auto& down = adjoint ? h->cols : h->rows;
+    void** buf = h->ws[prec].buf;
+    const long long groups = ipow(h->P, h->L);
+    int o = 0;   // buffer holding the current level's vectors
+    for (int s = 0; s < h->b; ++s) {
+        const LevelSide& lv = up[s];
+        UpArgs a{};
+        a.G = G;
+        a.lev = level_args(lv, prec);
+        a.s = s;
+        a.Ps = ipow(h->P, s);
+        a.ext = in_ext;
+        a.ld = ld;
+        a.in = buf[o ^ 1];
+        a.k_prev = s ? up[s - 1].d_k : nullptr;
+        a.yoff_prev = s ? up[s - 1].d_y_off : nullptr;
+        a.out = buf[o];
+        a.nrhs = nrhs;
+        const int ncand = s == 0 ? h->n0 : lv.nmax;
+        launch_checked(adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a, dim3((unsigned)groups, tiles),
+                            (size_t)ncand * rt * cs, st);
+        o ^= 1;
+    }
+    {
+        const Middle& M = h->mid;
+        MidArgs a{};
+        a.nr = M.d_nr;
+        a.nc = M.d_nc;
+        a.off = M.d_off;
+        a.S = M.S[prec];
+        a.pieces = M.pieces;
+        a.in_off = M.d_in_off;
+        a.in_len = M.d_in_len;
+        a.out_off = M.d_out_off;
+        a.out_len = M.d_out_len;
+        a.in = buf[o ^ 1];
+        a.out = buf[o];
+        a.nrhs = nrhs;
+        const int width = adjoint ? M.nr_max : M.nc_max;
+        for (long long b0 = 0; b0 < M.nblk; b0 += 65535) {
+            const long long cnt = std::min<long long>(65535, M.nblk - b0);
+            MidArgs ab = a;
+            ab.nr += b0; ab.nc += b0; ab.off += b0;
+            ab.in_off += b0 * M.pieces; ab.in_len += b0 * M.pieces;
+            ab.out_off += b0 * M.pieces; ab.out_len += b0 * M.pieces;
+            launch_checked(adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle, prec, rt, &ab,
+                                dim3((unsigned)cnt, tiles), (size_t)width * rt * cs, st);
+        }
+        o ^= 1;
+    }
+    for (int s = h->b - 1; s >= 0; --s) {
+        const LevelSide& lv = down[s];
+        DownArgs a{};
+        a.G = G;
+        a.lev = level_args(lv, prec);
+        a.s = s;
+        a.Ps = ipow(h->P, s);
+        a.in = buf[o ^ 1];
+        a.ext = out_ext;
+        a.ld = ld;
+        a.out = buf[o];
+        a.k_prev = s ? down[s - 1].d_k : nullptr;
+        a.yoff_prev = s ? down[s - 1].d_y_off : nullptr;
+        a.nrhs = nrhs;
+        a.ncand_max = lv.nmax;
+        launch_checked(adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
+                            dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st);
+        o ^= 1;
+    }
+}
+
+}  // namespace
+
+}  // namespace midbf
+
+using namespace midbf;
+
+extern "C" {
+
+midbf_status midbf_build(const midbf_params* p, void* stream, midbf_handle* out) {
+    if (!p || !out) return fail(MIDBF_ERR_ARG, "null argument");
+    *out = nullptr;
+    return guarded([&] { *out = build_plan(*p, (hipStream_t)stream); });
+}
+
+midbf_status midbf_apply(midbf_handle h, const void* f, void* g, int nrhs, long long ld, midbf_precision prec,
+                         void* stream) {
+    if (!h) return fail(MIDBF_ERR_ARG, "null handle");
+    return guarded([&] { run_apply(h, f, g, nrhs, ld, prec_index(prec), (hipStream_t)stream, false); });
+}
+
+midbf_status midbf_apply_adjoint(midbf_handle h, const void* g, void* f, int nrhs, long long ld,
+                                 midbf_precision prec, void* stream) {
+    if (!h) return fail(MIDBF_ERR_ARG, "null handle");
+    return guarded([&] { run_apply(h, g, f, nrhs, ld, prec_index(prec), (hipStream_t)stream, true); });
+}
+
+midbf_status midbf_apply_batched(int count, const midbf_handle* hs, const void* const* f, void* const* g,
+                                 const int* nrhs, midbf_precision prec, void* stream) {
+    if (count < 0 || (count > 0 && (!hs || !f || !g || !nrhs))) return fail(MIDBF_ERR_ARG, "null argument");
+    return guarded([&] {
+        for (int j = 0; j < count; ++j) {
+            MIDBF_CHECK(hs[j], MIDBF_ERR_ARG, "null handle in batch");
+            run_apply(hs[j], f[j], g[j], nrhs[j], hs[j]->N, prec_index(prec), (hipStream_t)stream, false);
+        }
+    });
+}
+
+midbf_status midbf_factor_stats(midbf_handle h, midbf_stats* out) {
+    if (!h || !out) return fail(MIDBF_ERR_ARG, "null argument");
+    *out = h->stats;
+    return MIDBF_OK;
+}
+
+midbf_status midbf_ranks(midbf_handle h, int side, int step, int* out, long long count) {
+    if (!h || !out) return fail(MIDBF_ERR_ARG, "null argument");
+    if (side < 0 || side > 1 || step < 0 || step >= h->b) return fail(MIDBF_ERR_ARG, "bad side or step");
+    const auto& lv = side == 0 ? h->rows[step] : h->cols[step];
+    if (count > (long long)lv.k.size()) return fail(MIDBF_ERR_ARG, "count exceeds the number of IDs");
+    std::memcpy(out, lv.k.data(), count * sizeof(int));
+    return MIDBF_OK;
+}
+
+midbf_status midbf_kernel_entries(const midbf_params* p, const int* rows, int nrows, const int* cols, int ncols,
+                                  void* out, void* stream) {
+    if (!p || (nrows > 0 && !rows) || (ncols > 0 && !cols) || !out) return fail(MIDBF_ERR_ARG, "null argument");
+    return guarded([&] {
+        kernel_entries(*p, rows, nrows, cols, ncols, out, (hipStream_t)stream);
+    });
+}
+
+midbf_status midbf_id_batch(void* X, int batch, int m, int n, double tol, int k_cap, int* k_dev, int* perm_dev,
+                            void* T_dev, void* stream) {
+    if (!X || !k_dev || !perm_dev || !T_dev) return fail(MIDBF_ERR_ARG, "null argument");
+    return guarded([&] { id_batch(X, batch, m, n, tol, k_cap, k_dev, perm_dev, T_dev, (hipStream_t)stream); });
+}
+
+void midbf_destroy(midbf_handle h) { destroy_plan(h); }
+
+const char* midbf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Host-side plan of a factorization: trees, per-step decomposition tables,
+// factor storage and apply workspaces.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "phase.h"
+
+namespace midbf {
+
+enum { SIDE_ROW = 0, SIDE_COL = 1 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, NPREC = 3 };
+
+// One unrolled MSCS step of one side (Sec. 3.5): decompositions of the
+// blocks (node at level la = L-s, partner at level lb = s+1), numbered
+// id = node * P^lb + partner.
+struct LevelSide {
+    int s = 0, side = 0, la = 0, lb = 0;
+    long long nid = 0;
+    int m = 0;                            // samples per decomposition
+    std::vector<int> k, n;                // rank and candidate count per ID
+    std::vector<long long> perm_off, y_off;
+    long long total_k = 0, total_n = 0, entries = 0;
+    int kmin = 0, kmax = 0, nmax = 0;
+    // device copies
+    int* d_k = nullptr;
+    int* d_n = nullptr;
+    long long* d_perm_off = nullptr;
+    long long* d_y_off = nullptr;
+    int* d_perm = nullptr;                // candidate positions, skeleton first
+    int* d_skel = nullptr;                // skeleton lattice point numbers at y_off
+    void** d_T[NPREC] = {nullptr, nullptr, nullptr};   // per-ID pointer to its T block
+    std::vector<void*> chunks;            // device allocations owned by this level
+};
+
+// Middle factor: one dense block per (row group, column group) pair.
+struct Middle {
+    long long nblk = 0;
+    int pieces = 1;                       // 1 (L odd) or P (L even)
+    std::vector<int> nr, nc;
+    std::vector<long long> off;
+    long long total = 0;
+    int nr_max = 0, nc_max = 0;
+    int* d_nr = nullptr;
+    int* d_nc = nullptr;
+    long long* d_off = nullptr;
+    // per block and piece: vector offset/length of the column (input) and row (output) pieces
+    long long* d_in_off = nullptr;
+    int* d_in_len = nullptr;
+    long long* d_out_off = nullptr;
+    int* d_out_len = nullptr;
+    void* S[NPREC] = {nullptr, nullptr, nullptr};       // column-major blocks at off
+};
+
+struct Workspace {
+    void* buf[2] = {nullptr, nullptr};
+    size_t bytes = 0;
+};
+
+}  // namespace midbf
+
+struct midbf_plan {
+    midbf_params p{};
+    midbf::PhaseDesc ph{};
+    int d = 0, n = 0, P = 0, L = 0, b = 0, hstar = 0, leaf = 0, n0 = 0;
+    long long N = 0;
+    std::vector<midbf::LevelSide> rows, cols;
+    midbf::Middle mid;
+    midbf::Workspace ws[midbf::NPREC];
+    midbf_stats stats{};
+    unsigned keep = 0;
+    long long max_total_k = 0;
+    int max_n = 0, max_k = 0;
+};

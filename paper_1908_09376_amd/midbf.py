@@ -1,0 +1,147 @@
+"""Python front end of the MIDBF library: the C calls with torch tensors.
+
+Vectors are torch CUDA tensors of shape (N,) or (nrhs, N) (each right-hand
+side contiguous = column-major N x nrhs with ld = N): complex128 for the
+FP64 apply, complex64 for FP32 and split-BF16.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, precisions=0,
+            workspace_bytes=0) -> L.Params:
+    p = L.Params()
+    p.d, p.n, p.tol = d, n, tol
+    p.leaf_box, p.oversample_t, p.k_cap = leaf_box, oversample_t, k_cap
+    p.phase = L.PHASES[phase]
+    p.U_dev = U.data_ptr() if U is not None else None
+    p.V_dev = V.data_ptr() if V is not None else None
+    p.r = U.shape[1] if U is not None else 0
+    p.precisions = precisions
+    p.build_workspace_bytes = workspace_bytes
+    return p
+
+
+_PREC = {"fp64": L.FP64, "fp32": L.FP32, "bf16x3": L.SPLIT_BF16}
+
+
+class MIDBF:
+    """A built factorization K ~ U^L...U^h S V^h...V^L (midbf_build)."""
+
+    def __init__(self, d: int, n: int, phase: str, tol: float = 1e-6, leaf_box: int = 8,
+                 oversample_t: int = 5, k_cap: int = 0, U: torch.Tensor | None = None,
+                 V: torch.Tensor | None = None, precisions: int = 0, workspace_bytes: int = 0,
+                 stream=None):
+        self.d, self.n, self.N = d, n, n ** d
+        if phase == "lowrank":
+            U = U.to(torch.float64).contiguous()
+            V = V.to(torch.float64).contiguous()
+        self._UV = (U, V)       # kept alive: the library reads them during the build
+        self._p = _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U, V, precisions,
+                          workspace_bytes)
+        h = C.c_void_p()
+        L.check(L.lib.midbf_build(C.byref(self._p), _stream_ptr(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib.midbf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- apply ------------------------------------------------------------
+    def _prep(self, x: torch.Tensor, precision: str):
+        want = torch.complex128 if precision == "fp64" else torch.complex64
+        if x.dtype != want or not x.is_cuda or not x.is_contiguous():
+            raise TypeError(f"expected a contiguous CUDA {want} tensor")
+        if x.shape[-1] != self.N or x.dim() > 2:
+            raise ValueError("expected shape (N,) or (nrhs, N)")
+        return (1 if x.dim() == 1 else x.shape[0])
+
+    def apply(self, f: torch.Tensor, out: torch.Tensor | None = None, precision: str = "fp64",
+              stream=None) -> torch.Tensor:
+        """g = K f (midbf_apply)."""
+        nrhs = self._prep(f, precision)
+        g = torch.empty_like(f) if out is None else out
+        L.check(L.lib.midbf_apply(self._h, f.data_ptr(), g.data_ptr(), nrhs, self.N, _PREC[precision],
+                                  _stream_ptr(stream)))
+        return g
+
+    def apply_adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None, precision: str = "fp64",
+                      stream=None) -> torch.Tensor:
+        """f = K^H g (midbf_apply_adjoint)."""
+        nrhs = self._prep(g, precision)
+        f = torch.empty_like(g) if out is None else out
+        L.check(L.lib.midbf_apply_adjoint(self._h, g.data_ptr(), f.data_ptr(), nrhs, self.N,
+                                          _PREC[precision], _stream_ptr(stream)))
+        return f
+
+    # -- inspection ---------------------------------------------------------
+    def stats(self) -> dict:
+        s = L.Stats()
+        L.check(L.lib.midbf_factor_stats(self._h, C.byref(s)))
+        return {name: getattr(s, name) for name, _ in L.Stats._fields_}
+
+    def ranks(self, side: int, step: int) -> np.ndarray:
+        st = self.stats()
+        count = (2 ** self.d) ** (st["L"] + 1)
+        out = np.zeros(count, dtype=np.int32)
+        L.check(L.lib.midbf_ranks(self._h, side, step, out.ctypes.data_as(C.POINTER(C.c_int)), count))
+        return out
+
+
+def apply_batched(handles: list[MIDBF], fs: list[torch.Tensor], outs: list[torch.Tensor] | None = None,
+                  precision: str = "fp64", stream=None) -> list[torch.Tensor]:
+    """g_j = K_j f_j for independent transforms (midbf_apply_batched)."""
+    count = len(handles)
+    outs = [torch.empty_like(f) for f in fs] if outs is None else outs
+    hs = (C.c_void_p * count)(*[h._h for h in handles])
+    fp = (C.c_void_p * count)(*[f.data_ptr() for f in fs])
+    gp = (C.c_void_p * count)(*[g.data_ptr() for g in outs])
+    nr = (C.c_int * count)(*[h._prep(f, precision) for h, f in zip(handles, fs)])
+    L.check(L.lib.midbf_apply_batched(count, hs, fp, gp, nr, _PREC[precision], _stream_ptr(stream)))
+    return outs
+
+
+def kernel_entries(d: int, n: int, phase: str, rows: torch.Tensor, cols: torch.Tensor,
+                   U: torch.Tensor | None = None, V: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """K(rows, cols) as a complex128 (len(rows), len(cols)) tensor (midbf_kernel_entries)."""
+    p = _params(d, n, phase, 1e-6, 1, 1, 0, U, V)
+    rows = rows.to(torch.int32).contiguous()
+    cols = cols.to(torch.int32).contiguous()
+    out = torch.empty((rows.numel(), cols.numel()), dtype=torch.complex128, device=rows.device)
+    L.check(L.lib.midbf_kernel_entries(C.byref(p), rows.data_ptr(), rows.numel(), cols.data_ptr(),
+                                       cols.numel(), out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def id_batch(X: torch.Tensor, tol: float, k_cap: int = 0, stream=None):
+    """Batched CPQR interpolative decomposition of X (batch, m, n) complex128 (midbf_id_batch).
+
+    Returns (k (batch,), perm (batch, n), T list of (k_b, n-k_b) tensors).  X is overwritten.
+    """
+    b, m, n = X.shape
+    k = torch.empty(b, dtype=torch.int32, device=X.device)
+    perm = torch.empty((b, n), dtype=torch.int32, device=X.device)
+    T = torch.empty((b, m * n), dtype=torch.complex128, device=X.device)
+    L.check(L.lib.midbf_id_batch(X.data_ptr(), b, m, n, tol, k_cap, k.data_ptr(), perm.data_ptr(),
+                                 T.data_ptr(), _stream_ptr(stream)))
+    kk = k.cpu().numpy()
+    Ts = [T[i, : kk[i] * (n - kk[i])].reshape(kk[i], n - kk[i]) for i in range(b)]
+    return kk, perm.cpu().numpy(), Ts

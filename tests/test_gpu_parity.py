@@ -1,0 +1,200 @@
+"""Parity of the HIP path with the CPU oracle (needs an MI355X).
+
+Every comparison is against the FP64 definition (the direct sum of eq. 1) or
+a closed form computed by the oracle on the same seeded inputs; the library
+is called through its C interface.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.kernel import Kernel, direct_sum, direct_sum_adjoint, fft_linear
+from oracle.metrics import rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _mod():
+    import paper_1908_09376_amd as M
+    return M
+
+
+def to_dev(a: np.ndarray, dtype=torch.complex128):
+    """(N, r) column-major numpy -> (r, N) contiguous CUDA tensor."""
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to(DEV).to(dtype)
+
+
+def from_dev(t) -> np.ndarray:
+    return t.to(torch.complex128).cpu().numpy().T
+
+
+# ---- kernel entries -------------------------------------------------------
+
+@pytest.mark.parametrize("d,n,phase", [(2, 64, "fio_ellipse"), (2, 512, "fio_ellipse"), (2, 256, "fio_piecewise"),
+                                       (2, 128, "linear"), (3, 32, "iso3d")])
+def test_kernel_entries_match_oracle(d, n, phase):
+    M = _mod()
+    N = n ** d
+    rows = W.index_sample(N, 300, 31, n)
+    cols = W.index_sample(N, 300, 32, n)
+    K = M.kernel_entries(d, n, phase, torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV))
+    ref = Kernel(d, n, phase).entries(rows, cols)
+    # |Phi| <= ~600 here: the oracle's unreduced FP64 phase carries ~2 pi |Phi| eps ~ 1e-12 of rounding
+    assert np.abs(K.cpu().numpy() - ref).max() < 2e-11
+
+
+def test_kernel_entries_lowrank():
+    M = _mod()
+    N = 32 * 32
+    U, V = W.random_lowrank_factors(N, 5, 33)
+    rows = W.index_sample(N, 200, 34)
+    cols = W.index_sample(N, 200, 35)
+    K = M.kernel_entries(2, 32, "lowrank", torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
+                         U=torch.from_numpy(U).to(DEV), V=torch.from_numpy(V).to(DEV))
+    ref = Kernel(2, 32, ("lowrank", U, V)).entries(rows, cols)
+    assert np.abs(K.cpu().numpy() - ref).max() < 1e-12
+
+
+# ---- batched interpolative decomposition -----------------------------------
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_id_batch_cpqr_bound_and_rank(tol):
+    M = _mod()
+    from oracle.midbf import Tree, column_id, mock_chebyshev_points
+    K = Kernel(2, 128, "fio_ellipse")
+    tr = Tree(2, 128, 8)
+    Xs = []
+    for j in range(6):
+        cand = np.concatenate([tr.points(4, 4 * (7 * j + 3) + t) for t in range(4)])   # 16x16 box, 256 cands
+        smp = mock_chebyshev_points(tr, 2, (5 * j + 1) % 16, 320)
+        Xs.append(K.entries(cand, smp).T)                                               # row-side matrix
+    X = np.stack(Xs)
+    m, n = X.shape[1:]
+    k, perm, T = M.id_batch(torch.from_numpy(X.copy()).to(DEV), tol)
+    for b in range(len(Xs)):
+        A = Xs[b]
+        kb = int(k[b])
+        p = perm[b]
+        assert sorted(p.tolist()) == list(range(n))
+        Tb = T[b].cpu().numpy()
+        rec = np.zeros_like(A)
+        rec[:, p] = A[:, p[:kb]] @ np.hstack([np.eye(kb), Tb])
+        ref2 = (np.abs(A) ** 2).sum(axis=0).max()
+        # ||X - X_skel [I T] Pi^T||_F = ||R22||_F <= sqrt(n-k) tol max_j ||X[:, j]||
+        assert np.linalg.norm(rec - A) <= np.sqrt(n - kb) * tol * np.sqrt(ref2) * (1 + 1e-6) + 1e-12
+        ko = column_id(A, tol)[0]
+        assert abs(kb - ko) <= max(3, int(0.05 * ko)), (kb, ko)
+
+
+def test_id_batch_exact_low_rank():
+    M = _mod()
+    rng = W.rng(36, 0)
+    A = (rng.standard_normal((3, 90, 9)) + 1j * rng.standard_normal((3, 90, 9))) @ \
+        (rng.standard_normal((3, 9, 70)) + 1j * rng.standard_normal((3, 9, 70)))
+    k, perm, T = M.id_batch(torch.from_numpy(A.copy()).to(DEV), 1e-10)
+    assert (k == 9).all()
+    for b in range(3):
+        rec = np.zeros_like(A[b])
+        rec[:, perm[b]] = A[b][:, perm[b][:9]] @ np.hstack([np.eye(9), T[b].cpu().numpy()])
+        assert rel_l2(rec, A[b]) < 1e-11
+
+
+# ---- whole-transform parity ------------------------------------------------
+
+def _build(n, phase, d=2, **kw):
+    M = _mod()
+    return M.MIDBF(d, n, phase, **kw)
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+@pytest.mark.parametrize("phase", ["fio_ellipse", "fio_piecewise"])
+def test_apply_fp64_matches_direct_sum_small(n, phase):
+    F = _build(n, phase)
+    K = Kernel(2, n, phase)
+    f = W.complex_gaussian(K.N, 1, 0)
+    g = from_dev(F.apply(to_dev(f)[0]).unsqueeze(0))
+    gd = direct_sum(K, f)
+    assert rel_l2(g, gd) < 1e-5
+
+
+def test_fio64_fp64_and_fp32():
+    # 64^2 ellipse phase, tolerance 1e-6, single RHS: full-vector error vs the direct sum
+    w = W.WORKLOADS["fio64"]
+    F = _build(w.n, w.phase, tol=w.tol)
+    K = Kernel(2, w.n, w.phase)
+    f = W.rhs_for(w)
+    gd = direct_sum(K, f)
+    g64 = from_dev(F.apply(to_dev(f)[0]).unsqueeze(0))
+    g32 = from_dev(F.apply(to_dev(f, torch.complex64)[0], precision="fp32").unsqueeze(0))
+    assert rel_l2(g64, gd) < 1e-5
+    assert rel_l2(g32, gd) < 1e-5
+    st = F.stats()
+    assert st["L"] == 3 and st["b"] == 2 and st["hstar"] == 2
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_linear_phase_matches_fft(n):
+    F = _build(n, "linear")
+    f = W.complex_gaussian(n * n, 3, 37)
+    g = from_dev(F.apply(to_dev(f)))
+    assert rel_l2(g, fft_linear(2, n, f)) < 1e-5
+
+
+def test_adjoint_identity_and_direct_adjoint():
+    F = _build(64, "fio_ellipse")
+    K = Kernel(2, 64, "fio_ellipse")
+    f = W.complex_gaussian(K.N, 2, 38)
+    h = W.complex_gaussian(K.N, 2, 39)
+    Kf = from_dev(F.apply(to_dev(f)))
+    KHh = from_dev(F.apply_adjoint(to_dev(h)))
+    lhs = np.vdot(h, Kf)
+    rhs = np.vdot(KHh, f)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-12
+    assert rel_l2(KHh, direct_sum_adjoint(K, h)) < 1e-5
+    KHh32 = from_dev(F.apply_adjoint(to_dev(h, torch.complex64), precision="fp32"))
+    assert rel_l2(KHh32, direct_sum_adjoint(K, h)) < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_multi_rhs_equals_single(precision):
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    F = _build(64, "fio_ellipse")
+    f = W.complex_gaussian(64 * 64, 11, 40)
+    many = from_dev(F.apply(to_dev(f, dt), precision=precision))
+    ones = np.stack([from_dev(F.apply(to_dev(f[:, j:j + 1], dt)[0], precision=precision).unsqueeze(0))[:, 0]
+                     for j in range(11)], axis=1)
+    assert rel_l2(many, ones) < (1e-14 if precision == "fp64" else 1e-6)
+
+
+def test_apply_is_deterministic():
+    F = _build(64, "fio_ellipse")
+    f = to_dev(W.complex_gaussian(64 * 64, 2, 41), torch.complex64)
+    a = F.apply(f, precision="fp32")
+    b = F.apply(f, precision="fp32")
+    assert torch.equal(a, b)
+
+
+def test_fio256_sampled_rows_fp64_fp32():
+    w = W.WORKLOADS["fio256"]
+    F = _build(w.n, w.phase, tol=w.tol)
+    K = Kernel(2, w.n, w.phase)
+    f = W.rhs_for(w)
+    rows = W.sample_rows(K.N, w.cfg)
+    gd = direct_sum(K, f, rows=rows)
+    g64 = from_dev(F.apply(to_dev(f)[0]).unsqueeze(0))
+    g32 = from_dev(F.apply(to_dev(f, torch.complex64)[0], precision="fp32").unsqueeze(0))
+    assert rel_l2(g64[rows], gd) < 1e-5
+    assert rel_l2(g32[rows], gd) < 1e-5
+
+
+def test_errors_reported():
+    M = _mod()
+    from paper_1908_09376_amd._lib import MidbfError
+    with pytest.raises(MidbfError):
+        M.MIDBF(2, 60, "fio_ellipse")          # 60 is not 8 * 2^L
+    F = _build(32, "fio_ellipse", precisions=1)
+    with pytest.raises(MidbfError):
+        F.apply(torch.zeros(1024, dtype=torch.complex64, device=DEV), precision="fp32")
