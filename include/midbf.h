@@ -167,6 +167,28 @@ midbf_status midbf_kernel_entries(const midbf_params* p, const int* rows_dev, in
 midbf_status midbf_id_batch(void* X_dev, int batch, int m, int n, double tol, int k_cap,
                             int* k_dev, int* perm_dev, void* T_dev, void* stream);
 
+/*
+ * Per-kernel timing of the applies (the paper's T_app, Sec. 4, split by
+ * kernel).  With profiling enabled, every level-kernel launch of
+ * midbf_apply / midbf_apply_adjoint is bracketed by HIP events on the
+ * apply's stream.  midbf_profile_read synchronizes those events and
+ * aggregates by kernel name: launches, total milliseconds, and the
+ * algorithmic bytes (factor entries once, index tables, input and output
+ * vectors) and flops (8 per complex multiply-add) of those launches.  It
+ * writes up to max_entries records, sets *count to the number of distinct
+ * kernels, and clears the records.
+ */
+typedef struct {
+    char name[48];
+    long long launches;
+    double total_ms;
+    double bytes;
+    double flops;
+} midbf_kernel_time;
+
+midbf_status midbf_profile_enable(midbf_handle h, int on);
+midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_entries, int* count);
+
 /* Release the factorization and its workspaces. */
 void midbf_destroy(midbf_handle h);
 

@@ -35,6 +35,11 @@ class Stats(C.Structure):
                 ("k_max", C.c_int), ("build_seconds", C.c_double)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_longlong), ("total_ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
 class MidbfError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -56,6 +61,8 @@ def _load():
         "midbf_ranks": (i, [vp, i, i, C.POINTER(i), ll]),
         "midbf_kernel_entries": (i, [C.POINTER(Params), vp, i, vp, i, vp, vp]),
         "midbf_id_batch": (i, [vp, i, i, i, C.c_double, i, vp, vp, vp, vp]),
+        "midbf_profile_enable": (i, [vp, i]),
+        "midbf_profile_read": (i, [vp, C.POINTER(KernelTime), i, C.POINTER(i)]),
         "midbf_destroy": (None, [vp]),
         "midbf_last_error": (C.c_char_p, []),
     }
@@ -76,4 +83,4 @@ def check(status: int) -> None:
 
 EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_batched",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",
-            "midbf_destroy", "midbf_last_error"]
+            "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error"]

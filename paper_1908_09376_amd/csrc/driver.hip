@@ -47,10 +47,50 @@ size_t csize(int prec) { return prec == PREC_FP64 ? 16 : 8; }
 
 constexpr size_t LDS_LIMIT = 64 * 1024;
 
-void launch_checked(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem, hipStream_t st) {
+const char* kernel_name(LevelKernel k) {
+    switch (k) {
+        case LevelKernel::Up: return "up";
+        case LevelKernel::Down: return "down";
+        case LevelKernel::Middle: return "middle";
+        case LevelKernel::AdjUp: return "adj_up";
+        case LevelKernel::AdjMiddle: return "adj_middle";
+        case LevelKernel::AdjDown: return "adj_down";
+    }
+    return "?";
+}
+
+hipEvent_t take_event(Profiler& P) {
+    if (P.pool.empty()) {
+        hipEvent_t e;
+        MIDBF_HIP(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = P.pool.back();
+    P.pool.pop_back();
+    return e;
+}
+
+// Launch one level kernel; with profiling on, bracket it with events on the
+// same stream and record its algorithmic bytes and flops.
+void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
+                    hipStream_t st, double bytes, double flops) {
     MIDBF_CHECK(smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
+    Profiler& P = h->prof;
+    if (!P.on) {
+        launch_level_kernel(which, prec, rt, args, grid, smem, st);
+        return;
+    }
+    ProfRecord r;
+    r.name = std::string(kernel_name(which)) + (prec == PREC_FP64 ? "_fp64" : "_fp32") + "_rt" + std::to_string(rt);
+    r.a = take_event(P);
+    r.b = take_event(P);
+    r.bytes = bytes;
+    r.flops = flops;
+    MIDBF_HIP(hipEventRecord(r.a, st));
     launch_level_kernel(which, prec, rt, args, grid, smem, st);
+    MIDBF_HIP(hipEventRecord(r.b, st));
+    P.recs.push_back(r);
 }
 
 void ensure_workspace(midbf_plan* h, int prec, int nrhs) {
@@ -101,8 +141,12 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         a.out = buf[o];
         a.nrhs = nrhs;
         const int ncand = s == 0 ? h->n0 : lv.nmax;
-        launch_checked(adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a, dim3((unsigned)groups, tiles),
-                            (size_t)ncand * rt * cs, st);
+        const double vin = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
+        const double vout = (double)lv.total_k * nrhs * cs;
+        const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
+        launch_checked(h, adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a,
+                       dim3((unsigned)groups, tiles), (size_t)ncand * rt * cs, st, fac + vin + vout,
+                       8.0 * lv.entries * nrhs);
         o ^= 1;
     }
     {
@@ -127,8 +171,11 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
             ab.nr += b0; ab.nc += b0; ab.off += b0;
             ab.in_off += b0 * M.pieces; ab.in_len += b0 * M.pieces;
             ab.out_off += b0 * M.pieces; ab.out_len += b0 * M.pieces;
-            launch_checked(adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle, prec, rt, &ab,
-                                dim3((unsigned)cnt, tiles), (size_t)width * rt * cs, st);
+            const double frac = (double)cnt / M.nblk;
+            const double vec = (double)(h->rows.back().total_k + h->cols.back().total_k) * nrhs * cs;
+            launch_checked(h, adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle, prec, rt, &ab,
+                           dim3((unsigned)cnt, tiles), (size_t)width * rt * cs, st,
+                           frac * ((double)M.total * cs + (double)M.nblk * 40 + vec), frac * 8.0 * M.total * nrhs);
         }
         o ^= 1;
     }
@@ -147,8 +194,12 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         a.yoff_prev = s ? down[s - 1].d_y_off : nullptr;
         a.nrhs = nrhs;
         a.ncand_max = lv.nmax;
-        launch_checked(adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
-                            dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st);
+        const double vin = (double)lv.total_k * nrhs * cs;
+        const double vout = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
+        const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
+        launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
+                       dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
+                       8.0 * lv.entries * nrhs);
         o ^= 1;
     }
 }
@@ -219,7 +270,49 @@ midbf_status midbf_id_batch(void* X, int batch, int m, int n, double tol, int k_
     return guarded([&] { id_batch(X, batch, m, n, tol, k_cap, k_dev, perm_dev, T_dev, (hipStream_t)stream); });
 }
 
-void midbf_destroy(midbf_handle h) { destroy_plan(h); }
+midbf_status midbf_profile_enable(midbf_handle h, int on) {
+    if (!h) return fail(MIDBF_ERR_ARG, "null handle");
+    h->prof.on = on != 0;
+    return MIDBF_OK;
+}
+
+midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_entries, int* count) {
+    if (!h || !count || (max_entries > 0 && !out)) return fail(MIDBF_ERR_ARG, "null argument");
+    return guarded([&] {
+        Profiler& P = h->prof;
+        std::vector<midbf_kernel_time> agg;
+        for (auto& r : P.recs) {
+            MIDBF_HIP(hipEventSynchronize(r.b));
+            float ms = 0.f;
+            MIDBF_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            auto it = std::find_if(agg.begin(), agg.end(),
+                                   [&](const midbf_kernel_time& t) { return r.name == t.name; });
+            if (it == agg.end()) {
+                midbf_kernel_time t{};
+                std::strncpy(t.name, r.name.c_str(), sizeof(t.name) - 1);
+                agg.push_back(t);
+                it = agg.end() - 1;
+            }
+            it->launches += 1;
+            it->total_ms += ms;
+            it->bytes += r.bytes;
+            it->flops += r.flops;
+            P.pool.push_back(r.a);
+            P.pool.push_back(r.b);
+        }
+        P.recs.clear();
+        *count = (int)agg.size();
+        for (int i = 0; i < (int)agg.size() && i < max_entries; ++i) out[i] = agg[i];
+    });
+}
+
+void midbf_destroy(midbf_handle h) {
+    if (h) {
+        for (auto& r : h->prof.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : h->prof.pool) (void)hipEventDestroy(e);
+    }
+    destroy_plan(h);
+}
 
 const char* midbf_last_error(void) { return g_last_error.c_str(); }
 

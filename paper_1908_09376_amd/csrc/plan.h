@@ -2,6 +2,7 @@
 // factor storage and apply workspaces.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -58,6 +59,19 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Per-launch HIP-event timing of the apply kernels (midbf_profile_*).
+struct ProfRecord {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes, flops;   // algorithmic bytes moved and flops of the launch
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRecord> recs;
+    std::vector<hipEvent_t> pool;
+};
+
 }  // namespace midbf
 
 struct midbf_plan {
@@ -72,4 +86,5 @@ struct midbf_plan {
     unsigned keep = 0;
     long long max_total_k = 0;
     int max_n = 0, max_k = 0;
+    midbf::Profiler prof;
 };

@@ -98,6 +98,18 @@ class MIDBF:
         L.check(L.lib.midbf_factor_stats(self._h, C.byref(s)))
         return {name: getattr(s, name) for name, _ in L.Stats._fields_}
 
+    def profile(self, on: bool = True) -> None:
+        """Bracket every level-kernel launch with HIP events (midbf_profile_enable)."""
+        L.check(L.lib.midbf_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> list[dict]:
+        """Per-kernel launches, total ms, algorithmic bytes and flops since the last read."""
+        buf = (L.KernelTime * 64)()
+        cnt = C.c_int()
+        L.check(L.lib.midbf_profile_read(self._h, buf, 64, C.byref(cnt)))
+        return [{"name": buf[i].name.decode(), "launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                 "bytes": buf[i].bytes, "flops": buf[i].flops} for i in range(min(cnt.value, 64))]
+
     def ranks(self, side: int, step: int) -> np.ndarray:
         st = self.stats()
         count = (2 ** self.d) ** (st["L"] + 1)
