@@ -485,7 +485,7 @@ void destroy_plan(midbf_plan* h) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(M.d_nr); f(M.d_nc); f(M.d_off); f(M.d_in_off); f(M.d_in_len); f(M.d_out_off); f(M.d_out_len);
     for (int q = 0; q < NPREC; ++q) f(M.S[q]);
-    for (int q = 0; q < NPREC; ++q) { f(h->ws[q].buf[0]); f(h->ws[q].buf[1]); }
+    for (int q = 0; q < NPREC; ++q) { f(h->ws[q].buf[0]); f(h->ws[q].buf[1]); f(h->ws[q].scratch); }
     delete h;
 }
 
@@ -552,6 +552,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
                 S.k_min = std::min(S.k_min, lv.kmin);
                 S.k_max = std::max(S.k_max, lv.kmax);
                 h->max_total_k = std::max(h->max_total_k, lv.total_k);
+                h->max_total_n = std::max(h->max_total_n, lv.total_n);
                 h->max_n = std::max(h->max_n, lv.nmax);
                 h->max_k = std::max(h->max_k, lv.kmax);
             }

@@ -5,6 +5,7 @@
 
 #include "apply.h"
 #include "build.h"
+#include "mfma.h"
 
 namespace midbf {
 
@@ -71,39 +72,59 @@ hipEvent_t take_event(Profiler& P) {
 }
 
 // Launch one level kernel; with profiling on, bracket it with events on the
-// same stream and record its algorithmic bytes and flops.
+// same stream and record its algorithmic bytes and flops.  mfma_count > 0
+// selects the matrix-core kernel with that many workgroups in x.
 void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
-                    hipStream_t st, double bytes, double flops) {
-    MIDBF_CHECK(smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
+                    hipStream_t st, double bytes, double flops, long long mfma_count = 0, int nrhs = 0) {
+    MIDBF_CHECK(mfma_count > 0 || smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
+    auto go = [&] {
+        if (mfma_count > 0 && which == LevelKernel::Down) {
+            const DownArgs& d = *(const DownArgs*)args;
+            launch_mfma_down(d, mfma_count * h->P, mfma_count, h->ws[prec].scratch, st);
+        } else if (mfma_count > 0) {
+            launch_mfma_kernel(which, args, mfma_count, nrhs, st);
+        }
+        else launch_level_kernel(which, prec, rt, args, grid, smem, st);
+    };
     Profiler& P = h->prof;
     if (!P.on) {
-        launch_level_kernel(which, prec, rt, args, grid, smem, st);
+        go();
         return;
     }
     ProfRecord r;
-    r.name = std::string(kernel_name(which)) + (prec == PREC_FP64 ? "_fp64" : "_fp32") + "_rt" + std::to_string(rt);
+    r.name = std::string(kernel_name(which)) + (mfma_count > 0 ? "_mfma" : "") +
+             (prec == PREC_FP64 ? "_fp64" : "_fp32") + (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
     r.a = take_event(P);
     r.b = take_event(P);
     r.bytes = bytes;
     r.flops = flops;
     MIDBF_HIP(hipEventRecord(r.a, st));
-    launch_level_kernel(which, prec, rt, args, grid, smem, st);
+    go();
     MIDBF_HIP(hipEventRecord(r.b, st));
     P.recs.push_back(r);
 }
 
-void ensure_workspace(midbf_plan* h, int prec, int nrhs) {
+void ensure_workspace(midbf_plan* h, int prec, int nrhs, bool scratch) {
     Workspace& w = h->ws[prec];
     const size_t need = (size_t)std::max<long long>(h->max_total_k, 1) * nrhs * csize(prec);
-    if (w.bytes >= need) return;
-    if (w.buf[0]) MIDBF_HIP(hipFree(w.buf[0]));
-    if (w.buf[1]) MIDBF_HIP(hipFree(w.buf[1]));
-    w.buf[0] = w.buf[1] = nullptr;
-    w.bytes = 0;
-    MIDBF_HIP(hipMalloc(&w.buf[0], need));
-    MIDBF_HIP(hipMalloc(&w.buf[1], need));
-    w.bytes = need;
+    if (w.bytes < need) {
+        if (w.buf[0]) MIDBF_HIP(hipFree(w.buf[0]));
+        if (w.buf[1]) MIDBF_HIP(hipFree(w.buf[1]));
+        w.buf[0] = w.buf[1] = nullptr;
+        w.bytes = 0;
+        MIDBF_HIP(hipMalloc(&w.buf[0], need));
+        MIDBF_HIP(hipMalloc(&w.buf[1], need));
+        w.bytes = need;
+    }
+    const size_t sneed = (size_t)std::max<long long>(h->max_total_n, 1) * nrhs * csize(prec);
+    if (scratch && w.scratch_bytes < sneed) {
+        if (w.scratch) MIDBF_HIP(hipFree(w.scratch));
+        w.scratch = nullptr;
+        w.scratch_bytes = 0;
+        MIDBF_HIP(hipMalloc(&w.scratch, sneed));
+        w.scratch_bytes = sneed;
+    }
 }
 
 // One application of the factor product (adjoint = false) or of its
@@ -116,7 +137,9 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
     MIDBF_CHECK(prec != PREC_BF16, MIDBF_ERR_UNIMPLEMENTED, "split-bf16 apply is served by the MFMA path only");
     const unsigned bit = 1u << prec;
     MIDBF_CHECK(h->keep & bit, MIDBF_ERR_ARG, "this precision's factors were not kept by the build");
-    ensure_workspace(h, prec, nrhs);
+    const bool mfma = prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && h->max_n <= MFMA_CROW_MAX &&
+                      h->mid.nr_max <= MFMA_CROW_MAX && h->mid.nc_max <= MFMA_CROW_MAX;
+    ensure_workspace(h, prec, nrhs, mfma);
     const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     const int tiles = (nrhs + rt - 1) / rt;
     const size_t cs = csize(prec);
@@ -146,7 +169,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         launch_checked(h, adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a,
                        dim3((unsigned)groups, tiles), (size_t)ncand * rt * cs, st, fac + vin + vout,
-                       8.0 * lv.entries * nrhs);
+                       8.0 * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs);
         o ^= 1;
     }
     {
@@ -175,7 +198,8 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
             const double vec = (double)(h->rows.back().total_k + h->cols.back().total_k) * nrhs * cs;
             launch_checked(h, adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle, prec, rt, &ab,
                            dim3((unsigned)cnt, tiles), (size_t)width * rt * cs, st,
-                           frac * ((double)M.total * cs + (double)M.nblk * 40 + vec), frac * 8.0 * M.total * nrhs);
+                           frac * ((double)M.total * cs + (double)M.nblk * 40 + vec), frac * 8.0 * M.total * nrhs,
+                           mfma ? cnt : 0, nrhs);
         }
         o ^= 1;
     }
@@ -199,7 +223,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
                        dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
-                       8.0 * lv.entries * nrhs);
+                       8.0 * lv.entries * nrhs, mfma ? groups : 0, nrhs);
         o ^= 1;
     }
 }

@@ -1,0 +1,396 @@
+// Many-right-hand-side apply on the matrix cores (FP32 in, FP32 accumulate).
+//
+// With 64 right-hand sides every factor block becomes a dense complex GEMM,
+// C (rows x 64) = A (rows x K) B (K x 64), computed as four real products
+// per complex product on v_mfma_f32_16x16x4f32:
+//     Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+// Lane l of a wave supplies A[l%16][l/16] and B[l/16][l%16] and receives
+// D[4(l/16)+v][l%16], v < 4 (checked on the device).  A (the factor) streams
+// from HBM exactly once per launch; B (the level vectors, gathered through
+// the candidate permutation) is staged through LDS in chunks of KC rows and
+// shared by the four waves; each wave owns up to MTW 16-row tiles x 64
+// columns of C.
+//   up     (column side, going up):  C = y[id] (k rows), A = T (k x (n-k), column-major),
+//          B = candidate rows perm[k..n), plus the skeleton rows perm[0..k).
+//   down   (row side, going down):   C = candidate rows perm[k..n), A = T^T (T
+//          row-major k x (n-k)), B = z[id]; each ID writes its contribution to
+//          a scratch block, then the 2^d contributions of a group are summed in
+//          a fixed order (no atomics, bitwise reproducible).
+//   middle: C = z rows, A = S (column-major), B = y rows.
+#include "apply.h"
+#include "mfma.h"
+
+namespace midbf {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int MT = 256;          // threads per workgroup
+constexpr int MW = MT / 64;      // waves
+constexpr int MTW = 3;           // 16-row tiles per wave
+constexpr int ROUND = MW * MTW * 16;
+constexpr int KC = 32;           // K rows per LDS chunk
+constexpr int NRHS = MFMA_NRHS;  // columns per workgroup (4 tiles of 16)
+constexpr int CROW_MAX = 2048;
+
+// One k-step of 4 for every (row tile, column tile) of a wave: the two
+// products of each accumulator are issued in separate sweeps so that
+// consecutive MFMAs never depend on each other.
+__device__ inline void kstep(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const float2 (&a)[MTW],
+                             const float2 (&b)[4], int ntiles) {
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+        if (mt < ntiles) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                cr[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].x, cr[mt][nt], 0, 0, 0);
+                ci[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].y, ci[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+        if (mt < ntiles) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                cr[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[mt].y, b[nt].y, cr[mt][nt], 0, 0, 0);
+                ci[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].y, b[nt].x, ci[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Row numbers of a group's candidate vector in the previous level buffer
+// (or lattice points of the leaf when s == 0).
+__device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a, long long partner, long long Ps,
+                              const int* k_prev, const long long* yoff_prev) {
+    if (s == 0) {
+        int origin[3];
+        node_origin(a, G.L, G.d, G.n, origin);
+        for (int c = threadIdx.x; c < G.n0; c += MT) crow[c] = (int)box_point(origin, G.leaf, c, G.d, G.n);
+        return G.n0;
+    }
+    int start = 0;
+    for (int t = 0; t < G.P; ++t) {
+        const long long idp = ((long long)G.P * a + t) * Ps + partner;
+        const int len = k_prev[idp];
+        const long long off = yoff_prev[idp];
+        for (int c = threadIdx.x; c < len; c += MT) crow[start + c] = (int)(off + c);
+        start += len;
+    }
+    return start;
+}
+
+// element (row, rhs) of a level buffer (row-major, nrhs wide) or of an
+// external column-major block (s == 0)
+__device__ inline float2 load_vec(bool ext, const float2* p, long long ld, int nrhs, int row, int r) {
+    return ext ? p[(long long)r * ld + row] : p[(long long)row * nrhs + r];
+}
+__device__ inline float2* vec_ptr(bool ext, float2* p, long long ld, int nrhs, int row, int r) {
+    return ext ? p + (long long)r * ld + row : p + (long long)row * nrhs + r;
+}
+
+// Blocks of 32 consecutive IDs spread over the eight XCDs so that the four
+// IDs of one group run on the same XCD (shared L2 for their candidate vector).
+__device__ inline long long xcd_group_order(long long b, long long nid, int P) {
+    if (P != 4 || (nid & 31) != 0) return b;
+    const long long x = b & 7, t = (b >> 3) & 3, q = b >> 5;
+    return ((q << 3) + x) * 4 + t;
+}
+
+__global__ __launch_bounds__(MT) void up_mfma(UpArgs A, long long nid) {
+    __shared__ int crow[CROW_MAX];
+    __shared__ float2 sB[KC * NRHS];
+    const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
+    const long long g = id / A.G.P;
+    const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    candidate_rows(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
+    const bool ext = A.s == 0;
+    const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
+    float2* out = (float2*)A.out;
+    const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+    const int* perm = A.lev.perm + A.lev.perm_off[id];
+    const float2* T = (const float2*)A.lev.T[id];
+    const long long yo = A.lev.y_off[id];
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    __syncthreads();
+    for (int m0 = 0; m0 < k; m0 += ROUND) {
+        const int base = m0 + wave * MTW * 16;
+        floatx4 cr[MTW][4], ci[MTW][4];
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
+        for (int c0 = 0; c0 < nred; c0 += KC) {
+            __syncthreads();
+            for (int e = tid; e < KC * NRHS; e += MT) {
+                const int jj = e / NRHS, r = e - jj * NRHS, j = c0 + jj;
+                sB[e] = (j < nred && r < nr) ? load_vec(ext, xin, A.ld, A.nrhs, crow[perm[k + j]], r0 + r)
+                                             : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            if (base < k) {
+                const int ntl = min(MTW, (k - base + 15) / 16);
+                float2 an[MTW];
+                auto loadA = [&](int ks, float2 (&dst)[MTW]) {
+                    const int j = c0 + ks * 4 + lk;
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) {
+                        const int row = base + mt * 16 + lr;
+                        dst[mt] = (mt < ntl && j < nred && row < k) ? T[(long long)j * k + row] : make_float2(0.f, 0.f);
+                    }
+                };
+                loadA(0, an);
+#pragma unroll 2
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    float2 a[MTW];
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
+                    if (ks + 1 < KC / 4) loadA(ks + 1, an);
+                    const int jl = ks * 4 + lk;
+                    float2 b[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) b[nt] = sB[jl * NRHS + nt * 16 + lr];
+                    kstep(cr, ci, a, b, ntl);
+                }
+            }
+        }
+        // C + skeleton rows of the candidate vector
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + mt * 16 + 4 * lk + v;
+                if (row < k) {
+                    const int src = crow[perm[row]];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) {
+                            const float2 s = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + s.x, ci[mt][nt][v] + s.y);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Going down, one workgroup per decomposition: its contribution to every
+// candidate row of its group -- z on the skeleton rows, T^T z on the
+// redundant rows -- goes to the scratch block scr[perm_off[id] + position].
+__global__ __launch_bounds__(MT) void down_mfma(DownArgs A, long long nid, float2* scr) {
+    __shared__ float2 sB[KC * NRHS];
+    const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const float2* zin = (const float2*)A.in;
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+    const int* perm = A.lev.perm + A.lev.perm_off[id];
+    const float2* T = (const float2*)A.lev.T[id];
+    const long long yo = A.lev.y_off[id];
+    float2* w = scr + A.lev.perm_off[id] * A.nrhs;
+    for (int e = tid; e < k * NRHS; e += MT) {
+        const int i = e / NRHS, r = e - i * NRHS;
+        if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
+    }
+    for (int m0 = 0; m0 < nred; m0 += ROUND) {
+        const int base = m0 + wave * MTW * 16;
+        floatx4 cr[MTW][4], ci[MTW][4];
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
+        for (int c0 = 0; c0 < k; c0 += KC) {
+            __syncthreads();
+            for (int e = tid; e < KC * NRHS; e += MT) {
+                const int ii = e / NRHS, r = e - ii * NRHS, i = c0 + ii;
+                sB[e] = (i < k && r < nr) ? zin[(yo + i) * A.nrhs + r0 + r] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            if (base < nred) {
+                const int ntl = min(MTW, (nred - base + 15) / 16);
+                float2 an[MTW];
+                auto loadA = [&](int ks, float2 (&dst)[MTW]) {
+                    const int i = c0 + ks * 4 + lk;
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) {
+                        const int row = base + mt * 16 + lr;
+                        dst[mt] = (mt < ntl && i < k && row < nred) ? T[(long long)i * nred + row]
+                                                                   : make_float2(0.f, 0.f);
+                    }
+                };
+                loadA(0, an);
+#pragma unroll 2
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    float2 a[MTW];
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
+                    if (ks + 1 < KC / 4) loadA(ks + 1, an);
+                    const int il = ks * 4 + lk;
+                    float2 b[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) b[nt] = sB[il * NRHS + nt * 16 + lr];
+                    kstep(cr, ci, a, b, ntl);
+                }
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + mt * 16 + 4 * lk + v;
+                if (row < nred) {
+                    float2* d = w + (long long)perm[k + row] * A.nrhs + r0;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) d[r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The 2^d contributions of a group summed in a fixed order and written to
+// the candidate rows (previous level buffer, or the leaf's lattice points).
+__global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
+    __shared__ int crow[CROW_MAX];
+    const long long g = blockIdx.x;
+    const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const int ncand = candidate_rows(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev);
+    __syncthreads();
+    const bool ext = A.s == 0;
+    float2* outp = ext ? (float2*)A.ext : (float2*)A.out;
+    const long long id0 = g * A.G.P;
+    for (int e = threadIdx.x; e < ncand * NRHS; e += MT) {
+        const int p = e / NRHS, r = e - p * NRHS;
+        if (r >= nr) continue;
+        float sx = 0.f, sy = 0.f;
+        for (int t = 0; t < A.G.P; ++t) {
+            const float2 v = scr[(A.lev.perm_off[id0 + t] + p) * A.nrhs + r0 + r];
+            sx += v.x;
+            sy += v.y;
+        }
+        *vec_ptr(ext, outp, A.ld, A.nrhs, crow[p], r0 + r) = make_float2(sx, sy);
+    }
+}
+
+__global__ __launch_bounds__(MT) void middle_mfma(MidArgs A) {
+    __shared__ int crow_in[CROW_MAX];
+    __shared__ int crow_out[CROW_MAX];
+    __shared__ float2 sB[KC * NRHS];
+    const long long bi = blockIdx.x;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const int M = A.nr[bi], K = A.nc[bi];
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    {
+        int s_in = 0, s_out = 0;
+        for (int t = 0; t < A.pieces; ++t) {
+            const long long oi = A.in_off[bi * A.pieces + t], oo = A.out_off[bi * A.pieces + t];
+            const int li = A.in_len[bi * A.pieces + t], lo = A.out_len[bi * A.pieces + t];
+            for (int c = tid; c < li; c += MT) crow_in[s_in + c] = (int)(oi + c);
+            for (int c = tid; c < lo; c += MT) crow_out[s_out + c] = (int)(oo + c);
+            s_in += li;
+            s_out += lo;
+        }
+    }
+    const float2* xin = (const float2*)A.in;
+    float2* zout = (float2*)A.out;
+    const float2* S = (const float2*)A.S + A.off[bi];
+    __syncthreads();
+    for (int m0 = 0; m0 < M; m0 += ROUND) {
+        const int base = m0 + wave * MTW * 16;
+        floatx4 cr[MTW][4], ci[MTW][4];
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
+        for (int c0 = 0; c0 < K; c0 += KC) {
+            __syncthreads();
+            for (int e = tid; e < KC * NRHS; e += MT) {
+                const int jj = e / NRHS, r = e - jj * NRHS, j = c0 + jj;
+                sB[e] = (j < K && r < nr) ? xin[(long long)crow_in[j] * A.nrhs + r0 + r] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            if (base < M) {
+                const int ntl = min(MTW, (M - base + 15) / 16);
+                float2 an[MTW];
+                auto loadA = [&](int ks, float2 (&dst)[MTW]) {
+                    const int j = c0 + ks * 4 + lk;
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) {
+                        const int row = base + mt * 16 + lr;
+                        dst[mt] = (mt < ntl && j < K && row < M) ? S[(long long)j * M + row] : make_float2(0.f, 0.f);
+                    }
+                };
+                loadA(0, an);
+#pragma unroll 2
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    float2 a[MTW];
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
+                    if (ks + 1 < KC / 4) loadA(ks + 1, an);
+                    const int jl = ks * 4 + lk;
+                    float2 b[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) b[nt] = sB[jl * NRHS + nt * 16 + lr];
+                    kstep(cr, ci, a, b, ntl);
+                }
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + mt * 16 + 4 * lk + v;
+                if (row < M) {
+                    const long long dst = crow_out[row];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) zout[dst * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void launch_mfma_kernel(LevelKernel which, const void* args, long long count, int nrhs, hipStream_t s) {
+    const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
+    switch (which) {
+        case LevelKernel::Up:
+            hipLaunchKernelGGL(up_mfma, grid, dim3(MT), 0, s, *(const UpArgs*)args, count);
+            break;
+        case LevelKernel::Down:
+            throw Error(MIDBF_ERR_ARG, "use launch_mfma_down");
+        case LevelKernel::Middle:
+            hipLaunchKernelGGL(middle_mfma, grid, dim3(MT), 0, s, *(const MidArgs*)args);
+            break;
+        default:
+            throw Error(MIDBF_ERR_UNIMPLEMENTED, "no matrix-core kernel for this level kind");
+    }
+    MIDBF_HIP(hipGetLastError());
+}
+
+void launch_mfma_down(const DownArgs& a, long long nid, long long groups, void* scratch, hipStream_t s) {
+    const unsigned tiles = (a.nrhs + NRHS - 1) / NRHS;
+    hipLaunchKernelGGL(down_mfma, dim3((unsigned)nid, tiles), dim3(MT), 0, s, a, nid, (float2*)scratch);
+    MIDBF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(down_sum, dim3((unsigned)groups, tiles), dim3(MT), 0, s, a, (const float2*)scratch);
+    MIDBF_HIP(hipGetLastError());
+}
+
+}  // namespace midbf

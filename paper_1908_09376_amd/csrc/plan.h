@@ -57,6 +57,8 @@ struct Middle {
 struct Workspace {
     void* buf[2] = {nullptr, nullptr};
     size_t bytes = 0;
+    void* scratch = nullptr;      // per-ID candidate contributions (matrix-core path going down)
+    size_t scratch_bytes = 0;
 };
 
 // Per-launch HIP-event timing of the apply kernels (midbf_profile_*).
@@ -84,7 +86,7 @@ struct midbf_plan {
     midbf::Workspace ws[midbf::NPREC];
     midbf_stats stats{};
     unsigned keep = 0;
-    long long max_total_k = 0;
+    long long max_total_k = 0, max_total_n = 0;
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
 };

@@ -198,3 +198,21 @@ def test_errors_reported():
     F = _build(32, "fio_ellipse", precisions=1)
     with pytest.raises(MidbfError):
         F.apply(torch.zeros(1024, dtype=torch.complex64, device=DEV), precision="fp32")
+
+
+# ---- matrix-core path (many right-hand sides, FP32) -------------------------
+
+@pytest.mark.parametrize("n,nrhs", [(64, 16), (64, 64), (64, 70), (128, 64), (256, 33)])
+def test_mfma_many_rhs_fp32(n, nrhs):
+    F = _build(n, "fio_ellipse")
+    K = Kernel(2, n, "fio_ellipse")
+    f = W.complex_gaussian(K.N, nrhs, 42, n)
+    g32 = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp32"))
+    g64 = from_dev(F.apply(to_dev(f)))
+    assert rel_l2(g32, g64) < 1e-5
+    rows = W.sample_rows(K.N, 0, 128)
+    gd = direct_sum(K, f, rows=rows)
+    assert rel_l2(g32[rows], gd) < 1e-5
+    # every right-hand side individually
+    per = np.linalg.norm(g32[rows] - gd, axis=0) / np.linalg.norm(gd, axis=0)
+    assert per.max() < 2e-5
