@@ -160,6 +160,14 @@ def main() -> int:
     log(f"[bench] built in {build_s:.2f} s: L={st['L']} ranks {st['k_min']}..{st['k_max']} "
         f"entries {st['entries'] / 1e9:.3f} G")
 
+    variants = None
+    tune_s = None
+    if args.precision == "fp32" and nrhs >= 16:
+        t0 = time.perf_counter()
+        variants = F.tune(nrhs, "fp32")
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] autotuned matrix-core variants (up, down, middle) = {variants} in {tune_s:.2f} s")
+
     f_np = W.complex_gaussian(w.N, nrhs, w.cfg)
     cdt = torch.complex128 if args.precision == "fp64" else torch.complex64
     f = torch.from_numpy(np.ascontiguousarray(f_np.T)).to("cuda:0").to(cdt)
@@ -218,6 +226,8 @@ def main() -> int:
         "rel_l2_err": err,
         "launches_per_s": round(args.steps / wall, 3),
         "build_s": round(build_s, 2),
+        "tuned_variants": variants,
+        "tune_s": None if tune_s is None else round(tune_s, 2),
         "factor_entries": st["entries"],
         "ranks": [st["k_min"], st["k_max"]],
         "fp64_gpu": fp64,

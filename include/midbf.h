@@ -189,6 +189,19 @@ typedef struct {
 midbf_status midbf_profile_enable(midbf_handle h, int on);
 midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_entries, int* count);
 
+/*
+ * midbf_tune -- autotuner of the many-right-hand-side (matrix-core) apply:
+ * times every tile variant (rows per wave, K chunk, pipelining) of the up,
+ * down and middle kernels on this factorization with nrhs right-hand sides
+ * and keeps the fastest per kernel kind.  Allocates and frees two N x nrhs
+ * buffers; synchronizes `stream`.  If variants != NULL, writes the chosen
+ * variants (up, down, middle) to variants[0..3).  Other precisions and
+ * nrhs below the matrix-core threshold leave the choice unchanged.
+ * midbf_set_variants installs a choice made earlier (e.g. a cached one).
+ */
+midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants);
+midbf_status midbf_set_variants(midbf_handle h, const int* variants);
+
 /* Release the factorization and its workspaces. */
 void midbf_destroy(midbf_handle h);
 

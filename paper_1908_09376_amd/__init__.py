@@ -4,5 +4,15 @@ factorization (Chen, Zhang, Ho, Yang) in hand-written HIP for gfx950.
 The library (libmidbf.so, C interface in include/midbf.h) builds the factors
 on the GPU (FP64 kernel entries and batched column-pivoted QR interpolative
 decompositions) and applies g = K f and f = K^H g level by level.
+
+The binding is loaded on first use, so that `build_lib` can run before the
+library exists.
 """
-from .midbf import MIDBF, apply_batched, id_batch, kernel_entries  # noqa: F401
+_EXPORTS = ("MIDBF", "apply_batched", "id_batch", "kernel_entries")
+
+
+def __getattr__(name):
+    if name in _EXPORTS:
+        from . import midbf
+        return getattr(midbf, name)
+    raise AttributeError(name)

@@ -61,6 +61,8 @@ def _load():
         "midbf_ranks": (i, [vp, i, i, C.POINTER(i), ll]),
         "midbf_kernel_entries": (i, [C.POINTER(Params), vp, i, vp, i, vp, vp]),
         "midbf_id_batch": (i, [vp, i, i, i, C.c_double, i, vp, vp, vp, vp]),
+        "midbf_tune": (i, [vp, i, i, vp, C.POINTER(i)]),
+        "midbf_set_variants": (i, [vp, C.POINTER(i)]),
         "midbf_profile_enable": (i, [vp, i]),
         "midbf_profile_read": (i, [vp, C.POINTER(KernelTime), i, C.POINTER(i)]),
         "midbf_destroy": (None, [vp]),
@@ -83,4 +85,4 @@ def check(status: int) -> None:
 
 EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_batched",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",
-            "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error"]
+            "midbf_tune", "midbf_set_variants", "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error"]

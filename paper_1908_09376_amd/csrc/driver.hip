@@ -79,11 +79,9 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     MIDBF_CHECK(mfma_count > 0 || smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
     auto go = [&] {
-        if (mfma_count > 0 && which == LevelKernel::Down) {
-            const DownArgs& d = *(const DownArgs*)args;
-            launch_mfma_down(d, mfma_count * h->P, mfma_count, h->ws[prec].scratch, st);
-        } else if (mfma_count > 0) {
-            launch_mfma_kernel(which, args, mfma_count, nrhs, st);
+        if (mfma_count > 0) {
+            const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Down ? 1 : 2);
+            launch_mfma_kernel(which, h->mfma_variant[kind], args, mfma_count, nrhs, h->ws[prec].scratch, st);
         }
         else launch_level_kernel(which, prec, rt, args, grid, smem, st);
     };
@@ -223,7 +221,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
                        dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
-                       8.0 * lv.entries * nrhs, mfma ? groups : 0, nrhs);
+                       8.0 * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs);
         o ^= 1;
     }
 }
@@ -292,6 +290,75 @@ midbf_status midbf_id_batch(void* X, int batch, int m, int n, double tol, int k_
                             void* T_dev, void* stream) {
     if (!X || !k_dev || !perm_dev || !T_dev) return fail(MIDBF_ERR_ARG, "null argument");
     return guarded([&] { id_batch(X, batch, m, n, tol, k_cap, k_dev, perm_dev, T_dev, (hipStream_t)stream); });
+}
+
+midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants) {
+    if (!h) return fail(MIDBF_ERR_ARG, "null handle");
+    return guarded([&] {
+        const int pi = prec_index(prec);
+        hipStream_t st = (hipStream_t)stream;
+        if (pi == PREC_FP32 && nrhs >= MFMA_MIN_NRHS && (h->keep & MIDBF_KEEP_FP32)) {
+            void* f = nullptr;
+            void* g = nullptr;
+            const size_t bytes = (size_t)h->N * nrhs * 8;
+            MIDBF_HIP(hipMalloc(&f, bytes));
+            if (hipMalloc(&g, bytes) != hipSuccess) {
+                (void)hipFree(f);
+                throw Error(MIDBF_ERR_OOM, "tuning buffers");
+            }
+            const bool was_on = h->prof.on;
+            const std::vector<ProfRecord> saved = h->prof.recs;
+            h->prof.recs.clear();
+            double best[3] = {1e300, 1e300, 1e300};
+            int pick[3] = {0, 0, 0};
+            try {
+                MIDBF_HIP(hipMemsetAsync(f, 0, bytes, st));
+                for (int v = 0; v < MFMA_VARIANTS; ++v) {
+                    for (int q = 0; q < 3; ++q) h->mfma_variant[q] = v;
+                    h->prof.on = false;
+                    run_apply(h, f, g, nrhs, h->N, pi, st, false);          // warm-up
+                    h->prof.on = true;
+                    run_apply(h, f, g, nrhs, h->N, pi, st, false);
+                    h->prof.on = false;
+                    double t[3] = {0, 0, 0};
+                    for (auto& r : h->prof.recs) {
+                        MIDBF_HIP(hipEventSynchronize(r.b));
+                        float ms = 0.f;
+                        MIDBF_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+                        const int q = r.name.rfind("up", 0) == 0 ? 0 : (r.name.rfind("down", 0) == 0 ? 1 : 2);
+                        t[q] += ms;
+                        h->prof.pool.push_back(r.a);
+                        h->prof.pool.push_back(r.b);
+                    }
+                    h->prof.recs.clear();
+                    for (int q = 0; q < 3; ++q)
+                        if (t[q] < best[q]) { best[q] = t[q]; pick[q] = v; }
+                }
+            } catch (...) {
+                h->prof.on = was_on;
+                h->prof.recs = saved;
+                (void)hipFree(f);
+                (void)hipFree(g);
+                throw;
+            }
+            h->prof.on = was_on;
+            h->prof.recs = saved;
+            MIDBF_HIP(hipStreamSynchronize(st));
+            (void)hipFree(f);
+            (void)hipFree(g);
+            for (int q = 0; q < 3; ++q) h->mfma_variant[q] = pick[q];
+        }
+        if (variants)
+            for (int q = 0; q < 3; ++q) variants[q] = h->mfma_variant[q];
+    });
+}
+
+midbf_status midbf_set_variants(midbf_handle h, const int* variants) {
+    if (!h || !variants) return fail(MIDBF_ERR_ARG, "null argument");
+    for (int q = 0; q < 3; ++q)
+        if (variants[q] < 0 || variants[q] >= MFMA_VARIANTS) return fail(MIDBF_ERR_ARG, "unknown variant");
+    for (int q = 0; q < 3; ++q) h->mfma_variant[q] = variants[q];
+    return MIDBF_OK;
 }
 
 midbf_status midbf_profile_enable(midbf_handle h, int on) {

@@ -9,11 +9,13 @@ constexpr int MFMA_NRHS = 64;        // right-hand sides per workgroup
 constexpr int MFMA_MIN_NRHS = 16;    // below this the VALU kernels are used
 constexpr int MFMA_CROW_MAX = 2048;  // largest candidate vector / middle block side
 
-// count = grid size in x: IDs (up), groups (down) or middle blocks.
-void launch_mfma_kernel(LevelKernel which, const void* args, long long count, int nrhs, hipStream_t s);
+constexpr int MFMA_VARIANTS = 8;     // tile variants (rows per wave, K chunk, pipelining)
 
-// Going down: per-ID contributions into `scratch` (total_n x nrhs complex64),
-// then the per-group sums into the previous level buffer / external output.
-void launch_mfma_down(const DownArgs& a, long long nid, long long groups, void* scratch, hipStream_t s);
+// One matrix-core level kernel.  count = workgroups in x: IDs (up, down) or
+// middle blocks.  Going down, each ID writes its contribution to `scratch`
+// (total_n x nrhs complex64) and a second kernel sums the 2^d contributions of
+// every group into the previous level buffer / external output.
+void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
+                        hipStream_t s);
 
 }  // namespace midbf

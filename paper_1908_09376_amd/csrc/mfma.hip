@@ -9,7 +9,8 @@
 // from HBM exactly once per launch; B (the level vectors, gathered through
 // the candidate permutation) is staged through LDS in chunks of KC rows and
 // shared by the four waves; each wave owns up to MTW 16-row tiles x 64
-// columns of C.
+// columns of C.  (MTW, KC, pipelining) come in a few variants that the
+// autotuner (midbf_tune) times on the factorization at hand.
 //   up     (column side, going up):  C = y[id] (k rows), A = T (k x (n-k), column-major),
 //          B = candidate rows perm[k..n), plus the skeleton rows perm[0..k).
 //   down   (row side, going down):   C = candidate rows perm[k..n), A = T^T (T
@@ -26,17 +27,15 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int MT = 256;          // threads per workgroup
+constexpr int MT = 256;          // threads per workgroup (up, down)
 constexpr int MW = MT / 64;      // waves
-constexpr int MTW = 3;           // 16-row tiles per wave
-constexpr int ROUND = MW * MTW * 16;
-constexpr int KC = 32;           // K rows per LDS chunk
 constexpr int NRHS = MFMA_NRHS;  // columns per workgroup (4 tiles of 16)
 constexpr int CROW_MAX = 2048;
 
 // One k-step of 4 for every (row tile, column tile) of a wave: the two
 // products of each accumulator are issued in separate sweeps so that
 // consecutive MFMAs never depend on each other.
+template <int MTW>
 __device__ inline void kstep(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const float2 (&a)[MTW],
                              const float2 (&b)[4], int ntiles) {
 #pragma unroll
@@ -61,14 +60,128 @@ __device__ inline void kstep(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const
     }
 }
 
+
+template <int MTW_, int KC_, bool PIPE_, int NT_ = MT>
+struct Cfg {
+    static constexpr int MTW = MTW_;      // 16-row tiles per wave
+    static constexpr int KC = KC_;        // K rows per LDS chunk
+    static constexpr bool PIPE = PIPE_;   // chunk-deep register prefetch + double-buffered LDS
+    static constexpr int NT = NT_;        // threads per workgroup
+    static constexpr int ROUND = NT / 64 * MTW * 16;
+};
+
+// Rows [base, base + 16 MTW) of C (+)= A B for one wave.  A is column-major
+// with leading dimension M; brow(j, r) returns B[j][r] (j < K, r < nr).
+// Every thread of the workgroup must call this (it synchronizes).
+//   PIPE: the wave's A fragments of chunk c+1 and this thread's B elements of
+//   chunk c+1 are loaded into registers while chunk c is multiplied from the
+//   other register set and the other LDS buffer; one barrier per chunk.
+//   otherwise: one LDS buffer, A prefetched one k-step ahead.
+template <class C, int NT, class BRow>
+__device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const float2* __restrict__ A, int M,
+                          int K, int base, BRow brow, int nr, float2* sB) {
+    constexpr int MTW = C::MTW, KC = C::KC;
+    constexpr int BPT = KC * NRHS / NT;   // B elements staged per thread and chunk
+    const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int ntl = base < M ? min(MTW, (M - base + 15) / 16) : 0;
+    const int nch = (K + KC - 1) / KC;
+    if (nch == 0) return;
+    auto loadA1 = [&](int col, float2 (&dst)[MTW]) {
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+            const int row = base + mt * 16 + lr;
+            dst[mt] = (mt < ntl && col < K && row < M) ? A[(long long)col * M + row] : make_float2(0.f, 0.f);
+        }
+    };
+    float2 bt[BPT];
+    auto loadB = [&](int c0) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e = tid + q * NT, jj = e / NRHS, r = e - jj * NRHS, j = c0 + jj;
+            bt[q] = (j < K && r < nr) ? brow(j, r) : make_float2(0.f, 0.f);
+        }
+    };
+    auto storeB = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) sB[buf * KC * NRHS + tid + q * NT] = bt[q];
+    };
+    if constexpr (C::PIPE) {
+        float2 acur[KC / 4][MTW], anext[KC / 4][MTW];
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) loadA1(ks * 4 + lk, acur[ks]);
+        loadB(0);
+        __syncthreads();          // the previous user of sB is done
+        storeB(0);
+        __syncthreads();
+        for (int c = 0; c < nch; ++c) {
+            const bool more = c + 1 < nch;
+            if (more) {
+#pragma unroll
+                for (int ks = 0; ks < KC / 4; ++ks) loadA1((c + 1) * KC + ks * 4 + lk, anext[ks]);
+                loadB((c + 1) * KC);
+            }
+            const float2* sb = sB + (c & 1) * KC * NRHS;
+            if (ntl > 0) {
+#pragma unroll
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    float2 bv[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) bv[nt] = sb[(ks * 4 + lk) * NRHS + nt * 16 + lr];
+                    kstep<MTW>(cr, ci, acur[ks], bv, ntl);
+                }
+            }
+            if (more) {
+                storeB((c + 1) & 1);
+#pragma unroll
+                for (int ks = 0; ks < KC / 4; ++ks)
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) acur[ks][mt] = anext[ks][mt];
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int c = 0; c < nch; ++c) {
+            loadB(c * KC);
+            __syncthreads();
+            storeB(0);
+            __syncthreads();
+            if (ntl > 0) {
+                float2 an[MTW];
+                loadA1(c * KC + lk, an);
+#pragma unroll 2
+                for (int ks = 0; ks < KC / 4; ++ks) {
+                    float2 a[MTW];
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
+                    if (ks + 1 < KC / 4) loadA1(c * KC + (ks + 1) * 4 + lk, an);
+                    float2 bv[4];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) bv[nt] = sB[(ks * 4 + lk) * NRHS + nt * 16 + lr];
+                    kstep<MTW>(cr, ci, a, bv, ntl);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int MTW>
+__device__ inline void zero_acc(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4]) {
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
+}
+
 // Row numbers of a group's candidate vector in the previous level buffer
 // (or lattice points of the leaf when s == 0).
+template <int NT>
 __device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a, long long partner, long long Ps,
                               const int* k_prev, const long long* yoff_prev) {
     if (s == 0) {
         int origin[3];
         node_origin(a, G.L, G.d, G.n, origin);
-        for (int c = threadIdx.x; c < G.n0; c += MT) crow[c] = (int)box_point(origin, G.leaf, c, G.d, G.n);
+        for (int c = threadIdx.x; c < G.n0; c += NT) crow[c] = (int)box_point(origin, G.leaf, c, G.d, G.n);
         return G.n0;
     }
     int start = 0;
@@ -76,7 +189,7 @@ __device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a,
         const long long idp = ((long long)G.P * a + t) * Ps + partner;
         const int len = k_prev[idp];
         const long long off = yoff_prev[idp];
-        for (int c = threadIdx.x; c < len; c += MT) crow[start + c] = (int)(off + c);
+        for (int c = threadIdx.x; c < len; c += NT) crow[start + c] = (int)(off + c);
         start += len;
     }
     return start;
@@ -99,15 +212,17 @@ __device__ inline long long xcd_group_order(long long b, long long nid, int P) {
     return ((q << 3) + x) * 4 + t;
 }
 
-__global__ __launch_bounds__(MT) void up_mfma(UpArgs A, long long nid) {
+template <class C>
+__global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
+    constexpr int MTW = C::MTW;
     __shared__ int crow[CROW_MAX];
-    __shared__ float2 sB[KC * NRHS];
+    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
-    candidate_rows(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
+    candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
     const bool ext = A.s == 0;
     const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
     float2* out = (float2*)A.out;
@@ -117,47 +232,13 @@ __global__ __launch_bounds__(MT) void up_mfma(UpArgs A, long long nid) {
     const long long yo = A.lev.y_off[id];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     __syncthreads();
-    for (int m0 = 0; m0 < k; m0 += ROUND) {
+    const int* red = perm + k;
+    auto brow = [&](int j, int r) { return load_vec(ext, xin, A.ld, A.nrhs, crow[red[j]], r0 + r); };
+    for (int m0 = 0; m0 < k; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
-#pragma unroll
-        for (int mt = 0; mt < MTW; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
-        for (int c0 = 0; c0 < nred; c0 += KC) {
-            __syncthreads();
-            for (int e = tid; e < KC * NRHS; e += MT) {
-                const int jj = e / NRHS, r = e - jj * NRHS, j = c0 + jj;
-                sB[e] = (j < nred && r < nr) ? load_vec(ext, xin, A.ld, A.nrhs, crow[perm[k + j]], r0 + r)
-                                             : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            if (base < k) {
-                const int ntl = min(MTW, (k - base + 15) / 16);
-                float2 an[MTW];
-                auto loadA = [&](int ks, float2 (&dst)[MTW]) {
-                    const int j = c0 + ks * 4 + lk;
-#pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt) {
-                        const int row = base + mt * 16 + lr;
-                        dst[mt] = (mt < ntl && j < nred && row < k) ? T[(long long)j * k + row] : make_float2(0.f, 0.f);
-                    }
-                };
-                loadA(0, an);
-#pragma unroll 2
-                for (int ks = 0; ks < KC / 4; ++ks) {
-                    float2 a[MTW];
-#pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
-                    if (ks + 1 < KC / 4) loadA(ks + 1, an);
-                    const int jl = ks * 4 + lk;
-                    float2 b[4];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) b[nt] = sB[jl * NRHS + nt * 16 + lr];
-                    kstep(cr, ci, a, b, ntl);
-                }
-            }
-        }
+        zero_acc<MTW>(cr, ci);
+        gemm_rows<C, C::NT>(cr, ci, T, k, nred, base, brow, nr, sB);
         // C + skeleton rows of the candidate vector
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
@@ -170,8 +251,8 @@ __global__ __launch_bounds__(MT) void up_mfma(UpArgs A, long long nid) {
                     for (int nt = 0; nt < 4; ++nt) {
                         const int r = nt * 16 + lr;
                         if (r < nr) {
-                            const float2 s = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + s.x, ci[mt][nt][v] + s.y);
+                            const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
                         }
                     }
                 }
@@ -183,8 +264,10 @@ __global__ __launch_bounds__(MT) void up_mfma(UpArgs A, long long nid) {
 // Going down, one workgroup per decomposition: its contribution to every
 // candidate row of its group -- z on the skeleton rows, T^T z on the
 // redundant rows -- goes to the scratch block scr[perm_off[id] + position].
-__global__ __launch_bounds__(MT) void down_mfma(DownArgs A, long long nid, float2* scr) {
-    __shared__ float2 sB[KC * NRHS];
+template <class C>
+__global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, float2* scr) {
+    constexpr int MTW = C::MTW;
+    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -195,51 +278,17 @@ __global__ __launch_bounds__(MT) void down_mfma(DownArgs A, long long nid, float
     const float2* T = (const float2*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
     float2* w = scr + A.lev.perm_off[id] * A.nrhs;
-    for (int e = tid; e < k * NRHS; e += MT) {
+    for (int e = tid; e < k * NRHS; e += C::NT) {
         const int i = e / NRHS, r = e - i * NRHS;
         if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
     }
-    for (int m0 = 0; m0 < nred; m0 += ROUND) {
+    const float2* z = zin + yo * A.nrhs + r0;
+    auto brow = [&](int i, int r) { return z[(long long)i * A.nrhs + r]; };
+    for (int m0 = 0; m0 < nred; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
-#pragma unroll
-        for (int mt = 0; mt < MTW; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
-        for (int c0 = 0; c0 < k; c0 += KC) {
-            __syncthreads();
-            for (int e = tid; e < KC * NRHS; e += MT) {
-                const int ii = e / NRHS, r = e - ii * NRHS, i = c0 + ii;
-                sB[e] = (i < k && r < nr) ? zin[(yo + i) * A.nrhs + r0 + r] : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            if (base < nred) {
-                const int ntl = min(MTW, (nred - base + 15) / 16);
-                float2 an[MTW];
-                auto loadA = [&](int ks, float2 (&dst)[MTW]) {
-                    const int i = c0 + ks * 4 + lk;
-#pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt) {
-                        const int row = base + mt * 16 + lr;
-                        dst[mt] = (mt < ntl && i < k && row < nred) ? T[(long long)i * nred + row]
-                                                                   : make_float2(0.f, 0.f);
-                    }
-                };
-                loadA(0, an);
-#pragma unroll 2
-                for (int ks = 0; ks < KC / 4; ++ks) {
-                    float2 a[MTW];
-#pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
-                    if (ks + 1 < KC / 4) loadA(ks + 1, an);
-                    const int il = ks * 4 + lk;
-                    float2 b[4];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) b[nt] = sB[il * NRHS + nt * 16 + lr];
-                    kstep(cr, ci, a, b, ntl);
-                }
-            }
-        }
+        zero_acc<MTW>(cr, ci);
+        gemm_rows<C, C::NT>(cr, ci, T, nred, k, base, brow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -266,7 +315,7 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
     const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
-    const int ncand = candidate_rows(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev);
+    const int ncand = candidate_rows<MT>(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev);
     __syncthreads();
     const bool ext = A.s == 0;
     float2* outp = ext ? (float2*)A.ext : (float2*)A.out;
@@ -284,10 +333,12 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
     }
 }
 
-__global__ __launch_bounds__(MT) void middle_mfma(MidArgs A) {
+template <class C>
+__global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
+    constexpr int MTW = C::MTW;
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
-    __shared__ float2 sB[KC * NRHS];
+    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
     const long long bi = blockIdx.x;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -298,8 +349,8 @@ __global__ __launch_bounds__(MT) void middle_mfma(MidArgs A) {
         for (int t = 0; t < A.pieces; ++t) {
             const long long oi = A.in_off[bi * A.pieces + t], oo = A.out_off[bi * A.pieces + t];
             const int li = A.in_len[bi * A.pieces + t], lo = A.out_len[bi * A.pieces + t];
-            for (int c = tid; c < li; c += MT) crow_in[s_in + c] = (int)(oi + c);
-            for (int c = tid; c < lo; c += MT) crow_out[s_out + c] = (int)(oo + c);
+            for (int c = tid; c < li; c += C::NT) crow_in[s_in + c] = (int)(oi + c);
+            for (int c = tid; c < lo; c += C::NT) crow_out[s_out + c] = (int)(oo + c);
             s_in += li;
             s_out += lo;
         }
@@ -308,46 +359,12 @@ __global__ __launch_bounds__(MT) void middle_mfma(MidArgs A) {
     float2* zout = (float2*)A.out;
     const float2* S = (const float2*)A.S + A.off[bi];
     __syncthreads();
-    for (int m0 = 0; m0 < M; m0 += ROUND) {
+    auto brow = [&](int j, int r) { return xin[(long long)crow_in[j] * A.nrhs + r0 + r]; };
+    for (int m0 = 0; m0 < M; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
-#pragma unroll
-        for (int mt = 0; mt < MTW; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
-        for (int c0 = 0; c0 < K; c0 += KC) {
-            __syncthreads();
-            for (int e = tid; e < KC * NRHS; e += MT) {
-                const int jj = e / NRHS, r = e - jj * NRHS, j = c0 + jj;
-                sB[e] = (j < K && r < nr) ? xin[(long long)crow_in[j] * A.nrhs + r0 + r] : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            if (base < M) {
-                const int ntl = min(MTW, (M - base + 15) / 16);
-                float2 an[MTW];
-                auto loadA = [&](int ks, float2 (&dst)[MTW]) {
-                    const int j = c0 + ks * 4 + lk;
-#pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt) {
-                        const int row = base + mt * 16 + lr;
-                        dst[mt] = (mt < ntl && j < K && row < M) ? S[(long long)j * M + row] : make_float2(0.f, 0.f);
-                    }
-                };
-                loadA(0, an);
-#pragma unroll 2
-                for (int ks = 0; ks < KC / 4; ++ks) {
-                    float2 a[MTW];
-#pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
-                    if (ks + 1 < KC / 4) loadA(ks + 1, an);
-                    const int jl = ks * 4 + lk;
-                    float2 b[4];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) b[nt] = sB[jl * NRHS + nt * 16 + lr];
-                    kstep(cr, ci, a, b, ntl);
-                }
-            }
-        }
+        zero_acc<MTW>(cr, ci);
+        gemm_rows<C, C::NT>(cr, ci, S, M, K, base, brow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -366,18 +383,32 @@ __global__ __launch_bounds__(MT) void middle_mfma(MidArgs A) {
     }
 }
 
-}  // namespace
+using V0 = Cfg<3, 32, false>;
+using V1 = Cfg<2, 32, false>;
+using V2 = Cfg<3, 16, true>;
+using V3 = Cfg<2, 16, true>;
+using V4 = Cfg<4, 32, false>;
+using V5 = Cfg<2, 16, true, 512>;
+using V6 = Cfg<1, 16, true, 512>;
+using V7 = Cfg<2, 32, false, 512>;
 
-void launch_mfma_kernel(LevelKernel which, const void* args, long long count, int nrhs, hipStream_t s) {
+template <class C>
+void launch_variant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch, hipStream_t s) {
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
     switch (which) {
         case LevelKernel::Up:
-            hipLaunchKernelGGL(up_mfma, grid, dim3(MT), 0, s, *(const UpArgs*)args, count);
+            hipLaunchKernelGGL(up_mfma<C>, grid, dim3(C::NT), 0, s, *(const UpArgs*)args, count);
             break;
-        case LevelKernel::Down:
-            throw Error(MIDBF_ERR_ARG, "use launch_mfma_down");
+        case LevelKernel::Down: {
+            const DownArgs& a = *(const DownArgs*)args;
+            const long long groups = count / a.G.P;
+            hipLaunchKernelGGL(down_mfma<C>, grid, dim3(C::NT), 0, s, a, count, (float2*)scratch);
+            MIDBF_HIP(hipGetLastError());
+            hipLaunchKernelGGL(down_sum, dim3((unsigned)groups, grid.y), dim3(MT), 0, s, a, (const float2*)scratch);
+            break;
+        }
         case LevelKernel::Middle:
-            hipLaunchKernelGGL(middle_mfma, grid, dim3(MT), 0, s, *(const MidArgs*)args);
+            hipLaunchKernelGGL(middle_mfma<C>, grid, dim3(C::NT), 0, s, *(const MidArgs*)args);
             break;
         default:
             throw Error(MIDBF_ERR_UNIMPLEMENTED, "no matrix-core kernel for this level kind");
@@ -385,12 +416,21 @@ void launch_mfma_kernel(LevelKernel which, const void* args, long long count, in
     MIDBF_HIP(hipGetLastError());
 }
 
-void launch_mfma_down(const DownArgs& a, long long nid, long long groups, void* scratch, hipStream_t s) {
-    const unsigned tiles = (a.nrhs + NRHS - 1) / NRHS;
-    hipLaunchKernelGGL(down_mfma, dim3((unsigned)nid, tiles), dim3(MT), 0, s, a, nid, (float2*)scratch);
-    MIDBF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(down_sum, dim3((unsigned)groups, tiles), dim3(MT), 0, s, a, (const float2*)scratch);
-    MIDBF_HIP(hipGetLastError());
+}  // namespace
+
+void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
+                        hipStream_t s) {
+    switch (variant) {
+        case 0: launch_variant<V0>(which, args, count, nrhs, scratch, s); break;
+        case 1: launch_variant<V1>(which, args, count, nrhs, scratch, s); break;
+        case 2: launch_variant<V2>(which, args, count, nrhs, scratch, s); break;
+        case 3: launch_variant<V3>(which, args, count, nrhs, scratch, s); break;
+        case 4: launch_variant<V4>(which, args, count, nrhs, scratch, s); break;
+        case 5: launch_variant<V5>(which, args, count, nrhs, scratch, s); break;
+        case 6: launch_variant<V6>(which, args, count, nrhs, scratch, s); break;
+        case 7: launch_variant<V7>(which, args, count, nrhs, scratch, s); break;
+        default: throw Error(MIDBF_ERR_ARG, "unknown matrix-core variant");
+    }
 }
 
 }  // namespace midbf

@@ -89,4 +89,5 @@ struct midbf_plan {
     long long max_total_k = 0, max_total_n = 0;
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
+    int mfma_variant[3] = {0, 0, 0};   // matrix-core tile variant for up, down, middle
 };

@@ -98,6 +98,16 @@ class MIDBF:
         L.check(L.lib.midbf_factor_stats(self._h, C.byref(s)))
         return {name: getattr(s, name) for name, _ in L.Stats._fields_}
 
+    def tune(self, nrhs: int, precision: str = "fp32", stream=None) -> list[int]:
+        """Pick the fastest matrix-core tile variants for nrhs right-hand sides (midbf_tune)."""
+        out = (C.c_int * 3)()
+        L.check(L.lib.midbf_tune(self._h, nrhs, _PREC[precision], _stream_ptr(stream), out))
+        return list(out)
+
+    def set_variants(self, variants) -> None:
+        arr = (C.c_int * 3)(*variants)
+        L.check(L.lib.midbf_set_variants(self._h, arr))
+
     def profile(self, on: bool = True) -> None:
         """Bracket every level-kernel launch with HIP events (midbf_profile_enable)."""
         L.check(L.lib.midbf_profile_enable(self._h, 1 if on else 0))
