@@ -9,7 +9,7 @@ constexpr int MFMA_NRHS = 64;        // right-hand sides per workgroup
 constexpr int MFMA_MIN_NRHS = 16;    // below this the VALU kernels are used
 constexpr int MFMA_CROW_MAX = 2048;  // largest candidate vector / middle block side
 
-constexpr int MFMA_VARIANTS = 8;     // tile variants (rows per wave, K chunk, pipelining)
+constexpr int MFMA_VARIANTS = 10;     // tile variants (rows per wave, K chunk, pipelining)
 
 // One matrix-core level kernel.  count = workgroups in x: IDs (up, down) or
 // middle blocks.  Going down, each ID writes its contribution to `scratch`

@@ -391,6 +391,8 @@ using V4 = Cfg<4, 32, false>;
 using V5 = Cfg<2, 16, true, 512>;
 using V6 = Cfg<1, 16, true, 512>;
 using V7 = Cfg<2, 32, false, 512>;
+using V8 = Cfg<1, 16, true, 1024>;
+using V9 = Cfg<1, 32, true, 512>;
 
 template <class C>
 void launch_variant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch, hipStream_t s) {
@@ -429,6 +431,8 @@ void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long l
         case 5: launch_variant<V5>(which, args, count, nrhs, scratch, s); break;
         case 6: launch_variant<V6>(which, args, count, nrhs, scratch, s); break;
         case 7: launch_variant<V7>(which, args, count, nrhs, scratch, s); break;
+        case 8: launch_variant<V8>(which, args, count, nrhs, scratch, s); break;
+        case 9: launch_variant<V9>(which, args, count, nrhs, scratch, s); break;
         default: throw Error(MIDBF_ERR_ARG, "unknown matrix-core variant");
     }
 }
