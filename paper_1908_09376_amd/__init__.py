@@ -15,4 +15,7 @@ def __getattr__(name):
     if name in _EXPORTS:
         from . import midbf
         return getattr(midbf, name)
+    if name == "midbf_matvec":
+        from .autograd import midbf_matvec
+        return midbf_matvec
     raise AttributeError(name)

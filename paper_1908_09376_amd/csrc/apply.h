@@ -66,7 +66,7 @@ struct MidArgs {
     int nrhs;
 };
 
-enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown };
+enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum };
 
 void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
                          hipStream_t s);

@@ -56,6 +56,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::AdjUp: return "adj_up";
         case LevelKernel::AdjMiddle: return "adj_middle";
         case LevelKernel::AdjDown: return "adj_down";
+        case LevelKernel::DownSum: return "down_sum";
     }
     return "?";
 }
@@ -80,7 +81,7 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
     auto go = [&] {
         if (mfma_count > 0) {
-            const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Down ? 1 : 2);
+            const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
             launch_mfma_kernel(which, h->mfma_variant[kind], args, mfma_count, nrhs, h->ws[prec].scratch, st);
         }
         else launch_level_kernel(which, prec, rt, args, grid, smem, st);
@@ -219,9 +220,18 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double vin = (double)lv.total_k * nrhs * cs;
         const double vout = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
-        launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
-                       dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
-                       8.0 * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs);
+        if (mfma) {
+            // per-ID contributions to the scratch block, then the ordered group sums
+            const double scr = (double)lv.total_n * nrhs * cs;
+            launch_checked(h, LevelKernel::Down, prec, rt, &a, dim3(), 0, st, fac + vin + scr, 8.0 * lv.entries * nrhs,
+                           lv.nid, nrhs);
+            launch_checked(h, LevelKernel::DownSum, prec, rt, &a, dim3(), 0, st, scr + vout,
+                           2.0 * (lv.total_n - lv.total_n / h->P) * nrhs, groups, nrhs);
+        } else {
+            launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
+                           dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
+                           8.0 * lv.entries * nrhs);
+        }
         o ^= 1;
     }
 }

@@ -11,10 +11,11 @@ constexpr int MFMA_CROW_MAX = 2048;  // largest candidate vector / middle block 
 
 constexpr int MFMA_VARIANTS = 10;     // tile variants (rows per wave, K chunk, pipelining)
 
-// One matrix-core level kernel.  count = workgroups in x: IDs (up, down) or
-// middle blocks.  Going down, each ID writes its contribution to `scratch`
-// (total_n x nrhs complex64) and a second kernel sums the 2^d contributions of
-// every group into the previous level buffer / external output.
+// One matrix-core level kernel.  count = workgroups in x: IDs (up, down),
+// groups (down-sum) or middle blocks.  Going down, each ID writes its
+// contribution to `scratch` (total_n x nrhs complex64) and the down-sum kernel
+// adds the 2^d contributions of every group into the previous level buffer /
+// external output.
 void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
                         hipStream_t s);
 

@@ -401,14 +401,12 @@ void launch_variant(LevelKernel which, const void* args, long long count, int nr
         case LevelKernel::Up:
             hipLaunchKernelGGL(up_mfma<C>, grid, dim3(C::NT), 0, s, *(const UpArgs*)args, count);
             break;
-        case LevelKernel::Down: {
-            const DownArgs& a = *(const DownArgs*)args;
-            const long long groups = count / a.G.P;
-            hipLaunchKernelGGL(down_mfma<C>, grid, dim3(C::NT), 0, s, a, count, (float2*)scratch);
-            MIDBF_HIP(hipGetLastError());
-            hipLaunchKernelGGL(down_sum, dim3((unsigned)groups, grid.y), dim3(MT), 0, s, a, (const float2*)scratch);
+        case LevelKernel::Down:
+            hipLaunchKernelGGL(down_mfma<C>, grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count, (float2*)scratch);
             break;
-        }
+        case LevelKernel::DownSum:
+            hipLaunchKernelGGL(down_sum, grid, dim3(MT), 0, s, *(const DownArgs*)args, (const float2*)scratch);
+            break;
         case LevelKernel::Middle:
             hipLaunchKernelGGL(middle_mfma<C>, grid, dim3(C::NT), 0, s, *(const MidArgs*)args);
             break;
