@@ -173,9 +173,9 @@ def main() -> int:
 
     variants = None
     tune_s = None
-    if args.precision == "fp32" and nrhs >= 16:
+    if (args.precision == "fp32" and nrhs >= 16) or args.precision == "bf16x3":
         t0 = time.perf_counter()
-        variants = F.tune(nrhs, "fp32")
+        variants = F.tune(nrhs, args.precision)
         tune_s = time.perf_counter() - t0
         log(f"[bench] autotuned matrix-core variants (up, down, middle) = {variants} in {tune_s:.2f} s")
 

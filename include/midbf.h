@@ -196,11 +196,12 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
  * and keeps the fastest per kernel kind.  Allocates and frees two N x nrhs
  * buffers; synchronizes `stream`.  If variants != NULL, writes the chosen
  * variants (up, down, middle) to variants[0..3).  Other precisions and
- * nrhs below the matrix-core threshold leave the choice unchanged.
+ * nrhs below the matrix-core threshold leave the choice unchanged.  FP32 and
+ * MIDBF_SPLIT_BF16 keep separate choices.
  * midbf_set_variants installs a choice made earlier (e.g. a cached one).
  */
 midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants);
-midbf_status midbf_set_variants(midbf_handle h, const int* variants);
+midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants);
 
 /* Release the factorization and its workspaces. */
 void midbf_destroy(midbf_handle h);

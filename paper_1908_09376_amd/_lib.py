@@ -62,7 +62,7 @@ def _load():
         "midbf_kernel_entries": (i, [C.POINTER(Params), vp, i, vp, i, vp, vp]),
         "midbf_id_batch": (i, [vp, i, i, i, C.c_double, i, vp, vp, vp, vp]),
         "midbf_tune": (i, [vp, i, i, vp, C.POINTER(i)]),
-        "midbf_set_variants": (i, [vp, C.POINTER(i)]),
+        "midbf_set_variants": (i, [vp, i, C.POINTER(i)]),
         "midbf_profile_enable": (i, [vp, i]),
         "midbf_profile_read": (i, [vp, C.POINTER(KernelTime), i, C.POINTER(i)]),
         "midbf_destroy": (None, [vp]),

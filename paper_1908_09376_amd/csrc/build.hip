@@ -8,6 +8,7 @@
 
 #include "build.h"
 #include "id.h"
+#include "mfma.h"
 
 namespace midbf {
 
@@ -242,11 +243,12 @@ void free_level(LevelSide& lv) {
 struct Scratch {
     double2* X = nullptr; double2* V = nullptr; double2* Y = nullptr;
     int* perm = nullptr; int* cand = nullptr; int* k = nullptr; int* n = nullptr; long long* toff = nullptr;
+    long long* tile_off = nullptr;
     int* samples = nullptr;
     long long wave = 0, xs = 0, vs = 0, ys = 0, nmax = 0;
     void release() {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
-        f(X); f(V); f(Y); f(perm); f(cand); f(k); f(n); f(toff); f(samples);
+        f(X); f(V); f(Y); f(perm); f(cand); f(k); f(n); f(toff); f(samples); f(tile_off);
         *this = Scratch();
     }
 };
@@ -307,6 +309,7 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
     sc.cand = dalloc<int>(wave * nmax);
     sc.k = dalloc<int>(wave);
     sc.toff = dalloc<long long>(wave);
+    sc.tile_off = dalloc<long long>(wave);
     sc.samples = dalloc<int>(m);
     upload(sc.samples, samples, st);
 
@@ -364,7 +367,24 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             }
             if (lv.d_T[PREC_FP64]) upload((void**)lv.d_T[PREC_FP64] + id0, p64, st);
             if (lv.d_T[PREC_FP32]) upload((void**)lv.d_T[PREC_FP32] + id0, p32, st);
-            if (lv.d_T[PREC_BF16]) upload((void**)lv.d_T[PREC_BF16] + id0, p32, st);
+            // split-bf16 fragment tiles: column side A = T (k x (n-k)), row side A = T^T
+            std::vector<long long> tile_off(cnt);
+            std::vector<void*> pbf(cnt);
+            if (lv.d_T[PREC_BF16]) {
+                long long tt = 0;
+                for (int w = 0; w < cnt; ++w) {
+                    const int k = kw[w], nn = lv.n[id0 + w];
+                    tile_off[w] = tt;
+                    tt += lv.side == SIDE_COL ? bf16_tiles(k, nn - k) : bf16_tiles(nn - k, k);
+                }
+                char* cb = (char*)dalloc<char>((size_t)std::max<long long>(tt, 1) * BF16_TILE_BYTES);
+                lv.chunks.push_back(cb);
+                lv.bf16_bytes += tt * BF16_TILE_BYTES;
+                upload(sc.tile_off, tile_off, st);
+                pack_bf16_slab(sc.X, sc.xs, sc.k, lv.d_n + id0, cnt, lv.side == SIDE_ROW, cb, sc.tile_off, st);
+                for (int w = 0; w < cnt; ++w) pbf[w] = cb + tile_off[w] * BF16_TILE_BYTES;
+                upload((void**)lv.d_T[PREC_BF16] + id0, pbf, st);
+            }
             MIDBF_HIP(hipStreamSynchronize(st));
         }
     } catch (...) {
@@ -470,6 +490,20 @@ void build_middle(midbf_plan* h, hipStream_t st) {
         hipLaunchKernelGGL(midgen_kernel, dim3(gx, (unsigned)cnt), dim3(BT), 0, st, mb);
         MIDBF_HIP(hipGetLastError());
     }
+    if (h->keep & MIDBF_KEEP_BF16) {
+        std::vector<long long> toff(M.nblk);
+        long long tt = 0;
+        for (long long bi = 0; bi < M.nblk; ++bi) {
+            toff[bi] = tt;
+            tt += bf16_tiles(M.nr[bi], M.nc[bi]);
+        }
+        M.d_tile_off = dalloc<long long>(M.nblk);
+        upload(M.d_tile_off, toff, st);
+        M.S[PREC_BF16] = dalloc<char>((size_t)std::max<long long>(tt, 1) * BF16_TILE_BYTES);
+        M.bf16_bytes = tt * BF16_TILE_BYTES;
+        pack_bf16_blocks(S32, M.d_off, M.d_nr, M.d_nc, M.nblk, M.S[PREC_BF16], M.d_tile_off, st);
+        MIDBF_HIP(hipStreamSynchronize(st));
+    }
     MIDBF_HIP(hipStreamSynchronize(st));
     (void)hipFree(d_pts);
     (void)hipFree(d_pts_off);
@@ -484,6 +518,7 @@ void destroy_plan(midbf_plan* h) {
     Middle& M = h->mid;
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(M.d_nr); f(M.d_nc); f(M.d_off); f(M.d_in_off); f(M.d_in_len); f(M.d_out_off); f(M.d_out_len);
+    f(M.d_tile_off);
     for (int q = 0; q < NPREC; ++q) f(M.S[q]);
     for (int q = 0; q < NPREC; ++q) { f(h->ws[q].buf[0]); f(h->ws[q].buf[1]); f(h->ws[q].scratch); }
     delete h;
@@ -559,7 +594,10 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         S.entries = ent;
         S.bytes_fp64 = (h->keep & MIDBF_KEEP_FP64) ? ent * 16 : 0;
         S.bytes_fp32 = (h->keep & MIDBF_KEEP_FP32) ? ent * 8 : 0;
-        S.bytes_bf16 = (h->keep & MIDBF_KEEP_BF16) ? ent * 8 : 0;
+        long long bfb = h->mid.bf16_bytes;
+        for (auto* side : {&h->rows, &h->cols})
+            for (auto& lv : *side) bfb += lv.bf16_bytes;
+        S.bytes_bf16 = (h->keep & MIDBF_KEEP_BF16) ? bfb : 0;
         S.index_bytes = idx;
         S.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     } catch (...) {

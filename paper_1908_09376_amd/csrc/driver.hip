@@ -82,7 +82,11 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     auto go = [&] {
         if (mfma_count > 0) {
             const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
-            launch_mfma_kernel(which, h->mfma_variant[kind], args, mfma_count, nrhs, h->ws[prec].scratch, st);
+            if (prec == PREC_BF16 && which != LevelKernel::DownSum)
+                launch_bf16_kernel(which, h->bf16_variant[kind], args, mfma_count, nrhs, h->ws[prec].scratch,
+                                   h->mid.d_tile_off, st);
+            else
+                launch_mfma_kernel(which, h->mfma_variant[kind], args, mfma_count, nrhs, h->ws[prec].scratch, st);
         }
         else launch_level_kernel(which, prec, rt, args, grid, smem, st);
     };
@@ -92,8 +96,9 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
         return;
     }
     ProfRecord r;
-    r.name = std::string(kernel_name(which)) + (mfma_count > 0 ? "_mfma" : "") +
-             (prec == PREC_FP64 ? "_fp64" : "_fp32") + (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
+    const char* pname = prec == PREC_FP64 ? "_fp64" : (prec == PREC_BF16 ? "_bf16x3" : "_fp32");
+    r.name = std::string(kernel_name(which)) + (mfma_count > 0 && prec != PREC_BF16 ? "_mfma" : "") + pname +
+             (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
     r.a = take_event(P);
     r.b = take_event(P);
     r.bytes = bytes;
@@ -133,11 +138,14 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
     MIDBF_CHECK(nrhs >= 1, MIDBF_ERR_ARG, "nrhs must be >= 1");
     MIDBF_CHECK(ld >= h->N, MIDBF_ERR_ARG, "ld must be >= N");
     MIDBF_CHECK(in_ext && out_ext, MIDBF_ERR_ARG, "null vector pointer");
-    MIDBF_CHECK(prec != PREC_BF16, MIDBF_ERR_UNIMPLEMENTED, "split-bf16 apply is served by the MFMA path only");
     const unsigned bit = 1u << prec;
     MIDBF_CHECK(h->keep & bit, MIDBF_ERR_ARG, "this precision's factors were not kept by the build");
-    const bool mfma = prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && h->max_n <= MFMA_CROW_MAX &&
-                      h->mid.nr_max <= MFMA_CROW_MAX && h->mid.nc_max <= MFMA_CROW_MAX;
+    const bool fits = h->max_n <= MFMA_CROW_MAX && h->mid.nr_max <= MFMA_CROW_MAX && h->mid.nc_max <= MFMA_CROW_MAX;
+    MIDBF_CHECK(prec != PREC_BF16 || (!adjoint && fits), MIDBF_ERR_UNIMPLEMENTED,
+                "the split-bf16 apply exists for the forward transform with candidate sets up to 2048");
+    // matrix cores: split-bf16 always, FP32 for many right-hand sides
+    const bool mfma = prec == PREC_BF16 || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
+    const double fl = prec == PREC_BF16 ? 24.0 : 8.0;   // flops per complex entry and RHS (bf16x3: three products)
     ensure_workspace(h, prec, nrhs, mfma);
     const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     const int tiles = (nrhs + rt - 1) / rt;
@@ -168,7 +176,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         launch_checked(h, adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a,
                        dim3((unsigned)groups, tiles), (size_t)ncand * rt * cs, st, fac + vin + vout,
-                       8.0 * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs);
+                       fl * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs);
         o ^= 1;
     }
     {
@@ -197,7 +205,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
             const double vec = (double)(h->rows.back().total_k + h->cols.back().total_k) * nrhs * cs;
             launch_checked(h, adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle, prec, rt, &ab,
                            dim3((unsigned)cnt, tiles), (size_t)width * rt * cs, st,
-                           frac * ((double)M.total * cs + (double)M.nblk * 40 + vec), frac * 8.0 * M.total * nrhs,
+                           frac * ((double)M.total * cs + (double)M.nblk * 40 + vec), frac * fl * M.total * nrhs,
                            mfma ? cnt : 0, nrhs);
         }
         o ^= 1;
@@ -223,7 +231,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         if (mfma) {
             // per-ID contributions to the scratch block, then the ordered group sums
             const double scr = (double)lv.total_n * nrhs * cs;
-            launch_checked(h, LevelKernel::Down, prec, rt, &a, dim3(), 0, st, fac + vin + scr, 8.0 * lv.entries * nrhs,
+            launch_checked(h, LevelKernel::Down, prec, rt, &a, dim3(), 0, st, fac + vin + scr, fl * lv.entries * nrhs,
                            lv.nid, nrhs);
             launch_checked(h, LevelKernel::DownSum, prec, rt, &a, dim3(), 0, st, scr + vout,
                            2.0 * (lv.total_n - lv.total_n / h->P) * nrhs, groups, nrhs);
@@ -307,7 +315,10 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
     return guarded([&] {
         const int pi = prec_index(prec);
         hipStream_t st = (hipStream_t)stream;
-        if (pi == PREC_FP32 && nrhs >= MFMA_MIN_NRHS && (h->keep & MIDBF_KEEP_FP32)) {
+        const bool bf = pi == PREC_BF16 && (h->keep & MIDBF_KEEP_BF16);
+        int* var = bf ? h->bf16_variant : h->mfma_variant;
+        const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
+        if (bf || (pi == PREC_FP32 && nrhs >= MFMA_MIN_NRHS && (h->keep & MIDBF_KEEP_FP32))) {
             void* f = nullptr;
             void* g = nullptr;
             const size_t bytes = (size_t)h->N * nrhs * 8;
@@ -323,8 +334,8 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
             int pick[3] = {0, 0, 0};
             try {
                 MIDBF_HIP(hipMemsetAsync(f, 0, bytes, st));
-                for (int v = 0; v < MFMA_VARIANTS; ++v) {
-                    for (int q = 0; q < 3; ++q) h->mfma_variant[q] = v;
+                for (int v = 0; v < nvar; ++v) {
+                    for (int q = 0; q < 3; ++q) var[q] = v;
                     h->prof.on = false;
                     run_apply(h, f, g, nrhs, h->N, pi, st, false);          // warm-up
                     h->prof.on = true;
@@ -356,18 +367,21 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
             MIDBF_HIP(hipStreamSynchronize(st));
             (void)hipFree(f);
             (void)hipFree(g);
-            for (int q = 0; q < 3; ++q) h->mfma_variant[q] = pick[q];
+            for (int q = 0; q < 3; ++q) var[q] = pick[q];
         }
         if (variants)
-            for (int q = 0; q < 3; ++q) variants[q] = h->mfma_variant[q];
+            for (int q = 0; q < 3; ++q) variants[q] = var[q];
     });
 }
 
-midbf_status midbf_set_variants(midbf_handle h, const int* variants) {
+midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants) {
     if (!h || !variants) return fail(MIDBF_ERR_ARG, "null argument");
+    const bool bf = prec == MIDBF_SPLIT_BF16;
+    if (!bf && prec != MIDBF_FP32) return fail(MIDBF_ERR_ARG, "variants exist for FP32 and split-bf16");
+    const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
     for (int q = 0; q < 3; ++q)
-        if (variants[q] < 0 || variants[q] >= MFMA_VARIANTS) return fail(MIDBF_ERR_ARG, "unknown variant");
-    for (int q = 0; q < 3; ++q) h->mfma_variant[q] = variants[q];
+        if (variants[q] < 0 || variants[q] >= nvar) return fail(MIDBF_ERR_ARG, "unknown variant");
+    for (int q = 0; q < 3; ++q) (bf ? h->bf16_variant : h->mfma_variant)[q] = variants[q];
     return MIDBF_OK;
 }
 

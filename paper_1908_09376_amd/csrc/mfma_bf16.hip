@@ -1,0 +1,476 @@
+// Split-bf16 matrix-core apply (complex64 vectors, FP32 accumulation).
+//
+// Every factor entry and every vector entry x is split into two bf16 values,
+// hi = bf16(x) and lo = bf16(x - hi), and each real product uses three bf16
+// products hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 (lane l supplies
+// A[l%16][8(l/16)+i] and B[8(l/16)+i][l%16], i < 8; checked on the device).
+// A complex product therefore costs 12 bf16 MFMAs:
+//     Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br,  each real product split three ways.
+//
+// Factors are stored as MFMA fragments: a 16-row x 32-column tile of A is
+// 64 lanes x (re_hi[8], im_hi[8], re_lo[8], im_lo[8]) bf16 = 4 KB, so one wave
+// loads a whole tile with four fully coalesced 16-byte loads per lane.  Tiles of
+// one block are stored row-tile major (all K tiles of row tile 0, then row tile 1...).
+// B (the level vectors) is split on the fly while it is staged through LDS in
+// the same fragment order.
+#include <algorithm>
+
+#include "apply.h"
+#include "mfma.h"
+
+namespace midbf {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+
+constexpr int NRHS = MFMA_NRHS;
+constexpr int KT = 32;                       // K per tile / per chunk
+constexpr int CROW_MAX = MFMA_CROW_MAX;
+
+struct Frag {
+    bf16x8 rh, ih, rl, il;
+};
+
+__device__ inline bf16x8 neg8(bf16x8 v) {
+    intx4 x = __builtin_bit_cast(intx4, v);
+    x ^= (int)0x80008000;
+    return __builtin_bit_cast(bf16x8, x);
+}
+
+template <int MTW>
+__device__ inline void kstep_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const Frag (&a)[MTW], const Frag (&b)[4],
+                                  int ntl) {
+#define MF(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0)
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+        if (mt >= ntl) continue;
+        const bf16x8 nih = neg8(a[mt].ih), nil = neg8(a[mt].il);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            MF(cr[mt][nt], a[mt].rh, b[nt].rh);
+            MF(ci[mt][nt], a[mt].rh, b[nt].ih);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            MF(cr[mt][nt], nih, b[nt].ih);
+            MF(ci[mt][nt], a[mt].ih, b[nt].rh);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            MF(cr[mt][nt], a[mt].rh, b[nt].rl);
+            MF(ci[mt][nt], a[mt].rh, b[nt].il);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            MF(cr[mt][nt], a[mt].rl, b[nt].rh);
+            MF(ci[mt][nt], a[mt].rl, b[nt].ih);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            MF(cr[mt][nt], nih, b[nt].il);
+            MF(ci[mt][nt], a[mt].ih, b[nt].rl);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            MF(cr[mt][nt], nil, b[nt].ih);
+            MF(ci[mt][nt], a[mt].il, b[nt].rh);
+        }
+    }
+#undef MF
+}
+
+template <int MTW_, int NT_>
+struct BCfg {
+    static constexpr int MTW = MTW_;
+    static constexpr int NT = NT_;
+    static constexpr int ROUND = NT / 64 * MTW * 16;
+};
+
+// Rows [base, base + 16 MTW) of C (+)= A B for one wave, where A's tiles of
+// row tile t start at Atiles + t * ktiles tiles.  brow(j, r) returns B[j][r].
+// Register prefetch of the next tile's A fragments and of this thread's next
+// B elements; double-buffered LDS; one barrier per K tile.
+template <class C, class BRow>
+__device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const Frag* __restrict__ Atiles,
+                               int M, int K, int base, BRow brow, int nr, Frag* sB) {
+    constexpr int MTW = C::MTW, NT = C::NT;
+    constexpr int BPT = KT * NRHS / NT;
+    const int tid = threadIdx.x, l = tid & 63;
+    const int ntl = base < M ? min(MTW, (M - base + 15) / 16) : 0;
+    const int ktiles = (K + KT - 1) / KT;
+    if (ktiles == 0) return;
+    const int mt0 = base / 16;
+    auto loadA = [&](int kt, Frag (&dst)[MTW]) {
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt)
+            if (mt < ntl) dst[mt] = Atiles[((long long)(mt0 + mt) * ktiles + kt) * 64 + l];
+    };
+    float2 bt[BPT];
+    auto loadB = [&](int kt) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e = tid + q * NT, jj = e / NRHS, r = e - jj * NRHS, j = kt * KT + jj;
+            bt[q] = (j < K && r < nr) ? brow(j, r) : make_float2(0.f, 0.f);
+        }
+    };
+    // element (jj, r) of the chunk goes to fragment (nt = r/16, lane (jj/8)*16 + r%16), slot jj%8
+    auto storeB = [&](int buf) {
+        __bf16* base_p = reinterpret_cast<__bf16*>(sB + buf * 4 * 64);
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int e = tid + q * NT, jj = e / NRHS, r = e - jj * NRHS;
+            const int nt = r >> 4, lane = (jj >> 3) * 16 + (r & 15), slot = jj & 7;
+            __bf16* f = base_p + (long long)(nt * 64 + lane) * 32;
+            const float x = bt[q].x, y = bt[q].y;
+            const __bf16 xh = (__bf16)x, yh = (__bf16)y;
+            f[slot] = xh;
+            f[8 + slot] = yh;
+            f[16 + slot] = (__bf16)(x - (float)xh);
+            f[24 + slot] = (__bf16)(y - (float)yh);
+        }
+    };
+    Frag acur[MTW], anext[MTW];
+    loadA(0, acur);
+    loadB(0);
+    __syncthreads();
+    storeB(0);
+    __syncthreads();
+    for (int kt = 0; kt < ktiles; ++kt) {
+        const bool more = kt + 1 < ktiles;
+        if (more) {
+            loadA(kt + 1, anext);
+            loadB(kt + 1);
+        }
+        if (ntl > 0) {
+            const Frag* sb = sB + (kt & 1) * 4 * 64;
+            Frag b[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) b[nt] = sb[nt * 64 + l];
+            kstep_bf16<MTW>(cr, ci, acur, b, ntl);
+        }
+        if (more) {
+            storeB((kt + 1) & 1);
+#pragma unroll
+            for (int mt = 0; mt < MTW; ++mt) acur[mt] = anext[mt];
+        }
+        __syncthreads();
+    }
+}
+
+template <int MTW>
+__device__ inline void zero_acc(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4]) {
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
+}
+
+template <int NT>
+__device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a, long long partner, long long Ps,
+                              const int* k_prev, const long long* yoff_prev) {
+    if (s == 0) {
+        int origin[3];
+        node_origin(a, G.L, G.d, G.n, origin);
+        for (int c = threadIdx.x; c < G.n0; c += NT) crow[c] = (int)box_point(origin, G.leaf, c, G.d, G.n);
+        return G.n0;
+    }
+    int start = 0;
+    for (int t = 0; t < G.P; ++t) {
+        const long long idp = ((long long)G.P * a + t) * Ps + partner;
+        const int len = k_prev[idp];
+        const long long off = yoff_prev[idp];
+        for (int c = threadIdx.x; c < len; c += NT) crow[start + c] = (int)(off + c);
+        start += len;
+    }
+    return start;
+}
+
+__device__ inline float2 load_vec(bool ext, const float2* p, long long ld, int nrhs, int row, int r) {
+    return ext ? p[(long long)r * ld + row] : p[(long long)row * nrhs + r];
+}
+
+__device__ inline long long xcd_group_order(long long b, long long nid, int P) {
+    if (P != 4 || (nid & 31) != 0) return b;
+    const long long x = b & 7, t = (b >> 3) & 3, q = b >> 5;
+    return ((q << 3) + x) * 4 + t;
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
+    constexpr int MTW = C::MTW;
+    __shared__ int crow[CROW_MAX];
+    __shared__ Frag sB[2 * 4 * 64];
+    const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
+    const long long g = id / A.G.P;
+    const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
+    const bool ext = A.s == 0;
+    const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
+    float2* out = (float2*)A.out;
+    const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+    const int* perm = A.lev.perm + A.lev.perm_off[id];
+    const Frag* Tt = (const Frag*)A.lev.T[id];
+    const long long yo = A.lev.y_off[id];
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    __syncthreads();
+    const int* red = perm + k;
+    auto brow = [&](int j, int r) { return load_vec(ext, xin, A.ld, A.nrhs, crow[red[j]], r0 + r); };
+    for (int m0 = 0; m0 < k; m0 += C::ROUND) {
+        const int base = m0 + wave * MTW * 16;
+        floatx4 cr[MTW][4], ci[MTW][4];
+        zero_acc<MTW>(cr, ci);
+        gemm_rows_bf16<C>(cr, ci, Tt, k, nred, base, brow, nr, sB);
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + mt * 16 + 4 * lk + v;
+                if (row < k) {
+                    const int src = crow[perm[row]];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) {
+                            const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, float2* scr) {
+    constexpr int MTW = C::MTW;
+    __shared__ Frag sB[2 * 4 * 64];
+    const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const float2* zin = (const float2*)A.in;
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+    const int* perm = A.lev.perm + A.lev.perm_off[id];
+    const Frag* Tt = (const Frag*)A.lev.T[id];
+    const long long yo = A.lev.y_off[id];
+    float2* w = scr + A.lev.perm_off[id] * A.nrhs;
+    for (int e = tid; e < k * NRHS; e += C::NT) {
+        const int i = e / NRHS, r = e - i * NRHS;
+        if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
+    }
+    const float2* z = zin + yo * A.nrhs + r0;
+    auto brow = [&](int i, int r) { return z[(long long)i * A.nrhs + r]; };
+    for (int m0 = 0; m0 < nred; m0 += C::ROUND) {
+        const int base = m0 + wave * MTW * 16;
+        floatx4 cr[MTW][4], ci[MTW][4];
+        zero_acc<MTW>(cr, ci);
+        gemm_rows_bf16<C>(cr, ci, Tt, nred, k, base, brow, nr, sB);
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + mt * 16 + 4 * lk + v;
+                if (row < nred) {
+                    float2* d = w + (long long)perm[k + row] * A.nrhs + r0;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) d[r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long* tile_off) {
+    constexpr int MTW = C::MTW;
+    __shared__ int crow_in[CROW_MAX];
+    __shared__ int crow_out[CROW_MAX];
+    __shared__ Frag sB[2 * 4 * 64];
+    const long long bi = blockIdx.x;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const int M = A.nr[bi], K = A.nc[bi];
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    {
+        int s_in = 0, s_out = 0;
+        for (int t = 0; t < A.pieces; ++t) {
+            const long long oi = A.in_off[bi * A.pieces + t], oo = A.out_off[bi * A.pieces + t];
+            const int li = A.in_len[bi * A.pieces + t], lo = A.out_len[bi * A.pieces + t];
+            for (int c = tid; c < li; c += C::NT) crow_in[s_in + c] = (int)(oi + c);
+            for (int c = tid; c < lo; c += C::NT) crow_out[s_out + c] = (int)(oo + c);
+            s_in += li;
+            s_out += lo;
+        }
+    }
+    const float2* xin = (const float2*)A.in;
+    float2* zout = (float2*)A.out;
+    const Frag* St = (const Frag*)A.S + tile_off[bi] * 64;
+    __syncthreads();
+    auto brow = [&](int j, int r) { return xin[(long long)crow_in[j] * A.nrhs + r0 + r]; };
+    for (int m0 = 0; m0 < M; m0 += C::ROUND) {
+        const int base = m0 + wave * MTW * 16;
+        floatx4 cr[MTW][4], ci[MTW][4];
+        zero_acc<MTW>(cr, ci);
+        gemm_rows_bf16<C>(cr, ci, St, M, K, base, brow, nr, sB);
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + mt * 16 + 4 * lk + v;
+                if (row < M) {
+                    const long long dst = crow_out[row];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) zout[dst * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+using W0 = BCfg<1, 512>;
+using W1 = BCfg<1, 256>;
+using W2 = BCfg<2, 256>;
+
+template <class C>
+void launch_bvariant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch,
+                     const long long* tile_off, hipStream_t s) {
+    const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
+    switch (which) {
+        case LevelKernel::Up:
+            hipLaunchKernelGGL(up_bf16<C>, grid, dim3(C::NT), 0, s, *(const UpArgs*)args, count);
+            break;
+        case LevelKernel::Down:
+            hipLaunchKernelGGL(down_bf16<C>, grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count,
+                               (float2*)scratch);
+            break;
+        case LevelKernel::Middle:
+            hipLaunchKernelGGL(middle_bf16<C>, grid, dim3(C::NT), 0, s, *(const MidArgs*)args, tile_off);
+            break;
+        default:
+            throw Error(MIDBF_ERR_UNIMPLEMENTED, "no split-bf16 kernel for this level kind");
+    }
+    MIDBF_HIP(hipGetLastError());
+}
+
+// ---- packing of factor blocks into fragment tiles (build time) --------------
+
+// A(row, col) of a block given by a column-major FP32 matrix (lda = M) or by T
+// inside an FP64 sample slab; tiles row-tile major, zero padded.
+struct PackTilesArgs {
+    int mode;                 // 0: FP64 slab, A(i, j) = T[i][j] (T at X[i*n + k + j]); 1: transposed T
+                              // 2: FP32 column-major block (lda = M)
+    const double2* X;         // mode 0/1: slab base
+    long long x_stride;
+    const int* k_w;
+    const int* n_w;
+    const float2* S;          // mode 2
+    const long long* s_off;   // mode 2: element offset per block
+    const int* nr;
+    const int* nc;
+    Frag* out;
+    const long long* tile_off;  // per block / ID: first tile
+};
+
+__global__ void pack_tiles_kernel(PackTilesArgs P) {
+    const int b = blockIdx.x;
+    int M, K;
+    const double2* X = nullptr;
+    const float2* S = nullptr;
+    int k = 0, n = 0;
+    if (P.mode == 2) {
+        M = P.nr[b];
+        K = P.nc[b];
+        S = P.S + P.s_off[b];
+    } else {
+        k = P.k_w[b];
+        n = P.n_w[b];
+        X = P.X + (long long)b * P.x_stride;
+        M = P.mode == 0 ? k : n - k;
+        K = P.mode == 0 ? n - k : k;
+    }
+    const int mtiles = (M + 15) / 16, ktiles = (K + KT - 1) / KT;
+    Frag* out = P.out + P.tile_off[b] * 64;
+    const long long nfr = (long long)mtiles * ktiles * 64;
+    for (long long e = threadIdx.x; e < nfr; e += blockDim.x) {
+        const int lane = (int)(e & 63);
+        const long long tile = e >> 6;
+        const int mt = (int)(tile / ktiles), kt = (int)(tile - (long long)mt * ktiles);
+        const int row = mt * 16 + (lane & 15);
+        const int c0 = kt * KT + (lane >> 4) * 8;
+        Frag f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int col = c0 + i;
+            float x = 0.f, y = 0.f;
+            if (row < M && col < K) {
+                if (P.mode == 2) {
+                    const float2 v = S[(long long)col * M + row];
+                    x = v.x;
+                    y = v.y;
+                } else {
+                    const int ti = P.mode == 0 ? row : col, tj = P.mode == 0 ? col : row;
+                    const double2 v = X[(long long)ti * n + k + tj];
+                    const float xh = (float)(__bf16)v.x, yh = (float)(__bf16)v.y;
+                    f.rh[i] = (__bf16)v.x;
+                    f.ih[i] = (__bf16)v.y;
+                    f.rl[i] = (__bf16)(v.x - (double)xh);
+                    f.il[i] = (__bf16)(v.y - (double)yh);
+                    continue;
+                }
+            }
+            const __bf16 xh = (__bf16)x, yh = (__bf16)y;
+            f.rh[i] = xh;
+            f.ih[i] = yh;
+            f.rl[i] = (__bf16)(x - (float)xh);
+            f.il[i] = (__bf16)(y - (float)yh);
+        }
+        out[e] = f;
+    }
+}
+
+}  // namespace
+
+void launch_bf16_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
+                        const long long* tile_off, hipStream_t s) {
+    switch (variant) {
+        case 0: launch_bvariant<W0>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 1: launch_bvariant<W1>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 2: launch_bvariant<W2>(which, args, count, nrhs, scratch, tile_off, s); break;
+        default: throw Error(MIDBF_ERR_ARG, "unknown split-bf16 variant");
+    }
+}
+
+long long bf16_tiles(int M, int K) { return (long long)((M + 15) / 16) * ((K + KT - 1) / KT); }
+
+void pack_bf16_slab(const double2* X, long long x_stride, const int* k_w, const int* n_w, int count, bool transposed,
+                    void* out, const long long* tile_off, hipStream_t s) {
+    if (count <= 0) return;
+    PackTilesArgs P{transposed ? 1 : 0, X, x_stride, k_w, n_w, nullptr, nullptr, nullptr, nullptr, (Frag*)out,
+                    tile_off};
+    hipLaunchKernelGGL(pack_tiles_kernel, dim3(count), dim3(256), 0, s, P);
+    MIDBF_HIP(hipGetLastError());
+}
+
+void pack_bf16_blocks(const float2* S, const long long* s_off, const int* nr, const int* nc, long long count, void* out,
+                      const long long* tile_off, hipStream_t s) {
+    for (long long b0 = 0; b0 < count; b0 += 65535) {
+        const long long cnt = std::min<long long>(65535, count - b0);
+        PackTilesArgs P{2, nullptr, 0, nullptr, nullptr, S, s_off + b0, nr + b0, nc + b0, (Frag*)out, tile_off + b0};
+        hipLaunchKernelGGL(pack_tiles_kernel, dim3((unsigned)cnt), dim3(256), 0, s, P);
+        MIDBF_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace midbf

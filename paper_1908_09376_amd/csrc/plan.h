@@ -22,7 +22,7 @@ struct LevelSide {
     int m = 0;                            // samples per decomposition
     std::vector<int> k, n;                // rank and candidate count per ID
     std::vector<long long> perm_off, y_off;
-    long long total_k = 0, total_n = 0, entries = 0;
+    long long total_k = 0, total_n = 0, entries = 0, bf16_bytes = 0;
     int kmin = 0, kmax = 0, nmax = 0;
     // device copies
     int* d_k = nullptr;
@@ -51,7 +51,9 @@ struct Middle {
     int* d_in_len = nullptr;
     long long* d_out_off = nullptr;
     int* d_out_len = nullptr;
-    void* S[NPREC] = {nullptr, nullptr, nullptr};       // column-major blocks at off
+    void* S[NPREC] = {nullptr, nullptr, nullptr};       // column-major blocks at off (bf16: fragment tiles)
+    long long* d_tile_off = nullptr;                    // first bf16 tile of each block
+    long long bf16_bytes = 0;
 };
 
 struct Workspace {
@@ -89,5 +91,6 @@ struct midbf_plan {
     long long max_total_k = 0, max_total_n = 0;
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
-    int mfma_variant[3] = {0, 0, 0};   // matrix-core tile variant for up, down, middle
+    int mfma_variant[3] = {0, 0, 0};   // matrix-core tile variant for up, down, middle (FP32)
+    int bf16_variant[3] = {0, 0, 0};   // the same for split-bf16
 };

@@ -104,9 +104,9 @@ class MIDBF:
         L.check(L.lib.midbf_tune(self._h, nrhs, _PREC[precision], _stream_ptr(stream), out))
         return list(out)
 
-    def set_variants(self, variants) -> None:
+    def set_variants(self, variants, precision: str = "fp32") -> None:
         arr = (C.c_int * 3)(*variants)
-        L.check(L.lib.midbf_set_variants(self._h, arr))
+        L.check(L.lib.midbf_set_variants(self._h, _PREC[precision], arr))
 
     def profile(self, on: bool = True) -> None:
         """Bracket every level-kernel launch with HIP events (midbf_profile_enable)."""

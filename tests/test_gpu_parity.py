@@ -223,7 +223,7 @@ def test_mfma_every_tile_variant(variant):
     F = _build(128, "fio_ellipse")
     f = W.complex_gaussian(128 * 128, 40, 43)
     g64 = from_dev(F.apply(to_dev(f)))
-    F.set_variants([variant] * 3)
+    F.set_variants([variant] * 3, precision="fp32")
     g32 = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp32"))
     assert rel_l2(g32, g64) < 1e-5
 
@@ -235,3 +235,29 @@ def test_autotuner_picks_valid_variants():
     f = W.complex_gaussian(64 * 64, 64, 44)
     g32 = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp32"))
     assert rel_l2(g32, from_dev(F.apply(to_dev(f)))) < 1e-5
+
+
+# ---- split-bf16 matrix-core path ---------------------------------------------
+
+@pytest.mark.parametrize("n,nrhs", [(64, 64), (128, 20), (256, 64)])
+def test_bf16x3_apply(n, nrhs):
+    F = _build(n, "fio_ellipse")
+    K = Kernel(2, n, "fio_ellipse")
+    f = W.complex_gaussian(K.N, nrhs, 45, n)
+    gb = from_dev(F.apply(to_dev(f, torch.complex64), precision="bf16x3"))
+    g64 = from_dev(F.apply(to_dev(f)))
+    err = rel_l2(gb, g64)
+    assert err < 1e-4, err           # split-bf16 target is 1e-3 against the direct sum
+    rows = W.sample_rows(K.N, 0, 64)
+    assert rel_l2(gb[rows], direct_sum(K, f, rows=rows)) < 1e-3
+
+
+@pytest.mark.parametrize("variant", range(3))
+def test_bf16x3_every_variant(variant):
+    F = _build(128, "fio_ellipse")
+    f = W.complex_gaussian(128 * 128, 64, 46)
+    g64 = from_dev(F.apply(to_dev(f)))
+    F.set_variants([variant] * 3, precision="bf16x3")
+    gb = from_dev(F.apply(to_dev(f, torch.complex64), precision="bf16x3"))
+    assert rel_l2(gb, g64) < 1e-4
+    assert F.tune(64, "bf16x3")[0] in range(3)
