@@ -176,7 +176,8 @@ midbf_status midbf_id_batch(void* X_dev, int batch, int m, int n, double tol, in
  * algorithmic bytes (factor entries once, index tables, input and output
  * vectors) and flops (8 per complex multiply-add) of those launches.  It
  * writes up to max_entries records, sets *count to the number of distinct
- * kernels, and clears the records.
+ * kernels, and clears the records.  on = 2 also splits each kernel by MSCS
+ * step (names end in _s<step>).
  */
 typedef struct {
     char name[48];
@@ -191,14 +192,15 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
 
 /*
  * midbf_tune -- autotuner of the many-right-hand-side (matrix-core) apply:
- * times every tile variant (rows per wave, K chunk, pipelining) of the up,
- * down and middle kernels on this factorization with nrhs right-hand sides
- * and keeps the fastest per kernel kind.  Allocates and frees two N x nrhs
- * buffers; synchronizes `stream`.  If variants != NULL, writes the chosen
- * variants (up, down, middle) to variants[0..3).  Other precisions and
+ * times every tile variant (rows per wave, K chunk, pipelining, workgroup
+ * width) of the up, down and middle kernels on this factorization with nrhs
+ * right-hand sides and keeps the fastest per kernel kind and MSCS step.
+ * Allocates and frees two N x nrhs buffers; synchronizes `stream`.  If
+ * variants != NULL, writes the choice for the top step of up and down and
+ * for the middle to variants[0..3).  midbf_set_variants installs one variant
+ * per kind for every step.  Other precisions and
  * nrhs below the matrix-core threshold leave the choice unchanged.  FP32 and
  * MIDBF_SPLIT_BF16 keep separate choices.
- * midbf_set_variants installs a choice made earlier (e.g. a cached one).
  */
 midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants);
 midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants);

@@ -1,5 +1,7 @@
 // Apply orchestration and the C interface (include/midbf.h).
 #include <algorithm>
+#include <cctype>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -76,17 +78,19 @@ hipEvent_t take_event(Profiler& P) {
 // same stream and record its algorithmic bytes and flops.  mfma_count > 0
 // selects the matrix-core kernel with that many workgroups in x.
 void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
-                    hipStream_t st, double bytes, double flops, long long mfma_count = 0, int nrhs = 0) {
+                    hipStream_t st, double bytes, double flops, long long mfma_count = 0, int nrhs = 0,
+                    int level = -1) {
     MIDBF_CHECK(mfma_count > 0 || smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
     auto go = [&] {
         if (mfma_count > 0) {
             const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
+            const int lv = std::max(0, std::min(level, midbf_plan::VMAXLEV - 1));
             if (prec == PREC_BF16 && which != LevelKernel::DownSum)
-                launch_bf16_kernel(which, h->bf16_variant[kind], args, mfma_count, nrhs, h->ws[prec].scratch,
+                launch_bf16_kernel(which, h->bf16_variant[kind][lv], args, mfma_count, nrhs, h->ws[prec].scratch,
                                    h->mid.d_tile_off, st);
             else
-                launch_mfma_kernel(which, h->mfma_variant[kind], args, mfma_count, nrhs, h->ws[prec].scratch, st);
+                launch_mfma_kernel(which, h->mfma_variant[kind][lv], args, mfma_count, nrhs, h->ws[prec].scratch, st);
         }
         else launch_level_kernel(which, prec, rt, args, grid, smem, st);
     };
@@ -99,6 +103,7 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     const char* pname = prec == PREC_FP64 ? "_fp64" : (prec == PREC_BF16 ? "_bf16x3" : "_fp32");
     r.name = std::string(kernel_name(which)) + (mfma_count > 0 && prec != PREC_BF16 ? "_mfma" : "") + pname +
              (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
+    if (P.by_level && level >= 0) r.name += "_s" + std::to_string(level);
     r.a = take_event(P);
     r.b = take_event(P);
     r.bytes = bytes;
@@ -176,7 +181,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         launch_checked(h, adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a,
                        dim3((unsigned)groups, tiles), (size_t)ncand * rt * cs, st, fac + vin + vout,
-                       fl * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs);
+                       fl * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs, s);
         o ^= 1;
     }
     {
@@ -232,9 +237,9 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
             // per-ID contributions to the scratch block, then the ordered group sums
             const double scr = (double)lv.total_n * nrhs * cs;
             launch_checked(h, LevelKernel::Down, prec, rt, &a, dim3(), 0, st, fac + vin + scr, fl * lv.entries * nrhs,
-                           lv.nid, nrhs);
+                           lv.nid, nrhs, s);
             launch_checked(h, LevelKernel::DownSum, prec, rt, &a, dim3(), 0, st, scr + vout,
-                           2.0 * (lv.total_n - lv.total_n / h->P) * nrhs, groups, nrhs);
+                           2.0 * (lv.total_n - lv.total_n / h->P) * nrhs, groups, nrhs, s);
         } else {
             launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
                            dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
@@ -310,14 +315,24 @@ midbf_status midbf_id_batch(void* X, int batch, int m, int n, double tol, int k_
     return guarded([&] { id_batch(X, batch, m, n, tol, k_cap, k_dev, perm_dev, T_dev, (hipStream_t)stream); });
 }
 
+// name of a profiled launch -> (kind, step): up / down(+sum) / middle, "_s<step>" suffix
+static void kind_level(const std::string& name, int& q, int& lv) {
+    q = name.rfind("up", 0) == 0 ? 0 : (name.rfind("down", 0) == 0 ? 1 : 2);
+    lv = 0;
+    const size_t p = name.rfind("_s");
+    if (p != std::string::npos && p + 2 < name.size() && isdigit((unsigned char)name[p + 2])) lv = std::atoi(name.c_str() + p + 2);
+    lv = std::min(lv, midbf_plan::VMAXLEV - 1);
+}
+
 midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants) {
     if (!h) return fail(MIDBF_ERR_ARG, "null handle");
     return guarded([&] {
         const int pi = prec_index(prec);
         hipStream_t st = (hipStream_t)stream;
         const bool bf = pi == PREC_BF16 && (h->keep & MIDBF_KEEP_BF16);
-        int* var = bf ? h->bf16_variant : h->mfma_variant;
+        auto& var = bf ? h->bf16_variant : h->mfma_variant;
         const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
+        constexpr int NL = midbf_plan::VMAXLEV;
         if (bf || (pi == PREC_FP32 && nrhs >= MFMA_MIN_NRHS && (h->keep & MIDBF_KEEP_FP32))) {
             void* f = nullptr;
             void* g = nullptr;
@@ -327,50 +342,61 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
                 (void)hipFree(f);
                 throw Error(MIDBF_ERR_OOM, "tuning buffers");
             }
-            const bool was_on = h->prof.on;
+            const bool was_on = h->prof.on, was_lv = h->prof.by_level;
             const std::vector<ProfRecord> saved = h->prof.recs;
             h->prof.recs.clear();
-            double best[3] = {1e300, 1e300, 1e300};
-            int pick[3] = {0, 0, 0};
+            std::vector<double> best(3 * NL, 1e300);
+            std::vector<int> pick(3 * NL, 0);
             try {
                 MIDBF_HIP(hipMemsetAsync(f, 0, bytes, st));
                 for (int v = 0; v < nvar; ++v) {
-                    for (int q = 0; q < 3; ++q) var[q] = v;
+                    for (int q = 0; q < 3; ++q)
+                        for (int l = 0; l < NL; ++l) var[q][l] = v;
                     h->prof.on = false;
                     run_apply(h, f, g, nrhs, h->N, pi, st, false);          // warm-up
                     h->prof.on = true;
+                    h->prof.by_level = true;
                     run_apply(h, f, g, nrhs, h->N, pi, st, false);
                     h->prof.on = false;
-                    double t[3] = {0, 0, 0};
+                    std::vector<double> t(3 * NL, 0.0);
                     for (auto& r : h->prof.recs) {
                         MIDBF_HIP(hipEventSynchronize(r.b));
                         float ms = 0.f;
                         MIDBF_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-                        const int q = r.name.rfind("up", 0) == 0 ? 0 : (r.name.rfind("down", 0) == 0 ? 1 : 2);
-                        t[q] += ms;
+                        int q, lv;
+                        kind_level(r.name, q, lv);
+                        t[q * NL + lv] += ms;
                         h->prof.pool.push_back(r.a);
                         h->prof.pool.push_back(r.b);
                     }
                     h->prof.recs.clear();
-                    for (int q = 0; q < 3; ++q)
-                        if (t[q] < best[q]) { best[q] = t[q]; pick[q] = v; }
+                    for (int i = 0; i < 3 * NL; ++i)
+                        if (t[i] > 0.0 && t[i] < best[i]) { best[i] = t[i]; pick[i] = v; }
                 }
             } catch (...) {
                 h->prof.on = was_on;
+                h->prof.by_level = was_lv;
                 h->prof.recs = saved;
                 (void)hipFree(f);
                 (void)hipFree(g);
                 throw;
             }
             h->prof.on = was_on;
+            h->prof.by_level = was_lv;
             h->prof.recs = saved;
             MIDBF_HIP(hipStreamSynchronize(st));
             (void)hipFree(f);
             (void)hipFree(g);
-            for (int q = 0; q < 3; ++q) var[q] = pick[q];
+            for (int q = 0; q < 3; ++q)
+                for (int l = 0; l < NL; ++l) var[q][l] = pick[q * NL + l];
         }
-        if (variants)
-            for (int q = 0; q < 3; ++q) variants[q] = var[q];
+        // reported: the choice for the largest step of each kind (up, down) and the middle
+        if (variants) {
+            const int top = std::max(0, std::min(h->b - 1, NL - 1));
+            variants[0] = var[0][top];
+            variants[1] = var[1][top];
+            variants[2] = var[2][0];
+        }
     });
 }
 
@@ -381,13 +407,15 @@ midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int*
     const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
     for (int q = 0; q < 3; ++q)
         if (variants[q] < 0 || variants[q] >= nvar) return fail(MIDBF_ERR_ARG, "unknown variant");
-    for (int q = 0; q < 3; ++q) (bf ? h->bf16_variant : h->mfma_variant)[q] = variants[q];
+    for (int q = 0; q < 3; ++q)
+        for (int l = 0; l < midbf_plan::VMAXLEV; ++l) (bf ? h->bf16_variant : h->mfma_variant)[q][l] = variants[q];
     return MIDBF_OK;
 }
 
 midbf_status midbf_profile_enable(midbf_handle h, int on) {
     if (!h) return fail(MIDBF_ERR_ARG, "null handle");
     h->prof.on = on != 0;
+    h->prof.by_level = on == 2;
     return MIDBF_OK;
 }
 

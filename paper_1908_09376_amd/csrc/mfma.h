@@ -21,7 +21,7 @@ void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long l
 
 // Split-bf16 variants of the up / down / middle kernels (factors stored as
 // MFMA fragment tiles; tile_off gives each middle block's first tile).
-constexpr int BF16_VARIANTS = 3;
+constexpr int BF16_VARIANTS = 5;
 void launch_bf16_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
                         const long long* tile_off, hipStream_t s);
 

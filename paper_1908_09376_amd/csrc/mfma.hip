@@ -216,6 +216,7 @@ template <class C>
 __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     constexpr int MTW = C::MTW;
     __shared__ int crow[CROW_MAX];
+    __shared__ int srcrow[CROW_MAX];
     __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
@@ -232,8 +233,9 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     const long long yo = A.lev.y_off[id];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     __syncthreads();
-    const int* red = perm + k;
-    auto brow = [&](int j, int r) { return load_vec(ext, xin, A.ld, A.nrhs, crow[red[j]], r0 + r); };
+    for (int j = tid; j < nred; j += C::NT) srcrow[j] = crow[perm[k + j]];
+    __syncthreads();
+    auto brow = [&](int j, int r) { return load_vec(ext, xin, A.ld, A.nrhs, srcrow[j], r0 + r); };
     for (int m0 = 0; m0 < k; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
@@ -311,21 +313,37 @@ __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, fl
 // the candidate rows (previous level buffer, or the leaf's lattice points).
 __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
     __shared__ int crow[CROW_MAX];
+    __shared__ long long base[8];
     const long long g = blockIdx.x;
     const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     const int ncand = candidate_rows<MT>(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev);
+    if (threadIdx.x < A.G.P) base[threadIdx.x] = A.lev.perm_off[g * A.G.P + threadIdx.x] * A.nrhs + r0;
     __syncthreads();
     const bool ext = A.s == 0;
     float2* outp = ext ? (float2*)A.ext : (float2*)A.out;
-    const long long id0 = g * A.G.P;
+    // two right-hand sides per thread (16-byte loads) when the row stride allows it
+    const bool pairs = (A.nrhs % 2 == 0) && (nr % 2 == 0) && !ext;
+    if (pairs) {
+        const int half = nr / 2;
+        for (int e = threadIdx.x; e < ncand * half; e += MT) {
+            const int p = e / half, r = 2 * (e - p * half);
+            float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int t = 0; t < A.G.P; ++t) {
+                const float4 v = *reinterpret_cast<const float4*>(scr + base[t] + (long long)p * A.nrhs + r);
+                acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            }
+            *reinterpret_cast<float4*>(outp + (long long)crow[p] * A.nrhs + r0 + r) = acc;
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < ncand * NRHS; e += MT) {
         const int p = e / NRHS, r = e - p * NRHS;
         if (r >= nr) continue;
         float sx = 0.f, sy = 0.f;
         for (int t = 0; t < A.G.P; ++t) {
-            const float2 v = scr[(A.lev.perm_off[id0 + t] + p) * A.nrhs + r0 + r];
+            const float2 v = scr[base[t] + (long long)p * A.nrhs + r];
             sx += v.x;
             sy += v.y;
         }

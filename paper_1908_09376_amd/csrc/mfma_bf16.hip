@@ -82,79 +82,137 @@ __device__ inline void kstep_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], 
 #undef MF
 }
 
-template <int MTW_, int NT_>
+// The same twelve products for a single column tile nt.
+template <int MTW>
+__device__ inline void kstep1_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const Frag (&a)[MTW], const Frag& b,
+                                   int nt, int ntl) {
+#define MF(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0)
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+        if (mt >= ntl) continue;
+        const bf16x8 nih = neg8(a[mt].ih), nil = neg8(a[mt].il);
+        MF(cr[mt][nt], a[mt].rh, b.rh);
+        MF(ci[mt][nt], a[mt].rh, b.ih);
+        MF(cr[mt][nt], nih, b.ih);
+        MF(ci[mt][nt], a[mt].ih, b.rh);
+        MF(cr[mt][nt], a[mt].rh, b.rl);
+        MF(ci[mt][nt], a[mt].rh, b.il);
+        MF(cr[mt][nt], a[mt].rl, b.rh);
+        MF(ci[mt][nt], a[mt].rl, b.ih);
+        MF(cr[mt][nt], nih, b.il);
+        MF(ci[mt][nt], a[mt].ih, b.rl);
+        MF(cr[mt][nt], nil, b.ih);
+        MF(ci[mt][nt], a[mt].il, b.rh);
+    }
+#undef MF
+}
+
+template <int MTW_, int NT_, int CT_>
 struct BCfg {
-    static constexpr int MTW = MTW_;
-    static constexpr int NT = NT_;
+    static constexpr int MTW = MTW_;     // 16-row tiles per wave
+    static constexpr int NT = NT_;       // threads per workgroup
+    static constexpr int CT = CT_;       // K tiles (of 32) per pipeline stage
     static constexpr int ROUND = NT / 64 * MTW * 16;
+    static_assert(NT >= 256 * CT, "at most one 8-row B block per thread and stage");
 };
 
 // Rows [base, base + 16 MTW) of C (+)= A B for one wave, where A's tiles of
-// row tile t start at Atiles + t * ktiles tiles.  brow(j, r) returns B[j][r].
-// Register prefetch of the next tile's A fragments and of this thread's next
-// B elements; double-buffered LDS; one barrier per K tile.
-template <class C, class BRow>
+// row tile t start at Atiles + t * ktiles tiles.  B[j][r] = src[srow(j) * ld + r].
+// One stage = CT K tiles: every thread loads 8 consecutive K rows of one B
+// column (coalesced across the wave), splits them into hi/lo planes and writes
+// them as four 16-byte pieces of one MFMA fragment; A fragments and B rows of
+// stage c+1 are in flight while stage c is multiplied; double-buffered LDS,
+// one barrier per stage.  Every thread of the workgroup must call this.
+template <class C, class SRow>
 __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const Frag* __restrict__ Atiles,
-                               int M, int K, int base, BRow brow, int nr, Frag* sB) {
-    constexpr int MTW = C::MTW, NT = C::NT;
-    constexpr int BPT = KT * NRHS / NT;
+                               int M, int K, int base, const float2* __restrict__ src, long long ld, SRow srow,
+                               int nr, Frag* sB) {
+    constexpr int MTW = C::MTW, CT = C::CT;
+    constexpr int KS = CT * KT;                     // K rows per stage
     const int tid = threadIdx.x, l = tid & 63;
     const int ntl = base < M ? min(MTW, (M - base + 15) / 16) : 0;
     const int ktiles = (K + KT - 1) / KT;
     if (ktiles == 0) return;
+    const int nst = (ktiles + CT - 1) / CT;
     const int mt0 = base / 16;
-    auto loadA = [&](int kt, Frag (&dst)[MTW]) {
+    // this thread's B column and 8-row block within a stage (threads beyond
+    // 256 CT stage nothing)
+    const bool stager = tid < 256 * CT;
+    const int br = tid & 63, bj = (tid >> 6) * 8;
+    auto loadA = [&](int st, Frag (&dst)[CT][MTW]) {
 #pragma unroll
-        for (int mt = 0; mt < MTW; ++mt)
-            if (mt < ntl) dst[mt] = Atiles[((long long)(mt0 + mt) * ktiles + kt) * 64 + l];
-    };
-    float2 bt[BPT];
-    auto loadB = [&](int kt) {
+        for (int c = 0; c < CT; ++c) {
+            const int kt = st * CT + c;
 #pragma unroll
-        for (int q = 0; q < BPT; ++q) {
-            const int e = tid + q * NT, jj = e / NRHS, r = e - jj * NRHS, j = kt * KT + jj;
-            bt[q] = (j < K && r < nr) ? brow(j, r) : make_float2(0.f, 0.f);
+            for (int mt = 0; mt < MTW; ++mt)
+                if (mt < ntl && kt < ktiles) dst[c][mt] = Atiles[((long long)(mt0 + mt) * ktiles + kt) * 64 + l];
         }
     };
-    // element (jj, r) of the chunk goes to fragment (nt = r/16, lane (jj/8)*16 + r%16), slot jj%8
+    float2 bt[8];
+    auto loadB = [&](int st) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = st * KS + bj + i;
+            bt[i] = (stager && j < K && br < nr) ? src[(long long)srow(j) * ld + br] : make_float2(0.f, 0.f);
+        }
+    };
     auto storeB = [&](int buf) {
-        __bf16* base_p = reinterpret_cast<__bf16*>(sB + buf * 4 * 64);
+        if (!stager) return;
+        bf16x8 rh, ih, rl, il;
 #pragma unroll
-        for (int q = 0; q < BPT; ++q) {
-            const int e = tid + q * NT, jj = e / NRHS, r = e - jj * NRHS;
-            const int nt = r >> 4, lane = (jj >> 3) * 16 + (r & 15), slot = jj & 7;
-            __bf16* f = base_p + (long long)(nt * 64 + lane) * 32;
-            const float x = bt[q].x, y = bt[q].y;
-            const __bf16 xh = (__bf16)x, yh = (__bf16)y;
-            f[slot] = xh;
-            f[8 + slot] = yh;
-            f[16 + slot] = (__bf16)(x - (float)xh);
-            f[24 + slot] = (__bf16)(y - (float)yh);
+        for (int i = 0; i < 8; ++i) {
+            const __bf16 xh = (__bf16)bt[i].x, yh = (__bf16)bt[i].y;
+            rh[i] = xh;
+            ih[i] = yh;
+            rl[i] = (__bf16)(bt[i].x - (float)xh);
+            il[i] = (__bf16)(bt[i].y - (float)yh);
         }
+        const int kt = bj / KT, kk = bj % KT;
+        Frag* f = sB + ((buf * CT + kt) * 4 + (br >> 4)) * 64 + (kk >> 3) * 16 + (br & 15);
+        f->rh = rh;
+        f->ih = ih;
+        f->rl = rl;
+        f->il = il;
     };
-    Frag acur[MTW], anext[MTW];
+    Frag acur[CT][MTW], anext[CT][MTW];
     loadA(0, acur);
     loadB(0);
     __syncthreads();
     storeB(0);
     __syncthreads();
-    for (int kt = 0; kt < ktiles; ++kt) {
-        const bool more = kt + 1 < ktiles;
+    for (int st = 0; st < nst; ++st) {
+        const bool more = st + 1 < nst;
         if (more) {
-            loadA(kt + 1, anext);
-            loadB(kt + 1);
+            loadA(st + 1, anext);
+            loadB(st + 1);
         }
         if (ntl > 0) {
-            const Frag* sb = sB + (kt & 1) * 4 * 64;
-            Frag b[4];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) b[nt] = sb[nt * 64 + l];
-            kstep_bf16<MTW>(cr, ci, acur, b, ntl);
+            for (int c = 0; c < CT; ++c) {
+                if (st * CT + c < ktiles) {
+                    const Frag* sb = sB + ((st & 1) * CT + c) * 4 * 64;
+                    if constexpr (C::NT >= 1024) {
+                        // one B fragment at a time (register budget of 16 waves)
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const Frag b = sb[nt * 64 + l];
+                            kstep1_bf16<MTW>(cr, ci, acur[c], b, nt, ntl);
+                        }
+                    } else {
+                        Frag b[4];
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) b[nt] = sb[nt * 64 + l];
+                        kstep_bf16<MTW>(cr, ci, acur[c], b, ntl);
+                    }
+                }
+            }
         }
         if (more) {
-            storeB((kt + 1) & 1);
+            storeB((st + 1) & 1);
 #pragma unroll
-            for (int mt = 0; mt < MTW; ++mt) acur[mt] = anext[mt];
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int mt = 0; mt < MTW; ++mt) acur[c][mt] = anext[c][mt];
         }
         __syncthreads();
     }
@@ -202,7 +260,8 @@ template <class C>
 __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     constexpr int MTW = C::MTW;
     __shared__ int crow[CROW_MAX];
-    __shared__ Frag sB[2 * 4 * 64];
+    __shared__ int srcrow[CROW_MAX];
+    __shared__ Frag sB[2 * C::CT * 4 * 64];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
@@ -218,13 +277,16 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     const long long yo = A.lev.y_off[id];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     __syncthreads();
-    const int* red = perm + k;
-    auto brow = [&](int j, int r) { return load_vec(ext, xin, A.ld, A.nrhs, crow[red[j]], r0 + r); };
+    for (int j = tid; j < nred; j += C::NT) srcrow[j] = crow[perm[k + j]];
+    __syncthreads();
+    // nred > 0 only above the leaves, where the input is a level buffer (row-major, nrhs wide)
+    const float2* xrows = ext ? xin : xin + r0;
+    auto srow = [&](int j) { return srcrow[j]; };
     for (int m0 = 0; m0 < k; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C>(cr, ci, Tt, k, nred, base, brow, nr, sB);
+        gemm_rows_bf16<C>(cr, ci, Tt, k, nred, base, xrows, A.nrhs, srow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -249,7 +311,7 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
 template <class C>
 __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, float2* scr) {
     constexpr int MTW = C::MTW;
-    __shared__ Frag sB[2 * 4 * 64];
+    __shared__ Frag sB[2 * C::CT * 4 * 64];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -265,12 +327,12 @@ __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, fl
         if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
     }
     const float2* z = zin + yo * A.nrhs + r0;
-    auto brow = [&](int i, int r) { return z[(long long)i * A.nrhs + r]; };
+    auto srow = [&](int i) { return i; };
     for (int m0 = 0; m0 < nred; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C>(cr, ci, Tt, nred, k, base, brow, nr, sB);
+        gemm_rows_bf16<C>(cr, ci, Tt, nred, k, base, z, A.nrhs, srow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -294,7 +356,7 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     constexpr int MTW = C::MTW;
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
-    __shared__ Frag sB[2 * 4 * 64];
+    __shared__ Frag sB[2 * C::CT * 4 * 64];
     const long long bi = blockIdx.x;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -315,12 +377,12 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     float2* zout = (float2*)A.out;
     const Frag* St = (const Frag*)A.S + tile_off[bi] * 64;
     __syncthreads();
-    auto brow = [&](int j, int r) { return xin[(long long)crow_in[j] * A.nrhs + r0 + r]; };
+    auto srow = [&](int j) { return crow_in[j]; };
     for (int m0 = 0; m0 < M; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C>(cr, ci, St, M, K, base, brow, nr, sB);
+        gemm_rows_bf16<C>(cr, ci, St, M, K, base, xin + r0, A.nrhs, srow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -339,9 +401,11 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     }
 }
 
-using W0 = BCfg<1, 512>;
-using W1 = BCfg<1, 256>;
-using W2 = BCfg<2, 256>;
+using W0 = BCfg<1, 512, 2>;
+using W1 = BCfg<1, 256, 1>;
+using W2 = BCfg<2, 256, 1>;
+using W3 = BCfg<1, 1024, 1>;
+using W4 = BCfg<1, 1024, 2>;
 
 template <class C>
 void launch_bvariant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch,
@@ -448,6 +512,8 @@ void launch_bf16_kernel(LevelKernel which, int variant, const void* args, long l
         case 0: launch_bvariant<W0>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 1: launch_bvariant<W1>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 2: launch_bvariant<W2>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 3: launch_bvariant<W3>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 4: launch_bvariant<W4>(which, args, count, nrhs, scratch, tile_off, s); break;
         default: throw Error(MIDBF_ERR_ARG, "unknown split-bf16 variant");
     }
 }

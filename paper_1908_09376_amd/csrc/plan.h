@@ -72,6 +72,7 @@ struct ProfRecord {
 
 struct Profiler {
     bool on = false;
+    bool by_level = false;   // append the step index to kernel names
     std::vector<ProfRecord> recs;
     std::vector<hipEvent_t> pool;
 };
@@ -91,6 +92,8 @@ struct midbf_plan {
     long long max_total_k = 0, max_total_n = 0;
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
-    int mfma_variant[3] = {0, 0, 0};   // matrix-core tile variant for up, down, middle (FP32)
-    int bf16_variant[3] = {0, 0, 0};   // the same for split-bf16
+    // matrix-core tile variant per kernel kind (up, down, middle) and MSCS step (FP32, split-bf16)
+    static constexpr int VMAXLEV = 16;
+    int mfma_variant[3][VMAXLEV] = {};
+    int bf16_variant[3][VMAXLEV] = {};
 };

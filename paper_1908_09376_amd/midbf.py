@@ -108,9 +108,9 @@ class MIDBF:
         arr = (C.c_int * 3)(*variants)
         L.check(L.lib.midbf_set_variants(self._h, _PREC[precision], arr))
 
-    def profile(self, on: bool = True) -> None:
+    def profile(self, on: bool = True, by_level: bool = False) -> None:
         """Bracket every level-kernel launch with HIP events (midbf_profile_enable)."""
-        L.check(L.lib.midbf_profile_enable(self._h, 1 if on else 0))
+        L.check(L.lib.midbf_profile_enable(self._h, (2 if by_level else 1) if on else 0))
 
     def profile_read(self) -> list[dict]:
         """Per-kernel launches, total ms, algorithmic bytes and flops since the last read."""
