@@ -34,6 +34,7 @@ struct UpArgs {
     const long long* yoff_prev;
     void* out;               // this level's buffer
     int nrhs;
+    int ncand_max;           // largest candidate count of the level (LDS strip size)
 };
 
 struct DownArgs {

@@ -102,6 +102,10 @@ __device__ void scatter_candidates(const C* s_w, const ApplyGeom& G, int s, long
 }
 
 // ---- forward, going up: y[id] = x[skel] + T x[red]  (T column-major k x (n-k)) ----
+// Wave t handles decomposition t of the group: its redundant inputs are first
+// gathered into a per-wave LDS strip (x[red] in order), then each lane owns
+// OPL outputs (o = lane + 64u) and sweeps the columns of T once; every column
+// read is OPL coalesced 64-lane loads.
 template <class C, int RT, int OPL>
 __global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
     extern __shared__ unsigned char smem_raw[];
@@ -110,17 +114,25 @@ __global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
     const int r0 = blockIdx.y * RT;
     const int nr = min(RT, A.nrhs - r0);
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
-    gather_candidates<C, RT>(s_x, A.G, A.s, a, ap, A.Ps, (const C*)A.ext, A.ld, (const C*)A.in, A.k_prev,
-                             A.yoff_prev, A.nrhs, r0, nr);
+    const int ncand = gather_candidates<C, RT>(s_x, A.G, A.s, a, ap, A.Ps, (const C*)A.ext, A.ld, (const C*)A.in,
+                                               A.k_prev, A.yoff_prev, A.nrhs, r0, nr);
+    C* s_red = s_x + (size_t)A.ncand_max * RT;     // single RHS: AW strips of ncand_max values
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     C* out = (C*)A.out;
+    C* strip = s_red + (size_t)wave * A.ncand_max;
     for (int t = wave; t < A.G.P; t += AW) {
         const long long id = g * A.G.P + t;
         const int k = A.lev.k[id], nred = A.lev.n[id] - k;
         const int* perm = A.lev.perm + A.lev.perm_off[id];
         const C* T = (const C*)A.lev.T[id];
         const long long yo = A.lev.y_off[id];
+        if constexpr (RT == 1) {
+            for (int j = lane; j < nred; j += 64) strip[j] = s_x[perm[k + j]];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         for (int o0 = 0; o0 < k; o0 += 64 * OPL) {
             C acc[OPL][RT];
 #pragma unroll
@@ -130,16 +142,22 @@ __global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
             int o[OPL];
 #pragma unroll
             for (int u = 0; u < OPL; ++u) o[u] = o0 + lane + 64 * u;
+            const int uact = min(OPL, (k - o0 + 63) / 64);     // wave-uniform
 #pragma unroll 4
             for (int j = 0; j < nred; ++j) {
-                const int pj = perm[k + j];
                 C xv[RT];
+                if constexpr (RT == 1) {
+                    xv[0] = strip[j];
+                } else {
+                    const int pj = perm[k + j];
 #pragma unroll
-                for (int r = 0; r < RT; ++r) xv[r] = s_x[pj * RT + r];
+                    for (int r = 0; r < RT; ++r) xv[r] = s_x[pj * RT + r];
+                }
+                const C* Tj = T + (long long)j * k;
 #pragma unroll
                 for (int u = 0; u < OPL; ++u) {
-                    if (o[u] < k) {
-                        const C tv = T[(long long)j * k + o[u]];
+                    if (u < uact && o[u] < k) {
+                        const C tv = Tj[o[u]];
 #pragma unroll
                         for (int r = 0; r < RT; ++r) cfma(acc[u][r], tv, xv[r]);
                     }
@@ -155,6 +173,7 @@ __global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
                 }
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -410,7 +429,7 @@ void launch_level(LevelKernel which, const void* args, dim3 grid, size_t smem, h
     switch (which) {
         case LevelKernel::Up:
             if (RT == 1)
-                hipLaunchKernelGGL((up_kernel<C, RT, 2>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
+                hipLaunchKernelGGL((up_kernel<C, RT, 4>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
             else
                 hipLaunchKernelGGL((up_kernel<C, RT, 1>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
             break;

@@ -48,7 +48,7 @@ LevelArgs level_args(const LevelSide& lv, int prec) {
 
 size_t csize(int prec) { return prec == PREC_FP64 ? 16 : 8; }
 
-constexpr size_t LDS_LIMIT = 64 * 1024;
+constexpr size_t LDS_LIMIT = 64 * 1024;    // dynamic LDS of the VALU level kernels
 
 const char* kernel_name(LevelKernel k) {
     switch (k) {
@@ -176,11 +176,14 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         a.out = buf[o];
         a.nrhs = nrhs;
         const int ncand = s == 0 ? h->n0 : lv.nmax;
+        a.ncand_max = ncand;
+        // forward VALU up kernel: candidate vector plus one redundant-input strip per wave
+        const size_t up_lds = (size_t)ncand * cs * (adjoint || rt > 1 ? rt : 1 + 4);
         const double vin = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
         const double vout = (double)lv.total_k * nrhs * cs;
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         launch_checked(h, adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a,
-                       dim3((unsigned)groups, tiles), (size_t)ncand * rt * cs, st, fac + vin + vout,
+                       dim3((unsigned)groups, tiles), mfma ? 0 : up_lds, st, fac + vin + vout,
                        fl * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs, s);
         o ^= 1;
     }
@@ -243,7 +246,7 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         } else {
             launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
                            dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
-                           8.0 * lv.entries * nrhs);
+                           8.0 * lv.entries * nrhs, 0, nrhs, s);
         }
         o ^= 1;
     }
