@@ -156,8 +156,8 @@ __global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
                 const C* Tj = T + (long long)j * k;
 #pragma unroll
                 for (int u = 0; u < OPL; ++u) {
-                    if (u < uact && o[u] < k) {
-                        const C tv = Tj[o[u]];
+                    if (u < uact) {                               // wave-uniform
+                        const C tv = Tj[min(o[u], k - 1)];        // clamped: every lane loads, no divergence
 #pragma unroll
                         for (int r = 0; r < RT; ++r) cfma(acc[u][r], tv, xv[r]);
                     }
