@@ -36,29 +36,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_sha() -> str:
+def kernel_sources(kernel: str) -> list[str]:
+    """Source files that define a profiled kernel family."""
+    if "bf16x3" in kernel:
+        return ["mfma_bf16.hip", "mfma.h"]
+    if "mfma" in kernel:
+        return ["mfma.hip", "mfma.h"]
+    return ["apply.hip"]
+
+
+def source_sha(files: list[str]) -> str:
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1908_09376_amd", "csrc", "*"))):
-        with open(p, "rb") as fh:
-            h.update(os.path.basename(p).encode())
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(ROOT, "paper_1908_09376_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, launches_per_step: int):
-    """HBM bytes per launch from the committed counter summary, if taken on this source."""
+def traffic_for(kernel: str, variant):
+    """HBM bytes per launch from the committed counter summary, if taken on this kernel source and variant."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
     rec = data.get(kernel)
-    if not rec or rec.get("source_sha") != source_sha():
+    if not rec or rec.get("source_sha") != source_sha(kernel_sources(kernel)):
+        return None
+    if rec.get("variant") is not None and rec["variant"] != variant:
         return None
     return rec["hbm_bytes_per_launch"]
 
 
-def roofline(dominant: dict, prec: str):
+def roofline(dominant: dict, prec: str, variant=None):
     launches = dominant["launches"]
     t = dominant["total_ms"] / 1e3 / launches
     bytes_per = dominant["bytes"] / launches
@@ -74,12 +85,12 @@ def roofline(dominant: dict, prec: str):
         bound = "mfma" if ("mfma" in dominant["name"] or prec == "bf16x3") else "alu"
         ach = flops_per / t / 1e12
         return {"bound": bound, "achieved": round(ach, 3), "peak": peak_tf, "unit": "TFLOP/s",
-                "frac": round(ach / peak_tf, 4), "traffic": traffic_for(dominant["name"], launches),
+                "frac": round(ach / peak_tf, 4), "traffic": traffic_for(dominant["name"], variant),
                 "kernel": dominant["name"], "avg_ms": round(t * 1e3, 4),
                 "algorithmic_bytes_per_launch": bytes_per, "flops_per_launch": flops_per}
     ach = bytes_per / t / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
-            "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": traffic_for(dominant["name"], launches),
+            "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": traffic_for(dominant["name"], variant),
             "kernel": dominant["name"], "avg_ms": round(t * 1e3, 4),
             "algorithmic_bytes_per_launch": bytes_per, "flops_per_launch": flops_per}
 
@@ -91,7 +102,7 @@ def time_applies(F, f, g, prec, steps, warmup, profile: bool):
     torch.cuda.synchronize()
     if profile:
         F.profile_read()           # drop warm-up records
-        F.profile(True)
+        F.profile(True, by_level=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -188,7 +199,11 @@ def main() -> int:
     value = nrhs * args.steps / wall
     log(f"[bench] {args.precision}: {ms:.3f} ms/step, {value:.1f} RHS-applies/s")
     dominant = max(kt, key=lambda r: r["total_ms"])
-    roof = roofline(dominant, args.precision)
+    dom_variant = None
+    if variants is not None:   # tuned variant of the dominant kernel's kind (up, down at the top step; middle)
+        kind = 2 if dominant["name"].startswith("middle") else (0 if dominant["name"].startswith("up") else 1)
+        dom_variant = variants[kind]
+    roof = roofline(dominant, args.precision, dom_variant)
     kernels = {r["name"]: {"launches": r["launches"], "avg_ms": round(r["total_ms"] / r["launches"], 4)}
                for r in kt}
     g_np = g.to(torch.complex128).cpu().numpy().T
