@@ -138,6 +138,89 @@ def cpu_baseline(w, f_np, rows):
                           f"host cpus={os.cpu_count()}"}
 
 
+def batch_bench(args) -> int:
+    """The uneven batch: 32 transforms, N drawn from {64^2, 128^2, 256^2}, one RHS each, FP32,
+    one grouped launch per level round, replayed from a hipGraph; beside it the same transforms
+    applied one midbf_apply call after another."""
+    import numpy as np
+    import torch
+
+    import paper_1908_09376_amd as M
+    import workloads as W
+    from oracle.kernel import Kernel, direct_sum
+
+    prec = args.precision if args.precision in ("fp32", "fp64") else "fp32"
+    ns = [int(n) for n in W.batch_sizes(32)]
+    cache, Fs = {}, []
+    t0 = time.perf_counter()
+    for n in ns:
+        if n not in cache:
+            cache[n] = M.MIDBF(2, n, "fio_ellipse", tol=1e-6, precisions=1 | 2)
+        Fs.append(cache[n])
+    build_s = time.perf_counter() - t0
+    cdt = torch.complex64 if prec == "fp32" else torch.complex128
+    fs_np = [W.batch_rhs(j, n) for j, n in enumerate(ns)]
+    fs = [torch.from_numpy(np.ascontiguousarray(f[:, 0])).to("cuda:0").to(cdt) for f in fs_np]
+    B = M.Batch(Fs, fs, precision=prec, graph=True)
+    st = B.stats()
+    for _ in range(args.warmup):
+        B.run()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(args.steps):
+        B.run()
+    ev[1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    # the same transforms one midbf_apply after another
+    outs = [torch.empty_like(f) for f in fs]
+    for F, f, g in zip(Fs, fs, outs):
+        F.apply(f, out=g, precision=prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        for F, f, g in zip(Fs, fs, outs):
+            F.apply(f, out=g, precision=prec)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t1) / args.steps * 1e3
+    err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        errs, tcpu, rows_done = [], 0.0, 0
+        for n in sorted(cache):
+            j = ns.index(n)
+            rows = W.sample_rows(n * n, 2, 64)
+            t2 = time.perf_counter()
+            ref = direct_sum(Kernel(2, n, "fio_ellipse"), fs_np[j], rows=rows)
+            tcpu += (time.perf_counter() - t2) * (n * n / len(rows)) * ns.count(n)
+            got = B.outs[j].to(torch.complex128).cpu().numpy()[rows]
+            errs.append(float(np.linalg.norm(got - ref[:, 0]) / np.linalg.norm(ref[:, 0])))
+        err = max(errs)
+        cpu = {"value": len(ns) / tcpu, "unit": "transforms/s", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": "FP64 direct sum (eq. 1) on 64 seeded rows of one transform per size, scaled to every "
+                         "row of all 32 transforms"}
+    ach = st["bytes"] / (ms / 1e3) / 1e9
+    out = {
+        "metric": "MIDBF uneven batch transforms/s (32 transforms, N in {64^2,128^2,256^2}, 1 RHS)",
+        "value": round(len(ns) * args.steps / wall, 2), "unit": "transforms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "batch32", "sizes": {str(n): ns.count(n) for n in sorted(cache)},
+                   "phase": "fio_ellipse", "tol": 1e-6, "precision": prec},
+        "rel_l2_err": err, "build_s": round(build_s, 2), "sequential_ms": round(seq_ms, 4), "batch": st,
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                     "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": None, "kernel": "grouped_kernel",
+                     "avg_ms": round(ms, 4), "algorithmic_bytes_per_launch": st["bytes"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +247,9 @@ def main() -> int:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is a design "
                                    "note, not an implementation", "n_gpus": args.gpus}))
         return 2
+
+    if args.workload == "batch32":
+        return batch_bench(args)
 
     import numpy as np
     import torch

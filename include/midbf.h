@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 typedef struct midbf_plan* midbf_handle;
+typedef struct midbf_batch_s* midbf_batch;
 
 typedef enum {
     MIDBF_OK = 0,
@@ -128,13 +129,50 @@ midbf_status midbf_apply_adjoint(midbf_handle h, const void* g_dev, void* f_dev,
 
 /*
  * midbf_apply_batched -- count independent transforms (different handles,
- * possibly different N) applied in one stream-ordered sequence of launches:
- * g_j = K~_j f_j.  hs, f_devs, g_devs, nrhs are host arrays of length count;
- * each f/g block is column-major with ld = N_j.
+ * possibly different N): g_j = K~_j f_j as one grouped launch per level
+ * round (midbf_batch_create + midbf_batch_run, then destroy; the call
+ * therefore synchronizes `stream`).  hs, f_devs, g_devs, nrhs are
+ * host arrays of length count; each f/g block is column-major with ld = N_j.
+ * FP64 or FP32.
  */
 midbf_status midbf_apply_batched(int count, const midbf_handle* hs, const void* const* f_devs,
                                  void* const* g_devs, const int* nrhs, midbf_precision prec,
                                  void* stream);
+
+/*
+ * Batches of forward transforms of uneven N (the batched apply of many
+ * transforms; the factor product of Sec. 3.5 per transform).
+ *
+ * midbf_batch_create -- prepare g_j = K~_j f_j for j < count.  The level
+ * launches of all transforms are grouped by round (every transform's first
+ * level, then every second level, ...): one launch per round covers the
+ * workgroups of that level of every transform, so a batch of any size takes
+ * 2 * max_j(b_j) + 1 launches.  hs, f_devs, g_devs, nrhs: host arrays of
+ * length count; f/g blocks column-major with ld = N_j; FP64 (complex128) or
+ * FP32 (complex64), through the VALU level kernels.  use_graph != 0 captures
+ * the launches in a hipGraph at creation; midbf_batch_run replays it.  The
+ * batch owns its level buffers and references the handles and the f/g
+ * buffers, which must outlive it.  Runs of one batch must not overlap.
+ * Errors: _ARG, _UNIMPLEMENTED (split-bf16, or candidate vectors beyond the
+ * LDS budget), _OOM, _HIP.
+ */
+typedef struct {
+    int stages;                 /* level launches folded into the batch              */
+    int rounds;                 /* launches per run                                  */
+    long long items;            /* workgroups over all rounds                        */
+    int graph;                  /* 1 if replayed from a captured hipGraph            */
+    long long lds_bytes;        /* dynamic LDS per workgroup                         */
+    double bytes, flops;        /* algorithmic bytes and flops of one run            */
+} midbf_batch_stats;
+
+midbf_status midbf_batch_create(int count, const midbf_handle* hs, const void* const* f_devs,
+                                void* const* g_devs, const int* nrhs, midbf_precision prec,
+                                int use_graph, void* stream, midbf_batch* out);
+/* Enqueue one run of the batch on `stream` (asynchronous). */
+midbf_status midbf_batch_run(midbf_batch b, void* stream);
+midbf_status midbf_batch_get_stats(midbf_batch b, midbf_batch_stats* out);
+/* Free the batch; waits for the device like hipFree. */
+void midbf_batch_destroy(midbf_batch b);
 
 /* Sizes and ranks of a built factorization. */
 midbf_status midbf_factor_stats(midbf_handle h, midbf_stats* out);

@@ -40,6 +40,11 @@ class KernelTime(C.Structure):
                 ("bytes", C.c_double), ("flops", C.c_double)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("stages", C.c_int), ("rounds", C.c_int), ("items", C.c_longlong), ("graph", C.c_int),
+                ("lds_bytes", C.c_longlong), ("bytes", C.c_double), ("flops", C.c_double)]
+
+
 class MidbfError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -57,6 +62,11 @@ def _load():
         "midbf_apply": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_adjoint": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_batched": (i, [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(i), i, vp]),
+        "midbf_batch_create": (i, [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(i), i, i, vp,
+                                   C.POINTER(vp)]),
+        "midbf_batch_run": (i, [vp, vp]),
+        "midbf_batch_get_stats": (i, [vp, C.POINTER(BatchStats)]),
+        "midbf_batch_destroy": (None, [vp]),
         "midbf_factor_stats": (i, [vp, C.POINTER(Stats)]),
         "midbf_ranks": (i, [vp, i, i, C.POINTER(i), ll]),
         "midbf_kernel_entries": (i, [C.POINTER(Params), vp, i, vp, i, vp, vp]),
@@ -84,5 +94,7 @@ def check(status: int) -> None:
 
 
 EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_batched",
+            "midbf_batch_create", "midbf_batch_run", "midbf_batch_get_stats",
+            "midbf_batch_destroy",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",
             "midbf_tune", "midbf_set_variants", "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error"]

@@ -72,4 +72,26 @@ enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum };
 void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
                          hipStream_t s);
 
+// One level launch of one transform inside a grouped batch launch.  The
+// level launches of many transforms are grouped by round (every transform's
+// first level, then every second level, ...); a round's stages are
+// consecutive in the table and its workgroups are numbered through them:
+// stage q owns blocks first .. first + items - 1 of its round's launch.
+struct BatchStage {
+    int kind;                // 0 up, 1 middle, 2 down (forward transform)
+    int tiles;               // right-hand-side tiles per group
+    long long items;         // workgroups: groups (or middle blocks) x tiles
+    long long first;         // first block of the stage within its round
+    union {
+        UpArgs up;
+        MidArgs mid;
+        DownArgs down;
+    } a;
+};
+
+// One launch of `items` workgroups over the stages [s0, s0 + ns) of the
+// device table d_st, with `smem` bytes of dynamic LDS.
+void launch_grouped(int prec, int rt, const BatchStage* d_st, int s0, int ns, long long items, size_t smem,
+                    hipStream_t s);
+
 }  // namespace midbf

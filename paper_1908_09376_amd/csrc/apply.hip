@@ -107,11 +107,9 @@ __device__ void scatter_candidates(const C* s_w, const ApplyGeom& G, int s, long
 // OPL outputs (o = lane + 64u) and sweeps the columns of T once; every column
 // read is OPL coalesced 64-lane loads.
 template <class C, int RT, int OPL>
-__global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
-    extern __shared__ unsigned char smem_raw[];
+__device__ __forceinline__ void up_body(const UpArgs& A, long long g, int tile, unsigned char* smem_raw) {
     C* s_x = reinterpret_cast<C*>(smem_raw);
-    const long long g = blockIdx.x;
-    const int r0 = blockIdx.y * RT;
+    const int r0 = tile * RT;
     const int nr = min(RT, A.nrhs - r0);
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
     const int ncand = gather_candidates<C, RT>(s_x, A.G, A.s, a, ap, A.Ps, (const C*)A.ext, A.ld, (const C*)A.in,
@@ -177,12 +175,16 @@ __global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
     }
 }
 
+template <class C, int RT, int OPL>
+__global__ __launch_bounds__(AT) void up_kernel(UpArgs A) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    up_body<C, RT, OPL>(A, blockIdx.x, blockIdx.y, smem_raw);
+}
+
 // ---- forward, going down: w(cand) = sum_t Pi_t [z_t ; T_t^T z_t]  (T row-major k x (n-k)) ----
 template <class C, int RT>
-__global__ __launch_bounds__(AT) void down_kernel(DownArgs A) {
-    extern __shared__ unsigned char smem_raw[];
-    const long long g = blockIdx.x;
-    const int r0 = blockIdx.y * RT;
+__device__ __forceinline__ void down_body(const DownArgs& A, long long g, int tile, unsigned char* smem_raw) {
+    const int r0 = tile * RT;
     const int nr = min(RT, A.nrhs - r0);
     const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
     const int ncand = A.lev.n[g * A.G.P];
@@ -228,13 +230,17 @@ __global__ __launch_bounds__(AT) void down_kernel(DownArgs A) {
                               A.nrhs, r0, nr);
 }
 
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void down_kernel(DownArgs A) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    down_body<C, RT>(A, blockIdx.x, blockIdx.y, smem_raw);
+}
+
 // ---- middle: z(rows) = S x(cols), S column-major nr x nc ----
 template <class C, int RT>
-__global__ __launch_bounds__(AT) void middle_kernel(MidArgs A) {
-    extern __shared__ unsigned char smem_raw[];
+__device__ __forceinline__ void middle_body(const MidArgs& A, long long bi, int tile, unsigned char* smem_raw) {
     C* s_x = reinterpret_cast<C*>(smem_raw);
-    const long long bi = blockIdx.x;
-    const int r0 = blockIdx.y * RT;
+    const int r0 = tile * RT;
     const int nrr = min(RT, A.nrhs - r0);
     const int nr = A.nr[bi], nc = A.nc[bi];
     const int tid = threadIdx.x;
@@ -276,10 +282,16 @@ __global__ __launch_bounds__(AT) void middle_kernel(MidArgs A) {
     }
 }
 
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void middle_kernel(MidArgs A) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    middle_body<C, RT>(A, blockIdx.x, blockIdx.y, smem_raw);
+}
+
 // ---- adjoint going up (row side): out_i = x[skel_i] + sum_j conj(T_ij) x[red_j], T row-major ----
 template <class C, int RT>
 __global__ __launch_bounds__(AT) void adj_up_kernel(UpArgs A) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     C* s_x = reinterpret_cast<C*>(smem_raw);
     const long long g = blockIdx.x;
     const int r0 = blockIdx.y * RT;
@@ -322,7 +334,7 @@ __global__ __launch_bounds__(AT) void adj_up_kernel(UpArgs A) {
 // ---- adjoint middle: x(cols) = S^H z(rows) ----
 template <class C, int RT>
 __global__ __launch_bounds__(AT) void adj_middle_kernel(MidArgs A) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     C* s_z = reinterpret_cast<C*>(smem_raw);
     const long long bi = blockIdx.x;
     const int r0 = blockIdx.y * RT;
@@ -372,7 +384,7 @@ __global__ __launch_bounds__(AT) void adj_middle_kernel(MidArgs A) {
 // ---- adjoint going down (column side): w(cand) = sum_t Pi_t [z_t ; T_t^H z_t], T column-major ----
 template <class C, int RT>
 __global__ __launch_bounds__(AT) void adj_down_kernel(DownArgs A) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const long long g = blockIdx.x;
     const int r0 = blockIdx.y * RT;
     const int nr = min(RT, A.nrhs - r0);
@@ -424,6 +436,39 @@ __global__ __launch_bounds__(AT) void adj_down_kernel(DownArgs A) {
                               A.nrhs, r0, nr);
 }
 
+// ---- grouped batch of forward transforms ----
+// One workgroup per item of the stages of one round: the block index is
+// located among the stages' first blocks, and the item runs the same body as
+// the stage's own level kernel would.  Stages of a round are independent
+// (different transforms); rounds are ordered by the stream.
+template <class C, int RT>
+__global__ __launch_bounds__(AT) void grouped_kernel(const BatchStage* __restrict__ st, int s0, int ns) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const long long t = blockIdx.x;
+    int lo = s0, hi = s0 + ns - 1;             // last stage with first <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st[mid].first <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int q = __builtin_amdgcn_readfirstlane(lo);
+    const long long item = t - st[q].first;
+    const int tiles = st[q].tiles;
+    const long long g = item / tiles;
+    const int tile = (int)(item - g * tiles);
+    const int kind = st[q].kind;
+    if (kind == 0) {
+        const UpArgs A = st[q].a.up;
+        up_body<C, RT, (RT == 1 ? 4 : 1)>(A, g, tile, smem_raw);
+    } else if (kind == 1) {
+        const MidArgs A = st[q].a.mid;
+        middle_body<C, RT>(A, g, tile, smem_raw);
+    } else {
+        const DownArgs A = st[q].a.down;
+        down_body<C, RT>(A, g, tile, smem_raw);
+    }
+}
+
 template <class C, int RT>
 void launch_level(LevelKernel which, const void* args, dim3 grid, size_t smem, hipStream_t s) {
     switch (which) {
@@ -453,6 +498,20 @@ void launch_level(LevelKernel which, const void* args, dim3 grid, size_t smem, h
 }
 
 }  // namespace
+
+void launch_grouped(int prec, int rt, const BatchStage* d_st, int s0, int ns, long long items, size_t smem,
+                    hipStream_t s) {
+    MIDBF_CHECK(items >= 1 && items <= 0x7fffffffLL, MIDBF_ERR_SHAPE, "grouped launch size out of range");
+    const dim3 grid((unsigned)items);
+    if (prec == PREC_FP64) {
+        if (rt == 1) hipLaunchKernelGGL((grouped_kernel<double2, 1>), grid, dim3(AT), smem, s, d_st, s0, ns);
+        else hipLaunchKernelGGL((grouped_kernel<double2, APPLY_RT64>), grid, dim3(AT), smem, s, d_st, s0, ns);
+    } else {
+        if (rt == 1) hipLaunchKernelGGL((grouped_kernel<float2, 1>), grid, dim3(AT), smem, s, d_st, s0, ns);
+        else hipLaunchKernelGGL((grouped_kernel<float2, APPLY_RT>), grid, dim3(AT), smem, s, d_st, s0, ns);
+    }
+    MIDBF_HIP(hipGetLastError());
+}
 
 void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
                          hipStream_t s) {

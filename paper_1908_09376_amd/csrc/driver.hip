@@ -3,6 +3,7 @@
 #include <cctype>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 
 #include "apply.h"
@@ -136,34 +137,43 @@ void ensure_workspace(midbf_plan* h, int prec, int nrhs, bool scratch) {
     }
 }
 
-// One application of the factor product (adjoint = false) or of its
-// conjugate transpose (adjoint = true).
-void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
-               hipStream_t st, bool adjoint) {
-    MIDBF_CHECK(nrhs >= 1, MIDBF_ERR_ARG, "nrhs must be >= 1");
-    MIDBF_CHECK(ld >= h->N, MIDBF_ERR_ARG, "ld must be >= N");
-    MIDBF_CHECK(in_ext && out_ext, MIDBF_ERR_ARG, "null vector pointer");
-    const unsigned bit = 1u << prec;
-    MIDBF_CHECK(h->keep & bit, MIDBF_ERR_ARG, "this precision's factors were not kept by the build");
-    const bool fits = h->max_n <= MFMA_CROW_MAX && h->mid.nr_max <= MFMA_CROW_MAX && h->mid.nc_max <= MFMA_CROW_MAX;
-    MIDBF_CHECK(prec != PREC_BF16 || (!adjoint && fits), MIDBF_ERR_UNIMPLEMENTED,
-                "the split-bf16 apply exists for the forward transform with candidate sets up to 2048");
-    // matrix cores: split-bf16 always, FP32 for many right-hand sides
-    const bool mfma = prec == PREC_BF16 || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
+// One level launch of an apply: which kernel, its argument block, shape and
+// the algorithmic bytes and flops it accounts for.
+struct LaunchDesc {
+    LevelKernel which;
+    union {
+        UpArgs up;
+        MidArgs mid;
+        DownArgs down;
+    } a;
+    dim3 grid;
+    size_t smem;
+    double bytes, flops;
+    long long mfma_count;   // > 0: matrix-core kernel with that many workgroups
+    int level;
+};
+
+// The launch sequence of one application of the factor product
+// (adjoint = false) or of its conjugate transpose (adjoint = true), with the
+// level vectors in bufs[0..1] (and the matrix-core down pass's per-ID
+// contributions in scratch), rt right-hand sides per VALU workgroup.
+// chunk_middle splits the middle into launches of at most 65535 blocks (grid
+// limit of a direct launch).
+std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
+                                   bool adjoint, bool mfma, void* const* buf, bool chunk_middle, int rt) {
     const double fl = prec == PREC_BF16 ? 24.0 : 8.0;   // flops per complex entry and RHS (bf16x3: three products)
-    ensure_workspace(h, prec, nrhs, mfma);
-    const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     const int tiles = (nrhs + rt - 1) / rt;
     const size_t cs = csize(prec);
     const ApplyGeom G{h->d, h->n, h->P, h->L, h->leaf, h->n0};
     const auto& up = adjoint ? h->rows : h->cols;
     const auto& down = adjoint ? h->cols : h->rows;
-    void** buf = h->ws[prec].buf;
     const long long groups = ipow(h->P, h->L);
+    std::vector<LaunchDesc> out;
     int o = 0;   // buffer holding the current level's vectors
     for (int s = 0; s < h->b; ++s) {
         const LevelSide& lv = up[s];
-        UpArgs a{};
+        LaunchDesc D{};
+        UpArgs& a = D.a.up;
         a.G = G;
         a.lev = level_args(lv, prec);
         a.s = s;
@@ -182,9 +192,14 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double vin = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
         const double vout = (double)lv.total_k * nrhs * cs;
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
-        launch_checked(h, adjoint ? LevelKernel::AdjUp : LevelKernel::Up, prec, rt, &a,
-                       dim3((unsigned)groups, tiles), mfma ? 0 : up_lds, st, fac + vin + vout,
-                       fl * lv.entries * nrhs, mfma ? lv.nid : 0, nrhs, s);
+        D.which = adjoint ? LevelKernel::AdjUp : LevelKernel::Up;
+        D.grid = dim3((unsigned)groups, tiles);
+        D.smem = mfma ? 0 : up_lds;
+        D.bytes = fac + vin + vout;
+        D.flops = fl * lv.entries * nrhs;
+        D.mfma_count = mfma ? lv.nid : 0;
+        D.level = s;
+        out.push_back(D);
         o ^= 1;
     }
     {
@@ -203,24 +218,32 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         a.out = buf[o];
         a.nrhs = nrhs;
         const int width = adjoint ? M.nr_max : M.nc_max;
-        for (long long b0 = 0; b0 < M.nblk; b0 += 65535) {
-            const long long cnt = std::min<long long>(65535, M.nblk - b0);
-            MidArgs ab = a;
+        const long long chunk = chunk_middle ? 65535 : std::max<long long>(M.nblk, 1);
+        for (long long b0 = 0; b0 < M.nblk; b0 += chunk) {
+            const long long cnt = std::min<long long>(chunk, M.nblk - b0);
+            LaunchDesc D{};
+            MidArgs& ab = D.a.mid;
+            ab = a;
             ab.nr += b0; ab.nc += b0; ab.off += b0;
             ab.in_off += b0 * M.pieces; ab.in_len += b0 * M.pieces;
             ab.out_off += b0 * M.pieces; ab.out_len += b0 * M.pieces;
             const double frac = (double)cnt / M.nblk;
             const double vec = (double)(h->rows.back().total_k + h->cols.back().total_k) * nrhs * cs;
-            launch_checked(h, adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle, prec, rt, &ab,
-                           dim3((unsigned)cnt, tiles), (size_t)width * rt * cs, st,
-                           frac * ((double)M.total * cs + (double)M.nblk * 40 + vec), frac * fl * M.total * nrhs,
-                           mfma ? cnt : 0, nrhs);
+            D.which = adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle;
+            D.grid = dim3((unsigned)cnt, tiles);
+            D.smem = (size_t)width * rt * cs;
+            D.bytes = frac * ((double)M.total * cs + (double)M.nblk * 40 + vec);
+            D.flops = frac * fl * M.total * nrhs;
+            D.mfma_count = mfma ? cnt : 0;
+            D.level = -1;
+            out.push_back(D);
         }
         o ^= 1;
     }
     for (int s = h->b - 1; s >= 0; --s) {
         const LevelSide& lv = down[s];
-        DownArgs a{};
+        LaunchDesc D{};
+        DownArgs& a = D.a.down;
         a.G = G;
         a.lev = level_args(lv, prec);
         a.s = s;
@@ -236,24 +259,181 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
         const double vin = (double)lv.total_k * nrhs * cs;
         const double vout = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
+        D.level = s;
         if (mfma) {
             // per-ID contributions to the scratch block, then the ordered group sums
             const double scr = (double)lv.total_n * nrhs * cs;
-            launch_checked(h, LevelKernel::Down, prec, rt, &a, dim3(), 0, st, fac + vin + scr, fl * lv.entries * nrhs,
-                           lv.nid, nrhs, s);
-            launch_checked(h, LevelKernel::DownSum, prec, rt, &a, dim3(), 0, st, scr + vout,
-                           2.0 * (lv.total_n - lv.total_n / h->P) * nrhs, groups, nrhs, s);
+            D.which = LevelKernel::Down;
+            D.grid = dim3();
+            D.smem = 0;
+            D.bytes = fac + vin + scr;
+            D.flops = fl * lv.entries * nrhs;
+            D.mfma_count = lv.nid;
+            out.push_back(D);
+            D.which = LevelKernel::DownSum;
+            D.bytes = scr + vout;
+            D.flops = 2.0 * (lv.total_n - lv.total_n / h->P) * nrhs;
+            D.mfma_count = groups;
+            out.push_back(D);
         } else {
-            launch_checked(h, adjoint ? LevelKernel::AdjDown : LevelKernel::Down, prec, rt, &a,
-                           dim3((unsigned)groups, tiles), (size_t)(lv.nmax + lv.kmax) * rt * cs, st, fac + vin + vout,
-                           8.0 * lv.entries * nrhs, 0, nrhs, s);
+            D.which = adjoint ? LevelKernel::AdjDown : LevelKernel::Down;
+            D.grid = dim3((unsigned)groups, tiles);
+            D.smem = (size_t)(lv.nmax + lv.kmax) * rt * cs;
+            D.bytes = fac + vin + vout;
+            D.flops = 8.0 * lv.entries * nrhs;
+            D.mfma_count = 0;
+            out.push_back(D);
         }
         o ^= 1;
     }
+    return out;
+}
+
+void check_apply_args(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec) {
+    MIDBF_CHECK(nrhs >= 1, MIDBF_ERR_ARG, "nrhs must be >= 1");
+    MIDBF_CHECK(ld >= h->N, MIDBF_ERR_ARG, "ld must be >= N");
+    MIDBF_CHECK(in_ext && out_ext, MIDBF_ERR_ARG, "null vector pointer");
+    MIDBF_CHECK(h->keep & (1u << prec), MIDBF_ERR_ARG, "this precision's factors were not kept by the build");
+}
+
+void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
+               hipStream_t st, bool adjoint) {
+    check_apply_args(h, in_ext, out_ext, nrhs, ld, prec);
+    const bool fits = h->max_n <= MFMA_CROW_MAX && h->mid.nr_max <= MFMA_CROW_MAX && h->mid.nc_max <= MFMA_CROW_MAX;
+    MIDBF_CHECK(prec != PREC_BF16 || (!adjoint && fits), MIDBF_ERR_UNIMPLEMENTED,
+                "the split-bf16 apply exists for the forward transform with candidate sets up to 2048");
+    // matrix cores: split-bf16 always, FP32 for many right-hand sides
+    const bool mfma = prec == PREC_BF16 || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
+    ensure_workspace(h, prec, nrhs, mfma);
+    const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
+    const auto launches = plan_apply(h, in_ext, out_ext, nrhs, ld, prec, adjoint, mfma, h->ws[prec].buf, true, rt);
+    for (const LaunchDesc& D : launches)
+        launch_checked(h, D.which, prec, rt, &D.a, D.grid, D.smem, st, D.bytes, D.flops, D.mfma_count, nrhs,
+                       D.level);
 }
 
 }  // namespace
 
+}  // namespace midbf
+
+// A batch of forward transforms (midbf_batch_*): the stage table on the
+// device, one pair of level buffers per transform, one grouped launch per
+// round, and optionally the captured graph of those launches.
+struct midbf_batch_s {
+    int prec = 0, rt = 1, nst = 0;
+    size_t smem = 0;
+    long long items = 0;
+    std::vector<int> round_s0, round_ns;
+    std::vector<long long> round_items;
+    std::vector<void*> bufs;
+    midbf::BatchStage* d_st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double bytes = 0, flops = 0;
+};
+
+namespace midbf {
+namespace {
+
+void free_batch(midbf_batch_s* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void* p : b->bufs) (void)hipFree(p);
+    if (b->d_st) (void)hipFree(b->d_st);
+    delete b;
+}
+
+void launch_rounds(const midbf_batch_s* b, hipStream_t st) {
+    for (size_t r = 0; r < b->round_s0.size(); ++r)
+        launch_grouped(b->prec, b->rt, b->d_st, b->round_s0[r], b->round_ns[r], b->round_items[r], b->smem, st);
+}
+
+midbf_batch_s* create_batch(int count, const midbf_handle* hs, const void* const* f, void* const* g, const int* nrhs,
+                            int prec, bool use_graph, hipStream_t st) {
+    MIDBF_CHECK(count >= 1, MIDBF_ERR_ARG, "empty batch");
+    MIDBF_CHECK(prec == PREC_FP64 || prec == PREC_FP32, MIDBF_ERR_UNIMPLEMENTED,
+                "the batched apply runs in FP64 or FP32");
+    bool single = true;
+    for (int j = 0; j < count; ++j) {
+        MIDBF_CHECK(hs[j], MIDBF_ERR_ARG, "null handle in batch");
+        check_apply_args(hs[j], f[j], g[j], nrhs[j], hs[j]->N, prec);
+        single = single && nrhs[j] == 1;
+    }
+    std::unique_ptr<midbf_batch_s, void (*)(midbf_batch_s*)> b(new midbf_batch_s, free_batch);
+    b->prec = prec;
+    b->rt = single ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
+    const size_t cs = csize(prec);
+    std::vector<std::vector<LaunchDesc>> seq(count);
+    size_t rounds = 0;
+    for (int j = 0; j < count; ++j) {
+        midbf_plan* h = hs[j];
+        void* buf[2] = {nullptr, nullptr};
+        const size_t need = (size_t)std::max<long long>(h->max_total_k, 1) * nrhs[j] * cs;
+        for (int i = 0; i < 2; ++i) {
+            MIDBF_HIP(hipMalloc(&buf[i], need));
+            b->bufs.push_back(buf[i]);
+        }
+        seq[j] = plan_apply(h, f[j], g[j], nrhs[j], h->N, prec, false, false, buf, false, b->rt);
+        rounds = std::max(rounds, seq[j].size());
+    }
+    // round r groups the r-th level launch of every transform that has one
+    std::vector<BatchStage> stages;
+    for (size_t r = 0; r < rounds; ++r) {
+        long long first = 0;
+        const int s0 = (int)stages.size();
+        for (int j = 0; j < count; ++j) {
+            if (r >= seq[j].size()) continue;
+            const LaunchDesc& D = seq[j][r];
+            MIDBF_CHECK(D.smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
+                        "candidate vectors of this factorization exceed the apply kernels' LDS budget");
+            BatchStage S{};
+            S.kind = D.which == LevelKernel::Up ? 0 : (D.which == LevelKernel::Middle ? 1 : 2);
+            S.tiles = (int)D.grid.y;
+            S.items = (long long)D.grid.x * D.grid.y;
+            S.first = first;
+            std::memcpy(&S.a, &D.a, sizeof(S.a));
+            stages.push_back(S);
+            first += S.items;
+            b->smem = std::max(b->smem, D.smem);
+            b->bytes += D.bytes;
+            b->flops += D.flops;
+        }
+        b->round_s0.push_back(s0);
+        b->round_ns.push_back((int)stages.size() - s0);
+        b->round_items.push_back(first);
+        b->items += first;
+    }
+    b->nst = (int)stages.size();
+    MIDBF_HIP(hipMalloc(&b->d_st, stages.size() * sizeof(BatchStage)));
+    MIDBF_HIP(hipMemcpyAsync(b->d_st, stages.data(), stages.size() * sizeof(BatchStage), hipMemcpyHostToDevice, st));
+    MIDBF_HIP(hipStreamSynchronize(st));
+    if (use_graph) {
+        hipStream_t cap;
+        MIDBF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        try {
+            MIDBF_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            launch_rounds(b.get(), cap);
+            MIDBF_HIP(hipStreamEndCapture(cap, &b->graph));
+            MIDBF_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        } catch (...) {
+            hipGraph_t dangling = nullptr;
+            (void)hipStreamEndCapture(cap, &dangling);
+            if (dangling) (void)hipGraphDestroy(dangling);
+            (void)hipStreamDestroy(cap);
+            throw;
+        }
+        MIDBF_HIP(hipStreamDestroy(cap));
+    }
+    return b.release();
+}
+
+void run_batch(midbf_batch_s* b, hipStream_t st) {
+    if (b->exec) MIDBF_HIP(hipGraphLaunch(b->exec, st));
+    else launch_rounds(b, st);
+}
+
+}  // namespace
 }  // namespace midbf
 
 using namespace midbf;
@@ -281,13 +461,43 @@ midbf_status midbf_apply_adjoint(midbf_handle h, const void* g, void* f, int nrh
 midbf_status midbf_apply_batched(int count, const midbf_handle* hs, const void* const* f, void* const* g,
                                  const int* nrhs, midbf_precision prec, void* stream) {
     if (count < 0 || (count > 0 && (!hs || !f || !g || !nrhs))) return fail(MIDBF_ERR_ARG, "null argument");
+    if (count == 0) return MIDBF_OK;
     return guarded([&] {
-        for (int j = 0; j < count; ++j) {
-            MIDBF_CHECK(hs[j], MIDBF_ERR_ARG, "null handle in batch");
-            run_apply(hs[j], f[j], g[j], nrhs[j], hs[j]->N, prec_index(prec), (hipStream_t)stream, false);
-        }
+        hipStream_t st = (hipStream_t)stream;
+        std::unique_ptr<midbf_batch_s, void (*)(midbf_batch_s*)> b(
+            create_batch(count, hs, f, g, nrhs, prec_index(prec), false, st), free_batch);
+        run_batch(b.get(), st);
+        MIDBF_HIP(hipStreamSynchronize(st));    // the batch's buffers are freed on return
     });
 }
+
+midbf_status midbf_batch_create(int count, const midbf_handle* hs, const void* const* f, void* const* g,
+                                const int* nrhs, midbf_precision prec, int use_graph, void* stream, midbf_batch* out) {
+    if (!out) return fail(MIDBF_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (count < 1 || !hs || !f || !g || !nrhs) return fail(MIDBF_ERR_ARG, "empty batch or null argument");
+    return guarded([&] { *out = create_batch(count, hs, f, g, nrhs, prec_index(prec), use_graph != 0,
+                                             (hipStream_t)stream); });
+}
+
+midbf_status midbf_batch_run(midbf_batch b, void* stream) {
+    if (!b) return fail(MIDBF_ERR_ARG, "null batch");
+    return guarded([&] { run_batch(b, (hipStream_t)stream); });
+}
+
+midbf_status midbf_batch_get_stats(midbf_batch b, midbf_batch_stats* out) {
+    if (!b || !out) return fail(MIDBF_ERR_ARG, "null argument");
+    out->stages = b->nst;
+    out->rounds = (int)b->round_s0.size();
+    out->items = b->items;
+    out->graph = b->exec != nullptr;
+    out->lds_bytes = (long long)b->smem;
+    out->bytes = b->bytes;
+    out->flops = b->flops;
+    return MIDBF_OK;
+}
+
+void midbf_batch_destroy(midbf_batch b) { free_batch(b); }
 
 midbf_status midbf_factor_stats(midbf_handle h, midbf_stats* out) {
     if (!h || !out) return fail(MIDBF_ERR_ARG, "null argument");

@@ -128,17 +128,70 @@ class MIDBF:
         return out
 
 
-def apply_batched(handles: list[MIDBF], fs: list[torch.Tensor], outs: list[torch.Tensor] | None = None,
-                  precision: str = "fp64", stream=None) -> list[torch.Tensor]:
-    """g_j = K_j f_j for independent transforms (midbf_apply_batched)."""
+def _batch_arrays(handles, fs, outs, precision):
     count = len(handles)
-    outs = [torch.empty_like(f) for f in fs] if outs is None else outs
+    if len(fs) != count or len(outs) != count:
+        raise ValueError("one input and one output per handle")
+    for f, g in zip(fs, outs):
+        if g.shape != f.shape or g.dtype != f.dtype or not g.is_contiguous():
+            raise ValueError("each output must match its input's shape and dtype")
     hs = (C.c_void_p * count)(*[h._h for h in handles])
     fp = (C.c_void_p * count)(*[f.data_ptr() for f in fs])
     gp = (C.c_void_p * count)(*[g.data_ptr() for g in outs])
     nr = (C.c_int * count)(*[h._prep(f, precision) for h, f in zip(handles, fs)])
+    return count, hs, fp, gp, nr
+
+
+def apply_batched(handles: list[MIDBF], fs: list[torch.Tensor], outs: list[torch.Tensor] | None = None,
+                  precision: str = "fp64", stream=None) -> list[torch.Tensor]:
+    """g_j = K_j f_j for independent transforms, one grouped launch per level round (midbf_apply_batched).
+
+    Synchronizes the stream.
+    """
+    outs = [torch.empty_like(f) for f in fs] if outs is None else outs
+    count, hs, fp, gp, nr = _batch_arrays(handles, fs, outs, precision)
     L.check(L.lib.midbf_apply_batched(count, hs, fp, gp, nr, _PREC[precision], _stream_ptr(stream)))
     return outs
+
+
+class Batch:
+    """A reusable batch g_j = K_j f_j of uneven transforms (midbf_batch_create / _run).
+
+    One grouped launch per level round covers that level of every transform.
+    The handles and the tensors fs, outs are referenced by the batch and kept
+    alive here; run() enqueues one replay (of the captured hipGraph when
+    graph=True) on the stream.
+    """
+
+    def __init__(self, handles: list[MIDBF], fs: list[torch.Tensor], outs: list[torch.Tensor] | None = None,
+                 precision: str = "fp32", graph: bool = True, stream=None):
+        self.outs = [torch.empty_like(f) for f in fs] if outs is None else outs
+        self._keep = (list(handles), list(fs), self.outs)
+        count, hs, fp, gp, nr = _batch_arrays(handles, fs, self.outs, precision)
+        b = C.c_void_p()
+        L.check(L.lib.midbf_batch_create(count, hs, fp, gp, nr, _PREC[precision], 1 if graph else 0,
+                                         _stream_ptr(stream), C.byref(b)))
+        self._b = b
+
+    def run(self, stream=None) -> list[torch.Tensor]:
+        L.check(L.lib.midbf_batch_run(self._b, _stream_ptr(stream)))
+        return self.outs
+
+    def stats(self) -> dict:
+        s = L.BatchStats()
+        L.check(L.lib.midbf_batch_get_stats(self._b, C.byref(s)))
+        return {name: getattr(s, name) for name, _ in L.BatchStats._fields_}
+
+    def close(self):
+        if getattr(self, "_b", None):
+            L.lib.midbf_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def kernel_entries(d: int, n: int, phase: str, rows: torch.Tensor, cols: torch.Tensor,
