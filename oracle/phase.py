@@ -16,10 +16,17 @@ comb tree (an MST of axis edges, BFS order = Manhattan distance from the
 root); rows and columns recovered in Alg. 6 are anchored at the recovered
 root column / root row of their block (in-place updates).
 
+An extension for phases on integer frequency lattices, where row steps of
+Phi exceed the unwrap limit of Alg. 4, follows at the end of the module:
+branch reconciliation of recovered rows against screened columns, with the
+samples drawn in splitmix64-seeded orders.
+
 Pins: tests/test_oracle_phase.py -- the Fig. 5 partition example, the
 Definition 2.3 properties of the paths, exact unwrapping of smooth vectors,
 the loop == prefix-sum identity of Alg. 4, Lemma 2.2's consistency in its
-regime, and exact recovery of low-rank matrices by Alg. 1.
+regime, exact recovery of low-rank matrices by Alg. 1, splitmix64's
+published outputs, the failure of the literal recovery on the integer
+lattice and the reconciled recovery of the closed-form phase there.
 """
 from __future__ import annotations
 
@@ -291,3 +298,111 @@ def low_rank_factorization(kfun_row, kfun_col, N, P1, P2, r, q, rng, tau=0.25):
     Cext = np.unique(np.concatenate([C, np.asarray(H.Dc, dtype=np.int64)]))
     U, sig, V = randomized_svd(H.row, H.col, N, N, Rext, Cext, r, rng)
     return U, V * sig[None, :], H
+
+
+# ---- Extension: branch reconciliation (outside Lemma 2.2) ---------------------
+#
+# On an integer frequency lattice a row of K samples exp(2 pi i Phi(x, .)) at
+# integer steps, so a step of Phi larger than 1/2 along the row is unwrapped to
+# Phi - m.xi (m integer) or, near the half-integer boundary, to a mix of
+# branches; columns (steps of size xi/n) stay inside the unwrap limit except
+# next to the Nyquist frequency.  Rows and columns recovered by Alg. 6 then
+# disagree at their intersections by integers and Alg. 1 mixes two matrices.
+# The extension keeps Alg. 7's order of steps and changes three things:
+#   1. a recovered vector is used only when every path increment inside its
+#      block is below tau_amb in magnitude (no step near the unwrap limit);
+#   2. each accepted row is fitted, over the accepted sampled columns, by
+#      Psi_col(i, j) - Psi_row(i, j) = m . xi_j + a with integer m and a, and
+#      accepted only when the fit is exact; the row is then shifted by m . xi + a;
+#   3. Alg. 1's pivots and extra rows / columns are taken inside the accepted
+#      samples (every vector it uses has passed 1 and 2).
+# In the Lemma 2.2 regime nothing is rejected and every m, a is zero.
+
+def splitmix64(z: np.ndarray) -> np.ndarray:
+    """The splitmix64 output function (Steele, Lea, Flood 2014) on uint64 counters."""
+    z = (z + np.uint64(0x9E3779B97F4A7C15)).astype(np.uint64)
+    z = ((z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)).astype(np.uint64)
+    z = ((z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)).astype(np.uint64)
+    return z ^ (z >> np.uint64(31))
+
+
+def sample_order(N: int, seed: int, stream: int) -> np.ndarray:
+    """A seeded random order of 0..N-1: indices sorted by splitmix64(seed + 2 i + stream)
+    (ties, which need a 64-bit collision, by index).  stream 0: rows, 1: columns."""
+    with np.errstate(over="ignore"):
+        ctr = (np.uint64(seed) + np.uint64(2) * np.arange(N, dtype=np.uint64) + np.uint64(stream))
+        h = splitmix64(ctr)
+    return np.lexsort((np.arange(N), h)).astype(np.int64)
+
+
+def max_block_increment(v: np.ndarray, P: np.ndarray, owner: np.ndarray) -> float:
+    """max |v(ed) - v(bg)| over the path edges whose ends lie in one block."""
+    bg, ed = P[:, 0], P[:, 1]
+    same = owner[bg] == owner[ed]
+    if not same.any():
+        return 0.0
+    return float(np.abs(v[ed[same]] - v[bg[same]]).max())
+
+
+def reconciled_low_rank_factorization(kfun_row, kfun_col, N, P1, P2, xi, r, q, seed, tau=0.25,
+                                      tau_amb=0.4, fit_tol=1e-6):
+    """Alg. 7 with branch reconciliation (the extension above).
+
+    xi: (N, d) coordinates of the column points.  Samples are drawn in the
+    seeded orders of sample_order (discontinuity nodes first).  Returns
+    (U, V, H, info) with info holding the accepted rows R, columns C and the
+    integer shifts m (|R| x d) and a (|R|).
+    """
+    H = recovery_matrix2(kfun_row, kfun_col, N, P1, P2, tau=tau)
+    want = r * q
+    # columns: accepted when no path step comes near the unwrap limit
+    cand_c = list(H.Dc) + [int(j) for j in sample_order(N, seed, 1) if int(j) not in set(H.Dc)]
+    C, cols = [], []
+    for j in cand_c:
+        v = H.col(j)
+        if max_block_increment(v, P1, H.owner_r) < tau_amb:
+            C.append(j)
+            cols.append(v)
+            if len(C) == want + len(H.Dc):
+                break
+    C = np.array(C, dtype=np.int64)
+    AC = np.array(cols).T                                   # N x |C|
+    Xc = np.c_[xi[C], np.ones(len(C))]
+    Xall = np.c_[xi, np.ones(N)]
+    cand_r = list(H.Dr) + [int(i) for i in sample_order(N, seed, 0) if int(i) not in set(H.Dr)]
+    R, rows, shifts = [], [], []
+    for i in cand_r:
+        v = H.row(i)
+        if max_block_increment(v, P2, H.owner_c) >= tau_amb:
+            continue
+        D = AC[i, :] - v[C]                                 # integers up to rounding
+        coef = mround(np.linalg.lstsq(Xc, D, rcond=None)[0])
+        if np.abs(D - Xc @ coef).max() > fit_tol:
+            continue
+        R.append(i)
+        rows.append(v + Xall @ coef)
+        shifts.append(coef)
+        if len(R) == want + len(H.Dr):
+            break
+    R = np.array(R, dtype=np.int64)
+    AR = np.array(rows)                                     # |R| x N
+    # Alg. 1 with pivots inside the accepted samples
+    A_RC = AR[:, C]
+    _, _, pc = sla.qr(A_RC, mode="economic", pivoting=True)
+    _, _, pr = sla.qr(A_RC.T, mode="economic", pivoting=True)
+    kc, kr_ = pc[:r], pr[:r]
+    Qc, _ = np.linalg.qr(AC[:, kc])
+    Qr, _ = np.linalg.qr(AR[kr_, :].T)
+    rest_r = [t for t in range(len(R)) if t not in set(kr_.tolist())][:r]
+    rest_c = [t for t in range(len(C)) if t not in set(kc.tolist())][:r]
+    It = np.concatenate([kr_, rest_r]).astype(np.int64)     # positions in R
+    Jt = np.concatenate([kc, rest_c]).astype(np.int64)      # positions in C
+    I, J = R[It], C[Jt]
+    AIJ = AR[It][:, J]
+    M = np.linalg.pinv(Qc[I, :]) @ AIJ @ np.linalg.pinv(Qr.T[:, J])
+    UM, sM, VMh = np.linalg.svd(M)
+    U = Qc @ UM[:, :r]
+    V = (Qr @ VMh.conj().T[:, :r]) * sM[None, :r]
+    shifts = np.array(shifts)
+    info = {"R": R, "C": C, "m": shifts[:, :-1].astype(np.int64), "a": shifts[:, -1].astype(np.int64)}
+    return U, V, H, info

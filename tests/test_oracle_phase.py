@@ -149,3 +149,98 @@ def test_low_rank_factorization_lemma22_regime(r):
     assert abs(H.row(i)[j] - H.col(j)[i]) < 1e-12
     # e^{2 pi i Psi} = K on recovered entries
     assert np.allclose(np.exp(2j * np.pi * H.row(i)), kr(i), atol=1e-12)
+
+
+# ---- branch reconciliation (the extension for integer frequency lattices) ----
+
+from oracle.kernel import Kernel, x_points, xi_points  # noqa: E402
+from oracle.phase import (max_block_increment, reconciled_low_rank_factorization,  # noqa: E402
+                          sample_order, splitmix64)
+
+
+def test_splitmix64_published_outputs():
+    # the first two outputs of splitmix64 from state 0 (Steele, Lea, Flood 2014; Vigna's reference code)
+    z = splitmix64(np.array([0, 0x9E3779B97F4A7C15], dtype=np.uint64))
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4]
+
+
+def test_sample_order_is_a_seeded_permutation():
+    a = sample_order(1000, 7, 0)
+    assert sorted(a.tolist()) == list(range(1000))
+    assert np.array_equal(a, sample_order(1000, 7, 0))
+    assert not np.array_equal(a, sample_order(1000, 7, 1))
+    assert not np.array_equal(a, sample_order(1000, 8, 0))
+
+
+def _iso3d_handles(n):
+    K = Kernel(3, n, "iso3d")
+    N = K.N
+    return K, (lambda i: K.entries([i], np.arange(N))[0]), (lambda j: K.entries(np.arange(N), [j])[:, 0])
+
+
+def _true_iso3d_phase(n, I, J):
+    x, xi = x_points(3, n)[I], xi_points(3, n)[J]
+    c = (3 + np.prod(np.sin(2 * np.pi * x), axis=1)) / 100
+    return x @ xi.T + c[:, None] * np.linalg.norm(xi, axis=1)[None, :]
+
+
+def test_literal_recovery_fails_on_integer_lattice():
+    """Outside Lemma 2.2 (steps of x.xi up to ~1 along rows) the literal Alg. 7 mixes branches."""
+    n = 16
+    K, kr, kc = _iso3d_handles(n)
+    N = K.N
+    P1 = recovery_path_lattice(3, n, (0, 0, 0))
+    P2 = recovery_path_lattice(3, n, (n // 2,) * 3)
+    U, V, H = low_rank_factorization(kr, kc, N, P1, P2, 8, 2, W.rng(24, 0))
+    i, j = int(np.ravel_multi_index((12, 1, 2), (n,) * 3)), 300
+    assert abs(H.row(i)[j] - H.col(j)[i]) > 0.5          # intersections disagree by an integer
+    S = W.index_sample(N, 128, 24, 1)
+    assert eps_K(K.entries(S, S), U, V, S) > 0.1
+
+
+def test_reconciled_recovery_returns_the_true_phase():
+    """Closed form: with both anchors at Phi = 0 (x = 0, xi = 0) and rank(Phi) = 4 <= r, the
+    reconciled recovery reproduces Phi = x.xi + c(x)|xi| itself."""
+    n = 16
+    K, kr, kc = _iso3d_handles(n)
+    N = K.N
+    P1 = recovery_path_lattice(3, n, (0, 0, 0))
+    P2 = recovery_path_lattice(3, n, (n // 2,) * 3)
+    U, V, H, info = reconciled_low_rank_factorization(kr, kc, N, P1, P2, xi_points(3, n), 8, 2, 99)
+    S = W.index_sample(N, 200, 24, 2)
+    T = W.index_sample(N, 200, 24, 3)
+    assert np.abs(U[S] @ V[T].T - _true_iso3d_phase(n, S, T)).max() < 1e-9
+    assert eps_K(K.entries(S, S), U, V, S) < 1e-12
+    # the integer shift of every accepted row undoes the aliasing x_d -> x_d - 1 of x_d > 1/2
+    x = x_points(3, n)[info["R"]]
+    assert np.array_equal(info["m"], (x > 0.5).astype(np.int64))
+    assert (info["a"] == 0).all()
+    # accepted rows and columns keep clear of the unwrap limit
+    assert not ((x > 0.4) & (x < 0.6)).any()
+    xi = xi_points(3, n)[info["C"]]
+    assert (np.abs(xi) <= 0.45 * n).all()
+    assert len(info["R"]) == len(info["C"]) == 17
+
+
+def test_reconciled_equals_literal_in_lemma22_regime():
+    """Inside Lemma 2.2 no vector is rejected, every shift is zero and both give Psi = Phi."""
+    n, d = 8, 3
+    pts = np.array(np.unravel_index(np.arange(n ** d), (n,) * d)).T / n
+    X1, X2 = pts, pts * 0.9
+    Phi = lambda I, J: X1[I] @ X2[J].T
+    kr = lambda i: np.exp(2j * np.pi * Phi([i], np.arange(n ** d))[0])
+    kc = lambda j: np.exp(2j * np.pi * Phi(np.arange(n ** d), [j])[:, 0])
+    P = recovery_path_lattice(d, n, (0,) * d)
+    U, V, H, info = reconciled_low_rank_factorization(kr, kc, n ** d, P, P, X2, 5, 2, 3)
+    assert (info["m"] == 0).all() and (info["a"] == 0).all()
+    order_r = [int(i) for i in sample_order(n ** d, 3, 0)]
+    assert info["R"].tolist() == [0] + [i for i in order_r if i != 0][:10]   # D_r = [root], then rq rows
+    S = W.index_sample(n ** d, 128, 25, 0)
+    assert np.abs(U[S] @ V[S].T - Phi(S, S)).max() < 1e-10
+
+
+def test_max_block_increment_ignores_cut_edges():
+    P = np.array([[0, 1], [1, 2], [2, 3]])
+    v = np.array([0.0, 0.1, 0.9, 1.0])
+    assert abs(max_block_increment(v, P, np.array([0, 0, 0, 0])) - 0.8) < 1e-15
+    assert abs(max_block_increment(v, P, np.array([0, 0, 1, 1])) - 0.1) < 1e-15
