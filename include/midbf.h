@@ -174,6 +174,60 @@ midbf_status midbf_batch_get_stats(midbf_batch b, midbf_batch_stats* out);
 /* Free the batch; waits for the device like hipFree. */
 void midbf_batch_destroy(midbf_batch b);
 
+/*
+ * Phase recovery (Section 2; Scenario 2 of Table 1: K is reachable only
+ * through O(1) of its rows and columns).
+ *
+ * midbf_sample_cb -- the caller's sampler: write row `index` (is_row != 0,
+ * K(x_index, :)) or column `index` (K(:, xi_index)) of K as N complex128
+ * values (interleaved re, im) to the host buffer `out`; return 0 on success.
+ */
+typedef int (*midbf_sample_cb)(void* user, int is_row, long long index, double* out);
+
+#define PHASE_RECOVER_MAX_SAMPLES 64
+
+typedef struct {
+    double tau;                    /* discontinuity threshold after the schedule (Sec. 2.3.4) */
+    int disc_rows, disc_cols;      /* flagged nodes on the root column / root row            */
+    int n_rows, n_cols;            /* accepted sampled rows / columns                        */
+    int rejected_rows, rejected_cols;
+    long long callbacks;           /* rows and columns fetched through the sampler           */
+    long long rows[PHASE_RECOVER_MAX_SAMPLES], cols[PHASE_RECOVER_MAX_SAMPLES];
+    int shift[PHASE_RECOVER_MAX_SAMPLES][4];   /* per accepted row: integer m (d entries), a  */
+} phase_recover_info;
+
+/*
+ * phase_recover -- a real N x r pair (U, V) with exp(2 pi i U V^T) ~ K
+ * (Alg. 7: RecoveryMatrix2 (Alg. 6, built on Alg. 4 along recovery paths),
+ * then the randomized SVD of Alg. 1), for the lattices of this library:
+ * x = {0..n-1}^d / n, xi = {0..n-1}^d - n/2.  The recovery paths are the
+ * dimension-ordered comb trees rooted at x = 0 and xi = 0.  X1, X2: host
+ * N x d row-major coordinates of the x and xi points, or NULL for the
+ * lattice coordinates (X2 enters the integer-shift fit below).
+ *
+ * The GPU form is Alg. 7 with branch reconciliation, for phases whose steps
+ * along rows exceed the unwrap limit of Alg. 4 on an integer frequency
+ * lattice: a recovered row or column is used only if every path step inside
+ * its block stays below 0.4 in magnitude; each accepted row is fitted
+ * against the accepted sampled columns by an integer shift m . xi + a (kept
+ * only if the fit is exact) and shifted; Alg. 1 takes its pivots and extra
+ * rows / columns inside the accepted samples.  Samples are drawn in
+ * splitmix64-seeded orders (sorted by splitmix64(seed + 2 i + stream),
+ * stream 0 rows, 1 columns), the discontinuity nodes first.  Inside the
+ * regime of Lemma 2.2 nothing is rejected and every shift is zero.
+ *
+ * r: rank (1..16); q: oversampling, r*q <= 32 rows and columns are sampled;
+ * tau: initial discontinuity threshold (1/4; raised by 1/40 while more than
+ * 16 nodes are flagged, up to 1/2).  U_dev, V_dev: caller-owned device
+ * buffers of N x r FP64, row-major (the layout of midbf_params.U_dev / V_dev).
+ * info may be NULL.  Synchronizes `stream`.
+ * Errors: _ARG, _RECOVERY (the sampler failed, or too few rows / columns
+ * passed the screening), _OOM, _HIP.
+ */
+midbf_status phase_recover(int d, int n, const double* X1, const double* X2, midbf_sample_cb cb, void* user,
+                           int r, int q, double tau, uint64_t seed, void* stream, double* U_dev,
+                           double* V_dev, phase_recover_info* info);
+
 /* Sizes and ranks of a built factorization. */
 midbf_status midbf_factor_stats(midbf_handle h, midbf_stats* out);
 

@@ -45,6 +45,16 @@ class BatchStats(C.Structure):
                 ("lds_bytes", C.c_longlong), ("bytes", C.c_double), ("flops", C.c_double)]
 
 
+class RecoverInfo(C.Structure):
+    _fields_ = [("tau", C.c_double), ("disc_rows", C.c_int), ("disc_cols", C.c_int), ("n_rows", C.c_int),
+                ("n_cols", C.c_int), ("rejected_rows", C.c_int), ("rejected_cols", C.c_int),
+                ("callbacks", C.c_longlong), ("rows", C.c_longlong * 64), ("cols", C.c_longlong * 64),
+                ("shift", (C.c_int * 4) * 64)]
+
+
+SAMPLE_CB = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_longlong, C.POINTER(C.c_double))
+
+
 class MidbfError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -75,6 +85,8 @@ def _load():
         "midbf_set_variants": (i, [vp, i, C.POINTER(i)]),
         "midbf_profile_enable": (i, [vp, i]),
         "midbf_profile_read": (i, [vp, C.POINTER(KernelTime), i, C.POINTER(i)]),
+        "phase_recover": (i, [i, i, C.POINTER(C.c_double), C.POINTER(C.c_double), SAMPLE_CB, vp, i, i, C.c_double,
+                              C.c_uint64, vp, vp, vp, C.POINTER(RecoverInfo)]),
         "midbf_destroy": (None, [vp]),
         "midbf_last_error": (C.c_char_p, []),
     }
@@ -97,4 +109,5 @@ EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_ba
             "midbf_batch_create", "midbf_batch_run", "midbf_batch_get_stats",
             "midbf_batch_destroy",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",
-            "midbf_tune", "midbf_set_variants", "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error"]
+            "midbf_tune", "midbf_set_variants", "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error",
+            "phase_recover"]

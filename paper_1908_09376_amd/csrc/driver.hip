@@ -9,6 +9,7 @@
 #include "apply.h"
 #include "build.h"
 #include "mfma.h"
+#include "recover.h"
 
 namespace midbf {
 
@@ -668,6 +669,14 @@ void midbf_destroy(midbf_handle h) {
         for (auto e : h->prof.pool) (void)hipEventDestroy(e);
     }
     destroy_plan(h);
+}
+
+midbf_status phase_recover(int d, int n, const double* X1, const double* X2, midbf_sample_cb cb, void* user, int r,
+                           int q, double tau, uint64_t seed, void* stream, double* U_dev, double* V_dev,
+                           phase_recover_info* info) {
+    return guarded([&] {
+        phase_recover_run(d, n, X1, X2, cb, user, r, q, tau, seed, (hipStream_t)stream, U_dev, V_dev, info);
+    });
 }
 
 const char* midbf_last_error(void) { return g_last_error.c_str(); }

@@ -220,3 +220,50 @@ def id_batch(X: torch.Tensor, tol: float, k_cap: int = 0, stream=None):
     kk = k.cpu().numpy()
     Ts = [T[i, : kk[i] * (n - kk[i])].reshape(kk[i], n - kk[i]) for i in range(b)]
     return kk, perm.cpu().numpy(), Ts
+
+
+def phase_recover(d: int, n: int, sample, r: int = 8, q: int = 2, tau: float = 0.25, seed: int = 0,
+                  X2: np.ndarray | None = None, stream=None):
+    """[U, V] with exp(2 pi i U V^T) ~ K from rows / columns of K (phase_recover).
+
+    sample(is_row, index) returns row `index` (is_row True) or column `index`
+    of K as N complex values; it runs on the host when the library asks.
+    Returns (U, V, info): (N, r) float64 CUDA tensors and a dict of the
+    recovery's threshold, flagged nodes, accepted samples and integer shifts.
+    """
+    N = n ** d
+    dev = torch.device("cuda", torch.cuda.current_device())
+    U = torch.empty((N, r), dtype=torch.float64, device=dev)
+    V = torch.empty((N, r), dtype=torch.float64, device=dev)
+    err = []
+
+    def cb(_user, is_row, index, out):
+        try:
+            vals = np.asarray(sample(bool(is_row), int(index)), dtype=np.complex128).reshape(N)
+            buf = np.ctypeslib.as_array(out, shape=(2 * N,))
+            buf[0::2] = vals.real
+            buf[1::2] = vals.imag
+            return 0
+        except Exception as e:          # reported after the call returns
+            err.append(e)
+            return 1
+
+    cfun = L.SAMPLE_CB(cb)
+    x2 = None
+    if X2 is not None:
+        x2a = np.ascontiguousarray(X2, dtype=np.float64).reshape(N, d)
+        x2 = x2a.ctypes.data_as(C.POINTER(C.c_double))
+    info = L.RecoverInfo()
+    st = L.lib.phase_recover(d, n, None, x2, cfun, None, r, q, tau, seed, _stream_ptr(stream),
+                             U.data_ptr(), V.data_ptr(), C.byref(info))
+    if err:
+        raise err[0]
+    L.check(st)
+    nr, nc = info.n_rows, info.n_cols
+    out = {"tau": info.tau, "disc_rows": info.disc_rows, "disc_cols": info.disc_cols,
+           "rejected_rows": info.rejected_rows, "rejected_cols": info.rejected_cols,
+           "callbacks": info.callbacks,
+           "R": np.array(info.rows[:nr], dtype=np.int64), "C": np.array(info.cols[:nc], dtype=np.int64),
+           "m": np.array([list(info.shift[a])[:d] for a in range(nr)], dtype=np.int64).reshape(nr, d),
+           "a": np.array([info.shift[a][d] for a in range(nr)], dtype=np.int64)}
+    return U, V, out
