@@ -65,6 +65,9 @@ struct MidArgs {
     const void* in;
     void* out;
     int nrhs;
+    int in_max, out_max;     // largest column / row count of a block (matrix-core index tables)
+    int chunk;               // VALU path: input entries staged in LDS per pass
+    int mchunks;             // matrix-core FP32 path: workgroups splitting the rows of one block
 };
 
 enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum };

@@ -237,6 +237,33 @@ __global__ __launch_bounds__(AT) void down_kernel(DownArgs A) {
 }
 
 // ---- middle: z(rows) = S x(cols), S column-major nr x nc ----
+// Entries [c0, c0 + cw) of the concatenation of a block's vector pieces
+// (offsets off[t], lengths len[t]) into LDS, RT right-hand sides each.
+template <class C, int RT>
+__device__ void stage_pieces(C* s, const C* src, const long long* off, const int* len, int pieces, int c0, int cw,
+                             int nrhs, int r0, int nrr) {
+    int start = 0;
+    for (int t = 0; t < pieces; ++t) {
+        const int l = len[t];
+        const int lo = max(c0, start), hi = min(c0 + cw, start + l);
+        for (int e = threadIdx.x; e < (hi - lo) * RT; e += AT) {
+            const int c = lo + e / RT, r = e - (e / RT) * RT;
+            s[(c - c0) * RT + r] = (r < nrr) ? src[(off[t] + (c - start)) * nrhs + r0 + r] : czero<C>();
+        }
+        start += l;
+    }
+}
+
+// position of entry `row` of the concatenated pieces
+__device__ inline long long piece_offset(const long long* off, const int* len, int pieces, int row) {
+    int t = 0, base = 0;
+    while (t + 1 < pieces && row >= base + len[t]) {
+        base += len[t];
+        ++t;
+    }
+    return off[t] + (row - base);
+}
+
 template <class C, int RT>
 __device__ __forceinline__ void middle_body(const MidArgs& A, long long bi, int tile, unsigned char* smem_raw) {
     C* s_x = reinterpret_cast<C*>(smem_raw);
@@ -246,39 +273,58 @@ __device__ __forceinline__ void middle_body(const MidArgs& A, long long bi, int 
     const int tid = threadIdx.x;
     const C* xin = (const C*)A.in;
     C* zout = (C*)A.out;
-    // input pieces (columns of S)
-    int start = 0;
-    for (int t = 0; t < A.pieces; ++t) {
-        const long long off = A.in_off[bi * A.pieces + t];
-        const int len = A.in_len[bi * A.pieces + t];
-        for (int e = tid; e < len * RT; e += AT) {
-            const int c = e / RT, r = e - c * RT;
-            s_x[(start + c) * RT + r] = (r < nrr) ? xin[(off + c) * A.nrhs + r0 + r] : czero<C>();
-        }
-        start += len;
-    }
-    __syncthreads();
+    const long long* in_off = A.in_off + bi * A.pieces;
+    const int* in_len = A.in_len + bi * A.pieces;
+    const long long* out_off = A.out_off + bi * A.pieces;
+    const int* out_len = A.out_len + bi * A.pieces;
     const C* S = (const C*)A.S + A.off[bi];
-    for (int row = tid; row < nr; row += AT) {
+    if (nc <= A.chunk) {
+        // the whole input vector fits in LDS: stage it once
+        stage_pieces<C, RT>(s_x, xin, in_off, in_len, A.pieces, 0, nc, A.nrhs, r0, nrr);
+        __syncthreads();
+        for (int row = tid; row < nr; row += AT) {
+            C acc[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+#pragma unroll 4
+            for (int c = 0; c < nc; ++c) {
+                const C sv = S[(long long)c * nr + row];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) cfma(acc[r], sv, s_x[c * RT + r]);
+            }
+            const long long off = piece_offset(out_off, out_len, A.pieces, row);
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                if (r < nrr) zout[off * A.nrhs + r0 + r] = acc[r];
+        }
+        return;
+    }
+    // larger blocks: per batch of rows, the input in chunks of A.chunk entries
+    for (int row0 = 0; row0 < nr; row0 += AT) {
+        const int row = row0 + tid;
         C acc[RT];
 #pragma unroll
         for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+        for (int c0 = 0; c0 < nc; c0 += A.chunk) {
+            const int cw = min(A.chunk, nc - c0);
+            __syncthreads();
+            stage_pieces<C, RT>(s_x, xin, in_off, in_len, A.pieces, c0, cw, A.nrhs, r0, nrr);
+            __syncthreads();
+            if (row < nr) {
 #pragma unroll 4
-        for (int c = 0; c < nc; ++c) {
-            const C sv = S[(long long)c * nr + row];
+                for (int c = 0; c < cw; ++c) {
+                    const C sv = S[(long long)(c0 + c) * nr + row];
 #pragma unroll
-            for (int r = 0; r < RT; ++r) cfma(acc[r], sv, s_x[c * RT + r]);
+                    for (int r = 0; r < RT; ++r) cfma(acc[r], sv, s_x[c * RT + r]);
+                }
+            }
         }
-        // output piece of this row
-        int t = 0, base = 0;
-        while (t + 1 < A.pieces && row >= base + A.out_len[bi * A.pieces + t]) {
-            base += A.out_len[bi * A.pieces + t];
-            ++t;
-        }
-        const long long off = A.out_off[bi * A.pieces + t] + (row - base);
+        if (row < nr) {
+            const long long off = piece_offset(out_off, out_len, A.pieces, row);
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
-            if (r < nrr) zout[off * A.nrhs + r0 + r] = acc[r];
+            for (int r = 0; r < RT; ++r)
+                if (r < nrr) zout[off * A.nrhs + r0 + r] = acc[r];
+        }
     }
 }
 
@@ -332,6 +378,8 @@ __global__ __launch_bounds__(AT) void adj_up_kernel(UpArgs A) {
 }
 
 // ---- adjoint middle: x(cols) = S^H z(rows) ----
+// The rows of z are staged in LDS in chunks of A.chunk entries; the
+// workgroup owns its block's outputs and adds each chunk's part to them.
 template <class C, int RT>
 __global__ __launch_bounds__(AT) void adj_middle_kernel(MidArgs A) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -343,40 +391,36 @@ __global__ __launch_bounds__(AT) void adj_middle_kernel(MidArgs A) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const C* zin = (const C*)A.in;
     C* xout = (C*)A.out;
-    int start = 0;
-    for (int t = 0; t < A.pieces; ++t) {          // input: row pieces
-        const long long off = A.out_off[bi * A.pieces + t];
-        const int len = A.out_len[bi * A.pieces + t];
-        for (int e = tid; e < len * RT; e += AT) {
-            const int c = e / RT, r = e - c * RT;
-            s_z[(start + c) * RT + r] = (r < nrr) ? zin[(off + c) * A.nrhs + r0 + r] : czero<C>();
-        }
-        start += len;
-    }
-    __syncthreads();
+    const long long* in_off = A.in_off + bi * A.pieces;
+    const int* in_len = A.in_len + bi * A.pieces;
     const C* S = (const C*)A.S + A.off[bi];
-    for (int col = wave; col < nc; col += AW) {
-        C acc[RT];
+    for (int q0 = 0; q0 < nr; q0 += A.chunk) {
+        const int qw = min(A.chunk, nr - q0);
+        __syncthreads();
+        stage_pieces<C, RT>(s_z, zin, A.out_off + bi * A.pieces, A.out_len + bi * A.pieces, A.pieces, q0, qw,
+                            A.nrhs, r0, nrr);
+        __syncthreads();
+        for (int col = wave; col < nc; col += AW) {
+            C acc[RT];
 #pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
-        const C* Sc = S + (long long)col * nr;
-        for (int row = lane; row < nr; row += 64) {
-            const C sv = Sc[row];
+            for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
+            const C* Sc = S + (long long)col * nr + q0;
+            for (int row = lane; row < qw; row += 64) {
+                const C sv = Sc[row];
 #pragma unroll
-            for (int r = 0; r < RT; ++r) cfmac(acc[r], sv, s_z[row * RT + r]);
-        }
-#pragma unroll
-        for (int r = 0; r < RT; ++r) acc[r] = wave_sum_c(acc[r]);
-        if (lane == 0) {
-            int t = 0, base = 0;
-            while (t + 1 < A.pieces && col >= base + A.in_len[bi * A.pieces + t]) {
-                base += A.in_len[bi * A.pieces + t];
-                ++t;
+                for (int r = 0; r < RT; ++r) cfmac(acc[r], sv, s_z[row * RT + r]);
             }
-            const long long off = A.in_off[bi * A.pieces + t] + (col - base);
 #pragma unroll
-            for (int r = 0; r < RT; ++r)
-                if (r < nrr) xout[off * A.nrhs + r0 + r] = acc[r];
+            for (int r = 0; r < RT; ++r) acc[r] = wave_sum_c(acc[r]);
+            if (lane == 0) {
+                const long long off = piece_offset(in_off, in_len, A.pieces, col);
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+                    if (r < nrr) {
+                        C* dst = xout + off * A.nrhs + r0 + r;
+                        *dst = q0 == 0 ? acc[r] : cadd(*dst, acc[r]);
+                    }
+            }
         }
     }
 }

@@ -218,7 +218,16 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.in = buf[o ^ 1];
         a.out = buf[o];
         a.nrhs = nrhs;
+        a.in_max = M.nc_max;
+        a.out_max = M.nr_max;
+        // FP32 matrix cores: split the rows of few large blocks over several workgroups
+        a.mchunks = (mfma && prec == PREC_FP32)
+                        ? (int)std::max<long long>(1, std::min<long long>((2048 + M.nblk - 1) / std::max<long long>(M.nblk, 1),
+                                                                          (M.nr_max + 127) / 128))
+                        : 1;
         const int width = adjoint ? M.nr_max : M.nc_max;
+        // VALU path: entries of the staged vector per LDS pass
+        a.chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(width, 1), LDS_LIMIT / (rt * cs)));
         const long long chunk = chunk_middle ? 65535 : std::max<long long>(M.nblk, 1);
         for (long long b0 = 0; b0 < M.nblk; b0 += chunk) {
             const long long cnt = std::min<long long>(chunk, M.nblk - b0);
@@ -232,7 +241,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
             const double vec = (double)(h->rows.back().total_k + h->cols.back().total_k) * nrhs * cs;
             D.which = adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle;
             D.grid = dim3((unsigned)cnt, tiles);
-            D.smem = (size_t)width * rt * cs;
+            D.smem = (size_t)std::min(width, ab.chunk) * rt * cs;
             D.bytes = frac * ((double)M.total * cs + (double)M.nblk * 40 + vec);
             D.flops = frac * fl * M.total * nrhs;
             D.mfma_count = mfma ? cnt : 0;
@@ -300,8 +309,10 @@ void check_apply_args(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs
 void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
                hipStream_t st, bool adjoint) {
     check_apply_args(h, in_ext, out_ext, nrhs, ld, prec);
-    const bool fits = h->max_n <= MFMA_CROW_MAX && h->mid.nr_max <= MFMA_CROW_MAX && h->mid.nc_max <= MFMA_CROW_MAX;
-    MIDBF_CHECK(prec != PREC_BF16 || (!adjoint && fits), MIDBF_ERR_UNIMPLEMENTED,
+    const bool fits = h->max_n <= MFMA_CROW_MAX && h->mid.nr_max + h->mid.nc_max <= 2 * MFMA_CROW_MAX;
+    const bool fits_bf16 =
+        h->max_n <= BF16_CROW_MAX && h->mid.nr_max <= BF16_CROW_MAX && h->mid.nc_max <= BF16_CROW_MAX;
+    MIDBF_CHECK(prec != PREC_BF16 || (!adjoint && fits_bf16), MIDBF_ERR_UNIMPLEMENTED,
                 "the split-bf16 apply exists for the forward transform with candidate sets up to 2048");
     // matrix cores: split-bf16 always, FP32 for many right-hand sides
     const bool mfma = prec == PREC_BF16 || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);

@@ -30,7 +30,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int MT = 256;          // threads per workgroup (up, down)
 constexpr int MW = MT / 64;      // waves
 constexpr int NRHS = MFMA_NRHS;  // columns per workgroup (4 tiles of 16)
-constexpr int CROW_MAX = 2048;
 
 // One k-step of 4 for every (row tile, column tile) of a wave: the two
 // products of each accumulator are issued in separate sweeps so that
@@ -215,8 +214,9 @@ __device__ inline long long xcd_group_order(long long b, long long nid, int P) {
 template <class C>
 __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     constexpr int MTW = C::MTW;
-    __shared__ int crow[CROW_MAX];
-    __shared__ int srcrow[CROW_MAX];
+    extern __shared__ int dyn_rows[];          // ncand_max candidate rows, then as many source rows
+    int* crow = dyn_rows;
+    int* srcrow = dyn_rows + A.ncand_max;
     __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, fl
 // The 2^d contributions of a group summed in a fixed order and written to
 // the candidate rows (previous level buffer, or the leaf's lattice points).
 __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
-    __shared__ int crow[CROW_MAX];
+    extern __shared__ int crow[];               // ncand_max candidate rows
     __shared__ long long base[8];
     const long long g = blockIdx.x;
     const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
@@ -354,10 +354,12 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
 template <class C>
 __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     constexpr int MTW = C::MTW;
-    __shared__ int crow_in[CROW_MAX];
-    __shared__ int crow_out[CROW_MAX];
+    extern __shared__ int dyn_rows[];          // in_max input rows, then out_max output rows
+    int* crow_in = dyn_rows;
+    int* crow_out = dyn_rows + A.in_max;
     __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
-    const long long bi = blockIdx.x;
+    const long long bi = blockIdx.x / A.mchunks;
+    const int chunk = (int)(blockIdx.x - bi * A.mchunks);
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     const int M = A.nr[bi], K = A.nc[bi];
@@ -378,7 +380,10 @@ __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     const float2* S = (const float2*)A.S + A.off[bi];
     __syncthreads();
     auto brow = [&](int j, int r) { return xin[(long long)crow_in[j] * A.nrhs + r0 + r]; };
-    for (int m0 = 0; m0 < M; m0 += C::ROUND) {
+    // rows of this workgroup: a run of whole rounds
+    const int per = ((M + A.mchunks - 1) / A.mchunks + C::ROUND - 1) / C::ROUND * C::ROUND;
+    const int mlo = chunk * per, mhi = min(M, mlo + per);
+    for (int m0 = mlo; m0 < mhi; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
@@ -416,18 +421,26 @@ template <class C>
 void launch_variant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch, hipStream_t s) {
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
     switch (which) {
-        case LevelKernel::Up:
-            hipLaunchKernelGGL(up_mfma<C>, grid, dim3(C::NT), 0, s, *(const UpArgs*)args, count);
+        case LevelKernel::Up: {
+            const UpArgs& a = *(const UpArgs*)args;
+            hipLaunchKernelGGL(up_mfma<C>, grid, dim3(C::NT), 2 * sizeof(int) * a.ncand_max, s, a, count);
             break;
+        }
         case LevelKernel::Down:
             hipLaunchKernelGGL(down_mfma<C>, grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count, (float2*)scratch);
             break;
-        case LevelKernel::DownSum:
-            hipLaunchKernelGGL(down_sum, grid, dim3(MT), 0, s, *(const DownArgs*)args, (const float2*)scratch);
+        case LevelKernel::DownSum: {
+            const DownArgs& a = *(const DownArgs*)args;
+            hipLaunchKernelGGL(down_sum, grid, dim3(MT), sizeof(int) * a.ncand_max, s, a, (const float2*)scratch);
             break;
-        case LevelKernel::Middle:
-            hipLaunchKernelGGL(middle_mfma<C>, grid, dim3(C::NT), 0, s, *(const MidArgs*)args);
+        }
+        case LevelKernel::Middle: {
+            const MidArgs& a = *(const MidArgs*)args;
+            MIDBF_CHECK(a.mchunks >= 1, MIDBF_ERR_ARG, "middle row split must be >= 1");
+            const dim3 mgrid((unsigned)(count * a.mchunks), grid.y);
+            hipLaunchKernelGGL(middle_mfma<C>, mgrid, dim3(C::NT), sizeof(int) * (a.in_max + a.out_max), s, a);
             break;
+        }
         default:
             throw Error(MIDBF_ERR_UNIMPLEMENTED, "no matrix-core kernel for this level kind");
     }

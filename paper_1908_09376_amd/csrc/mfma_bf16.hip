@@ -28,7 +28,7 @@ typedef int intx4 __attribute__((ext_vector_type(4)));
 
 constexpr int NRHS = MFMA_NRHS;
 constexpr int KT = 32;                       // K per tile / per chunk
-constexpr int CROW_MAX = MFMA_CROW_MAX;
+constexpr int CROW_MAX = BF16_CROW_MAX;
 
 struct Frag {
     bf16x8 rh, ih, rl, il;
