@@ -106,6 +106,43 @@ __device__ void scatter_candidates(const C* s_w, const ApplyGeom& G, int s, long
 // gathered into a per-wave LDS strip (x[red] in order), then each lane owns
 // OPL outputs (o = lane + 64u) and sweeps the columns of T once; every column
 // read is OPL coalesced 64-lane loads.
+// Single right-hand side: rows o = o0 + lane + 64u (u < U) of T x_red,
+// accumulated over the columns in order; each batch of JB columns is loaded
+// before it is used, so JB * U loads per lane are in flight.
+template <class C, int U>
+__device__ __forceinline__ void up_rows1(C (&acc)[4], const C* __restrict__ T, int k, int nred, const C* strip,
+                                         int o0, int lane) {
+    constexpr int JB = sizeof(C) == 8 ? 8 : 4;
+#if defined(__HIP_DEVICE_COMPILE__)
+    using GC = __attribute__((address_space(1))) const C;     // factor blocks live in global memory
+#else
+    using GC = const C;                                        // (host pass: never executed)
+#endif
+    const GC* Tg = (const GC*)T;
+    int orow[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) orow[u] = min(o0 + lane + 64 * u, k - 1);     // clamped: no divergence
+    int j = 0;
+    for (; j + JB <= nred; j += JB) {
+        C tv[JB][U];
+#pragma unroll
+        for (int q = 0; q < JB; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) tv[q][u] = Tg[(long long)(j + q) * k + orow[u]];
+#pragma unroll
+        for (int q = 0; q < JB; ++q) {
+            const C xv = strip[j + q];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cfma(acc[u], tv[q][u], xv);
+        }
+    }
+    for (; j < nred; ++j) {
+        const C xv = strip[j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cfma(acc[u], Tg[(long long)j * k + orow[u]], xv);
+    }
+}
+
 template <class C, int RT, int OPL>
 __device__ __forceinline__ void up_body(const UpArgs& A, long long g, int tile, unsigned char* smem_raw) {
     C* s_x = reinterpret_cast<C*>(smem_raw);
@@ -141,23 +178,34 @@ __device__ __forceinline__ void up_body(const UpArgs& A, long long g, int tile, 
 #pragma unroll
             for (int u = 0; u < OPL; ++u) o[u] = o0 + lane + 64 * u;
             const int uact = min(OPL, (k - o0 + 63) / 64);     // wave-uniform
+            if constexpr (RT == 1) {
+                static_assert(OPL == 4, "single-RHS path keeps four rows per lane");
+                C acc1[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc1[u] = czero<C>();
+                switch (uact) {
+                    case 1: up_rows1<C, 1>(acc1, T, k, nred, strip, o0, lane); break;
+                    case 2: up_rows1<C, 2>(acc1, T, k, nred, strip, o0, lane); break;
+                    case 3: up_rows1<C, 3>(acc1, T, k, nred, strip, o0, lane); break;
+                    default: up_rows1<C, 4>(acc1, T, k, nred, strip, o0, lane); break;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u][0] = acc1[u];
+            } else {
 #pragma unroll 4
-            for (int j = 0; j < nred; ++j) {
-                C xv[RT];
-                if constexpr (RT == 1) {
-                    xv[0] = strip[j];
-                } else {
+                for (int j = 0; j < nred; ++j) {
+                    C xv[RT];
                     const int pj = perm[k + j];
 #pragma unroll
                     for (int r = 0; r < RT; ++r) xv[r] = s_x[pj * RT + r];
-                }
-                const C* Tj = T + (long long)j * k;
+                    const C* Tj = T + (long long)j * k;
 #pragma unroll
-                for (int u = 0; u < OPL; ++u) {
-                    if (u < uact) {                               // wave-uniform
-                        const C tv = Tj[min(o[u], k - 1)];        // clamped: every lane loads, no divergence
+                    for (int u = 0; u < OPL; ++u) {
+                        if (u < uact) {                               // wave-uniform
+                            const C tv = Tj[min(o[u], k - 1)];
 #pragma unroll
-                        for (int r = 0; r < RT; ++r) cfma(acc[u][r], tv, xv[r]);
+                            for (int r = 0; r < RT; ++r) cfma(acc[u][r], tv, xv[r]);
+                        }
                     }
                 }
             }
@@ -517,7 +565,7 @@ template <class C, int RT>
 void launch_level(LevelKernel which, const void* args, dim3 grid, size_t smem, hipStream_t s) {
     switch (which) {
         case LevelKernel::Up:
-            if (RT == 1)
+            if constexpr (RT == 1)
                 hipLaunchKernelGGL((up_kernel<C, RT, 4>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
             else
                 hipLaunchKernelGGL((up_kernel<C, RT, 1>), grid, dim3(AT), smem, s, *(const UpArgs*)args);
