@@ -24,6 +24,18 @@ constexpr int AT = 256;   // threads per workgroup
 constexpr int AW = AT / 64;
 
 template <class C> __device__ inline C czero() { return cplx_traits<C>::zero(); }
+
+// Factor blocks are read through pointers loaded from tables; marking them
+// global lets the compiler issue global (not flat) loads and batch them.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class C> using gconst = __attribute__((address_space(1))) const C;
+#else
+template <class C> using gconst = const C;      // host pass: never executed
+#endif
+template <class C> __device__ __forceinline__ const gconst<C>* gptr(const C* p) { return (const gconst<C>*)p; }
+
+// loads per batch: 8 complex FP32 or 4 complex FP64 values per lane
+template <class C> constexpr int load_batch() { return sizeof(C) == 8 ? 8 : 4; }
 __device__ inline double2 ld_c(const double2* p) { return *p; }
 __device__ inline float2 ld_c(const float2* p) { return *p; }
 
@@ -112,13 +124,8 @@ __device__ void scatter_candidates(const C* s_w, const ApplyGeom& G, int s, long
 template <class C, int U>
 __device__ __forceinline__ void up_rows1(C (&acc)[4], const C* __restrict__ T, int k, int nred, const C* strip,
                                          int o0, int lane) {
-    constexpr int JB = sizeof(C) == 8 ? 8 : 4;
-#if defined(__HIP_DEVICE_COMPILE__)
-    using GC = __attribute__((address_space(1))) const C;     // factor blocks live in global memory
-#else
-    using GC = const C;                                        // (host pass: never executed)
-#endif
-    const GC* Tg = (const GC*)T;
+    constexpr int JB = load_batch<C>();
+    const gconst<C>* Tg = gptr(T);
     int orow[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) orow[u] = min(o0 + lane + 64 * u, k - 1);     // clamped: no divergence
@@ -258,13 +265,24 @@ __device__ __forceinline__ void down_body(const DownArgs& A, long long g, int ti
             const int ps = perm[i];
             s_w[ps * RT + r] = cadd(s_w[ps * RT + r], s_z[e]);
         }
+        const gconst<C>* Tg = gptr(T);
+        constexpr int IB = load_batch<C>();
         for (int j = tid; j < nred; j += AT) {
             C acc[RT];
 #pragma unroll
             for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
-#pragma unroll 4
-            for (int i = 0; i < k; ++i) {
-                const C tv = T[(long long)i * nred + j];
+            int i = 0;
+            for (; i + IB <= k; i += IB) {
+                C tv[IB];
+#pragma unroll
+                for (int q = 0; q < IB; ++q) tv[q] = Tg[(long long)(i + q) * nred + j];
+#pragma unroll
+                for (int q = 0; q < IB; ++q)
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) cfma(acc[r], tv[q], s_z[(i + q) * RT + r]);
+            }
+            for (; i < k; ++i) {
+                const C tv = Tg[(long long)i * nred + j];
 #pragma unroll
                 for (int r = 0; r < RT; ++r) cfma(acc[r], tv, s_z[i * RT + r]);
             }
@@ -312,6 +330,29 @@ __device__ inline long long piece_offset(const long long* off, const int* len, i
     return off[t] + (row - base);
 }
 
+// acc += S(row, c0 + c) x_c for c < cw (x staged in LDS from entry c0), in
+// order, with batches of loads issued before use.
+template <class C, int RT>
+__device__ __forceinline__ void middle_cols(C (&acc)[RT], const gconst<C>* Sg, int nr, int row, int c0, int cw,
+                                            const C* s_x) {
+    constexpr int CB = load_batch<C>();
+    int c = 0;
+    for (; c + CB <= cw; c += CB) {
+        C sv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) sv[q] = Sg[(long long)(c0 + c + q) * nr + row];
+#pragma unroll
+        for (int q = 0; q < CB; ++q)
+#pragma unroll
+            for (int r = 0; r < RT; ++r) cfma(acc[r], sv[q], s_x[(c + q) * RT + r]);
+    }
+    for (; c < cw; ++c) {
+        const C sv = Sg[(long long)(c0 + c) * nr + row];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) cfma(acc[r], sv, s_x[c * RT + r]);
+    }
+}
+
 template <class C, int RT>
 __device__ __forceinline__ void middle_body(const MidArgs& A, long long bi, int tile, unsigned char* smem_raw) {
     C* s_x = reinterpret_cast<C*>(smem_raw);
@@ -325,7 +366,7 @@ __device__ __forceinline__ void middle_body(const MidArgs& A, long long bi, int 
     const int* in_len = A.in_len + bi * A.pieces;
     const long long* out_off = A.out_off + bi * A.pieces;
     const int* out_len = A.out_len + bi * A.pieces;
-    const C* S = (const C*)A.S + A.off[bi];
+    const gconst<C>* Sg = gptr((const C*)A.S + A.off[bi]);
     if (nc <= A.chunk) {
         // the whole input vector fits in LDS: stage it once
         stage_pieces<C, RT>(s_x, xin, in_off, in_len, A.pieces, 0, nc, A.nrhs, r0, nrr);
@@ -334,12 +375,7 @@ __device__ __forceinline__ void middle_body(const MidArgs& A, long long bi, int 
             C acc[RT];
 #pragma unroll
             for (int r = 0; r < RT; ++r) acc[r] = czero<C>();
-#pragma unroll 4
-            for (int c = 0; c < nc; ++c) {
-                const C sv = S[(long long)c * nr + row];
-#pragma unroll
-                for (int r = 0; r < RT; ++r) cfma(acc[r], sv, s_x[c * RT + r]);
-            }
+            middle_cols<C, RT>(acc, Sg, nr, row, 0, nc, s_x);
             const long long off = piece_offset(out_off, out_len, A.pieces, row);
 #pragma unroll
             for (int r = 0; r < RT; ++r)
@@ -358,14 +394,7 @@ __device__ __forceinline__ void middle_body(const MidArgs& A, long long bi, int 
             __syncthreads();
             stage_pieces<C, RT>(s_x, xin, in_off, in_len, A.pieces, c0, cw, A.nrhs, r0, nrr);
             __syncthreads();
-            if (row < nr) {
-#pragma unroll 4
-                for (int c = 0; c < cw; ++c) {
-                    const C sv = S[(long long)(c0 + c) * nr + row];
-#pragma unroll
-                    for (int r = 0; r < RT; ++r) cfma(acc[r], sv, s_x[c * RT + r]);
-                }
-            }
+            if (row < nr) middle_cols<C, RT>(acc, Sg, nr, row, c0, cw, s_x);
         }
         if (row < nr) {
             const long long off = piece_offset(out_off, out_len, A.pieces, row);
