@@ -1,9 +1,9 @@
 // Many-right-hand-side apply on the matrix cores (FP32 in, FP32 accumulate).
 //
 // With 64 right-hand sides every factor block becomes a dense complex GEMM,
-// C (rows x 64) = A (rows x K) B (K x 64), computed as four real products
-// per complex product on v_mfma_f32_16x16x4f32:
-//     Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+// C (rows x 64) = A (rows x K) B (K x 64), computed as three real products
+// per complex product on v_mfma_f32_16x16x4f32 (Gauss's form):
+//     Cr = Ar Br - Ai Bi,   Ci = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi.
 // Lane l of a wave supplies A[l%16][l/16] and B[l/16][l%16] and receives
 // D[4(l/16)+v][l%16], v < 4 (checked on the device).  A (the factor) streams
 // from HBM exactly once per launch; B (the level vectors, gathered through
@@ -31,32 +31,43 @@ constexpr int MT = 256;          // threads per workgroup (up, down)
 constexpr int MW = MT / 64;      // waves
 constexpr int NRHS = MFMA_NRHS;  // columns per workgroup (4 tiles of 16)
 
-// One k-step of 4 for every (row tile, column tile) of a wave: the two
-// products of each accumulator are issued in separate sweeps so that
-// consecutive MFMAs never depend on each other.
+// One k-step of 4 for every (row tile, column tile) of a wave, with three real
+// products per complex product (Gauss): p1 += Ar Br, p2 += Ai Bi,
+// p3 += (Ar + Ai)(Br + Bi); then Cr = p1 - p2 and Ci = p3 - p1 - p2
+// (finish_gauss).  Each sweep issues independent MFMAs back to back.
 template <int MTW>
-__device__ inline void kstep(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const float2 (&a)[MTW],
-                             const float2 (&b)[4], int ntiles) {
+__device__ inline void kstep(floatx4 (&p1)[MTW][4], floatx4 (&p2)[MTW][4], floatx4 (&p3)[MTW][4],
+                             const float2 (&a)[MTW], const float2 (&b)[4], int ntiles) {
+    float as[MTW], bs[4];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) as[mt] = a[mt].x + a[mt].y;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bs[nt] = b[nt].x + b[nt].y;
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
         if (mt < ntiles) {
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                cr[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].x, cr[mt][nt], 0, 0, 0);
-                ci[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].y, ci[mt][nt], 0, 0, 0);
+                p1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].x, p1[mt][nt], 0, 0, 0);
+                p2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].y, b[nt].y, p2[mt][nt], 0, 0, 0);
+                p3[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[mt], bs[nt], p3[mt][nt], 0, 0, 0);
             }
         }
     }
+}
+
+template <int MTW>
+__device__ inline void finish_gauss(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const floatx4 (&p3)[MTW][4]) {
 #pragma unroll
-    for (int mt = 0; mt < MTW; ++mt) {
-        if (mt < ntiles) {
+    for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                cr[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[mt].y, b[nt].y, cr[mt][nt], 0, 0, 0);
-                ci[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].y, b[nt].x, ci[mt][nt], 0, 0, 0);
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float r = cr[mt][nt][v] - ci[mt][nt][v];
+                ci[mt][nt][v] = p3[mt][nt][v] - cr[mt][nt][v] - ci[mt][nt][v];
+                cr[mt][nt][v] = r;
             }
-        }
-    }
 }
 
 
@@ -85,6 +96,12 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
     const int ntl = base < M ? min(MTW, (M - base + 15) / 16) : 0;
     const int nch = (K + KC - 1) / KC;
     if (nch == 0) return;
+    // cr, ci enter as zero and collect Ar Br and Ai Bi; p3 the sum product
+    floatx4 p3[MTW][4];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) p3[mt][nt] = floatx4{0, 0, 0, 0};
     auto loadA1 = [&](int col, float2 (&dst)[MTW]) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
@@ -126,7 +143,7 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
                     float2 bv[4];
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) bv[nt] = sb[(ks * 4 + lk) * NRHS + nt * 16 + lr];
-                    kstep<MTW>(cr, ci, acur[ks], bv, ntl);
+                    kstep<MTW>(cr, ci, p3, acur[ks], bv, ntl);
                 }
             }
             if (more) {
@@ -138,6 +155,7 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
             }
             __syncthreads();
         }
+        finish_gauss<MTW>(cr, ci, p3);
     } else {
         for (int c = 0; c < nch; ++c) {
             loadB(c * KC);
@@ -156,11 +174,12 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
                     float2 bv[4];
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) bv[nt] = sB[(ks * 4 + lk) * NRHS + nt * 16 + lr];
-                    kstep<MTW>(cr, ci, a, bv, ntl);
+                    kstep<MTW>(cr, ci, p3, a, bv, ntl);
                 }
             }
         }
         __syncthreads();
+        finish_gauss<MTW>(cr, ci, p3);
     }
 }
 
