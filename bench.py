@@ -38,7 +38,7 @@ def log(*a):
 
 def kernel_sources(kernel: str) -> list[str]:
     """Source files that define a profiled kernel family."""
-    if "bf16x3" in kernel:
+    if "bf16x3" in kernel or "fp16x3" in kernel:
         return ["mfma_bf16.hip", "mfma.h"]
     if "mfma" in kernel:
         return ["mfma.hip", "mfma.h"]
@@ -74,15 +74,15 @@ def roofline(dominant: dict, prec: str, variant=None):
     t = dominant["total_ms"] / 1e3 / launches
     bytes_per = dominant["bytes"] / launches
     flops_per = dominant["flops"] / launches
-    if prec == "bf16x3":
-        peak_tf = PEAK["bf16_mfma_TF"]
+    if prec in ("bf16x3", "fp16x3"):
+        peak_tf = PEAK["bf16_mfma_TF"]      # dense bf16 and fp16 matrix peaks are equal
     elif prec == "fp64":
         peak_tf = PEAK["fp64_vector_TF"]
     else:
         peak_tf = PEAK["fp32_mfma_TF"] if "mfma" in dominant["name"] else PEAK["fp32_vector_TF"]
     ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
     if flops_per / max(bytes_per, 1.0) > ridge:
-        bound = "mfma" if ("mfma" in dominant["name"] or prec == "bf16x3") else "alu"
+        bound = "mfma" if ("mfma" in dominant["name"] or prec in ("bf16x3", "fp16x3")) else "alu"
         ach = flops_per / t / 1e12
         return {"bound": bound, "achieved": round(ach, 3), "peak": peak_tf, "unit": "TFLOP/s",
                 "frac": round(ach / peak_tf, 4), "traffic": traffic_for(dominant["name"], variant),
@@ -226,7 +226,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "fp16x3"])
     ap.add_argument("--workload", default="fio512x64")
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -259,7 +259,7 @@ def main() -> int:
 
     w = W.WORKLOADS[args.workload]
     nrhs = args.nrhs or w.nrhs
-    keep = 1 | 2 | 4
+    keep = 1 | 2 | {"fp16x3": 8}.get(args.precision, 4)
     log(f"[bench] building {w.name}: d={w.d} n={w.n} tol={w.tol} on {torch.cuda.get_device_name(0)}")
     recover = None
     if w.phase == "iso3d":
@@ -293,7 +293,7 @@ def main() -> int:
 
     variants = None
     tune_s = None
-    if (args.precision == "fp32" and nrhs >= 16) or args.precision == "bf16x3":
+    if (args.precision == "fp32" and nrhs >= 16) or args.precision in ("bf16x3", "fp16x3"):
         t0 = time.perf_counter()
         variants = F.tune(nrhs, args.precision)
         tune_s = time.perf_counter() - t0
@@ -354,7 +354,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[args.precision],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3", "fp16x3": "fp16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "d": w.d, "N": w.N, "nrhs": nrhs, "phase": w.phase, "tol": w.tol,
                    "leaf": f"{w.leaf_box}^{w.d}", "precision": args.precision},

@@ -17,7 +17,7 @@
  *     Applies are asynchronous on `stream`; build and phase_recover may
  *     synchronize it.
  *   - Complex vectors are interleaved (re, im): complex128 for MIDBF_FP64,
- *     complex64 for MIDBF_FP32 and MIDBF_SPLIT_BF16.  A block of nrhs vectors
+ *     complex64 for MIDBF_FP32, MIDBF_SPLIT_BF16 and MIDBF_SPLIT_FP16.  A block of nrhs vectors
  *     is column-major: element (point p, rhs r) at [r * ld + p], ld >= N.
  *   - No call throws; each returns a midbf_status and, on failure, leaves a
  *     message for midbf_last_error() (per thread).
@@ -63,14 +63,17 @@ typedef enum {
 typedef enum {
     MIDBF_FP64 = 0,          /* FP64 factors and arithmetic                              */
     MIDBF_FP32 = 1,          /* FP32 factors, FP32 accumulation                          */
-    MIDBF_SPLIT_BF16 = 2     /* factors and inputs split into bf16 hi + lo, three bf16
+    MIDBF_SPLIT_BF16 = 2,    /* factors and inputs split into bf16 hi + lo, three bf16
                                 products per real product, FP32 accumulation (MFMA)      */
+    MIDBF_SPLIT_FP16 = 3     /* the same with fp16 hi + lo: ~2^-22 per split value; vector
+                                and factor entries must stay below 65504 in magnitude    */
 } midbf_precision;
 
 /* Bits of midbf_params.precisions: which factor copies the build keeps. */
 #define MIDBF_KEEP_FP64 1u
 #define MIDBF_KEEP_FP32 2u
 #define MIDBF_KEEP_BF16 4u
+#define MIDBF_KEEP_FP16 8u
 
 typedef struct {
     int d;               /* 2 or 3                                                     */
@@ -83,7 +86,7 @@ typedef struct {
     const double* U_dev; /* MIDBF_PHASE_LOWRANK: N x r row-major FP64 (x side)          */
     const double* V_dev; /* MIDBF_PHASE_LOWRANK: N x r row-major FP64 (xi side)         */
     int r;               /* rank of U V^T                                               */
-    unsigned precisions; /* MIDBF_KEEP_* bits; 0 = all three                            */
+    unsigned precisions; /* MIDBF_KEEP_* bits; 0 = FP64, FP32 and split-bf16            */
     size_t build_workspace_bytes; /* cap on transient build memory; 0 = 16 GiB          */
 } midbf_params;
 
@@ -95,6 +98,7 @@ typedef struct {
     long long index_bytes;      /* permutation and offset tables read by an apply      */
     int k_min, k_max;           /* ranks over all IDs                                  */
     double build_seconds;       /* wall time of midbf_build                            */
+    long long bytes_fp16;       /* bytes of the split-fp16 factor copy                 */
 } midbf_stats;
 
 /*
@@ -291,8 +295,8 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
  * variants != NULL, writes the choice for the top step of up and down and
  * for the middle to variants[0..3).  midbf_set_variants installs one variant
  * per kind for every step.  Other precisions and
- * nrhs below the matrix-core threshold leave the choice unchanged.  FP32 and
- * MIDBF_SPLIT_BF16 keep separate choices.
+ * nrhs below the matrix-core threshold leave the choice unchanged.  FP32,
+ * MIDBF_SPLIT_BF16 and MIDBF_SPLIT_FP16 keep separate choices.
  */
 midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants);
 midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants);

@@ -17,8 +17,8 @@ STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_OOM", -4: "ERR_RANK_
           -5: "ERR_RECOVERY", -6: "ERR_HIP", -7: "ERR_UNIMPLEMENTED"}
 
 PHASES = {"linear": 0, "fio_ellipse": 1, "fio_piecewise": 2, "iso3d": 3, "lowrank": 4}
-FP64, FP32, SPLIT_BF16 = 0, 1, 2
-KEEP_FP64, KEEP_FP32, KEEP_BF16 = 1, 2, 4
+FP64, FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2, 3
+KEEP_FP64, KEEP_FP32, KEEP_BF16, KEEP_FP16 = 1, 2, 4, 8
 
 
 class Params(C.Structure):
@@ -32,7 +32,7 @@ class Stats(C.Structure):
     _fields_ = [("L", C.c_int), ("b", C.c_int), ("hstar", C.c_int), ("ids", C.c_longlong),
                 ("entries", C.c_longlong), ("bytes_fp64", C.c_longlong), ("bytes_fp32", C.c_longlong),
                 ("bytes_bf16", C.c_longlong), ("index_bytes", C.c_longlong), ("k_min", C.c_int),
-                ("k_max", C.c_int), ("build_seconds", C.c_double)]
+                ("k_max", C.c_int), ("build_seconds", C.c_double), ("bytes_fp16", C.c_longlong)]
 
 
 class KernelTime(C.Structure):

@@ -354,7 +354,7 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             double2* c64 = nullptr;
             float2* c32 = nullptr;
             if (h->keep & MIDBF_KEEP_FP64) { c64 = dalloc<double2>(tw); lv.chunks.push_back(c64); }
-            if (h->keep & (MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16)) { c32 = dalloc<float2>(tw); lv.chunks.push_back(c32); }
+            if (h->keep & MIDBF_KEEP_FP32) { c32 = dalloc<float2>(tw); lv.chunks.push_back(c32); }
             PackArgs pa{lv.side, id0, sc.k, lv.d_n + id0, sc.X, sc.xs, sc.perm, nmax, sc.cand, (int)nmax, sc.toff,
                         c64, c32, lv.d_perm_off, lv.d_y_off, lv.d_perm, lv.d_skel};
             hipLaunchKernelGGL(pack_kernel, dim3(cnt), dim3(BT), 0, st, pa);
@@ -367,23 +367,28 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             }
             if (lv.d_T[PREC_FP64]) upload((void**)lv.d_T[PREC_FP64] + id0, p64, st);
             if (lv.d_T[PREC_FP32]) upload((void**)lv.d_T[PREC_FP32] + id0, p32, st);
-            // split-bf16 fragment tiles: column side A = T (k x (n-k)), row side A = T^T
+            // split 16-bit fragment tiles: column side A = T (k x (n-k)), row side A = T^T
             std::vector<long long> tile_off(cnt);
             std::vector<void*> pbf(cnt);
-            if (lv.d_T[PREC_BF16]) {
+            if (lv.d_T[PREC_BF16] || lv.d_T[PREC_FP16]) {
                 long long tt = 0;
                 for (int w = 0; w < cnt; ++w) {
                     const int k = kw[w], nn = lv.n[id0 + w];
                     tile_off[w] = tt;
                     tt += lv.side == SIDE_COL ? bf16_tiles(k, nn - k) : bf16_tiles(nn - k, k);
                 }
-                char* cb = (char*)dalloc<char>((size_t)std::max<long long>(tt, 1) * BF16_TILE_BYTES);
-                lv.chunks.push_back(cb);
                 lv.bf16_bytes += tt * BF16_TILE_BYTES;
                 upload(sc.tile_off, tile_off, st);
-                pack_bf16_slab(sc.X, sc.xs, sc.k, lv.d_n + id0, cnt, lv.side == SIDE_ROW, cb, sc.tile_off, st);
-                for (int w = 0; w < cnt; ++w) pbf[w] = cb + tile_off[w] * BF16_TILE_BYTES;
-                upload((void**)lv.d_T[PREC_BF16] + id0, pbf, st);
+                for (int q : {PREC_BF16, PREC_FP16}) {
+                    if (!lv.d_T[q]) continue;
+                    char* cb = (char*)dalloc<char>((size_t)std::max<long long>(tt, 1) * BF16_TILE_BYTES);
+                    lv.chunks.push_back(cb);
+                    pack_bf16_slab(q == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, sc.X, sc.xs, sc.k, lv.d_n + id0, cnt,
+                                   lv.side == SIDE_ROW, cb, sc.tile_off, st);
+                    for (int w = 0; w < cnt; ++w) pbf[w] = cb + tile_off[w] * BF16_TILE_BYTES;
+                    upload((void**)lv.d_T[q] + id0, pbf, st);
+                    MIDBF_HIP(hipStreamSynchronize(st));      // pbf is reused by the next copy
+                }
             }
             MIDBF_HIP(hipStreamSynchronize(st));
         }
@@ -477,7 +482,7 @@ void build_middle(midbf_plan* h, hipStream_t st) {
     double2* S64 = nullptr;
     float2* S32 = nullptr;
     if (h->keep & MIDBF_KEEP_FP64) S64 = dalloc<double2>(tot);
-    if (h->keep & (MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16)) S32 = dalloc<float2>(tot);
+    if (h->keep & (MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) S32 = dalloc<float2>(tot);
     M.S[PREC_FP64] = S64;
     M.S[PREC_FP32] = S32;
     MidGenArgs ma{h->ph, M.d_nr, M.d_nc, M.d_off, d_pts_off, d_pts, S64, S32};
@@ -490,7 +495,7 @@ void build_middle(midbf_plan* h, hipStream_t st) {
         hipLaunchKernelGGL(midgen_kernel, dim3(gx, (unsigned)cnt), dim3(BT), 0, st, mb);
         MIDBF_HIP(hipGetLastError());
     }
-    if (h->keep & MIDBF_KEEP_BF16) {
+    if (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) {
         std::vector<long long> toff(M.nblk);
         long long tt = 0;
         for (long long bi = 0; bi < M.nblk; ++bi) {
@@ -499,10 +504,18 @@ void build_middle(midbf_plan* h, hipStream_t st) {
         }
         M.d_tile_off = dalloc<long long>(M.nblk);
         upload(M.d_tile_off, toff, st);
-        M.S[PREC_BF16] = dalloc<char>((size_t)std::max<long long>(tt, 1) * BF16_TILE_BYTES);
         M.bf16_bytes = tt * BF16_TILE_BYTES;
-        pack_bf16_blocks(S32, M.d_off, M.d_nr, M.d_nc, M.nblk, M.S[PREC_BF16], M.d_tile_off, st);
+        for (int q : {PREC_BF16, PREC_FP16}) {
+            if (!(h->keep & (1u << q))) continue;
+            M.S[q] = dalloc<char>((size_t)std::max<long long>(tt, 1) * BF16_TILE_BYTES);
+            pack_bf16_blocks(q == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, S32, M.d_off, M.d_nr, M.d_nc, M.nblk,
+                             M.S[q], M.d_tile_off, st);
+        }
         MIDBF_HIP(hipStreamSynchronize(st));
+        if (!(h->keep & MIDBF_KEEP_FP32)) {
+            (void)hipFree(S32);          // kept only as the source of the tiles
+            M.S[PREC_FP32] = nullptr;
+        }
     }
     MIDBF_HIP(hipStreamSynchronize(st));
     (void)hipFree(d_pts);
@@ -547,6 +560,8 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         h->p = p;
         if (h->p.build_workspace_bytes == 0) h->p.build_workspace_bytes = (size_t)16 << 30;
         h->keep = p.precisions ? p.precisions : (MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16);
+        MIDBF_CHECK((h->keep & ~(MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) == 0,
+                    MIDBF_ERR_ARG, "unknown precision bits");
         h->d = p.d; h->n = p.n; h->P = 1 << p.d; h->L = L; h->leaf = p.leaf_box;
         h->n0 = (int)ipow(p.leaf_box, p.d);
         h->N = ipow(p.n, p.d);
@@ -598,6 +613,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         for (auto* side : {&h->rows, &h->cols})
             for (auto& lv : *side) bfb += lv.bf16_bytes;
         S.bytes_bf16 = (h->keep & MIDBF_KEEP_BF16) ? bfb : 0;
+        S.bytes_fp16 = (h->keep & MIDBF_KEEP_FP16) ? bfb : 0;
         S.index_bytes = idx;
         S.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     } catch (...) {

@@ -40,6 +40,7 @@ int prec_index(midbf_precision p) {
         case MIDBF_FP64: return PREC_FP64;
         case MIDBF_FP32: return PREC_FP32;
         case MIDBF_SPLIT_BF16: return PREC_BF16;
+        case MIDBF_SPLIT_FP16: return PREC_FP16;
     }
     throw Error(MIDBF_ERR_ARG, "unknown precision");
 }
@@ -88,9 +89,10 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
         if (mfma_count > 0) {
             const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
             const int lv = std::max(0, std::min(level, midbf_plan::VMAXLEV - 1));
-            if (prec == PREC_BF16 && which != LevelKernel::DownSum)
-                launch_bf16_kernel(which, h->bf16_variant[kind][lv], args, mfma_count, nrhs, h->ws[prec].scratch,
-                                   h->mid.d_tile_off, st);
+            if (is_split16(prec) && which != LevelKernel::DownSum)
+                launch_bf16_kernel(prec == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, which,
+                                   (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[kind][lv], args,
+                                   mfma_count, nrhs, h->ws[prec].scratch, h->mid.d_tile_off, st);
             else
                 launch_mfma_kernel(which, h->mfma_variant[kind][lv], args, mfma_count, nrhs, h->ws[prec].scratch, st);
         }
@@ -102,8 +104,11 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
         return;
     }
     ProfRecord r;
-    const char* pname = prec == PREC_FP64 ? "_fp64" : (prec == PREC_BF16 ? "_bf16x3" : "_fp32");
-    r.name = std::string(kernel_name(which)) + (mfma_count > 0 && prec != PREC_BF16 ? "_mfma" : "") + pname +
+    const char* pname = prec == PREC_FP64   ? "_fp64"
+                        : prec == PREC_BF16 ? "_bf16x3"
+                        : prec == PREC_FP16 ? "_fp16x3"
+                                            : "_fp32";
+    r.name = std::string(kernel_name(which)) + (mfma_count > 0 && !is_split16(prec) ? "_mfma" : "") + pname +
              (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
     if (P.by_level && level >= 0) r.name += "_s" + std::to_string(level);
     r.a = take_event(P);
@@ -162,7 +167,7 @@ struct LaunchDesc {
 // limit of a direct launch).
 std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
                                    bool adjoint, bool mfma, void* const* buf, bool chunk_middle, int rt) {
-    const double fl = prec == PREC_BF16 ? 24.0 : 8.0;   // flops per complex entry and RHS (bf16x3: three products)
+    const double fl = is_split16(prec) ? 24.0 : 8.0;   // flops per complex entry and RHS (split-16: three products)
     const int tiles = (nrhs + rt - 1) / rt;
     const size_t cs = csize(prec);
     const ApplyGeom G{h->d, h->n, h->P, h->L, h->leaf, h->n0};
@@ -312,10 +317,10 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
     const bool fits = h->max_n <= MFMA_CROW_MAX && h->mid.nr_max + h->mid.nc_max <= 2 * MFMA_CROW_MAX;
     const bool fits_bf16 =
         h->max_n <= BF16_CROW_MAX && h->mid.nr_max <= BF16_CROW_MAX && h->mid.nc_max <= BF16_CROW_MAX;
-    MIDBF_CHECK(prec != PREC_BF16 || (!adjoint && fits_bf16), MIDBF_ERR_UNIMPLEMENTED,
-                "the split-bf16 apply exists for the forward transform with candidate sets up to 2048");
-    // matrix cores: split-bf16 always, FP32 for many right-hand sides
-    const bool mfma = prec == PREC_BF16 || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
+    MIDBF_CHECK(!is_split16(prec) || (!adjoint && fits_bf16), MIDBF_ERR_UNIMPLEMENTED,
+                "the split 16-bit applies exist for the forward transform with candidate sets up to 2048");
+    // matrix cores: split 16-bit always, FP32 for many right-hand sides
+    const bool mfma = is_split16(prec) || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
     ensure_workspace(h, prec, nrhs, mfma);
     const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     const auto launches = plan_apply(h, in_ext, out_ext, nrhs, ld, prec, adjoint, mfma, h->ws[prec].buf, true, rt);
@@ -554,8 +559,8 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
     return guarded([&] {
         const int pi = prec_index(prec);
         hipStream_t st = (hipStream_t)stream;
-        const bool bf = pi == PREC_BF16 && (h->keep & MIDBF_KEEP_BF16);
-        auto& var = bf ? h->bf16_variant : h->mfma_variant;
+        const bool bf = is_split16(pi) && (h->keep & (1u << pi));
+        auto& var = pi == PREC_FP16 ? h->fp16_variant : (pi == PREC_BF16 ? h->bf16_variant : h->mfma_variant);
         const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
         constexpr int NL = midbf_plan::VMAXLEV;
         if (bf || (pi == PREC_FP32 && nrhs >= MFMA_MIN_NRHS && (h->keep & MIDBF_KEEP_FP32))) {
@@ -627,13 +632,15 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
 
 midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants) {
     if (!h || !variants) return fail(MIDBF_ERR_ARG, "null argument");
-    const bool bf = prec == MIDBF_SPLIT_BF16;
-    if (!bf && prec != MIDBF_FP32) return fail(MIDBF_ERR_ARG, "variants exist for FP32 and split-bf16");
+    const bool bf = prec == MIDBF_SPLIT_BF16 || prec == MIDBF_SPLIT_FP16;
+    if (!bf && prec != MIDBF_FP32) return fail(MIDBF_ERR_ARG, "variants exist for FP32 and the split 16-bit applies");
     const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
     for (int q = 0; q < 3; ++q)
         if (variants[q] < 0 || variants[q] >= nvar) return fail(MIDBF_ERR_ARG, "unknown variant");
+    auto& var = prec == MIDBF_SPLIT_FP16 ? h->fp16_variant
+                                          : (prec == MIDBF_SPLIT_BF16 ? h->bf16_variant : h->mfma_variant);
     for (int q = 0; q < 3; ++q)
-        for (int l = 0; l < midbf_plan::VMAXLEV; ++l) (bf ? h->bf16_variant : h->mfma_variant)[q][l] = variants[q];
+        for (int l = 0; l < midbf_plan::VMAXLEV; ++l) var[q][l] = variants[q];
     return MIDBF_OK;
 }
 

@@ -20,21 +20,23 @@ constexpr int MFMA_VARIANTS = 10;     // tile variants (rows per wave, K chunk, 
 void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
                         hipStream_t s);
 
-// Split-bf16 variants of the up / down / middle kernels (factors stored as
-// MFMA fragment tiles; tile_off gives each middle block's first tile).
+// Split 16-bit variants of the up / down / middle kernels (factors stored as
+// MFMA fragment tiles; tile_off gives each middle block's first tile), for
+// elem = SPLIT16_BF16 or SPLIT16_FP16.
 constexpr int BF16_VARIANTS = 5;
-void launch_bf16_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
-                        const long long* tile_off, hipStream_t s);
+enum { SPLIT16_BF16 = 0, SPLIT16_FP16 = 1 };
+void launch_bf16_kernel(int elem, LevelKernel which, int variant, const void* args, long long count, int nrhs,
+                        void* scratch, const long long* tile_off, hipStream_t s);
 
 // Fragment tiles (16 x 32, 4 KB each) of an M x K block.
 long long bf16_tiles(int M, int K);
 constexpr long long BF16_TILE_BYTES = 4096;
 // Pack T of each decomposition of a build wave (FP64 slab) into tiles: the
 // column side stores A = T (k x (n-k)), the row side (transposed = true) A = T^T.
-void pack_bf16_slab(const double2* X, long long x_stride, const int* k_w, const int* n_w, int count, bool transposed,
-                    void* out, const long long* tile_off, hipStream_t s);
+void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k_w, const int* n_w, int count,
+                    bool transposed, void* out, const long long* tile_off, hipStream_t s);
 // Pack column-major FP32 middle blocks into tiles.
-void pack_bf16_blocks(const float2* S, const long long* s_off, const int* nr, const int* nc, long long count, void* out,
-                      const long long* tile_off, hipStream_t s);
+void pack_bf16_blocks(int elem, const float2* S, const long long* s_off, const int* nr, const int* nc,
+                      long long count, void* out, const long long* tile_off, hipStream_t s);
 
 }  // namespace midbf

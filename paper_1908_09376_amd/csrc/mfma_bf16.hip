@@ -1,10 +1,13 @@
-// Split-bf16 matrix-core apply (complex64 vectors, FP32 accumulation).
+// Split 16-bit matrix-core apply (complex64 vectors, FP32 accumulation), with
+// E = bf16 or fp16.
 //
-// Every factor entry and every vector entry x is split into two bf16 values,
-// hi = bf16(x) and lo = bf16(x - hi), and each real product uses three bf16
-// products hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 (lane l supplies
+// Every factor entry and every vector entry x is split into two 16-bit values,
+// hi = E(x) and lo = E(x - hi), and each real product uses three products
+// hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_{bf16,f16} (lane l supplies
 // A[l%16][8(l/16)+i] and B[8(l/16)+i][l%16], i < 8; checked on the device).
-// A complex product therefore costs 12 bf16 MFMAs:
+// bf16 keeps FP32's range with ~2^-16 relative error per split value; fp16
+// keeps ~2^-22 but needs |x| < 65504 (and loses digits below ~6e-5 in lo).
+// A complex product costs 12 MFMAs:
 //     Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br,  each real product split three ways.
 //
 // Factors are stored as MFMA fragments: a 16-row x 32-column tile of A is
@@ -23,31 +26,48 @@ namespace midbf {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx4 __attribute__((ext_vector_type(4)));
+
+// The two 16-bit element types of the split (bf16: 8-bit mantissa, wide
+// range; fp16: 11-bit mantissa, |x| < 65504) and their 8-wide MFMA operands.
+template <class E> struct Split16;
+template <> struct Split16<__bf16> {
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+};
+template <> struct Split16<_Float16> {
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+};
+template <class E> using V8 = typename Split16<E>::v8;
+
+__device__ inline floatx4 mfma16(V8<__bf16> a, V8<__bf16> b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline floatx4 mfma16(V8<_Float16> a, V8<_Float16> b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 
 constexpr int NRHS = MFMA_NRHS;
 constexpr int KT = 32;                       // K per tile / per chunk
 constexpr int CROW_MAX = BF16_CROW_MAX;
 
-struct Frag {
-    bf16x8 rh, ih, rl, il;
+template <class E> struct Frag {
+    V8<E> rh, ih, rl, il;
 };
 
-__device__ inline bf16x8 neg8(bf16x8 v) {
+template <class V> __device__ inline V neg8(V v) {     // sign flip of eight 16-bit values
     intx4 x = __builtin_bit_cast(intx4, v);
     x ^= (int)0x80008000;
-    return __builtin_bit_cast(bf16x8, x);
+    return __builtin_bit_cast(V, x);
 }
 
-template <int MTW>
-__device__ inline void kstep_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const Frag (&a)[MTW], const Frag (&b)[4],
-                                  int ntl) {
-#define MF(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0)
+template <class E, int MTW>
+__device__ inline void kstep_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const Frag<E> (&a)[MTW],
+                                  const Frag<E> (&b)[4], int ntl) {
+#define MF(acc, x, y) acc = mfma16(x, y, acc)
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
         if (mt >= ntl) continue;
-        const bf16x8 nih = neg8(a[mt].ih), nil = neg8(a[mt].il);
+        const V8<E> nih = neg8(a[mt].ih), nil = neg8(a[mt].il);
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             MF(cr[mt][nt], a[mt].rh, b[nt].rh);
@@ -83,14 +103,14 @@ __device__ inline void kstep_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], 
 }
 
 // The same twelve products for a single column tile nt.
-template <int MTW>
-__device__ inline void kstep1_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const Frag (&a)[MTW], const Frag& b,
-                                   int nt, int ntl) {
-#define MF(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0)
+template <class E, int MTW>
+__device__ inline void kstep1_bf16(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const Frag<E> (&a)[MTW],
+                                   const Frag<E>& b, int nt, int ntl) {
+#define MF(acc, x, y) acc = mfma16(x, y, acc)
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
         if (mt >= ntl) continue;
-        const bf16x8 nih = neg8(a[mt].ih), nil = neg8(a[mt].il);
+        const V8<E> nih = neg8(a[mt].ih), nil = neg8(a[mt].il);
         MF(cr[mt][nt], a[mt].rh, b.rh);
         MF(ci[mt][nt], a[mt].rh, b.ih);
         MF(cr[mt][nt], nih, b.ih);
@@ -123,10 +143,10 @@ struct BCfg {
 // them as four 16-byte pieces of one MFMA fragment; A fragments and B rows of
 // stage c+1 are in flight while stage c is multiplied; double-buffered LDS,
 // one barrier per stage.  Every thread of the workgroup must call this.
-template <class C, class SRow>
-__device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const Frag* __restrict__ Atiles,
+template <class C, class E, class SRow>
+__device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const Frag<E>* __restrict__ Atiles,
                                int M, int K, int base, const float2* __restrict__ src, long long ld, SRow srow,
-                               int nr, Frag* sB) {
+                               int nr, Frag<E>* sB) {
     constexpr int MTW = C::MTW, CT = C::CT;
     constexpr int KS = CT * KT;                     // K rows per stage
     const int tid = threadIdx.x, l = tid & 63;
@@ -139,7 +159,7 @@ __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4
     // 256 CT stage nothing)
     const bool stager = tid < 256 * CT;
     const int br = tid & 63, bj = (tid >> 6) * 8;
-    auto loadA = [&](int st, Frag (&dst)[CT][MTW]) {
+    auto loadA = [&](int st, Frag<E> (&dst)[CT][MTW]) {
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int kt = st * CT + c;
@@ -158,23 +178,23 @@ __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4
     };
     auto storeB = [&](int buf) {
         if (!stager) return;
-        bf16x8 rh, ih, rl, il;
+        V8<E> rh, ih, rl, il;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const __bf16 xh = (__bf16)bt[i].x, yh = (__bf16)bt[i].y;
+            const E xh = (E)bt[i].x, yh = (E)bt[i].y;
             rh[i] = xh;
             ih[i] = yh;
-            rl[i] = (__bf16)(bt[i].x - (float)xh);
-            il[i] = (__bf16)(bt[i].y - (float)yh);
+            rl[i] = (E)(bt[i].x - (float)xh);
+            il[i] = (E)(bt[i].y - (float)yh);
         }
         const int kt = bj / KT, kk = bj % KT;
-        Frag* f = sB + ((buf * CT + kt) * 4 + (br >> 4)) * 64 + (kk >> 3) * 16 + (br & 15);
+        Frag<E>* f = sB + ((buf * CT + kt) * 4 + (br >> 4)) * 64 + (kk >> 3) * 16 + (br & 15);
         f->rh = rh;
         f->ih = ih;
         f->rl = rl;
         f->il = il;
     };
-    Frag acur[CT][MTW], anext[CT][MTW];
+    Frag<E> acur[CT][MTW], anext[CT][MTW];
     loadA(0, acur);
     loadB(0);
     __syncthreads();
@@ -190,19 +210,19 @@ __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 if (st * CT + c < ktiles) {
-                    const Frag* sb = sB + ((st & 1) * CT + c) * 4 * 64;
+                    const Frag<E>* sb = sB + ((st & 1) * CT + c) * 4 * 64;
                     if constexpr (C::NT >= 1024) {
                         // one B fragment at a time (register budget of 16 waves)
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
-                            const Frag b = sb[nt * 64 + l];
-                            kstep1_bf16<MTW>(cr, ci, acur[c], b, nt, ntl);
+                            const Frag<E> b = sb[nt * 64 + l];
+                            kstep1_bf16<E, MTW>(cr, ci, acur[c], b, nt, ntl);
                         }
                     } else {
-                        Frag b[4];
+                        Frag<E> b[4];
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) b[nt] = sb[nt * 64 + l];
-                        kstep_bf16<MTW>(cr, ci, acur[c], b, ntl);
+                        kstep_bf16<E, MTW>(cr, ci, acur[c], b, ntl);
                     }
                 }
             }
@@ -256,12 +276,12 @@ __device__ inline long long xcd_group_order(long long b, long long nid, int P) {
     return ((q << 3) + x) * 4 + t;
 }
 
-template <class C>
+template <class C, class E>
 __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     constexpr int MTW = C::MTW;
     __shared__ int crow[CROW_MAX];
     __shared__ int srcrow[CROW_MAX];
-    __shared__ Frag sB[2 * C::CT * 4 * 64];
+    __shared__ Frag<E> sB[2 * C::CT * 4 * 64];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
@@ -273,7 +293,7 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     float2* out = (float2*)A.out;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
     const int* perm = A.lev.perm + A.lev.perm_off[id];
-    const Frag* Tt = (const Frag*)A.lev.T[id];
+    const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     __syncthreads();
@@ -286,7 +306,7 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C>(cr, ci, Tt, k, nred, base, xrows, A.nrhs, srow, nr, sB);
+        gemm_rows_bf16<C, E>(cr, ci, Tt, k, nred, base, xrows, A.nrhs, srow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -308,10 +328,10 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     }
 }
 
-template <class C>
+template <class C, class E>
 __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, float2* scr) {
     constexpr int MTW = C::MTW;
-    __shared__ Frag sB[2 * C::CT * 4 * 64];
+    __shared__ Frag<E> sB[2 * C::CT * 4 * 64];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -319,7 +339,7 @@ __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, fl
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
     const int* perm = A.lev.perm + A.lev.perm_off[id];
-    const Frag* Tt = (const Frag*)A.lev.T[id];
+    const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
     float2* w = scr + A.lev.perm_off[id] * A.nrhs;
     for (int e = tid; e < k * NRHS; e += C::NT) {
@@ -332,7 +352,7 @@ __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, fl
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C>(cr, ci, Tt, nred, k, base, z, A.nrhs, srow, nr, sB);
+        gemm_rows_bf16<C, E>(cr, ci, Tt, nred, k, base, z, A.nrhs, srow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -351,12 +371,12 @@ __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, fl
     }
 }
 
-template <class C>
+template <class C, class E>
 __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long* tile_off) {
     constexpr int MTW = C::MTW;
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
-    __shared__ Frag sB[2 * C::CT * 4 * 64];
+    __shared__ Frag<E> sB[2 * C::CT * 4 * 64];
     const long long bi = blockIdx.x;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -375,14 +395,14 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     }
     const float2* xin = (const float2*)A.in;
     float2* zout = (float2*)A.out;
-    const Frag* St = (const Frag*)A.S + tile_off[bi] * 64;
+    const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
     __syncthreads();
     auto srow = [&](int j) { return crow_in[j]; };
     for (int m0 = 0; m0 < M; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C>(cr, ci, St, M, K, base, xin + r0, A.nrhs, srow, nr, sB);
+        gemm_rows_bf16<C, E>(cr, ci, St, M, K, base, xin + r0, A.nrhs, srow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -407,20 +427,20 @@ using W2 = BCfg<2, 256, 1>;
 using W3 = BCfg<1, 1024, 1>;
 using W4 = BCfg<1, 1024, 2>;
 
-template <class C>
+template <class C, class E>
 void launch_bvariant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch,
                      const long long* tile_off, hipStream_t s) {
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
     switch (which) {
         case LevelKernel::Up:
-            hipLaunchKernelGGL(up_bf16<C>, grid, dim3(C::NT), 0, s, *(const UpArgs*)args, count);
+            hipLaunchKernelGGL((up_bf16<C, E>), grid, dim3(C::NT), 0, s, *(const UpArgs*)args, count);
             break;
         case LevelKernel::Down:
-            hipLaunchKernelGGL(down_bf16<C>, grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count,
+            hipLaunchKernelGGL((down_bf16<C, E>), grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count,
                                (float2*)scratch);
             break;
         case LevelKernel::Middle:
-            hipLaunchKernelGGL(middle_bf16<C>, grid, dim3(C::NT), 0, s, *(const MidArgs*)args, tile_off);
+            hipLaunchKernelGGL((middle_bf16<C, E>), grid, dim3(C::NT), 0, s, *(const MidArgs*)args, tile_off);
             break;
         default:
             throw Error(MIDBF_ERR_UNIMPLEMENTED, "no split-bf16 kernel for this level kind");
@@ -443,10 +463,11 @@ struct PackTilesArgs {
     const long long* s_off;   // mode 2: element offset per block
     const int* nr;
     const int* nc;
-    Frag* out;
+    void* out;
     const long long* tile_off;  // per block / ID: first tile
 };
 
+template <class E>
 __global__ void pack_tiles_kernel(PackTilesArgs P) {
     const int b = blockIdx.x;
     int M, K;
@@ -465,7 +486,7 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
         K = P.mode == 0 ? n - k : k;
     }
     const int mtiles = (M + 15) / 16, ktiles = (K + KT - 1) / KT;
-    Frag* out = P.out + P.tile_off[b] * 64;
+    Frag<E>* out = (Frag<E>*)P.out + P.tile_off[b] * 64;
     const long long nfr = (long long)mtiles * ktiles * 64;
     for (long long e = threadIdx.x; e < nfr; e += blockDim.x) {
         const int lane = (int)(e & 63);
@@ -473,7 +494,7 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
         const int mt = (int)(tile / ktiles), kt = (int)(tile - (long long)mt * ktiles);
         const int row = mt * 16 + (lane & 15);
         const int c0 = kt * KT + (lane >> 4) * 8;
-        Frag f;
+        Frag<E> f;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int col = c0 + i;
@@ -486,19 +507,19 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
                 } else {
                     const int ti = P.mode == 0 ? row : col, tj = P.mode == 0 ? col : row;
                     const double2 v = X[(long long)ti * n + k + tj];
-                    const float xh = (float)(__bf16)v.x, yh = (float)(__bf16)v.y;
-                    f.rh[i] = (__bf16)v.x;
-                    f.ih[i] = (__bf16)v.y;
-                    f.rl[i] = (__bf16)(v.x - (double)xh);
-                    f.il[i] = (__bf16)(v.y - (double)yh);
+                    const float xh = (float)(E)v.x, yh = (float)(E)v.y;
+                    f.rh[i] = (E)v.x;
+                    f.ih[i] = (E)v.y;
+                    f.rl[i] = (E)(v.x - (double)xh);
+                    f.il[i] = (E)(v.y - (double)yh);
                     continue;
                 }
             }
-            const __bf16 xh = (__bf16)x, yh = (__bf16)y;
+            const E xh = (E)x, yh = (E)y;
             f.rh[i] = xh;
             f.ih[i] = yh;
-            f.rl[i] = (__bf16)(x - (float)xh);
-            f.il[i] = (__bf16)(y - (float)yh);
+            f.rl[i] = (E)(x - (float)xh);
+            f.il[i] = (E)(y - (float)yh);
         }
         out[e] = f;
     }
@@ -506,36 +527,48 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
 
 }  // namespace
 
-void launch_bf16_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
-                        const long long* tile_off, hipStream_t s) {
+namespace {
+template <class E>
+void launch_split16(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
+                    const long long* tile_off, hipStream_t s) {
     switch (variant) {
-        case 0: launch_bvariant<W0>(which, args, count, nrhs, scratch, tile_off, s); break;
-        case 1: launch_bvariant<W1>(which, args, count, nrhs, scratch, tile_off, s); break;
-        case 2: launch_bvariant<W2>(which, args, count, nrhs, scratch, tile_off, s); break;
-        case 3: launch_bvariant<W3>(which, args, count, nrhs, scratch, tile_off, s); break;
-        case 4: launch_bvariant<W4>(which, args, count, nrhs, scratch, tile_off, s); break;
-        default: throw Error(MIDBF_ERR_ARG, "unknown split-bf16 variant");
+        case 0: launch_bvariant<W0, E>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 1: launch_bvariant<W1, E>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 2: launch_bvariant<W2, E>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 3: launch_bvariant<W3, E>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 4: launch_bvariant<W4, E>(which, args, count, nrhs, scratch, tile_off, s); break;
+        default: throw Error(MIDBF_ERR_ARG, "unknown split-16-bit variant");
     }
+}
+
+void launch_pack(const PackTilesArgs& P, int elem, unsigned count, hipStream_t s) {
+    if (elem == SPLIT16_FP16) hipLaunchKernelGGL(pack_tiles_kernel<_Float16>, dim3(count), dim3(256), 0, s, P);
+    else hipLaunchKernelGGL(pack_tiles_kernel<__bf16>, dim3(count), dim3(256), 0, s, P);
+    MIDBF_HIP(hipGetLastError());
+}
+}  // namespace
+
+void launch_bf16_kernel(int elem, LevelKernel which, int variant, const void* args, long long count, int nrhs,
+                        void* scratch, const long long* tile_off, hipStream_t s) {
+    if (elem == SPLIT16_FP16) launch_split16<_Float16>(which, variant, args, count, nrhs, scratch, tile_off, s);
+    else launch_split16<__bf16>(which, variant, args, count, nrhs, scratch, tile_off, s);
 }
 
 long long bf16_tiles(int M, int K) { return (long long)((M + 15) / 16) * ((K + KT - 1) / KT); }
 
-void pack_bf16_slab(const double2* X, long long x_stride, const int* k_w, const int* n_w, int count, bool transposed,
-                    void* out, const long long* tile_off, hipStream_t s) {
+void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k_w, const int* n_w, int count,
+                    bool transposed, void* out, const long long* tile_off, hipStream_t s) {
     if (count <= 0) return;
-    PackTilesArgs P{transposed ? 1 : 0, X, x_stride, k_w, n_w, nullptr, nullptr, nullptr, nullptr, (Frag*)out,
-                    tile_off};
-    hipLaunchKernelGGL(pack_tiles_kernel, dim3(count), dim3(256), 0, s, P);
-    MIDBF_HIP(hipGetLastError());
+    PackTilesArgs P{transposed ? 1 : 0, X, x_stride, k_w, n_w, nullptr, nullptr, nullptr, nullptr, out, tile_off};
+    launch_pack(P, elem, (unsigned)count, s);
 }
 
-void pack_bf16_blocks(const float2* S, const long long* s_off, const int* nr, const int* nc, long long count, void* out,
-                      const long long* tile_off, hipStream_t s) {
+void pack_bf16_blocks(int elem, const float2* S, const long long* s_off, const int* nr, const int* nc,
+                      long long count, void* out, const long long* tile_off, hipStream_t s) {
     for (long long b0 = 0; b0 < count; b0 += 65535) {
         const long long cnt = std::min<long long>(65535, count - b0);
-        PackTilesArgs P{2, nullptr, 0, nullptr, nullptr, S, s_off + b0, nr + b0, nc + b0, (Frag*)out, tile_off + b0};
-        hipLaunchKernelGGL(pack_tiles_kernel, dim3((unsigned)cnt), dim3(256), 0, s, P);
-        MIDBF_HIP(hipGetLastError());
+        PackTilesArgs P{2, nullptr, 0, nullptr, nullptr, S, s_off + b0, nr + b0, nc + b0, out, tile_off + b0};
+        launch_pack(P, elem, (unsigned)cnt, s);
     }
 }
 

@@ -11,7 +11,9 @@
 namespace midbf {
 
 enum { SIDE_ROW = 0, SIDE_COL = 1 };
-enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, NPREC = 3 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, PREC_FP16 = 3, NPREC = 4 };
+
+inline bool is_split16(int prec) { return prec == PREC_BF16 || prec == PREC_FP16; }
 
 // One unrolled MSCS step of one side (Sec. 3.5): decompositions of the
 // blocks (node at level la = L-s, partner at level lb = s+1), numbered
@@ -22,7 +24,7 @@ struct LevelSide {
     int m = 0;                            // samples per decomposition
     std::vector<int> k, n;                // rank and candidate count per ID
     std::vector<long long> perm_off, y_off;
-    long long total_k = 0, total_n = 0, entries = 0, bf16_bytes = 0;
+    long long total_k = 0, total_n = 0, entries = 0, bf16_bytes = 0;   // bf16_bytes: one split-16 tile copy
     int kmin = 0, kmax = 0, nmax = 0;
     // device copies
     int* d_k = nullptr;
@@ -31,7 +33,7 @@ struct LevelSide {
     long long* d_y_off = nullptr;
     int* d_perm = nullptr;                // candidate positions, skeleton first
     int* d_skel = nullptr;                // skeleton lattice point numbers at y_off
-    void** d_T[NPREC] = {nullptr, nullptr, nullptr};   // per-ID pointer to its T block
+    void** d_T[NPREC] = {};               // per-ID pointer to its T block
     std::vector<void*> chunks;            // device allocations owned by this level
 };
 
@@ -51,7 +53,7 @@ struct Middle {
     int* d_in_len = nullptr;
     long long* d_out_off = nullptr;
     int* d_out_len = nullptr;
-    void* S[NPREC] = {nullptr, nullptr, nullptr};       // column-major blocks at off (bf16: fragment tiles)
+    void* S[NPREC] = {};                                // column-major blocks at off (split-16: fragment tiles)
     long long* d_tile_off = nullptr;                    // first bf16 tile of each block
     long long bf16_bytes = 0;
 };
@@ -92,8 +94,9 @@ struct midbf_plan {
     long long max_total_k = 0, max_total_n = 0;
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
-    // matrix-core tile variant per kernel kind (up, down, middle) and MSCS step (FP32, split-bf16)
+    // matrix-core tile variant per kernel kind (up, down, middle) and MSCS step (FP32, split-bf16, split-fp16)
     static constexpr int VMAXLEV = 16;
     int mfma_variant[3][VMAXLEV] = {};
     int bf16_variant[3][VMAXLEV] = {};
+    int fp16_variant[3][VMAXLEV] = {};
 };

@@ -33,7 +33,7 @@ def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, pre
     return p
 
 
-_PREC = {"fp64": L.FP64, "fp32": L.FP32, "bf16x3": L.SPLIT_BF16}
+_PREC = {"fp64": L.FP64, "fp32": L.FP32, "bf16x3": L.SPLIT_BF16, "fp16x3": L.SPLIT_FP16}
 
 
 class MIDBF:

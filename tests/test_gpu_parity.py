@@ -261,3 +261,38 @@ def test_bf16x3_every_variant(variant):
     gb = from_dev(F.apply(to_dev(f, torch.complex64), precision="bf16x3"))
     assert rel_l2(gb, g64) < 1e-4
     assert F.tune(64, "bf16x3")[0] in range(5)
+
+
+# ---- split-fp16 matrix-core path ---------------------------------------------
+
+@pytest.mark.parametrize("n,nrhs", [(64, 64), (128, 20), (256, 64)])
+def test_fp16x3_apply(n, nrhs):
+    """fp16 hi + lo keeps ~2^-22 per split value: FP32-level error against the FP64 apply."""
+    F = _build(n, "fio_ellipse", precisions=1 | 2 | 8)
+    K = Kernel(2, n, "fio_ellipse")
+    f = W.complex_gaussian(K.N, nrhs, 47, n)
+    gh = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp16x3"))
+    g64 = from_dev(F.apply(to_dev(f)))
+    assert rel_l2(gh, g64) < 5e-6
+    rows = W.sample_rows(K.N, 0, 64)
+    assert rel_l2(gh[rows], direct_sum(K, f, rows=rows)) < 1e-5
+    assert F.stats()["bytes_fp16"] > 0
+
+
+@pytest.mark.parametrize("variant", range(5))
+def test_fp16x3_every_variant(variant):
+    F = _build(128, "fio_ellipse", precisions=1 | 8)
+    f = W.complex_gaussian(128 * 128, 64, 48)
+    g64 = from_dev(F.apply(to_dev(f)))
+    F.set_variants([variant] * 3, precision="fp16x3")
+    gh = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp16x3"))
+    assert rel_l2(gh, g64) < 5e-6
+    assert F.tune(64, "fp16x3")[0] in range(5)
+
+
+def test_split16_precisions_need_their_copy():
+    F = _build(64, "fio_ellipse", precisions=1 | 2)
+    from paper_1908_09376_amd._lib import MidbfError
+    f = to_dev(W.complex_gaussian(64 * 64, 16, 49), torch.complex64)
+    with pytest.raises(MidbfError, match="ERR_ARG"):
+        F.apply(f, precision="fp16x3")
