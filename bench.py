@@ -3,7 +3,9 @@
 
 Default workload: the 512^2 ellipse-phase transform (Example 1 shape on the
 integer frequency grid), 64 complex Gaussian right-hand sides in one launch
-sequence, FP32 apply.  A "step" is one full apply of the factor product to
+sequence, split-fp16 matrix-core apply (fp16 hi + lo, FP32 accumulation;
+its error against the FP64 direct sum is reported next to the result, with
+the FP32 and FP64 applies timed beside it).  A "step" is one full apply of the factor product to
 the 64 right-hand sides (every level kernel, the middle, both permutations);
 inputs are resident in HBM before timing starts.
 
@@ -226,7 +228,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "fp16x3"])
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "fp64", "bf16x3", "fp16x3"],
+                    help="auto: split-fp16 matrix cores for >= 16 right-hand sides on 2-D lattices, else FP32")
     ap.add_argument("--workload", default="fio512x64")
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -259,7 +262,9 @@ def main() -> int:
 
     w = W.WORKLOADS[args.workload]
     nrhs = args.nrhs or w.nrhs
-    keep = 1 | 2 | {"fp16x3": 8}.get(args.precision, 4)
+    if args.precision == "auto":
+        args.precision = "fp16x3" if (nrhs >= 16 and w.d == 2) else "fp32"
+    keep = 1 | 2 | {"fp16x3": 8, "bf16x3": 4}.get(args.precision, 0)
     log(f"[bench] building {w.name}: d={w.d} n={w.n} tol={w.tol} on {torch.cuda.get_device_name(0)}")
     recover = None
     if w.phase == "iso3d":
@@ -317,6 +322,24 @@ def main() -> int:
                for r in kt}
     g_np = g.to(torch.complex128).cpu().numpy().T
 
+    # the FP32 apply beside a split-16 result (matrix cores when nrhs >= 16)
+    fp32 = None
+    g32_np = None
+    if args.precision in ("bf16x3", "fp16x3"):
+        v32 = F.tune(nrhs, "fp32") if nrhs >= 16 else None
+        f32 = f.clone()
+        g32 = torch.empty_like(f32)
+        wall32, kt32 = time_applies(F, f32, g32, "fp32", args.steps, args.warmup, profile=True)
+        dom32 = max(kt32, key=lambda r: r["total_ms"])
+        dv32 = None
+        if v32 is not None:
+            dv32 = v32[2 if dom32["name"].startswith("middle") else (0 if dom32["name"].startswith("up") else 1)]
+        fp32 = {"value": round(nrhs * args.steps / wall32, 2), "ms_per_step": round(wall32 / args.steps * 1e3, 4),
+                "tuned_variants": v32, "roofline": roofline(dom32, "fp32", dv32)}
+        g32_np = g32.to(torch.complex128).cpu().numpy().T
+        del f32, g32
+        log(f"[bench] fp32 beside: {fp32['ms_per_step']:.3f} ms/step, {fp32['value']:.1f} RHS-applies/s")
+
     fp64 = None
     g64_np = None
     if not args.no_fp64 and args.precision != "fp64":
@@ -341,6 +364,8 @@ def main() -> int:
         per_rhs = np.linalg.norm(g_np[rows] - gd, axis=0) / np.linalg.norm(gd, axis=0)
         if fp64 is not None:
             fp64["rel_l2_err"] = float(np.linalg.norm((g64_np[rows] - gd).ravel()) / den)
+        if fp32 is not None:
+            fp32["rel_l2_err"] = float(np.linalg.norm((g32_np[rows] - gd).ravel()) / den)
         log(f"[bench] rel L2 error vs direct sum on {len(rows)} rows: {err:.3e} (max per RHS {per_rhs.max():.3e})")
 
     out = {
@@ -366,6 +391,7 @@ def main() -> int:
         "factor_entries": st["entries"],
         "ranks": [st["k_min"], st["k_max"]],
         "fp64_gpu": fp64,
+        "fp32_gpu": fp32,
         "phase_recovery": recover,
         "kernels": kernels,
         "roofline": roof,
