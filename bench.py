@@ -318,7 +318,8 @@ def main() -> int:
         kind = 2 if dominant["name"].startswith("middle") else (0 if dominant["name"].startswith("up") else 1)
         dom_variant = variants[kind]
     roof = roofline(dominant, args.precision, dom_variant)
-    kernels = {r["name"]: {"launches": r["launches"], "avg_ms": round(r["total_ms"] / r["launches"], 4)}
+    kernels = {r["name"]: {"launches": r["launches"], "avg_ms": round(r["total_ms"] / r["launches"], 4),
+                           "GB": round(r["bytes"] / r["launches"] / 1e9, 4)}
                for r in kt}
     g_np = g.to(torch.complex128).cpu().numpy().T
 
