@@ -50,6 +50,7 @@ struct DownArgs {
     const long long* yoff_prev;
     int nrhs;
     int ncand_max;
+    int kmax;                // largest rank of the level
 };
 
 struct MidArgs {

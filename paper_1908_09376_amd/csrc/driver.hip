@@ -271,6 +271,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.yoff_prev = s ? down[s - 1].d_y_off : nullptr;
         a.nrhs = nrhs;
         a.ncand_max = lv.nmax;
+        a.kmax = lv.kmax;
         const double vin = (double)lv.total_k * nrhs * cs;
         const double vout = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;

@@ -421,6 +421,94 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     }
 }
 
+// Going down with the whole z block resident in LDS (k <= 32 RES_KT): one
+// workgroup per decomposition stages z once, split into fragments; then each
+// wave streams the fragment tiles of A = T^T row tile by row tile, two tiles
+// ahead, with no barrier in the loop.  The down GEMMs are short in K (k) and
+// long in M (n - k), so the shared B never needs restaging.
+constexpr int RES_KT = 8;
+
+template <class E, int NT>
+__global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, float2* scr) {
+    constexpr int NW = NT / 64;
+    __shared__ Frag<E> sB[RES_KT * 4 * 64];
+    const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const float2* zin = (const float2*)A.in;
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+    const int* perm = A.lev.perm + A.lev.perm_off[id];
+    const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
+    const long long yo = A.lev.y_off[id];
+    float2* w = scr + A.lev.perm_off[id] * A.nrhs;
+    for (int e = tid; e < k * NRHS; e += NT) {
+        const int i = e / NRHS, r = e - i * NRHS;
+        if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
+    }
+    if (nred == 0) return;
+    const int ktiles = (k + KT - 1) / KT;           // <= RES_KT (checked at launch)
+    // z (k x 64) as fragments: one fragment = 8 K rows of one column, four planes
+    const float2* z = zin + yo * A.nrhs + r0;
+    for (int f = tid; f < ktiles * 256; f += NT) {
+        const int kt = f >> 8, rem = f & 255, kb = rem >> 6, col = rem & 63;
+        V8<E> rh, ih, rl, il;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = kt * KT + kb * 8 + i;
+            const float2 v = (j < k && col < nr) ? z[(long long)j * A.nrhs + col] : make_float2(0.f, 0.f);
+            const E xh = (E)v.x, yh = (E)v.y;
+            rh[i] = xh;
+            ih[i] = yh;
+            rl[i] = (E)(v.x - (float)xh);
+            il[i] = (E)(v.y - (float)yh);
+        }
+        Frag<E>* d = sB + (kt * 4 + (col >> 4)) * 64 + kb * 16 + (col & 15);
+        d->rh = rh;
+        d->ih = ih;
+        d->rl = rl;
+        d->il = il;
+    }
+    __syncthreads();
+    const int mtiles = (nred + 15) / 16;
+    const int mine = mtiles > wave ? (mtiles - wave + NW - 1) / NW : 0;   // row tiles of this wave
+    const int total = mine * ktiles;
+    auto tile_at = [&](int q) {
+        const int mt = wave + (q / ktiles) * NW, kt = q - (q / ktiles) * ktiles;
+        return Tt[((long long)mt * ktiles + kt) * 64 + l];
+    };
+    Frag<E> f0[1], f1, f2;
+    if (total > 0) f0[0] = tile_at(0);
+    if (total > 1) f1 = tile_at(1);
+    floatx4 cr[1][4], ci[1][4];
+    for (int q = 0; q < total; ++q) {
+        if (q + 2 < total) f2 = tile_at(q + 2);
+        const int kt = q - (q / ktiles) * ktiles;
+        if (kt == 0) zero_acc<1>(cr, ci);
+        Frag<E> b[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) b[nt] = sB[(kt * 4 + nt) * 64 + l];
+        kstep_bf16<E, 1>(cr, ci, f0, b, 1);
+        if (kt == ktiles - 1) {
+            const int base = (wave + (q / ktiles) * NW) * 16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + 4 * lk + v;
+                if (row < nred) {
+                    float2* d = w + (long long)perm[k + row] * A.nrhs + r0;
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) d[r] = make_float2(cr[0][nt][v], ci[0][nt][v]);
+                    }
+                }
+            }
+        }
+        f0[0] = f1;
+        f1 = f2;
+    }
+}
+
 using W0 = BCfg<1, 512, 2>;
 using W1 = BCfg<1, 256, 1>;
 using W2 = BCfg<2, 256, 1>;
@@ -537,6 +625,26 @@ void launch_split16(LevelKernel which, int variant, const void* args, long long 
         case 2: launch_bvariant<W2, E>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 3: launch_bvariant<W3, E>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 4: launch_bvariant<W4, E>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 5:
+        case 6: {
+            // down with z resident in LDS (variant 5: 512 threads, 6: 1024); other kinds, or ranks
+            // beyond the resident capacity, run W0 / W3
+            const bool res = which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT;
+            if (!res) {
+                if (variant == 5) launch_bvariant<W0, E>(which, args, count, nrhs, scratch, tile_off, s);
+                else launch_bvariant<W3, E>(which, args, count, nrhs, scratch, tile_off, s);
+                break;
+            }
+            const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
+            if (variant == 5)
+                hipLaunchKernelGGL((down_res16<E, 512>), grid, dim3(512), 0, s, *(const DownArgs*)args, count,
+                                   (float2*)scratch);
+            else
+                hipLaunchKernelGGL((down_res16<E, 1024>), grid, dim3(1024), 0, s, *(const DownArgs*)args, count,
+                                   (float2*)scratch);
+            MIDBF_HIP(hipGetLastError());
+            break;
+        }
         default: throw Error(MIDBF_ERR_ARG, "unknown split-16-bit variant");
     }
 }
