@@ -509,6 +509,194 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
     }
 }
 
+// Rows [base, base + 16) of C = A B for one wave (one row tile), over K in
+// stages of RCT K-tiles: B stages double-buffered in LDS (all threads split and
+// store them), A fragments streamed per wave two tiles ahead across stage
+// boundaries.  Every thread of the workgroup must call this.
+constexpr int RCT = 4;
+
+template <class E, int NT, class SRow>
+__device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
+                           int K, int base, const float2* __restrict__ src, long long ld, SRow srow, int nr,
+                           Frag<E>* sB) {
+    constexpr int FPT = RCT * 256 / NT;            // B fragments staged per thread and stage
+    static_assert(FPT >= 1 && FPT * NT == RCT * 256, "stage must split evenly over the threads");
+    const int tid = threadIdx.x, l = tid & 63;
+    const int ktiles = (K + KT - 1) / KT;
+    if (ktiles == 0) return;
+    const int nst = (ktiles + RCT - 1) / RCT;
+    const bool active = base < M;
+    const int mt = base / 16;
+    float2 bt[FPT][8];
+    auto loadB = [&](int st) {
+#pragma unroll
+        for (int q = 0; q < FPT; ++q) {
+            const int f = tid + q * NT, kt = f >> 8, kb = (f & 255) >> 6, col = f & 63;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int j = (st * RCT + kt) * KT + kb * 8 + i;
+                bt[q][i] = (j < K && col < nr) ? src[(long long)srow(j) * ld + col] : make_float2(0.f, 0.f);
+            }
+        }
+    };
+    auto storeB = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < FPT; ++q) {
+            const int f = tid + q * NT, kt = f >> 8, kb = (f & 255) >> 6, col = f & 63;
+            V8<E> rh, ih, rl, il;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const E xh = (E)bt[q][i].x, yh = (E)bt[q][i].y;
+                rh[i] = xh;
+                ih[i] = yh;
+                rl[i] = (E)(bt[q][i].x - (float)xh);
+                il[i] = (E)(bt[q][i].y - (float)yh);
+            }
+            Frag<E>* d = sB + ((buf * RCT + kt) * 4 + (col >> 4)) * 64 + kb * 16 + (col & 15);
+            d->rh = rh;
+            d->ih = ih;
+            d->rl = rl;
+            d->il = il;
+        }
+    };
+    auto tile_at = [&](int kt) { return Atiles[((long long)mt * ktiles + kt) * 64 + l]; };
+    Frag<E> f0[1], f1, f2;
+    if (active) {
+        f0[0] = tile_at(0);
+        if (ktiles > 1) f1 = tile_at(1);
+    }
+    loadB(0);
+    __syncthreads();          // the previous user of sB is done
+    storeB(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const bool more = st + 1 < nst;
+        if (more) loadB(st + 1);
+        const Frag<E>* sb = sB + (st & 1) * RCT * 4 * 64;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < RCT; ++c) {
+                const int kt = st * RCT + c;
+                if (kt < ktiles) {
+                    if (kt + 2 < ktiles) f2 = tile_at(kt + 2);
+                    if constexpr (NT >= 1024) {
+                        // one B fragment at a time (register budget of 16 waves)
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const Frag<E> b = sb[(c * 4 + nt) * 64 + l];
+                            kstep1_bf16<E, 1>(cr, ci, f0, b, nt, 1);
+                        }
+                    } else {
+                        Frag<E> b[4];
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) b[nt] = sb[(c * 4 + nt) * 64 + l];
+                        kstep_bf16<E, 1>(cr, ci, f0, b, 1);
+                    }
+                    f0[0] = f1;
+                    f1 = f2;
+                }
+            }
+        }
+        if (more) storeB((st + 1) & 1);
+        __syncthreads();
+    }
+}
+
+template <class E, int NT>
+__global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
+    constexpr int NW = NT / 64;
+    __shared__ int crow[CROW_MAX];
+    __shared__ int srcrow[CROW_MAX];
+    __shared__ Frag<E> sB[2 * RCT * 4 * 64];
+    const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
+    const long long g = id / A.G.P;
+    const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    candidate_rows<NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
+    const bool ext = A.s == 0;
+    const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
+    float2* out = (float2*)A.out;
+    const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+    const int* perm = A.lev.perm + A.lev.perm_off[id];
+    const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
+    const long long yo = A.lev.y_off[id];
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    __syncthreads();
+    for (int j = tid; j < nred; j += NT) srcrow[j] = crow[perm[k + j]];
+    __syncthreads();
+    const float2* xrows = ext ? xin : xin + r0;
+    auto srow = [&](int j) { return srcrow[j]; };
+    for (int m0 = 0; m0 < k; m0 += NW * 16) {
+        const int base = m0 + wave * 16;
+        floatx4 cr[1][4], ci[1][4];
+        zero_acc<1>(cr, ci);
+        gemm_res16<E, NT>(cr, ci, Tt, k, nred, base, xrows, A.nrhs, srow, nr, sB);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = base + 4 * lk + v;
+            if (row < k) {
+                const int src = crow[perm[row]];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int r = nt * 16 + lr;
+                    if (r < nr) {
+                        const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                        out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv.x, ci[0][nt][v] + sv.y);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <class E, int NT>
+__global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* tile_off) {
+    constexpr int NW = NT / 64;
+    __shared__ int crow_in[CROW_MAX];
+    __shared__ int crow_out[CROW_MAX];
+    __shared__ Frag<E> sB[2 * RCT * 4 * 64];
+    const long long bi = blockIdx.x;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const int M = A.nr[bi], K = A.nc[bi];
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    {
+        int s_in = 0, s_out = 0;
+        for (int t = 0; t < A.pieces; ++t) {
+            const long long oi = A.in_off[bi * A.pieces + t], oo = A.out_off[bi * A.pieces + t];
+            const int li = A.in_len[bi * A.pieces + t], lo = A.out_len[bi * A.pieces + t];
+            for (int c = tid; c < li; c += NT) crow_in[s_in + c] = (int)(oi + c);
+            for (int c = tid; c < lo; c += NT) crow_out[s_out + c] = (int)(oo + c);
+            s_in += li;
+            s_out += lo;
+        }
+    }
+    const float2* xin = (const float2*)A.in;
+    float2* zout = (float2*)A.out;
+    const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
+    __syncthreads();
+    auto srow = [&](int j) { return crow_in[j]; };
+    for (int m0 = 0; m0 < M; m0 += NW * 16) {
+        const int base = m0 + wave * 16;
+        floatx4 cr[1][4], ci[1][4];
+        zero_acc<1>(cr, ci);
+        gemm_res16<E, NT>(cr, ci, St, M, K, base, xin + r0, A.nrhs, srow, nr, sB);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = base + 4 * lk + v;
+            if (row < M) {
+                const long long dst = crow_out[row];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int r = nt * 16 + lr;
+                    if (r < nr) zout[dst * A.nrhs + r0 + r] = make_float2(cr[0][nt][v], ci[0][nt][v]);
+                }
+            }
+        }
+    }
+}
+
 using W0 = BCfg<1, 512, 2>;
 using W1 = BCfg<1, 256, 1>;
 using W2 = BCfg<2, 256, 1>;
@@ -625,6 +813,34 @@ void launch_split16(LevelKernel which, int variant, const void* args, long long 
         case 2: launch_bvariant<W2, E>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 3: launch_bvariant<W3, E>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 4: launch_bvariant<W4, E>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 7:
+        case 8: {
+            // up and middle with four-tile B stages and streamed A (7: 512 threads, 8: 1024); down resident
+            const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
+            const bool big = variant == 8;
+            if (which == LevelKernel::Up) {
+                if (big) hipLaunchKernelGGL((up_res16<E, 1024>), grid, dim3(1024), 0, s, *(const UpArgs*)args, count);
+                else hipLaunchKernelGGL((up_res16<E, 512>), grid, dim3(512), 0, s, *(const UpArgs*)args, count);
+            } else if (which == LevelKernel::Middle) {
+                if (big)
+                    hipLaunchKernelGGL((middle_res16<E, 1024>), grid, dim3(1024), 0, s, *(const MidArgs*)args,
+                                       tile_off);
+                else
+                    hipLaunchKernelGGL((middle_res16<E, 512>), grid, dim3(512), 0, s, *(const MidArgs*)args,
+                                       tile_off);
+            } else if (((const DownArgs*)args)->kmax <= RES_KT * KT) {
+                if (big)
+                    hipLaunchKernelGGL((down_res16<E, 1024>), grid, dim3(1024), 0, s, *(const DownArgs*)args,
+                                       count, (float2*)scratch);
+                else
+                    hipLaunchKernelGGL((down_res16<E, 512>), grid, dim3(512), 0, s, *(const DownArgs*)args,
+                                       count, (float2*)scratch);
+            } else {
+                launch_bvariant<W0, E>(which, args, count, nrhs, scratch, tile_off, s);
+            }
+            MIDBF_HIP(hipGetLastError());
+            break;
+        }
         case 5:
         case 6: {
             // down with z resident in LDS (variant 5: 512 threads, 6: 1024); other kinds, or ranks
