@@ -54,6 +54,41 @@ template <class E> struct Frag {
     V8<E> rh, ih, rl, il;
 };
 
+// One fragment tile staged in LDS, plane-major: the 64 lanes' 16-byte pieces
+// of each plane are contiguous, so a wave's ds_read_b128 / ds_write_b128 of
+// one plane touches consecutive banks (the lane-major Frag order would put
+// the lanes 64 bytes apart, a four-way bank conflict).
+template <class E> struct LFrag {
+    V8<E> rh[64], ih[64], rl[64], il[64];
+};
+
+template <class E> __device__ inline Frag<E> lds_frag(const LFrag<E>* t, int lane) {
+    Frag<E> f;
+    f.rh = t->rh[lane];
+    f.ih = t->ih[lane];
+    f.rl = t->rl[lane];
+    f.il = t->il[lane];
+    return f;
+}
+
+// Split eight complex values (one fragment lane: 8 K rows of one column) into
+// hi/lo planes and store them at lane `lane` of tile t.
+template <class E> __device__ inline void lds_split_store(LFrag<E>* t, int lane, const float2 (&v)[8]) {
+    V8<E> rh, ih, rl, il;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const E xh = (E)v[i].x, yh = (E)v[i].y;
+        rh[i] = xh;
+        ih[i] = yh;
+        rl[i] = (E)(v[i].x - (float)xh);
+        il[i] = (E)(v[i].y - (float)yh);
+    }
+    t->rh[lane] = rh;
+    t->ih[lane] = ih;
+    t->rl[lane] = rl;
+    t->il[lane] = il;
+}
+
 template <class V> __device__ inline V neg8(V v) {     // sign flip of eight 16-bit values
     intx4 x = __builtin_bit_cast(intx4, v);
     x ^= (int)0x80008000;
@@ -137,16 +172,16 @@ struct BCfg {
 };
 
 // Rows [base, base + 16 MTW) of C (+)= A B for one wave, where A's tiles of
-// row tile t start at Atiles + t * ktiles tiles.  B[j][r] = src[srow(j) * ld + r].
+// row tile t start at Atiles + t * ktiles tiles.  B[j][r] = src[boff(j, r)].
 // One stage = CT K tiles: every thread loads 8 consecutive K rows of one B
 // column (coalesced across the wave), splits them into hi/lo planes and writes
 // them as four 16-byte pieces of one MFMA fragment; A fragments and B rows of
 // stage c+1 are in flight while stage c is multiplied; double-buffered LDS,
 // one barrier per stage.  Every thread of the workgroup must call this.
-template <class C, class E, class SRow>
+template <class C, class E, class BOff>
 __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const Frag<E>* __restrict__ Atiles,
-                               int M, int K, int base, const float2* __restrict__ src, long long ld, SRow srow,
-                               int nr, Frag<E>* sB) {
+                               int M, int K, int base, const float2* __restrict__ src, BOff boff, int nr,
+                               LFrag<E>* sB) {
     constexpr int MTW = C::MTW, CT = C::CT;
     constexpr int KS = CT * KT;                     // K rows per stage
     const int tid = threadIdx.x, l = tid & 63;
@@ -173,26 +208,13 @@ __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int j = st * KS + bj + i;
-            bt[i] = (stager && j < K && br < nr) ? src[(long long)srow(j) * ld + br] : make_float2(0.f, 0.f);
+            bt[i] = (stager && j < K && br < nr) ? src[boff(j, br)] : make_float2(0.f, 0.f);
         }
     };
     auto storeB = [&](int buf) {
         if (!stager) return;
-        V8<E> rh, ih, rl, il;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const E xh = (E)bt[i].x, yh = (E)bt[i].y;
-            rh[i] = xh;
-            ih[i] = yh;
-            rl[i] = (E)(bt[i].x - (float)xh);
-            il[i] = (E)(bt[i].y - (float)yh);
-        }
         const int kt = bj / KT, kk = bj % KT;
-        Frag<E>* f = sB + ((buf * CT + kt) * 4 + (br >> 4)) * 64 + (kk >> 3) * 16 + (br & 15);
-        f->rh = rh;
-        f->ih = ih;
-        f->rl = rl;
-        f->il = il;
+        lds_split_store(sB + (buf * CT + kt) * 4 + (br >> 4), (kk >> 3) * 16 + (br & 15), bt);
     };
     Frag<E> acur[CT][MTW], anext[CT][MTW];
     loadA(0, acur);
@@ -210,18 +232,18 @@ __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 if (st * CT + c < ktiles) {
-                    const Frag<E>* sb = sB + ((st & 1) * CT + c) * 4 * 64;
+                    const LFrag<E>* sb = sB + ((st & 1) * CT + c) * 4;
                     if constexpr (C::NT >= 1024) {
                         // one B fragment at a time (register budget of 16 waves)
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
-                            const Frag<E> b = sb[nt * 64 + l];
+                            const Frag<E> b = lds_frag(sb + nt, l);
                             kstep1_bf16<E, MTW>(cr, ci, acur[c], b, nt, ntl);
                         }
                     } else {
                         Frag<E> b[4];
 #pragma unroll
-                        for (int nt = 0; nt < 4; ++nt) b[nt] = sb[nt * 64 + l];
+                        for (int nt = 0; nt < 4; ++nt) b[nt] = lds_frag(sb + nt, l);
                         kstep_bf16<E, MTW>(cr, ci, acur[c], b, ntl);
                     }
                 }
@@ -281,7 +303,7 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     constexpr int MTW = C::MTW;
     __shared__ int crow[CROW_MAX];
     __shared__ int srcrow[CROW_MAX];
-    __shared__ Frag<E> sB[2 * C::CT * 4 * 64];
+    __shared__ LFrag<E> sB[2 * C::CT * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
@@ -299,39 +321,44 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     __syncthreads();
     for (int j = tid; j < nred; j += C::NT) srcrow[j] = crow[perm[k + j]];
     __syncthreads();
-    // nred > 0 only above the leaves, where the input is a level buffer (row-major, nrhs wide)
-    const float2* xrows = ext ? xin : xin + r0;
-    auto srow = [&](int j) { return srcrow[j]; };
-    for (int m0 = 0; m0 < k; m0 += C::ROUND) {
-        const int base = m0 + wave * MTW * 16;
-        floatx4 cr[MTW][4], ci[MTW][4];
-        zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C, E>(cr, ci, Tt, k, nred, base, xrows, A.nrhs, srow, nr, sB);
+    auto run = [&](const float2* xb, auto boff) {
+        for (int m0 = 0; m0 < k; m0 += C::ROUND) {
+            const int base = m0 + wave * MTW * 16;
+            floatx4 cr[MTW][4], ci[MTW][4];
+            zero_acc<MTW>(cr, ci);
+            gemm_rows_bf16<C, E>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB);
 #pragma unroll
-        for (int mt = 0; mt < MTW; ++mt) {
+            for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = base + mt * 16 + 4 * lk + v;
-                if (row < k) {
-                    const int src = crow[perm[row]];
+                for (int v = 0; v < 4; ++v) {
+                    const int row = base + mt * 16 + 4 * lk + v;
+                    if (row < k) {
+                        const int src = crow[perm[row]];
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const int r = nt * 16 + lr;
-                        if (r < nr) {
-                            const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const int r = nt * 16 + lr;
+                            if (r < nr) {
+                                const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                                out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
+                            }
                         }
                     }
                 }
             }
         }
-    }
+    };
+    // B rows are input rows: at the leaves the caller's column-major input
+    // (ld apart per right-hand side), above them a level buffer (nrhs wide)
+    if (ext)
+        run(xin + (long long)r0 * A.ld, [&](int j, int c) { return (long long)c * A.ld + srcrow[j]; });
+    else
+        run(xin + r0, [&](int j, int c) { return (long long)srcrow[j] * A.nrhs + c; });
 }
 
 template <class C, class E>
 __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, float2* scr) {
     constexpr int MTW = C::MTW;
-    __shared__ Frag<E> sB[2 * C::CT * 4 * 64];
+    __shared__ LFrag<E> sB[2 * C::CT * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -347,12 +374,12 @@ __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, fl
         if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
     }
     const float2* z = zin + yo * A.nrhs + r0;
-    auto srow = [&](int i) { return i; };
+    auto boff = [&](int i, int c) { return (long long)i * A.nrhs + c; };
     for (int m0 = 0; m0 < nred; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C, E>(cr, ci, Tt, nred, k, base, z, A.nrhs, srow, nr, sB);
+        gemm_rows_bf16<C, E>(cr, ci, Tt, nred, k, base, z, boff, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -376,7 +403,7 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     constexpr int MTW = C::MTW;
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
-    __shared__ Frag<E> sB[2 * C::CT * 4 * 64];
+    __shared__ LFrag<E> sB[2 * C::CT * 4];
     const long long bi = blockIdx.x;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -397,12 +424,12 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     float2* zout = (float2*)A.out;
     const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
     __syncthreads();
-    auto srow = [&](int j) { return crow_in[j]; };
+    auto boff = [&](int j, int c) { return (long long)crow_in[j] * A.nrhs + c; };
     for (int m0 = 0; m0 < M; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C, E>(cr, ci, St, M, K, base, xin + r0, A.nrhs, srow, nr, sB);
+        gemm_rows_bf16<C, E>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -431,7 +458,7 @@ constexpr int RES_KT = 8;
 template <class E, int NT>
 __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, float2* scr) {
     constexpr int NW = NT / 64;
-    __shared__ Frag<E> sB[RES_KT * 4 * 64];
+    __shared__ LFrag<E> sB[RES_KT * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -452,22 +479,13 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
     const float2* z = zin + yo * A.nrhs + r0;
     for (int f = tid; f < ktiles * 256; f += NT) {
         const int kt = f >> 8, rem = f & 255, kb = rem >> 6, col = rem & 63;
-        V8<E> rh, ih, rl, il;
+        float2 v[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int j = kt * KT + kb * 8 + i;
-            const float2 v = (j < k && col < nr) ? z[(long long)j * A.nrhs + col] : make_float2(0.f, 0.f);
-            const E xh = (E)v.x, yh = (E)v.y;
-            rh[i] = xh;
-            ih[i] = yh;
-            rl[i] = (E)(v.x - (float)xh);
-            il[i] = (E)(v.y - (float)yh);
+            v[i] = (j < k && col < nr) ? z[(long long)j * A.nrhs + col] : make_float2(0.f, 0.f);
         }
-        Frag<E>* d = sB + (kt * 4 + (col >> 4)) * 64 + kb * 16 + (col & 15);
-        d->rh = rh;
-        d->ih = ih;
-        d->rl = rl;
-        d->il = il;
+        lds_split_store(sB + kt * 4 + (col >> 4), kb * 16 + (col & 15), v);
     }
     __syncthreads();
     const int mtiles = (nred + 15) / 16;
@@ -487,7 +505,7 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
         if (kt == 0) zero_acc<1>(cr, ci);
         Frag<E> b[4];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) b[nt] = sB[(kt * 4 + nt) * 64 + l];
+        for (int nt = 0; nt < 4; ++nt) b[nt] = lds_frag(sB + kt * 4 + nt, l);
         kstep_bf16<E, 1>(cr, ci, f0, b, 1);
         if (kt == ktiles - 1) {
             const int base = (wave + (q / ktiles) * NW) * 16;
@@ -515,10 +533,9 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
 // boundaries.  Every thread of the workgroup must call this.
 constexpr int RCT = 4;
 
-template <class E, int NT, class SRow>
+template <class E, int NT, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
-                           int K, int base, const float2* __restrict__ src, long long ld, SRow srow, int nr,
-                           Frag<E>* sB) {
+                           int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB) {
     constexpr int FPT = RCT * 256 / NT;            // B fragments staged per thread and stage
     static_assert(FPT >= 1 && FPT * NT == RCT * 256, "stage must split evenly over the threads");
     const int tid = threadIdx.x, l = tid & 63;
@@ -535,7 +552,7 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int j = (st * RCT + kt) * KT + kb * 8 + i;
-                bt[q][i] = (j < K && col < nr) ? src[(long long)srow(j) * ld + col] : make_float2(0.f, 0.f);
+                bt[q][i] = (j < K && col < nr) ? src[boff(j, col)] : make_float2(0.f, 0.f);
             }
         }
     };
@@ -543,20 +560,7 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
 #pragma unroll
         for (int q = 0; q < FPT; ++q) {
             const int f = tid + q * NT, kt = f >> 8, kb = (f & 255) >> 6, col = f & 63;
-            V8<E> rh, ih, rl, il;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const E xh = (E)bt[q][i].x, yh = (E)bt[q][i].y;
-                rh[i] = xh;
-                ih[i] = yh;
-                rl[i] = (E)(bt[q][i].x - (float)xh);
-                il[i] = (E)(bt[q][i].y - (float)yh);
-            }
-            Frag<E>* d = sB + ((buf * RCT + kt) * 4 + (col >> 4)) * 64 + kb * 16 + (col & 15);
-            d->rh = rh;
-            d->ih = ih;
-            d->rl = rl;
-            d->il = il;
+            lds_split_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q]);
         }
     };
     auto tile_at = [&](int kt) { return Atiles[((long long)mt * ktiles + kt) * 64 + l]; };
@@ -572,7 +576,7 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
     for (int st = 0; st < nst; ++st) {
         const bool more = st + 1 < nst;
         if (more) loadB(st + 1);
-        const Frag<E>* sb = sB + (st & 1) * RCT * 4 * 64;
+        const LFrag<E>* sb = sB + (st & 1) * RCT * 4;
         if (active) {
 #pragma unroll
             for (int c = 0; c < RCT; ++c) {
@@ -583,13 +587,13 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
                         // one B fragment at a time (register budget of 16 waves)
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
-                            const Frag<E> b = sb[(c * 4 + nt) * 64 + l];
+                            const Frag<E> b = lds_frag(sb + c * 4 + nt, l);
                             kstep1_bf16<E, 1>(cr, ci, f0, b, nt, 1);
                         }
                     } else {
                         Frag<E> b[4];
 #pragma unroll
-                        for (int nt = 0; nt < 4; ++nt) b[nt] = sb[(c * 4 + nt) * 64 + l];
+                        for (int nt = 0; nt < 4; ++nt) b[nt] = lds_frag(sb + c * 4 + nt, l);
                         kstep_bf16<E, 1>(cr, ci, f0, b, 1);
                     }
                     f0[0] = f1;
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     constexpr int NW = NT / 64;
     __shared__ int crow[CROW_MAX];
     __shared__ int srcrow[CROW_MAX];
-    __shared__ Frag<E> sB[2 * RCT * 4 * 64];
+    __shared__ LFrag<E> sB[2 * RCT * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
@@ -625,29 +629,35 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     __syncthreads();
     for (int j = tid; j < nred; j += NT) srcrow[j] = crow[perm[k + j]];
     __syncthreads();
-    const float2* xrows = ext ? xin : xin + r0;
-    auto srow = [&](int j) { return srcrow[j]; };
-    for (int m0 = 0; m0 < k; m0 += NW * 16) {
-        const int base = m0 + wave * 16;
-        floatx4 cr[1][4], ci[1][4];
-        zero_acc<1>(cr, ci);
-        gemm_res16<E, NT>(cr, ci, Tt, k, nred, base, xrows, A.nrhs, srow, nr, sB);
+    auto run = [&](const float2* xb, auto boff) {
+        for (int m0 = 0; m0 < k; m0 += NW * 16) {
+            const int base = m0 + wave * 16;
+            floatx4 cr[1][4], ci[1][4];
+            zero_acc<1>(cr, ci);
+            gemm_res16<E, NT>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = base + 4 * lk + v;
-            if (row < k) {
-                const int src = crow[perm[row]];
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + 4 * lk + v;
+                if (row < k) {
+                    const int src = crow[perm[row]];
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    const int r = nt * 16 + lr;
-                    if (r < nr) {
-                        const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                        out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv.x, ci[0][nt][v] + sv.y);
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        if (r < nr) {
+                            const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv.x, ci[0][nt][v] + sv.y);
+                        }
                     }
                 }
             }
         }
-    }
+    };
+    // B rows are input rows: at the leaves the caller's column-major input
+    // (ld apart per right-hand side), above them a level buffer (nrhs wide)
+    if (ext)
+        run(xin + (long long)r0 * A.ld, [&](int j, int c) { return (long long)c * A.ld + srcrow[j]; });
+    else
+        run(xin + r0, [&](int j, int c) { return (long long)srcrow[j] * A.nrhs + c; });
 }
 
 template <class E, int NT>
@@ -655,7 +665,7 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     constexpr int NW = NT / 64;
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
-    __shared__ Frag<E> sB[2 * RCT * 4 * 64];
+    __shared__ LFrag<E> sB[2 * RCT * 4];
     const long long bi = blockIdx.x;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -676,12 +686,12 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     float2* zout = (float2*)A.out;
     const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
     __syncthreads();
-    auto srow = [&](int j) { return crow_in[j]; };
+    auto boff = [&](int j, int c) { return (long long)crow_in[j] * A.nrhs + c; };
     for (int m0 = 0; m0 < M; m0 += NW * 16) {
         const int base = m0 + wave * 16;
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
-        gemm_res16<E, NT>(cr, ci, St, M, K, base, xin + r0, A.nrhs, srow, nr, sB);
+        gemm_res16<E, NT>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;

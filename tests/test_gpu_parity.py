@@ -296,3 +296,31 @@ def test_split16_precisions_need_their_copy():
     f = to_dev(W.complex_gaussian(64 * 64, 16, 49), torch.complex64)
     with pytest.raises(MidbfError, match="ERR_ARG"):
         F.apply(f, precision="fp16x3")
+
+
+# ---- rank-deficient leaves ---------------------------------------------------
+
+@pytest.mark.parametrize("precision,variant", [("fp32", None), ("bf16x3", 0), ("bf16x3", 8), ("fp16x3", 2),
+                                               ("fp16x3", 7)])
+def test_compressible_leaves_many_rhs(precision, variant):
+    """A slowly varying low-rank phase: the leaf column IDs keep few of their 64 columns, so the
+    first up step multiplies T by the redundant rows of the caller's column-major input (70
+    right-hand sides: a second, ragged block of 64)."""
+    M = _mod()
+    n = 64
+    N = n * n
+    U, V = W.random_lowrank_factors(N, 2, 61)
+    U, V = U * 0.1, V * 0.1
+    F = M.MIDBF(2, n, "lowrank", U=torch.from_numpy(U).to(DEV), V=torch.from_numpy(V).to(DEV),
+                precisions=1 | 2 | 4 | 8)
+    k0 = F.ranks(1, 0)
+    assert 0 < k0.max() < 64
+    if variant is not None:
+        F.set_variants([variant] * 3, precision=precision)
+    f = W.complex_gaussian(N, 70, 62)
+    g = from_dev(F.apply(to_dev(f, torch.complex64), precision=precision))
+    g64 = from_dev(F.apply(to_dev(f)))
+    assert rel_l2(g, g64) < (1e-4 if precision == "bf16x3" else 5e-6)
+    rows = W.sample_rows(N, 4, 64)
+    gd = direct_sum(Kernel(2, n, ("lowrank", U, V)), f, rows=rows)
+    assert rel_l2(g64[rows], gd) < 1e-5
