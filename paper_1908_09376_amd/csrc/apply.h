@@ -12,6 +12,24 @@ struct ApplyGeom {
     int d, n, P, L, leaf, n0;
 };
 
+constexpr int MAX_P = 8;        // P = 2^d children per node, d <= 3
+
+// Ranks and previous-level-buffer offsets of the P child pieces that make up
+// the candidate vector of group (a, partner) at step s >= 1.  The loads are
+// issued together, so the P round trips overlap.
+__device__ inline void child_pieces(int (&len)[MAX_P], long long (&off)[MAX_P], int P, long long a,
+                                    long long partner, long long Ps, const int* k_prev,
+                                    const long long* yoff_prev) {
+#pragma unroll
+    for (int t = 0; t < MAX_P; ++t) {
+        if (t < P) {
+            const long long idp = ((long long)P * a + t) * Ps + partner;
+            len[t] = k_prev[idp];
+            off[t] = yoff_prev[idp];
+        }
+    }
+}
+
 // Tables of one level (one step, one side) as seen by a kernel.
 struct LevelArgs {
     const int* k;
@@ -70,6 +88,34 @@ struct MidArgs {
     int chunk;               // VALU path: input entries staged in LDS per pass
     int mchunks;             // matrix-core FP32 path: workgroups splitting the rows of one block
 };
+
+// Input and output row numbers of middle block bi (the concatenations of its
+// pieces in the level buffers) written to LDS; pieces <= MAX_P, and the piece
+// tables are loaded together.
+template <int NT>
+__device__ inline void middle_rows(int* crow_in, int* crow_out, const MidArgs& A, long long bi) {
+    long long oi[MAX_P], oo[MAX_P];
+    int li[MAX_P], lo[MAX_P];
+#pragma unroll
+    for (int t = 0; t < MAX_P; ++t) {
+        if (t < A.pieces) {
+            oi[t] = A.in_off[bi * A.pieces + t];
+            oo[t] = A.out_off[bi * A.pieces + t];
+            li[t] = A.in_len[bi * A.pieces + t];
+            lo[t] = A.out_len[bi * A.pieces + t];
+        }
+    }
+    int s_in = 0, s_out = 0;
+#pragma unroll
+    for (int t = 0; t < MAX_P; ++t) {
+        if (t < A.pieces) {
+            for (int c = threadIdx.x; c < li[t]; c += NT) crow_in[s_in + c] = (int)(oi[t] + c);
+            for (int c = threadIdx.x; c < lo[t]; c += NT) crow_out[s_out + c] = (int)(oo[t] + c);
+            s_in += li[t];
+            s_out += lo[t];
+        }
+    }
+}
 
 enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum };
 

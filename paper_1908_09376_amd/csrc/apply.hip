@@ -70,16 +70,19 @@ __device__ int gather_candidates(C* s_x, const ApplyGeom& G, int s, long long a,
         }
         return G.n0;
     }
+    int len[MAX_P];
+    long long off[MAX_P];
+    child_pieces(len, off, G.P, a, partner, Ps, k_prev, yoff_prev);
     int start = 0;
-    for (int t = 0; t < G.P; ++t) {
-        const long long idp = ((long long)G.P * a + t) * Ps + partner;
-        const int len = k_prev[idp];
-        const long long off = yoff_prev[idp];
-        for (int e = tid; e < len * RT; e += AT) {
-            const int c = e / RT, r = e - c * RT;
-            s_x[(start + c) * RT + r] = (r < nr) ? prev_buf[(off + c) * nrhs + r0 + r] : czero<C>();
+#pragma unroll
+    for (int t = 0; t < MAX_P; ++t) {
+        if (t < G.P) {
+            for (int e = tid; e < len[t] * RT; e += AT) {
+                const int c = e / RT, r = e - c * RT;
+                s_x[(start + c) * RT + r] = (r < nr) ? prev_buf[(off[t] + c) * nrhs + r0 + r] : czero<C>();
+            }
+            start += len[t];
         }
-        start += len;
     }
     return start;
 }
@@ -100,16 +103,19 @@ __device__ void scatter_candidates(const C* s_w, const ApplyGeom& G, int s, long
         }
         return;
     }
+    int len[MAX_P];
+    long long off[MAX_P];
+    child_pieces(len, off, G.P, a, partner, Ps, k_prev, yoff_prev);
     int start = 0;
-    for (int t = 0; t < G.P; ++t) {
-        const long long idp = ((long long)G.P * a + t) * Ps + partner;
-        const int len = k_prev[idp];
-        const long long off = yoff_prev[idp];
-        for (int e = tid; e < len * RT; e += AT) {
-            const int c = e / RT, r = e - c * RT;
-            if (r < nr) prev_buf[(off + c) * nrhs + r0 + r] = s_w[(start + c) * RT + r];
+#pragma unroll
+    for (int t = 0; t < MAX_P; ++t) {
+        if (t < G.P) {
+            for (int e = tid; e < len[t] * RT; e += AT) {
+                const int c = e / RT, r = e - c * RT;
+                if (r < nr) prev_buf[(off[t] + c) * nrhs + r0 + r] = s_w[(start + c) * RT + r];
+            }
+            start += len[t];
         }
-        start += len;
     }
 }
 

@@ -23,7 +23,7 @@ void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long l
 // Split 16-bit variants of the up / down / middle kernels (factors stored as
 // MFMA fragment tiles; tile_off gives each middle block's first tile), for
 // elem = SPLIT16_BF16 or SPLIT16_FP16.
-constexpr int BF16_VARIANTS = 9;
+constexpr int BF16_VARIANTS = 10;
 enum { SPLIT16_BF16 = 0, SPLIT16_FP16 = 1 };
 void launch_bf16_kernel(int elem, LevelKernel which, int variant, const void* args, long long count, int nrhs,
                         void* scratch, const long long* tile_off, hipStream_t s);

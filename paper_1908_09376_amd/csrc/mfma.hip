@@ -202,13 +202,16 @@ __device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a,
         for (int c = threadIdx.x; c < G.n0; c += NT) crow[c] = (int)box_point(origin, G.leaf, c, G.d, G.n);
         return G.n0;
     }
+    int len[MAX_P];
+    long long off[MAX_P];
+    child_pieces(len, off, G.P, a, partner, Ps, k_prev, yoff_prev);
     int start = 0;
-    for (int t = 0; t < G.P; ++t) {
-        const long long idp = ((long long)G.P * a + t) * Ps + partner;
-        const int len = k_prev[idp];
-        const long long off = yoff_prev[idp];
-        for (int c = threadIdx.x; c < len; c += NT) crow[start + c] = (int)(off + c);
-        start += len;
+#pragma unroll
+    for (int t = 0; t < MAX_P; ++t) {
+        if (t < G.P) {
+            for (int c = threadIdx.x; c < len[t]; c += NT) crow[start + c] = (int)(off[t] + c);
+            start += len[t];
+        }
     }
     return start;
 }
@@ -383,17 +386,7 @@ __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     const int nr = min(NRHS, A.nrhs - r0);
     const int M = A.nr[bi], K = A.nc[bi];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
-    {
-        int s_in = 0, s_out = 0;
-        for (int t = 0; t < A.pieces; ++t) {
-            const long long oi = A.in_off[bi * A.pieces + t], oo = A.out_off[bi * A.pieces + t];
-            const int li = A.in_len[bi * A.pieces + t], lo = A.out_len[bi * A.pieces + t];
-            for (int c = tid; c < li; c += C::NT) crow_in[s_in + c] = (int)(oi + c);
-            for (int c = tid; c < lo; c += C::NT) crow_out[s_out + c] = (int)(oo + c);
-            s_in += li;
-            s_out += lo;
-        }
-    }
+    middle_rows<C::NT>(crow_in, crow_out, A, bi);
     const float2* xin = (const float2*)A.in;
     float2* zout = (float2*)A.out;
     const float2* S = (const float2*)A.S + A.off[bi];

@@ -277,13 +277,16 @@ __device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a,
         for (int c = threadIdx.x; c < G.n0; c += NT) crow[c] = (int)box_point(origin, G.leaf, c, G.d, G.n);
         return G.n0;
     }
+    int len[MAX_P];
+    long long off[MAX_P];
+    child_pieces(len, off, G.P, a, partner, Ps, k_prev, yoff_prev);
     int start = 0;
-    for (int t = 0; t < G.P; ++t) {
-        const long long idp = ((long long)G.P * a + t) * Ps + partner;
-        const int len = k_prev[idp];
-        const long long off = yoff_prev[idp];
-        for (int c = threadIdx.x; c < len; c += NT) crow[start + c] = (int)(off + c);
-        start += len;
+#pragma unroll
+    for (int t = 0; t < MAX_P; ++t) {
+        if (t < G.P) {
+            for (int c = threadIdx.x; c < len[t]; c += NT) crow[start + c] = (int)(off[t] + c);
+            start += len[t];
+        }
     }
     return start;
 }
@@ -409,17 +412,7 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
     const int nr = min(NRHS, A.nrhs - r0);
     const int M = A.nr[bi], K = A.nc[bi];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
-    {
-        int s_in = 0, s_out = 0;
-        for (int t = 0; t < A.pieces; ++t) {
-            const long long oi = A.in_off[bi * A.pieces + t], oo = A.out_off[bi * A.pieces + t];
-            const int li = A.in_len[bi * A.pieces + t], lo = A.out_len[bi * A.pieces + t];
-            for (int c = tid; c < li; c += C::NT) crow_in[s_in + c] = (int)(oi + c);
-            for (int c = tid; c < lo; c += C::NT) crow_out[s_out + c] = (int)(oo + c);
-            s_in += li;
-            s_out += lo;
-        }
-    }
+    middle_rows<C::NT>(crow_in, crow_out, A, bi);
     const float2* xin = (const float2*)A.in;
     float2* zout = (float2*)A.out;
     const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
@@ -530,12 +523,14 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
 // Rows [base, base + 16) of C = A B for one wave (one row tile), over K in
 // stages of RCT K-tiles: B stages double-buffered in LDS (all threads split and
 // store them), A fragments streamed per wave two tiles ahead across stage
-// boundaries.  Every thread of the workgroup must call this.
-constexpr int RCT = 4;
+// boundaries.  Every thread of the workgroup must call this.  RCT * 256
+// fragment lanes per stage split evenly over NT threads.
+template <int NT> constexpr int rct_for() { return NT == 768 ? 3 : 4; }
 
 template <class E, int NT, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
                            int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB) {
+    constexpr int RCT = rct_for<NT>();
     constexpr int FPT = RCT * 256 / NT;            // B fragments staged per thread and stage
     static_assert(FPT >= 1 && FPT * NT == RCT * 256, "stage must split evenly over the threads");
     const int tid = threadIdx.x, l = tid & 63;
@@ -583,8 +578,8 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
                 const int kt = st * RCT + c;
                 if (kt < ktiles) {
                     if (kt + 2 < ktiles) f2 = tile_at(kt + 2);
-                    if constexpr (NT >= 1024) {
-                        // one B fragment at a time (register budget of 16 waves)
+                    if constexpr (NT >= 768) {
+                        // one B fragment at a time (register budget of 12 or 16 waves)
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
                             const Frag<E> b = lds_frag(sb + c * 4 + nt, l);
@@ -611,7 +606,7 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     constexpr int NW = NT / 64;
     __shared__ int crow[CROW_MAX];
     __shared__ int srcrow[CROW_MAX];
-    __shared__ LFrag<E> sB[2 * RCT * 4];
+    __shared__ LFrag<E> sB[2 * rct_for<NT>() * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
@@ -665,23 +660,13 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     constexpr int NW = NT / 64;
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
-    __shared__ LFrag<E> sB[2 * RCT * 4];
+    __shared__ LFrag<E> sB[2 * rct_for<NT>() * 4];
     const long long bi = blockIdx.x;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     const int M = A.nr[bi], K = A.nc[bi];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
-    {
-        int s_in = 0, s_out = 0;
-        for (int t = 0; t < A.pieces; ++t) {
-            const long long oi = A.in_off[bi * A.pieces + t], oo = A.out_off[bi * A.pieces + t];
-            const int li = A.in_len[bi * A.pieces + t], lo = A.out_len[bi * A.pieces + t];
-            for (int c = tid; c < li; c += NT) crow_in[s_in + c] = (int)(oi + c);
-            for (int c = tid; c < lo; c += NT) crow_out[s_out + c] = (int)(oo + c);
-            s_in += li;
-            s_out += lo;
-        }
-    }
+    middle_rows<NT>(crow_in, crow_out, A, bi);
     const float2* xin = (const float2*)A.in;
     float2* zout = (float2*)A.out;
     const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
@@ -814,6 +799,24 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
 }  // namespace
 
 namespace {
+// Up and middle with multi-tile B stages and streamed A; down with z resident
+// (ranks beyond the resident capacity run W0).  NT = 512, 768 or 1024 threads.
+template <class E, int NT>
+void launch_res16(LevelKernel which, const void* args, long long count, int nrhs, void* scratch,
+                  const long long* tile_off, hipStream_t s) {
+    const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
+    if (which == LevelKernel::Up)
+        hipLaunchKernelGGL((up_res16<E, NT>), grid, dim3(NT), 0, s, *(const UpArgs*)args, count);
+    else if (which == LevelKernel::Middle)
+        hipLaunchKernelGGL((middle_res16<E, NT>), grid, dim3(NT), 0, s, *(const MidArgs*)args, tile_off);
+    else if (which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT)
+        hipLaunchKernelGGL((down_res16<E, NT>), grid, dim3(NT), 0, s, *(const DownArgs*)args, count,
+                           (float2*)scratch);
+    else
+        launch_bvariant<W0, E>(which, args, count, nrhs, scratch, tile_off, s);
+    MIDBF_HIP(hipGetLastError());
+}
+
 template <class E>
 void launch_split16(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
                     const long long* tile_off, hipStream_t s) {
@@ -823,34 +826,9 @@ void launch_split16(LevelKernel which, int variant, const void* args, long long 
         case 2: launch_bvariant<W2, E>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 3: launch_bvariant<W3, E>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 4: launch_bvariant<W4, E>(which, args, count, nrhs, scratch, tile_off, s); break;
-        case 7:
-        case 8: {
-            // up and middle with four-tile B stages and streamed A (7: 512 threads, 8: 1024); down resident
-            const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
-            const bool big = variant == 8;
-            if (which == LevelKernel::Up) {
-                if (big) hipLaunchKernelGGL((up_res16<E, 1024>), grid, dim3(1024), 0, s, *(const UpArgs*)args, count);
-                else hipLaunchKernelGGL((up_res16<E, 512>), grid, dim3(512), 0, s, *(const UpArgs*)args, count);
-            } else if (which == LevelKernel::Middle) {
-                if (big)
-                    hipLaunchKernelGGL((middle_res16<E, 1024>), grid, dim3(1024), 0, s, *(const MidArgs*)args,
-                                       tile_off);
-                else
-                    hipLaunchKernelGGL((middle_res16<E, 512>), grid, dim3(512), 0, s, *(const MidArgs*)args,
-                                       tile_off);
-            } else if (((const DownArgs*)args)->kmax <= RES_KT * KT) {
-                if (big)
-                    hipLaunchKernelGGL((down_res16<E, 1024>), grid, dim3(1024), 0, s, *(const DownArgs*)args,
-                                       count, (float2*)scratch);
-                else
-                    hipLaunchKernelGGL((down_res16<E, 512>), grid, dim3(512), 0, s, *(const DownArgs*)args,
-                                       count, (float2*)scratch);
-            } else {
-                launch_bvariant<W0, E>(which, args, count, nrhs, scratch, tile_off, s);
-            }
-            MIDBF_HIP(hipGetLastError());
-            break;
-        }
+        case 7: launch_res16<E, 512>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 8: launch_res16<E, 1024>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 9: launch_res16<E, 768>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 5:
         case 6: {
             // down with z resident in LDS (variant 5: 512 threads, 6: 1024); other kinds, or ranks

@@ -252,7 +252,7 @@ def test_bf16x3_apply(n, nrhs):
     assert rel_l2(gb[rows], direct_sum(K, f, rows=rows)) < 1e-3
 
 
-@pytest.mark.parametrize("variant", range(9))
+@pytest.mark.parametrize("variant", range(10))
 def test_bf16x3_every_variant(variant):
     F = _build(128, "fio_ellipse")
     f = W.complex_gaussian(128 * 128, 64, 46)
@@ -260,7 +260,7 @@ def test_bf16x3_every_variant(variant):
     F.set_variants([variant] * 3, precision="bf16x3")
     gb = from_dev(F.apply(to_dev(f, torch.complex64), precision="bf16x3"))
     assert rel_l2(gb, g64) < 1e-4
-    assert F.tune(64, "bf16x3")[0] in range(9)
+    assert F.tune(64, "bf16x3")[0] in range(10)
 
 
 # ---- split-fp16 matrix-core path ---------------------------------------------
@@ -279,7 +279,7 @@ def test_fp16x3_apply(n, nrhs):
     assert F.stats()["bytes_fp16"] > 0
 
 
-@pytest.mark.parametrize("variant", range(9))
+@pytest.mark.parametrize("variant", range(10))
 def test_fp16x3_every_variant(variant):
     F = _build(128, "fio_ellipse", precisions=1 | 8)
     f = W.complex_gaussian(128 * 128, 64, 48)
@@ -287,7 +287,7 @@ def test_fp16x3_every_variant(variant):
     F.set_variants([variant] * 3, precision="fp16x3")
     gh = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp16x3"))
     assert rel_l2(gh, g64) < 5e-6
-    assert F.tune(64, "fp16x3")[0] in range(9)
+    assert F.tune(64, "fp16x3")[0] in range(10)
 
 
 def test_split16_precisions_need_their_copy():
@@ -301,7 +301,7 @@ def test_split16_precisions_need_their_copy():
 # ---- rank-deficient leaves ---------------------------------------------------
 
 @pytest.mark.parametrize("precision,variant", [("fp32", None), ("bf16x3", 0), ("bf16x3", 8), ("fp16x3", 2),
-                                               ("fp16x3", 7)])
+                                               ("fp16x3", 7), ("fp16x3", 9)])
 def test_compressible_leaves_many_rhs(precision, variant):
     """A slowly varying low-rank phase: the leaf column IDs keep few of their 64 columns, so the
     first up step multiplies T by the redundant rows of the caller's column-major input (70
