@@ -117,7 +117,18 @@ __device__ inline void middle_rows(int* crow_in, int* crow_out, const MidArgs& A
     }
 }
 
-enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum };
+enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum, Transpose };
+
+// Complex64 block transpose from a row-major N x nrhs copy (element (p, r)
+// at src[p * nrhs + r]) to the external column-major layout (element (p, r)
+// at dst[r * ld + p]).
+struct TransposeArgs {
+    const void* src;
+    void* dst;
+    long long ld;
+    long long N;
+    int nrhs;
+};
 
 void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
                          hipStream_t s);

@@ -533,7 +533,12 @@ void destroy_plan(midbf_plan* h) {
     f(M.d_nr); f(M.d_nc); f(M.d_off); f(M.d_in_off); f(M.d_in_len); f(M.d_out_off); f(M.d_out_len);
     f(M.d_tile_off);
     for (int q = 0; q < NPREC; ++q) f(M.S[q]);
-    for (int q = 0; q < NPREC; ++q) { f(h->ws[q].buf[0]); f(h->ws[q].buf[1]); f(h->ws[q].scratch); }
+    for (int q = 0; q < NPREC; ++q) {
+        f(h->ws[q].buf[0]);
+        f(h->ws[q].buf[1]);
+        f(h->ws[q].scratch);
+        f(h->ws[q].lat);
+    }
     delete h;
 }
 

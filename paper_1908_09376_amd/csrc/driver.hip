@@ -62,6 +62,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::AdjMiddle: return "adj_middle";
         case LevelKernel::AdjDown: return "adj_down";
         case LevelKernel::DownSum: return "down_sum";
+        case LevelKernel::Transpose: return "transpose";
     }
     return "?";
 }
@@ -86,6 +87,10 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     MIDBF_CHECK(mfma_count > 0 || smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
     auto go = [&] {
+        if (which == LevelKernel::Transpose) {
+            launch_transpose(*(const TransposeArgs*)args, st);
+            return;
+        }
         if (mfma_count > 0) {
             const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
             const int lv = std::max(0, std::min(level, midbf_plan::VMAXLEV - 1));
@@ -108,9 +113,14 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
                         : prec == PREC_BF16 ? "_bf16x3"
                         : prec == PREC_FP16 ? "_fp16x3"
                                             : "_fp32";
-    r.name = std::string(kernel_name(which)) + (mfma_count > 0 && !is_split16(prec) ? "_mfma" : "") + pname +
-             (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
-    if (P.by_level && level >= 0) r.name += "_s" + std::to_string(level);
+    if (which == LevelKernel::Transpose) {
+        r.name = std::string(kernel_name(which)) + pname;
+        if (P.by_level) r.name += "_out";
+    } else {
+        r.name = std::string(kernel_name(which)) + (mfma_count > 0 && !is_split16(prec) ? "_mfma" : "") + pname +
+                 (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
+        if (P.by_level && level >= 0) r.name += "_s" + std::to_string(level);
+    }
     r.a = take_event(P);
     r.b = take_event(P);
     r.bytes = bytes;
@@ -121,7 +131,7 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     P.recs.push_back(r);
 }
 
-void ensure_workspace(midbf_plan* h, int prec, int nrhs, bool scratch) {
+void ensure_workspace(midbf_plan* h, int prec, int nrhs, bool scratch, bool lat) {
     Workspace& w = h->ws[prec];
     const size_t need = (size_t)std::max<long long>(h->max_total_k, 1) * nrhs * csize(prec);
     if (w.bytes < need) {
@@ -141,6 +151,14 @@ void ensure_workspace(midbf_plan* h, int prec, int nrhs, bool scratch) {
         MIDBF_HIP(hipMalloc(&w.scratch, sneed));
         w.scratch_bytes = sneed;
     }
+    const size_t lneed = (size_t)h->N * nrhs * csize(prec);
+    if (lat && w.lat_bytes < lneed) {
+        if (w.lat) MIDBF_HIP(hipFree(w.lat));
+        w.lat = nullptr;
+        w.lat_bytes = 0;
+        MIDBF_HIP(hipMalloc(&w.lat, lneed));
+        w.lat_bytes = lneed;
+    }
 }
 
 // One level launch of an apply: which kernel, its argument block, shape and
@@ -151,6 +169,7 @@ struct LaunchDesc {
         UpArgs up;
         MidArgs mid;
         DownArgs down;
+        TransposeArgs tr;
     } a;
     dim3 grid;
     size_t smem;
@@ -164,9 +183,14 @@ struct LaunchDesc {
 // level vectors in bufs[0..1] (and the matrix-core down pass's per-ID
 // contributions in scratch), rt right-hand sides per VALU workgroup.
 // chunk_middle splits the middle into launches of at most 65535 blocks (grid
-// limit of a direct launch).
+// limit of a direct launch).  With lat (N x nrhs), the last down-sum writes
+// its rows there (row-major, lattice order: whole 512-byte rows instead of
+// strided columns) and a final transpose writes the output block.  (The leaf
+// up kernels read the input block directly: measured faster than a transpose
+// in front of them.)
 std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
-                                   bool adjoint, bool mfma, void* const* buf, bool chunk_middle, int rt) {
+                                   bool adjoint, bool mfma, void* const* buf, bool chunk_middle, int rt,
+                                   void* lat = nullptr) {
     const double fl = is_split16(prec) ? 24.0 : 8.0;   // flops per complex entry and RHS (split-16: three products)
     const int tiles = (nrhs + rt - 1) / rt;
     const size_t cs = csize(prec);
@@ -264,9 +288,9 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.s = s;
         a.Ps = ipow(h->P, s);
         a.in = buf[o ^ 1];
-        a.ext = out_ext;
+        a.ext = lat && s == 0 ? nullptr : out_ext;
         a.ld = ld;
-        a.out = buf[o];
+        a.out = lat && s == 0 ? lat : buf[o];
         a.k_prev = s ? down[s - 1].d_k : nullptr;
         a.yoff_prev = s ? down[s - 1].d_y_off : nullptr;
         a.nrhs = nrhs;
@@ -302,6 +326,14 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         }
         o ^= 1;
     }
+    if (lat) {
+        LaunchDesc D{};
+        D.a.tr = TransposeArgs{lat, out_ext, ld, h->N, nrhs};
+        D.which = LevelKernel::Transpose;
+        D.bytes = 2.0 * h->N * nrhs * cs;
+        D.level = 1;
+        out.push_back(D);
+    }
     return out;
 }
 
@@ -322,9 +354,11 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
                 "the split 16-bit applies exist for the forward transform with candidate sets up to 2048");
     // matrix cores: split 16-bit always, FP32 for many right-hand sides
     const bool mfma = is_split16(prec) || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
-    ensure_workspace(h, prec, nrhs, mfma);
+    const bool lat = mfma && nrhs > 1;   // row-major lattice copy around the leaf levels
+    ensure_workspace(h, prec, nrhs, mfma, lat);
     const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
-    const auto launches = plan_apply(h, in_ext, out_ext, nrhs, ld, prec, adjoint, mfma, h->ws[prec].buf, true, rt);
+    const auto launches = plan_apply(h, in_ext, out_ext, nrhs, ld, prec, adjoint, mfma, h->ws[prec].buf, true, rt,
+                                     lat ? h->ws[prec].lat : nullptr);
     for (const LaunchDesc& D : launches)
         launch_checked(h, D.which, prec, rt, &D.a, D.grid, D.smem, st, D.bytes, D.flops, D.mfma_count, nrhs,
                        D.level);
@@ -596,7 +630,7 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
                         MIDBF_HIP(hipEventElapsedTime(&ms, r.a, r.b));
                         int q, lv;
                         kind_level(r.name, q, lv);
-                        t[q * NL + lv] += ms;
+                        if (r.name.rfind("transpose", 0) != 0) t[q * NL + lv] += ms;
                         h->prof.pool.push_back(r.a);
                         h->prof.pool.push_back(r.b);
                     }

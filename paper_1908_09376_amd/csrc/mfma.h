@@ -20,6 +20,9 @@ constexpr int MFMA_VARIANTS = 10;     // tile variants (rows per wave, K chunk, 
 void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
                         hipStream_t s);
 
+// The external <-> row-major transposes around a matrix-core apply.
+void launch_transpose(const TransposeArgs& A, hipStream_t s);
+
 // Split 16-bit variants of the up / down / middle kernels (factors stored as
 // MFMA fragment tiles; tile_off gives each middle block's first tile), for
 // elem = SPLIT16_BF16 or SPLIT16_FP16.

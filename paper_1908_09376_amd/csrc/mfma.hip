@@ -246,7 +246,8 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
-    const bool ext = A.s == 0;
+    // the leaves read the caller's block, or its row-major copy (A.ext null)
+    const bool ext = A.s == 0 && A.ext;
     const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
     float2* out = (float2*)A.out;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
     const int ncand = candidate_rows<MT>(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev);
     if (threadIdx.x < A.G.P) base[threadIdx.x] = A.lev.perm_off[g * A.G.P + threadIdx.x] * A.nrhs + r0;
     __syncthreads();
-    const bool ext = A.s == 0;
+    const bool ext = A.s == 0 && A.ext;
     float2* outp = ext ? (float2*)A.ext : (float2*)A.out;
     // two right-hand sides per thread (16-byte loads) when the row stride allows it
     const bool pairs = (A.nrhs % 2 == 0) && (nr % 2 == 0) && !ext;
@@ -459,7 +460,36 @@ void launch_variant(LevelKernel which, const void* args, long long count, int nr
     MIDBF_HIP(hipGetLastError());
 }
 
+// Row-major N x nrhs -> external column-major block, in 64 x 64 tiles through
+// LDS (rows padded to 65 entries: the column reads of each half-wave touch
+// distinct banks); both global sides are coalesced.
+__global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
+    __shared__ float2 t[64][65];
+    const long long p0 = (long long)blockIdx.x * 64;
+    const int r0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const float2* src = (const float2*)A.src;
+    float2* dst = (float2*)A.dst;
+    for (int pp = ty; pp < 64; pp += 4) {
+        const long long p = p0 + pp;
+        const int r = r0 + tx;
+        if (p < A.N && r < A.nrhs) t[pp][tx] = src[p * A.nrhs + r];
+    }
+    __syncthreads();
+    for (int rr = ty; rr < 64; rr += 4) {
+        const long long p = p0 + tx;
+        const int r = r0 + rr;
+        if (p < A.N && r < A.nrhs) dst[(long long)r * A.ld + p] = t[tx][rr];
+    }
+}
+
 }  // namespace
+
+void launch_transpose(const TransposeArgs& A, hipStream_t s) {
+    const dim3 grid((unsigned)((A.N + 63) / 64), (unsigned)((A.nrhs + 63) / 64));
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, A);
+    MIDBF_HIP(hipGetLastError());
+}
 
 void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
                         hipStream_t s) {

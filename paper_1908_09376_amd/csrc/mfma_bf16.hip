@@ -313,7 +313,7 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
-    const bool ext = A.s == 0;
+    const bool ext = A.s == 0 && A.ext;   // else the leaves read the row-major copy in A.in
     const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
     float2* out = (float2*)A.out;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
@@ -448,15 +448,76 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
 // long in M (n - k), so the shared B never needs restaging.
 constexpr int RES_KT = 8;
 
+// C = A B for every row tile of an M x K block, B (K <= RES_KT * KT rows,
+// B[j][c] = src[boff(j, c)]) resident in LDS: B is staged once, split into
+// fragments; then wave w takes row tiles w, w + NW, ... and streams their A
+// tiles two ahead with no barrier in the loop.  epi(base, cr, ci) stores the
+// finished row tile of rows [base, base + 16) (also for K = 0, with zeros).
+// ONE_B: read one B fragment at a time (fewer registers).  Every thread of the
+// workgroup must call this.
+template <class E, int NT, bool ONE_B, class BOff, class Epi>
+__device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, const float2* __restrict__ src,
+                              BOff boff, int nr, LFrag<E>* sB, Epi epi) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+    const int ktiles = (K + KT - 1) / KT;
+    const int mtiles = (M + 15) / 16;
+    const int mine = mtiles > wave ? (mtiles - wave + NW - 1) / NW : 0;   // row tiles of this wave
+    floatx4 cr[1][4], ci[1][4];
+    if (ktiles == 0) {
+        zero_acc<1>(cr, ci);
+        for (int t = 0; t < mine; ++t) epi((wave + t * NW) * 16, cr, ci);
+        return;
+    }
+    for (int f = tid; f < ktiles * 256; f += NT) {
+        const int kt = f >> 8, rem = f & 255, kb = rem >> 6, col = rem & 63;
+        float2 v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int j = kt * KT + kb * 8 + i;
+            v[i] = (j < K && col < nr) ? src[boff(j, col)] : make_float2(0.f, 0.f);
+        }
+        lds_split_store(sB + kt * 4 + (col >> 4), kb * 16 + (col & 15), v);
+    }
+    __syncthreads();
+    const int total = mine * ktiles;
+    auto tile_at = [&](int q) {
+        const int mt = wave + (q / ktiles) * NW, kt = q - (q / ktiles) * ktiles;
+        return Atiles[((long long)mt * ktiles + kt) * 64 + l];
+    };
+    Frag<E> f0[1], f1, f2;
+    if (total > 0) f0[0] = tile_at(0);
+    if (total > 1) f1 = tile_at(1);
+    for (int q = 0; q < total; ++q) {
+        if (q + 2 < total) f2 = tile_at(q + 2);
+        const int kt = q - (q / ktiles) * ktiles;
+        if (kt == 0) zero_acc<1>(cr, ci);
+        if constexpr (ONE_B) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const Frag<E> b = lds_frag(sB + kt * 4 + nt, l);
+                kstep1_bf16<E, 1>(cr, ci, f0, b, nt, 1);
+            }
+        } else {
+            Frag<E> b[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) b[nt] = lds_frag(sB + kt * 4 + nt, l);
+            kstep_bf16<E, 1>(cr, ci, f0, b, 1);
+        }
+        if (kt == ktiles - 1) epi((wave + (q / ktiles) * NW) * 16, cr, ci);
+        f0[0] = f1;
+        f1 = f2;
+    }
+}
+
 template <class E, int NT>
 __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, float2* scr) {
-    constexpr int NW = NT / 64;
     __shared__ LFrag<E> sB[RES_KT * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     const float2* zin = (const float2*)A.in;
-    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
     const int* perm = A.lev.perm + A.lev.perm_off[id];
     const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
@@ -467,57 +528,23 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
         if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
     }
     if (nred == 0) return;
-    const int ktiles = (k + KT - 1) / KT;           // <= RES_KT (checked at launch)
-    // z (k x 64) as fragments: one fragment = 8 K rows of one column, four planes
-    const float2* z = zin + yo * A.nrhs + r0;
-    for (int f = tid; f < ktiles * 256; f += NT) {
-        const int kt = f >> 8, rem = f & 255, kb = rem >> 6, col = rem & 63;
-        float2 v[8];
+    // z (k x 64) resident (k <= RES_KT * KT, checked at launch); rows of T^T z scattered by perm
+    auto epi = [&](int base, const floatx4 (&cr)[1][4], const floatx4 (&ci)[1][4]) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int j = kt * KT + kb * 8 + i;
-            v[i] = (j < k && col < nr) ? z[(long long)j * A.nrhs + col] : make_float2(0.f, 0.f);
-        }
-        lds_split_store(sB + kt * 4 + (col >> 4), kb * 16 + (col & 15), v);
-    }
-    __syncthreads();
-    const int mtiles = (nred + 15) / 16;
-    const int mine = mtiles > wave ? (mtiles - wave + NW - 1) / NW : 0;   // row tiles of this wave
-    const int total = mine * ktiles;
-    auto tile_at = [&](int q) {
-        const int mt = wave + (q / ktiles) * NW, kt = q - (q / ktiles) * ktiles;
-        return Tt[((long long)mt * ktiles + kt) * 64 + l];
-    };
-    Frag<E> f0[1], f1, f2;
-    if (total > 0) f0[0] = tile_at(0);
-    if (total > 1) f1 = tile_at(1);
-    floatx4 cr[1][4], ci[1][4];
-    for (int q = 0; q < total; ++q) {
-        if (q + 2 < total) f2 = tile_at(q + 2);
-        const int kt = q - (q / ktiles) * ktiles;
-        if (kt == 0) zero_acc<1>(cr, ci);
-        Frag<E> b[4];
+        for (int v = 0; v < 4; ++v) {
+            const int row = base + 4 * lk + v;
+            if (row < nred) {
+                float2* d = w + (long long)perm[k + row] * A.nrhs + r0;
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) b[nt] = lds_frag(sB + kt * 4 + nt, l);
-        kstep_bf16<E, 1>(cr, ci, f0, b, 1);
-        if (kt == ktiles - 1) {
-            const int base = (wave + (q / ktiles) * NW) * 16;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = base + 4 * lk + v;
-                if (row < nred) {
-                    float2* d = w + (long long)perm[k + row] * A.nrhs + r0;
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const int r = nt * 16 + lr;
-                        if (r < nr) d[r] = make_float2(cr[0][nt][v], ci[0][nt][v]);
-                    }
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int r = nt * 16 + lr;
+                    if (r < nr) d[r] = make_float2(cr[0][nt][v], ci[0][nt][v]);
                 }
             }
         }
-        f0[0] = f1;
-        f1 = f2;
-    }
+    };
+    gemm_resident<E, NT, (NT >= 1024)>(Tt, nred, k, zin + yo * A.nrhs + r0,
+                         [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
 }
 
 // Rows [base, base + 16) of C = A B for one wave (one row tile), over K in
@@ -606,14 +633,14 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     constexpr int NW = NT / 64;
     __shared__ int crow[CROW_MAX];
     __shared__ int srcrow[CROW_MAX];
-    __shared__ LFrag<E> sB[2 * rct_for<NT>() * 4];
+    __shared__ LFrag<E> sB[std::max(2 * rct_for<NT>(), RES_KT) * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     candidate_rows<NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
-    const bool ext = A.s == 0;
+    const bool ext = A.s == 0 && A.ext;   // else the leaves read the row-major copy in A.in
     const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
     float2* out = (float2*)A.out;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
@@ -624,27 +651,34 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     __syncthreads();
     for (int j = tid; j < nred; j += NT) srcrow[j] = crow[perm[k + j]];
     __syncthreads();
+    auto epi = [&](int base, const floatx4 (&cr)[1][4], const floatx4 (&ci)[1][4]) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = base + 4 * lk + v;
+            if (row < k) {
+                const int src = crow[perm[row]];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int r = nt * 16 + lr;
+                    if (r < nr) {
+                        const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                        out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv.x, ci[0][nt][v] + sv.y);
+                    }
+                }
+            }
+        }
+    };
     auto run = [&](const float2* xb, auto boff) {
+        if (nred <= RES_KT * KT) {       // the redundant inputs fit in LDS: staged once
+            gemm_resident<E, NT, (NT >= 768)>(Tt, k, nred, xb, boff, nr, sB, epi);
+            return;
+        }
         for (int m0 = 0; m0 < k; m0 += NW * 16) {
             const int base = m0 + wave * 16;
             floatx4 cr[1][4], ci[1][4];
             zero_acc<1>(cr, ci);
             gemm_res16<E, NT>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = base + 4 * lk + v;
-                if (row < k) {
-                    const int src = crow[perm[row]];
-#pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const int r = nt * 16 + lr;
-                        if (r < nr) {
-                            const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv.x, ci[0][nt][v] + sv.y);
-                        }
-                    }
-                }
-            }
+            epi(base, cr, ci);
         }
     };
     // B rows are input rows: at the leaves the caller's column-major input

@@ -63,6 +63,8 @@ struct Workspace {
     size_t bytes = 0;
     void* scratch = nullptr;      // per-ID candidate contributions (matrix-core path going down)
     size_t scratch_bytes = 0;
+    void* lat = nullptr;          // N x nrhs row-major copy of the output (matrix-core path)
+    size_t lat_bytes = 0;
 };
 
 // Per-launch HIP-event timing of the apply kernels (midbf_profile_*).
