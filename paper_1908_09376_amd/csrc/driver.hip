@@ -63,6 +63,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::AdjDown: return "adj_down";
         case LevelKernel::DownSum: return "down_sum";
         case LevelKernel::Transpose: return "transpose";
+        case LevelKernel::DownGroup: return "down_group";
     }
     return "?";
 }
@@ -94,7 +95,7 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
         if (mfma_count > 0) {
             const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
             const int lv = std::max(0, std::min(level, midbf_plan::VMAXLEV - 1));
-            if (is_split16(prec) && which != LevelKernel::DownSum)
+            if (is_split16(prec) && which != LevelKernel::DownSum)   // (DownGroup is split-16 only)
                 launch_bf16_kernel(prec == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, which,
                                    (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[kind][lv], args,
                                    mfma_count, nrhs, h->ws[prec].scratch, h->mid.d_tile_off, st);
@@ -300,7 +301,17 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         const double vout = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         D.level = s;
-        if (mfma) {
+        const int dvar = (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[1][std::min(s, midbf_plan::VMAXLEV - 1)];
+        if (mfma && is_split16(prec) && dvar >= 5 && lv.kmax <= SPLIT16_RESIDENT_K && (nrhs == 1 || lat || s > 0)) {
+            // split 16-bit with z resident: the siblings of each group add into its candidate rows
+            D.which = LevelKernel::DownGroup;
+            D.grid = dim3();
+            D.smem = 0;
+            D.bytes = fac + vin + vout;
+            D.flops = fl * lv.entries * nrhs;
+            D.mfma_count = groups;
+            out.push_back(D);
+        } else if (mfma) {
             // per-ID contributions to the scratch block, then the ordered group sums
             const double scr = (double)lv.total_n * nrhs * cs;
             D.which = LevelKernel::Down;

@@ -27,6 +27,9 @@ void launch_transpose(const TransposeArgs& A, hipStream_t s);
 // MFMA fragment tiles; tile_off gives each middle block's first tile), for
 // elem = SPLIT16_BF16 or SPLIT16_FP16.
 constexpr int BF16_VARIANTS = 10;
+// Ranks up to which the split down kernels keep z in LDS (variants 5-9 then
+// run the grouped down pass, LevelKernel::DownGroup).
+constexpr int SPLIT16_RESIDENT_K = 256;
 enum { SPLIT16_BF16 = 0, SPLIT16_FP16 = 1 };
 void launch_bf16_kernel(int elem, LevelKernel which, int variant, const void* args, long long count, int nrhs,
                         void* scratch, const long long* tile_off, hipStream_t s);

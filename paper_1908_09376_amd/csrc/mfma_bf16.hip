@@ -447,14 +447,16 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
 // ahead, with no barrier in the loop.  The down GEMMs are short in K (k) and
 // long in M (n - k), so the shared B never needs restaging.
 constexpr int RES_KT = 8;
+static_assert(RES_KT * KT == SPLIT16_RESIDENT_K, "resident rank limit");
 
 // C = A B for every row tile of an M x K block, B (K <= RES_KT * KT rows,
 // B[j][c] = src[boff(j, c)]) resident in LDS: B is staged once, split into
 // fragments; then wave w takes row tiles w, w + NW, ... and streams their A
-// tiles two ahead with no barrier in the loop.  epi(base, cr, ci) stores the
-// finished row tile of rows [base, base + 16) (also for K = 0, with zeros).
-// ONE_B: read one B fragment at a time (fewer registers).  Every thread of the
-// workgroup must call this.
+// tiles two ahead with no barrier in the loop (the first two are requested
+// before B is staged).  epi(base, cr, ci) stores the finished row tile of
+// rows [base, base + 16) (also for K = 0, with zeros).  ONE_B: read one B
+// fragment at a time (fewer registers).  Every thread of the workgroup must
+// call this.
 template <class E, int NT, bool ONE_B, class BOff, class Epi>
 __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, const float2* __restrict__ src,
                               BOff boff, int nr, LFrag<E>* sB, Epi epi) {
@@ -469,6 +471,14 @@ __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, 
         for (int t = 0; t < mine; ++t) epi((wave + t * NW) * 16, cr, ci);
         return;
     }
+    const int total = mine * ktiles;
+    auto tile_at = [&](int q) {
+        const int mt = wave + (q / ktiles) * NW, kt = q - (q / ktiles) * ktiles;
+        return Atiles[((long long)mt * ktiles + kt) * 64 + l];
+    };
+    Frag<E> f0[1], f1, f2;
+    if (total > 0) f0[0] = tile_at(0);
+    if (total > 1) f1 = tile_at(1);
     for (int f = tid; f < ktiles * 256; f += NT) {
         const int kt = f >> 8, rem = f & 255, kb = rem >> 6, col = rem & 63;
         float2 v[8];
@@ -480,14 +490,6 @@ __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, 
         lds_split_store(sB + kt * 4 + (col >> 4), kb * 16 + (col & 15), v);
     }
     __syncthreads();
-    const int total = mine * ktiles;
-    auto tile_at = [&](int q) {
-        const int mt = wave + (q / ktiles) * NW, kt = q - (q / ktiles) * ktiles;
-        return Atiles[((long long)mt * ktiles + kt) * 64 + l];
-    };
-    Frag<E> f0[1], f1, f2;
-    if (total > 0) f0[0] = tile_at(0);
-    if (total > 1) f1 = tile_at(1);
     for (int q = 0; q < total; ++q) {
         if (q + 2 < total) f2 = tile_at(q + 2);
         const int kt = q - (q / ktiles) * ktiles;
@@ -544,7 +546,82 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
         }
     };
     gemm_resident<E, NT, (NT >= 1024)>(Tt, nred, k, zin + yo * A.nrhs + r0,
-                         [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
+                                       [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
+}
+
+// Going down, one workgroup per group of 2^d sibling decompositions (same
+// candidate set): sibling t's contribution -- z_t on its skeleton rows, T_t^T
+// z_t on its redundant rows -- is added to the group's candidate rows in the
+// order t = 0, 1, ... (t = 0 writes, the others read-add-write; a barrier
+// separates the siblings), so no per-ID scratch and no separate sum pass are
+// needed.  The candidate rows are rows of the previous level buffer, or of the
+// row-major lattice copy at the leaves (both nrhs wide; with one right-hand
+// side the caller's block itself).  z_t resident (k <= RES_KT * KT).
+template <class E, int NT>
+__global__ __launch_bounds__(NT) void down_group16(DownArgs A) {
+    extern __shared__ __align__(16) int crow[];            // ncand_max candidate rows
+    __shared__ LFrag<E> sB[RES_KT * 4];
+    const long long g = blockIdx.x;
+    const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    candidate_rows<NT>(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev);
+    float2* outp = (A.s == 0 && A.ext) ? (float2*)A.ext : (float2*)A.out;
+    const float2* zin = (const float2*)A.in;
+    const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4;
+    for (int t = 0; t < A.G.P; ++t) {
+        __syncthreads();          // crow ready; the previous sibling's rows written and sB free
+        const long long id = g * A.G.P + t;
+        const int k = A.lev.k[id], nred = A.lev.n[id] - k;
+        const int* perm = A.lev.perm + A.lev.perm_off[id];
+        const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
+        const long long yo = A.lev.y_off[id];
+        const bool first = t == 0;
+        for (int e = tid; e < k * NRHS; e += NT) {
+            const int i = e / NRHS, r = e - i * NRHS;
+            if (r < nr) {
+                float2* d = outp + (long long)crow[perm[i]] * A.nrhs + r0 + r;
+                const float2 v = zin[(yo + i) * A.nrhs + r0 + r];
+                if (first) {
+                    *d = v;
+                } else {
+                    const float2 o = *d;
+                    *d = make_float2(o.x + v.x, o.y + v.y);
+                }
+            }
+        }
+        auto dst_row = [&](int row) { return outp + (long long)crow[perm[k + row]] * A.nrhs + r0; };
+        auto epi = [&](int base, const floatx4 (&cr)[1][4], const floatx4 (&ci)[1][4]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + 4 * lk + v;
+                if (row < nred) {
+                    float2* d = dst_row(row);
+                    if (first) {
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const int r = nt * 16 + lr;
+                            if (r < nr) d[r] = make_float2(cr[0][nt][v], ci[0][nt][v]);
+                        }
+                    } else {
+                        float2 o[4];
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const int r = nt * 16 + lr;
+                            if (r < nr) o[nt] = d[r];
+                        }
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt) {
+                            const int r = nt * 16 + lr;
+                            if (r < nr) d[r] = make_float2(o[nt].x + cr[0][nt][v], o[nt].y + ci[0][nt][v]);
+                        }
+                    }
+                }
+            }
+        };
+        gemm_resident<E, NT, (NT >= 768)>(Tt, nred, k, zin + yo * A.nrhs + r0,
+                                          [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
+    }
 }
 
 // Rows [base, base + 16) of C = A B for one wave (one row tile), over K in
@@ -846,6 +923,12 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
     else if (which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT)
         hipLaunchKernelGGL((down_res16<E, NT>), grid, dim3(NT), 0, s, *(const DownArgs*)args, count,
                            (float2*)scratch);
+    else if (which == LevelKernel::DownGroup) {
+        const DownArgs& a = *(const DownArgs*)args;
+        MIDBF_CHECK(a.kmax <= RES_KT * KT, MIDBF_ERR_ARG, "grouped down pass needs ranks <= 256");
+        constexpr int GNT = NT == 1024 ? 768 : NT;     // the 16-wave build would spill
+        hipLaunchKernelGGL((down_group16<E, GNT>), grid, dim3(GNT), sizeof(int) * a.ncand_max, s, a);
+    }
     else
         launch_bvariant<W0, E>(which, args, count, nrhs, scratch, tile_off, s);
     MIDBF_HIP(hipGetLastError());
@@ -867,6 +950,11 @@ void launch_split16(LevelKernel which, int variant, const void* args, long long 
         case 6: {
             // down with z resident in LDS (variant 5: 512 threads, 6: 1024); other kinds, or ranks
             // beyond the resident capacity, run W0 / W3
+            if (which == LevelKernel::DownGroup) {
+                if (variant == 5) launch_res16<E, 512>(which, args, count, nrhs, scratch, tile_off, s);
+                else launch_res16<E, 1024>(which, args, count, nrhs, scratch, tile_off, s);
+                break;
+            }
             const bool res = which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT;
             if (!res) {
                 if (variant == 5) launch_bvariant<W0, E>(which, args, count, nrhs, scratch, tile_off, s);
