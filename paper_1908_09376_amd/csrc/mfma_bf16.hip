@@ -772,10 +772,25 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
     __shared__ LFrag<E> sB[2 * rct_for<NT>() * 4];
-    const long long bi = blockIdx.x;
+    // workgroup -> (block, chunk of NW row tiles).  Workgroups are dealt to the
+    // eight XCDs in turn, so the chunks of a block are numbered eight apart:
+    // they run on one XCD at about the same time and share its input rows in L2.
+    const int mc = A.mchunks;
+    const long long b = blockIdx.x, cnt = gridDim.x / mc;
+    long long bi;
+    int chunk;
+    if (cnt % 8 == 0) {
+        const long long q = b >> 3;
+        bi = (q / mc) * 8 + (b & 7);
+        chunk = (int)(q % mc);
+    } else {
+        bi = b / mc;
+        chunk = (int)(b % mc);
+    }
+    const int M = A.nr[bi], K = A.nc[bi];
+    if (chunk * NW * 16 >= M) return;        // (uniform over the workgroup)
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
-    const int M = A.nr[bi], K = A.nc[bi];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     middle_rows<NT>(crow_in, crow_out, A, bi);
     const float2* xin = (const float2*)A.in;
@@ -783,7 +798,7 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
     __syncthreads();
     auto boff = [&](int j, int c) { return (long long)crow_in[j] * A.nrhs + c; };
-    for (int m0 = 0; m0 < M; m0 += NW * 16) {
+    for (int m0 = chunk * NW * 16; m0 < M; m0 += mc * NW * 16) {
         const int base = m0 + wave * 16;
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
@@ -918,8 +933,13 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
     if (which == LevelKernel::Up)
         hipLaunchKernelGGL((up_res16<E, NT>), grid, dim3(NT), 0, s, *(const UpArgs*)args, count);
-    else if (which == LevelKernel::Middle)
-        hipLaunchKernelGGL((middle_res16<E, NT>), grid, dim3(NT), 0, s, *(const MidArgs*)args, tile_off);
+    else if (which == LevelKernel::Middle) {
+        // one workgroup per chunk of NT / 64 row tiles of a block
+        MidArgs a = *(const MidArgs*)args;
+        a.mchunks = std::max(1, (a.out_max + NT / 4 - 1) / (NT / 4));
+        const dim3 mgrid((unsigned)(count * a.mchunks), grid.y);
+        hipLaunchKernelGGL((middle_res16<E, NT>), mgrid, dim3(NT), 0, s, a, tile_off);
+    }
     else if (which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT)
         hipLaunchKernelGGL((down_res16<E, NT>), grid, dim3(NT), 0, s, *(const DownArgs*)args, count,
                            (float2*)scratch);
