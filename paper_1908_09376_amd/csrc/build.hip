@@ -408,6 +408,64 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
     return true;
 }
 
+// The dense split 16-bit blocks of the groups of a row step s >= 1 (plan.h).
+// Skipped (groups = 0) where a block exceeds the kernels' row tables.
+void build_group_dense(midbf_plan* h, LevelSide& lv, const LevelSide& prev, hipStream_t st) {
+    const int P = h->P;
+    const long long G = lv.nid / P, Ps = ipow(P, lv.s);
+    std::vector<int> nr(G), nc(G), in_len(G * P), out_len(G * P);
+    std::vector<long long> toff(G), in_off(G * P), out_off(G * P);
+    long long tiles = 0, entries = 0;
+    int nr_max = 0, nc_max = 0;
+    for (long long g = 0; g < G; ++g) {
+        const long long a = g / Ps, ap = g - a * Ps;
+        int sk = 0;
+        for (int t = 0; t < P; ++t) {
+            const long long id = g * P + t, idp = ((long long)P * a + t) * Ps + ap;
+            in_off[g * P + t] = lv.y_off[id];
+            in_len[g * P + t] = lv.k[id];
+            out_off[g * P + t] = prev.y_off[idp];
+            out_len[g * P + t] = prev.k[idp];
+            sk += lv.k[id];
+        }
+        nr[g] = lv.n[g * P];
+        nc[g] = sk;
+        toff[g] = tiles;
+        tiles += bf16_tiles(nr[g], nc[g]);
+        entries += (long long)nr[g] * nc[g];
+        nr_max = std::max(nr_max, nr[g]);
+        nc_max = std::max(nc_max, nc[g]);
+    }
+    if (nr_max > BF16_CROW_MAX || nc_max > BF16_CROW_MAX) return;
+    auto own = [&](auto* p) { lv.chunks.push_back((void*)p); return p; };
+    lv.d_g_nr = own(dalloc<int>(G));
+    lv.d_g_nc = own(dalloc<int>(G));
+    lv.d_g_tile_off = own(dalloc<long long>(G));
+    lv.d_g_in_off = own(dalloc<long long>(G * P));
+    lv.d_g_in_len = own(dalloc<int>(G * P));
+    lv.d_g_out_off = own(dalloc<long long>(G * P));
+    lv.d_g_out_len = own(dalloc<int>(G * P));
+    upload(lv.d_g_nr, nr, st);
+    upload(lv.d_g_nc, nc, st);
+    upload(lv.d_g_tile_off, toff, st);
+    upload(lv.d_g_in_off, in_off, st);
+    upload(lv.d_g_in_len, in_len, st);
+    upload(lv.d_g_out_off, out_off, st);
+    upload(lv.d_g_out_len, out_len, st);
+    for (int q : {PREC_BF16, PREC_FP16}) {
+        if (!lv.d_T[q]) continue;
+        lv.g_T[q] = own(dalloc<char>((size_t)std::max<long long>(tiles, 1) * BF16_TILE_BYTES));
+        pack_group_tiles(q == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, P, lv.d_k, lv.d_perm_off, lv.d_perm,
+                         lv.d_T[q], lv.d_g_nr, lv.d_g_nc, lv.d_g_tile_off, G, lv.g_T[q], st);
+    }
+    MIDBF_HIP(hipStreamSynchronize(st));
+    lv.groups = G;
+    lv.g_tiles = tiles;
+    lv.g_entries = entries;
+    lv.g_nr_max = nr_max;
+    lv.g_nc_max = nc_max;
+}
+
 void build_middle(midbf_plan* h, hipStream_t st) {
     Middle& M = h->mid;
     const int P = h->P;
@@ -591,6 +649,8 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
                     want *= 2;    // the sample set was too small: enlarge it (Sec. 3.2)
                 }
                 khat[side] = lv.kmax;
+                if (side == SIDE_ROW && s > 0 && (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)))
+                    build_group_dense(h, lv, *prev, st);
             }
         }
         build_middle(h, st);
@@ -616,7 +676,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         S.bytes_fp32 = (h->keep & MIDBF_KEEP_FP32) ? ent * 8 : 0;
         long long bfb = h->mid.bf16_bytes;
         for (auto* side : {&h->rows, &h->cols})
-            for (auto& lv : *side) bfb += lv.bf16_bytes;
+            for (auto& lv : *side) bfb += lv.bf16_bytes + lv.g_tiles * BF16_TILE_BYTES;
         S.bytes_bf16 = (h->keep & MIDBF_KEEP_BF16) ? bfb : 0;
         S.bytes_fp16 = (h->keep & MIDBF_KEEP_FP16) ? bfb : 0;
         S.index_bytes = idx;

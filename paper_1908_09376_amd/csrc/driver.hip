@@ -64,6 +64,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::DownSum: return "down_sum";
         case LevelKernel::Transpose: return "transpose";
         case LevelKernel::DownGroup: return "down_group";
+        case LevelKernel::DownDense: return "down_dense";
     }
     return "?";
 }
@@ -95,10 +96,15 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
         if (mfma_count > 0) {
             const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
             const int lv = std::max(0, std::min(level, midbf_plan::VMAXLEV - 1));
-            if (is_split16(prec) && which != LevelKernel::DownSum)   // (DownGroup is split-16 only)
+            // (DownGroup and DownDense are split-16 only; DownDense runs the middle
+            // kernels on the group blocks, whose first-tile table travels in MidArgs::off)
+            if (is_split16(prec) && which != LevelKernel::DownSum)
                 launch_bf16_kernel(prec == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, which,
                                    (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[kind][lv], args,
-                                   mfma_count, nrhs, h->ws[prec].scratch, h->mid.d_tile_off, st);
+                                   mfma_count, nrhs, h->ws[prec].scratch,
+                                   which == LevelKernel::DownDense ? ((const MidArgs*)args)->off
+                                                                   : h->mid.d_tile_off,
+                                   st);
             else
                 launch_mfma_kernel(which, h->mfma_variant[kind][lv], args, mfma_count, nrhs, h->ws[prec].scratch, st);
         }
@@ -302,7 +308,33 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         const double fac = (double)lv.entries * cs + (double)lv.total_n * 4 + (double)lv.nid * 32;
         D.level = s;
         const int dvar = (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[1][std::min(s, midbf_plan::VMAXLEV - 1)];
-        if (mfma && is_split16(prec) && dvar >= 5 && lv.kmax <= SPLIT16_RESIDENT_K && (nrhs == 1 || lat || s > 0)) {
+        if (mfma && is_split16(prec) && lv.groups > 0 && !adjoint) {
+            // split 16-bit, s >= 1: one dense block per group, run by the middle kernels
+            MidArgs m{};
+            m.nr = lv.d_g_nr;
+            m.nc = lv.d_g_nc;
+            m.off = lv.d_g_tile_off;
+            m.S = lv.g_T[prec];
+            m.pieces = h->P;
+            m.in_off = lv.d_g_in_off;
+            m.in_len = lv.d_g_in_len;
+            m.out_off = lv.d_g_out_off;
+            m.out_len = lv.d_g_out_len;
+            m.in = buf[o ^ 1];
+            m.out = buf[o];
+            m.nrhs = nrhs;
+            m.in_max = lv.g_nc_max;
+            m.out_max = lv.g_nr_max;
+            m.mchunks = 1;
+            D.a.mid = m;
+            D.which = LevelKernel::DownDense;
+            D.grid = dim3();
+            D.smem = 0;
+            D.bytes = (double)lv.g_tiles * BF16_TILE_BYTES + (double)lv.groups * 48 + vin + vout;
+            D.flops = fl * lv.g_entries * nrhs;
+            D.mfma_count = lv.groups;
+            out.push_back(D);
+        } else if (mfma && is_split16(prec) && dvar >= 5 && lv.kmax <= SPLIT16_RESIDENT_K && (nrhs == 1 || lat || s > 0)) {
             // split 16-bit with z resident: the siblings of each group add into its candidate rows
             D.which = LevelKernel::DownGroup;
             D.grid = dim3();

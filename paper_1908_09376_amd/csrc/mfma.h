@@ -25,7 +25,8 @@ void launch_transpose(const TransposeArgs& A, hipStream_t s);
 
 // Split 16-bit variants of the up / down / middle kernels (factors stored as
 // MFMA fragment tiles; tile_off gives each middle block's first tile), for
-// elem = SPLIT16_BF16 or SPLIT16_FP16.
+// elem = SPLIT16_BF16 or SPLIT16_FP16.  DownDense runs the middle kernels on
+// the group blocks of a down step (MidArgs; tile_off = their first tiles).
 constexpr int BF16_VARIANTS = 10;
 // Ranks up to which the split down kernels keep z in LDS (variants 5-9 then
 // run the grouped down pass, LevelKernel::DownGroup).
@@ -41,6 +42,12 @@ constexpr long long BF16_TILE_BYTES = 4096;
 // column side stores A = T (k x (n-k)), the row side (transposed = true) A = T^T.
 void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k_w, const int* n_w, int count,
                     bool transposed, void* out, const long long* tile_off, hipStream_t s);
+// Pack the dense candidate-order block of every group of P sibling row
+// decompositions (one step, going down) from the siblings' own tiles; per group
+// nr = n rows, nc = sum of k columns, first tile at tile_off.
+void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, const int* perm, void* const* T,
+                      const int* nr, const int* nc, const long long* tile_off, long long groups, void* out,
+                      hipStream_t s);
 // Pack column-major FP32 middle blocks into tiles.
 void pack_bf16_blocks(int elem, const float2* S, const long long* s_off, const int* nr, const int* nc,
                       long long count, void* out, const long long* tile_off, hipStream_t s);

@@ -922,7 +922,98 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
     }
 }
 
+// The dense block of a group of P sibling row decompositions (one step):
+// U_g(r, off_t + i) = entry (r, i) of Pi_t [I; T_t^T], r a candidate position
+// (0 <= r < n, shared by the siblings), i < k_t, off_t = k_0 + ... + k_{t-1}.
+// Built from the siblings' own split tiles (A_t = T_t^T, (n - k_t) x k_t), so
+// the hi / lo values are the same ones; the identity entries are exact.
+struct PackGroupArgs {
+    int P;
+    const int* k;                 // per ID
+    const long long* perm_off;
+    const int* perm;
+    void* const* T;               // per ID: its split tiles
+    const int* nr;                // per group: n
+    const int* nc;                // per group: sum of k
+    const long long* tile_off;    // per group: first tile
+    void* out;
+    long long g0;                 // first group of this launch
+};
+
+constexpr int GROUP_NMAX = BF16_CROW_MAX;
+
+template <class E>
+__global__ __launch_bounds__(256) void pack_group_kernel(PackGroupArgs A) {
+    __shared__ int inv[MAX_P][GROUP_NMAX];       // candidate position -> place in sibling t's permutation
+    __shared__ int kt_[MAX_P], off_[MAX_P + 1];
+    const long long g = A.g0 + blockIdx.x;
+    const int n = A.nr[g], nc = A.nc[g], P = A.P;
+    if (threadIdx.x == 0) {
+        off_[0] = 0;
+        for (int t = 0; t < P; ++t) {
+            kt_[t] = A.k[g * P + t];
+            off_[t + 1] = off_[t] + kt_[t];
+        }
+    }
+    for (int t = 0; t < P; ++t) {
+        const int* perm = A.perm + A.perm_off[g * P + t];
+        for (int p = threadIdx.x; p < n; p += blockDim.x) inv[t][perm[p]] = p;
+    }
+    __syncthreads();
+    const int mtiles = (n + 15) / 16, ktiles = (nc + KT - 1) / KT;
+    Frag<E>* out = (Frag<E>*)A.out + A.tile_off[g] * 64;
+    const long long nfr = (long long)mtiles * ktiles * 64;
+    for (long long e = threadIdx.x; e < nfr; e += blockDim.x) {
+        const int lane = (int)(e & 63);
+        const long long tile = e >> 6;
+        const int mt = (int)(tile / ktiles), kt = (int)(tile - (long long)mt * ktiles);
+        const int row = mt * 16 + (lane & 15);
+        const int c0 = kt * KT + (lane >> 4) * 8;
+        Frag<E> f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int col = c0 + i;
+            E rh = (E)0.f, ih = (E)0.f, rl = (E)0.f, il = (E)0.f;
+            if (row < n && col < nc) {
+                int t = 0;
+                while (col >= off_[t + 1]) ++t;
+                const int ii = col - off_[t], k = kt_[t], pos = inv[t][row];
+                if (pos < k) {
+                    if (pos == ii) rh = (E)1.f;
+                } else {
+                    // element (j, ii) of A_t = T_t^T in its own tiles
+                    const int j = pos - k, ktl = (k + KT - 1) / KT;
+                    const long long stile = (long long)(j >> 4) * ktl + (ii >> 5);
+                    const int sl = (j & 15) + 16 * ((ii & 31) >> 3), si = ii & 7;
+                    const E* src = (const E*)((const Frag<E>*)A.T[g * P + t] + stile * 64 + sl);
+                    rh = src[si];
+                    ih = src[8 + si];
+                    rl = src[16 + si];
+                    il = src[24 + si];
+                }
+            }
+            f.rh[i] = rh;
+            f.ih[i] = ih;
+            f.rl[i] = rl;
+            f.il[i] = il;
+        }
+        out[e] = f;
+    }
+}
+
 }  // namespace
+
+void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, const int* perm, void* const* T,
+                      const int* nr, const int* nc, const long long* tile_off, long long groups, void* out,
+                      hipStream_t s) {
+    for (long long g0 = 0; g0 < groups; g0 += 65535) {
+        const unsigned cnt = (unsigned)std::min<long long>(65535, groups - g0);
+        PackGroupArgs A{P, k, perm_off, perm, T, nr, nc, tile_off, out, g0};
+        if (elem == SPLIT16_FP16) hipLaunchKernelGGL(pack_group_kernel<_Float16>, dim3(cnt), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL(pack_group_kernel<__bf16>, dim3(cnt), dim3(256), 0, s, A);
+        MIDBF_HIP(hipGetLastError());
+    }
+}
 
 namespace {
 // Up and middle with multi-tile B stages and streamed A; down with z resident
@@ -1004,6 +1095,7 @@ void launch_pack(const PackTilesArgs& P, int elem, unsigned count, hipStream_t s
 
 void launch_bf16_kernel(int elem, LevelKernel which, int variant, const void* args, long long count, int nrhs,
                         void* scratch, const long long* tile_off, hipStream_t s) {
+    if (which == LevelKernel::DownDense) which = LevelKernel::Middle;     // same kernels, group blocks
     if (elem == SPLIT16_FP16) launch_split16<_Float16>(which, variant, args, count, nrhs, scratch, tile_off, s);
     else launch_split16<__bf16>(which, variant, args, count, nrhs, scratch, tile_off, s);
 }

@@ -34,6 +34,21 @@ struct LevelSide {
     int* d_perm = nullptr;                // candidate positions, skeleton first
     int* d_skel = nullptr;                // skeleton lattice point numbers at y_off
     void** d_T[NPREC] = {};               // per-ID pointer to its T block
+    // Split 16-bit, row side, s >= 1: per group of P siblings (IDs g P + t) the
+    // dense candidate-order block [Pi_0 [I; T_0^T] ... Pi_{P-1} [I; T_{P-1}^T]]
+    // (n x sum k) as fragment tiles, with piece tables in the middle's form:
+    // inputs = the siblings' z vectors, outputs = the candidate rows (the
+    // children's pieces of the previous level).  groups = 0: not built.
+    long long groups = 0, g_tiles = 0, g_entries = 0;
+    int g_nr_max = 0, g_nc_max = 0;
+    int* d_g_nr = nullptr;
+    int* d_g_nc = nullptr;
+    long long* d_g_tile_off = nullptr;
+    long long* d_g_in_off = nullptr;
+    int* d_g_in_len = nullptr;
+    long long* d_g_out_off = nullptr;
+    int* d_g_out_len = nullptr;
+    void* g_T[NPREC] = {};
     std::vector<void*> chunks;            // device allocations owned by this level
 };
 
