@@ -626,12 +626,12 @@ __global__ __launch_bounds__(NT) void down_group16(DownArgs A) {
 
 // Rows [base, base + 16) of C = A B for one wave (one row tile), over K in
 // stages of RCT K-tiles: B stages double-buffered in LDS (all threads split and
-// store them), A fragments streamed per wave two tiles ahead across stage
+// store them), A fragments streamed per wave AD tiles ahead across stage
 // boundaries.  Every thread of the workgroup must call this.  RCT * 256
 // fragment lanes per stage split evenly over NT threads.
 template <int NT> constexpr int rct_for() { return NT == 768 ? 3 : 4; }
 
-template <class E, int NT, class BOff>
+template <class E, int NT, int AD, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
                            int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB) {
     constexpr int RCT = rct_for<NT>();
@@ -663,10 +663,11 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
         }
     };
     auto tile_at = [&](int kt) { return Atiles[((long long)mt * ktiles + kt) * 64 + l]; };
-    Frag<E> f0[1], f1, f2;
+    Frag<E> fa[AD + 1];                             // the tile in use and AD requested ahead
     if (active) {
-        f0[0] = tile_at(0);
-        if (ktiles > 1) f1 = tile_at(1);
+#pragma unroll
+        for (int i = 0; i < AD; ++i)
+            if (i < ktiles) fa[i] = tile_at(i);
     }
     loadB(0);
     __syncthreads();          // the previous user of sB is done
@@ -681,22 +682,23 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
             for (int c = 0; c < RCT; ++c) {
                 const int kt = st * RCT + c;
                 if (kt < ktiles) {
-                    if (kt + 2 < ktiles) f2 = tile_at(kt + 2);
+                    if (kt + AD < ktiles) fa[AD] = tile_at(kt + AD);
+                    const Frag<E> a0[1] = {fa[0]};
                     if constexpr (NT >= 768) {
                         // one B fragment at a time (register budget of 12 or 16 waves)
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
                             const Frag<E> b = lds_frag(sb + c * 4 + nt, l);
-                            kstep1_bf16<E, 1>(cr, ci, f0, b, nt, 1);
+                            kstep1_bf16<E, 1>(cr, ci, a0, b, nt, 1);
                         }
                     } else {
                         Frag<E> b[4];
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) b[nt] = lds_frag(sb + c * 4 + nt, l);
-                        kstep_bf16<E, 1>(cr, ci, f0, b, 1);
+                        kstep_bf16<E, 1>(cr, ci, a0, b, 1);
                     }
-                    f0[0] = f1;
-                    f1 = f2;
+#pragma unroll
+                    for (int i = 0; i < AD; ++i) fa[i] = fa[i + 1];
                 }
             }
         }
@@ -754,7 +756,7 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
             const int base = m0 + wave * 16;
             floatx4 cr[1][4], ci[1][4];
             zero_acc<1>(cr, ci);
-            gemm_res16<E, NT>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB);
+            gemm_res16<E, NT, 2>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB);
             epi(base, cr, ci);
         }
     };
@@ -802,7 +804,7 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
         const int base = m0 + wave * 16;
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
-        gemm_res16<E, NT>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB);
+        gemm_res16<E, NT, 2>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
