@@ -66,7 +66,7 @@ def traffic_for(kernel: str, variant):
     rec = data.get(kernel)
     if not rec or rec.get("source_sha") != source_sha(kernel_sources(kernel)):
         return None
-    if rec.get("variant") is not None and rec["variant"] != variant:
+    if rec.get("variants") is not None and variant not in rec["variants"]:
         return None
     return rec["hbm_bytes_per_launch"]
 
