@@ -56,22 +56,23 @@ def source_sha(files: list[str]) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, variant):
-    """HBM bytes per launch from the committed counter summary, if taken on this kernel source and variant."""
+def traffic_for(kernel: str, variant, workload: str):
+    """HBM bytes per launch from the committed counter summary, if taken on this workload, kernel source
+    and variant."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
     rec = data.get(kernel)
-    if not rec or rec.get("source_sha") != source_sha(kernel_sources(kernel)):
+    if not rec or rec.get("workload") != workload or rec.get("source_sha") != source_sha(kernel_sources(kernel)):
         return None
     if rec.get("variants") is not None and variant not in rec["variants"]:
         return None
     return rec["hbm_bytes_per_launch"]
 
 
-def roofline(dominant: dict, prec: str, variant=None):
+def roofline(dominant: dict, prec: str, variant=None, workload: str = ""):
     launches = dominant["launches"]
     t = dominant["total_ms"] / 1e3 / launches
     bytes_per = dominant["bytes"] / launches
@@ -87,12 +88,12 @@ def roofline(dominant: dict, prec: str, variant=None):
         bound = "mfma" if ("mfma" in dominant["name"] or prec in ("bf16x3", "fp16x3")) else "alu"
         ach = flops_per / t / 1e12
         return {"bound": bound, "achieved": round(ach, 3), "peak": peak_tf, "unit": "TFLOP/s",
-                "frac": round(ach / peak_tf, 4), "traffic": traffic_for(dominant["name"], variant),
+                "frac": round(ach / peak_tf, 4), "traffic": traffic_for(dominant["name"], variant, workload),
                 "kernel": dominant["name"], "avg_ms": round(t * 1e3, 4),
                 "algorithmic_bytes_per_launch": bytes_per, "flops_per_launch": flops_per}
     ach = bytes_per / t / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
-            "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": traffic_for(dominant["name"], variant),
+            "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": traffic_for(dominant["name"], variant, workload),
             "kernel": dominant["name"], "avg_ms": round(t * 1e3, 4),
             "algorithmic_bytes_per_launch": bytes_per, "flops_per_launch": flops_per}
 
@@ -317,7 +318,7 @@ def main() -> int:
     if variants is not None:   # tuned variant of the dominant kernel's kind (up, down at the top step; middle)
         kind = 2 if dominant["name"].startswith("middle") else (0 if dominant["name"].startswith("up") else 1)
         dom_variant = variants[kind]
-    roof = roofline(dominant, args.precision, dom_variant)
+    roof = roofline(dominant, args.precision, dom_variant, w.name)
     kernels = {r["name"]: {"launches": r["launches"], "avg_ms": round(r["total_ms"] / r["launches"], 4),
                            "GB": round(r["bytes"] / r["launches"] / 1e9, 4)}
                for r in kt}
@@ -336,7 +337,7 @@ def main() -> int:
         if v32 is not None:
             dv32 = v32[2 if dom32["name"].startswith("middle") else (0 if dom32["name"].startswith("up") else 1)]
         fp32 = {"value": round(nrhs * args.steps / wall32, 2), "ms_per_step": round(wall32 / args.steps * 1e3, 4),
-                "tuned_variants": v32, "roofline": roofline(dom32, "fp32", dv32)}
+                "tuned_variants": v32, "roofline": roofline(dom32, "fp32", dv32, w.name)}
         g32_np = g32.to(torch.complex128).cpu().numpy().T
         del f32, g32
         log(f"[bench] fp32 beside: {fp32['ms_per_step']:.3f} ms/step, {fp32['value']:.1f} RHS-applies/s")
