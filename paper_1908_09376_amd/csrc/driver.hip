@@ -65,6 +65,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::Transpose: return "transpose";
         case LevelKernel::DownGroup: return "down_group";
         case LevelKernel::DownDense: return "down_dense";
+        case LevelKernel::UpLeafCopy: return "up_copy";
     }
     return "?";
 }
@@ -91,6 +92,10 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     auto go = [&] {
         if (which == LevelKernel::Transpose) {
             launch_transpose(*(const TransposeArgs*)args, st);
+            return;
+        }
+        if (which == LevelKernel::UpLeafCopy) {
+            launch_up_leaf_copy(*(const UpArgs*)args, mfma_count, nrhs, st);
             return;
         }
         if (mfma_count > 0) {
@@ -236,6 +241,12 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         D.flops = fl * lv.entries * nrhs;
         D.mfma_count = mfma ? lv.nid : 0;
         D.level = s;
+        if (mfma && s == 0 && lv.entries == 0 && h->n0 <= 64 && !adjoint) {
+            // every leaf keeps all its points: a staged copy per leaf (vin read once)
+            D.which = LevelKernel::UpLeafCopy;
+            D.mfma_count = groups;
+            D.flops = 0;
+        }
         out.push_back(D);
         o ^= 1;
     }

@@ -22,6 +22,10 @@ void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long l
 
 // The external <-> row-major transposes around a matrix-core apply.
 void launch_transpose(const TransposeArgs& A, hipStream_t s);
+// The first up step when every leaf decomposition keeps all its points (no T):
+// per leaf, the caller's block is staged once and copied to the P partners'
+// skeleton rows.  groups = leaves; complex64.
+void launch_up_leaf_copy(const UpArgs& A, long long groups, int nrhs, hipStream_t s);
 
 // Split 16-bit variants of the up / down / middle kernels (factors stored as
 // MFMA fragment tiles; tile_off gives each middle block's first tile), for

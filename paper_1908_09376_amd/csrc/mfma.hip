@@ -483,7 +483,47 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
     }
 }
 
+// The first up step when no leaf decomposition has redundant points: y rows of
+// partner t are x at the leaf points perm_t[i].  The leaf's 64-column block of
+// x is read once (runs of consecutive lattice points, coalesced per column)
+// into LDS and written as whole rows for each of the P partners.
+__global__ __launch_bounds__(256) void up_leaf_copy(UpArgs A) {
+    extern __shared__ __align__(16) float2 xs[];      // n0 x (NRHS + 1)
+    __shared__ int crow[4096];
+    const long long g = blockIdx.x;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const int n0 = candidate_rows<256>(crow, A.G, 0, g, 0, 1, nullptr, nullptr);
+    __syncthreads();
+    const float2* x = (const float2*)A.ext;
+    for (int e = threadIdx.x; e < n0 * NRHS; e += 256) {
+        const int r = e / n0, c = e - r * n0;
+        xs[c * (NRHS + 1) + r] = r < nr ? x[(long long)(r0 + r) * A.ld + crow[c]] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float2* out = (float2*)A.out;
+    for (int t = 0; t < A.G.P; ++t) {
+        const long long id = g * A.G.P + t;
+        const int k = A.lev.k[id];
+        const int* perm = A.lev.perm + A.lev.perm_off[id];
+        const long long yo = A.lev.y_off[id];
+        for (int e = threadIdx.x; e < k * NRHS; e += 256) {
+            const int i = e / NRHS, r = e - i * NRHS;
+            if (r < nr) out[(yo + i) * A.nrhs + r0 + r] = xs[perm[i] * (NRHS + 1) + r];
+        }
+    }
+}
+
 }  // namespace
+
+void launch_up_leaf_copy(const UpArgs& A, long long groups, int nrhs, hipStream_t s) {
+    MIDBF_CHECK(A.G.n0 <= 4096 && A.ext, MIDBF_ERR_ARG, "leaf copy needs the external block and n0 <= 4096");
+    const size_t smem = (size_t)A.G.n0 * (NRHS + 1) * sizeof(float2);
+    MIDBF_CHECK(smem <= 64 * 1024, MIDBF_ERR_UNIMPLEMENTED, "leaf block exceeds the copy kernel's LDS");
+    const dim3 grid((unsigned)groups, (nrhs + NRHS - 1) / NRHS);
+    hipLaunchKernelGGL(up_leaf_copy, grid, dim3(256), smem, s, A);
+    MIDBF_HIP(hipGetLastError());
+}
 
 void launch_transpose(const TransposeArgs& A, hipStream_t s) {
     const dim3 grid((unsigned)((A.N + 63) / 64), (unsigned)((A.nrhs + 63) / 64));
