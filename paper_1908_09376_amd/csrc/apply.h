@@ -118,7 +118,7 @@ __device__ inline void middle_rows(int* crow_in, int* crow_out, const MidArgs& A
 }
 
 enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum, Transpose, DownGroup, DownDense,
-                         UpLeafCopy };
+                         UpLeafCopy, DownLeaf };
 
 // Complex64 block transpose from a row-major N x nrhs copy (element (p, r)
 // at src[p * nrhs + r]) to the external column-major layout (element (p, r)

@@ -66,6 +66,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::DownGroup: return "down_group";
         case LevelKernel::DownDense: return "down_dense";
         case LevelKernel::UpLeafCopy: return "up_copy";
+        case LevelKernel::DownLeaf: return "down_leaf";
     }
     return "?";
 }
@@ -344,6 +345,15 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
             D.bytes = (double)lv.g_tiles * BF16_TILE_BYTES + (double)lv.groups * 48 + vin + vout;
             D.flops = fl * lv.g_entries * nrhs;
             D.mfma_count = lv.groups;
+            out.push_back(D);
+        } else if (mfma && is_split16(prec) && s == 0 && h->n0 <= 64 && !adjoint && (nrhs == 1 || lat)) {
+            // split 16-bit leaves: the P siblings summed in LDS, each point's row written once
+            D.which = LevelKernel::DownLeaf;
+            D.grid = dim3();
+            D.smem = 0;
+            D.bytes = fac + vin + vout;
+            D.flops = fl * lv.entries * nrhs;
+            D.mfma_count = groups;
             out.push_back(D);
         } else if (mfma && is_split16(prec) && dvar >= 5 && lv.kmax <= SPLIT16_RESIDENT_K && (nrhs == 1 || lat || s > 0)) {
             // split 16-bit with z resident: the siblings of each group add into its candidate rows

@@ -624,6 +624,86 @@ __global__ __launch_bounds__(NT) void down_group16(DownArgs A) {
     }
 }
 
+// The last down step (the leaves, n0 <= 64 points): one workgroup per leaf
+// sums its P siblings' contributions in LDS and writes each point's row once
+// (row-major, nrhs wide: the lattice copy, or with one right-hand side the
+// caller's block).  Every point first gets the z_t rows of the siblings that
+// keep it as a skeleton, in sibling order (one thread per point and column, so
+// the P loads are in flight together); then T_t^T z_t is added on the other
+// points, sibling by sibling.  z_t resident (k <= n0 <= 64).
+constexpr int LEAF_MAX = 64;
+
+template <class E>
+__global__ __launch_bounds__(256) void down_leaf16(DownArgs A) {
+    __shared__ float2 acc[LEAF_MAX][NRHS + 1];
+    __shared__ int crow[LEAF_MAX];
+    __shared__ int inv[MAX_P][LEAF_MAX];
+    __shared__ int ks[MAX_P];
+    __shared__ long long yos[MAX_P];
+    __shared__ LFrag<E> sB[2 * 4];
+    const long long g = blockIdx.x;
+    const int r0 = blockIdx.y * NRHS;
+    const int nr = min(NRHS, A.nrhs - r0);
+    const int n0 = A.G.n0, P = A.G.P;
+    const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4;
+    candidate_rows<256>(crow, A.G, 0, g, 0, 1, nullptr, nullptr);
+    if (tid < P) {
+        ks[tid] = A.lev.k[g * P + tid];
+        yos[tid] = A.lev.y_off[g * P + tid];
+    }
+    for (int e = tid; e < P * n0; e += 256) {
+        const int t = e / n0, p = e - t * n0;
+        inv[t][A.lev.perm[A.lev.perm_off[g * P + t] + p]] = p;
+    }
+    __syncthreads();
+    const float2* zin = (const float2*)A.in;
+    for (int e = tid; e < n0 * NRHS; e += 256) {
+        const int p = e / NRHS, r = e - p * NRHS;
+        float2 sum = make_float2(0.f, 0.f);
+        if (r < nr) {
+#pragma unroll
+            for (int t = 0; t < MAX_P; ++t) {
+                if (t < P && inv[t][p] < ks[t]) {
+                    const float2 v = zin[(yos[t] + inv[t][p]) * A.nrhs + r0 + r];
+                    sum = make_float2(sum.x + v.x, sum.y + v.y);
+                }
+            }
+        }
+        acc[p][r] = sum;
+    }
+    for (int t = 0; t < P; ++t) {
+        const long long id = g * P + t;
+        const int k = ks[t], nred = n0 - k;
+        if (nred == 0) continue;      // (uniform over the workgroup)
+        __syncthreads();          // acc holds the earlier contributions; sB free
+        const int* perm = A.lev.perm + A.lev.perm_off[id];
+        const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
+        const long long yo = yos[t];
+        auto epi = [&](int base, const floatx4 (&cr)[1][4], const floatx4 (&ci)[1][4]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + 4 * lk + v;
+                if (row < nred) {
+                    float2* d = acc[perm[k + row]];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const int r = nt * 16 + lr;
+                        d[r] = make_float2(d[r].x + cr[0][nt][v], d[r].y + ci[0][nt][v]);
+                    }
+                }
+            }
+        };
+        gemm_resident<E, 256, false>(Tt, nred, k, zin + yo * A.nrhs + r0,
+                                     [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
+    }
+    __syncthreads();
+    float2* outp = A.ext ? (float2*)A.ext : (float2*)A.out;
+    for (int e = tid; e < n0 * NRHS; e += 256) {
+        const int p = e / NRHS, r = e - p * NRHS;
+        if (r < nr) outp[(long long)crow[p] * A.nrhs + r0 + r] = acc[p][r];
+    }
+}
+
 // Rows [base, base + 16) of C = A B for one wave (one row tile), over K in
 // stages of RCT K-tiles: B stages double-buffered in LDS (all threads split and
 // store them), A fragments streamed per wave AD tiles ahead across stage
@@ -1098,6 +1178,15 @@ void launch_pack(const PackTilesArgs& P, int elem, unsigned count, hipStream_t s
 void launch_bf16_kernel(int elem, LevelKernel which, int variant, const void* args, long long count, int nrhs,
                         void* scratch, const long long* tile_off, hipStream_t s) {
     if (which == LevelKernel::DownDense) which = LevelKernel::Middle;     // same kernels, group blocks
+    if (which == LevelKernel::DownLeaf) {
+        const DownArgs& a = *(const DownArgs*)args;
+        MIDBF_CHECK(a.G.n0 <= LEAF_MAX && a.s == 0, MIDBF_ERR_ARG, "leaf down pass needs n0 <= 64 at the leaves");
+        const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
+        if (elem == SPLIT16_FP16) hipLaunchKernelGGL(down_leaf16<_Float16>, grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(down_leaf16<__bf16>, grid, dim3(256), 0, s, a);
+        MIDBF_HIP(hipGetLastError());
+        return;
+    }
     if (elem == SPLIT16_FP16) launch_split16<_Float16>(which, variant, args, count, nrhs, scratch, tile_off, s);
     else launch_split16<__bf16>(which, variant, args, count, nrhs, scratch, tile_off, s);
 }
