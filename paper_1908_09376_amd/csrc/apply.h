@@ -87,6 +87,7 @@ struct MidArgs {
     int in_max, out_max;     // largest column / row count of a block (matrix-core index tables)
     int chunk;               // VALU path: input entries staged in LDS per pass
     int mchunks;             // matrix-core FP32 path: workgroups splitting the rows of one block
+    const int* ang;          // split 16-bit: the blocks' phase tiles (see mfma.h), or null
 };
 
 // Input and output row numbers of middle block bi (the concatenations of its

@@ -569,6 +569,10 @@ void build_middle(midbf_plan* h, hipStream_t st) {
             pack_bf16_blocks(q == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, S32, M.d_off, M.d_nr, M.d_nc, M.nblk,
                              M.S[q], M.d_tile_off, st);
         }
+        // the same blocks as their phases, one copy for both 16-bit types
+        M.ang_bytes = tt * ANGLE_TILE_BYTES;
+        M.ang = dalloc<char>((size_t)std::max<long long>(tt, 1) * ANGLE_TILE_BYTES);
+        pack_angle_tiles(h->ph, M.d_nr, M.d_nc, d_pts_off, d_pts, M.d_tile_off, M.nblk, M.ang, st);
         MIDBF_HIP(hipStreamSynchronize(st));
         if (!(h->keep & MIDBF_KEEP_FP32)) {
             (void)hipFree(S32);          // kept only as the source of the tiles
@@ -590,6 +594,7 @@ void destroy_plan(midbf_plan* h) {
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(M.d_nr); f(M.d_nc); f(M.d_off); f(M.d_in_off); f(M.d_in_len); f(M.d_out_off); f(M.d_out_len);
     f(M.d_tile_off);
+    f(M.ang);
     for (int q = 0; q < NPREC; ++q) f(M.S[q]);
     for (int q = 0; q < NPREC; ++q) {
         f(h->ws[q].buf[0]);

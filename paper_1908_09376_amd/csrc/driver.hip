@@ -268,6 +268,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.nrhs = nrhs;
         a.in_max = M.nc_max;
         a.out_max = M.nr_max;
+        a.ang = (is_split16(prec) && !adjoint) ? (const int*)M.ang : nullptr;
         // FP32 matrix cores: split the rows of few large blocks over several workgroups
         a.mchunks = (mfma && prec == PREC_FP32)
                         ? (int)std::max<long long>(1, std::min<long long>((2048 + M.nblk - 1) / std::max<long long>(M.nblk, 1),

@@ -52,6 +52,14 @@ void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k
 void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, const int* perm, void* const* T,
                       const int* nr, const int* nc, const long long* tile_off, long long groups, void* out,
                       hipStream_t s);
+// The middle blocks K(rows, cols) = exp(2 pi i Phi) stored by their phases:
+// per 16 x 32 tile, lane l holds the eight entries of row l % 16, columns
+// 8 (l / 16) + i, as frac(Phi) - [frac(Phi) >= 1/2] in units of 2^-32 turns
+// (int32, 32 B per lane, 2 KB per tile; tiles at the blocks' tile_off).
+// pts: per block its nr row points, then its nc column points, at pts_off.
+constexpr long long ANGLE_TILE_BYTES = 2048;
+void pack_angle_tiles(const PhaseDesc& ph, const int* nr, const int* nc, const long long* pts_off, const int* pts,
+                      const long long* tile_off, long long count, void* out, hipStream_t s);
 // Pack column-major FP32 middle blocks into tiles.
 void pack_bf16_blocks(int elem, const float2* S, const long long* s_off, const int* nr, const int* nc,
                       long long count, void* out, const long long* tile_off, hipStream_t s);

@@ -17,6 +17,7 @@
 // B (the level vectors) is split on the fly while it is staged through LDS in
 // the same fragment order.
 #include <algorithm>
+#include <type_traits>
 
 #include "apply.h"
 #include "mfma.h"
@@ -93,6 +94,29 @@ template <class V> __device__ inline V neg8(V v) {     // sign flip of eight 16-
     intx4 x = __builtin_bit_cast(intx4, v);
     x ^= (int)0x80008000;
     return __builtin_bit_cast(V, x);
+}
+
+// One lane's eight entries exp(2 pi i t) of a phase tile (t in units of 2^-32
+// turns, |t| <= 1/2), split into hi / lo planes.  v_sin_f32 / v_cos_f32 take
+// their argument in turns.
+struct AngRaw {
+    intx4 a0, a1;
+};
+
+template <class E> __device__ inline Frag<E> angle_frag(const AngRaw& r) {
+    const intx4 a0 = r.a0, a1 = r.a1;
+    Frag<E> f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float t = (float)(i < 4 ? a0[i] : a1[i - 4]) * 0x1p-32f;
+        const float c = __builtin_amdgcn_cosf(t), s = __builtin_amdgcn_sinf(t);
+        const E ch = (E)c, sh = (E)s;
+        f.rh[i] = ch;
+        f.ih[i] = sh;
+        f.rl[i] = (E)(c - (float)ch);
+        f.il[i] = (E)(s - (float)sh);
+    }
+    return f;
 }
 
 template <class E, int MTW>
@@ -711,9 +735,10 @@ __global__ __launch_bounds__(256) void down_leaf16(DownArgs A) {
 // fragment lanes per stage split evenly over NT threads.
 template <int NT> constexpr int rct_for() { return NT == 768 ? 3 : 4; }
 
-template <class E, int NT, int AD, class BOff>
+template <class E, int NT, int AD, bool ANG = false, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
-                           int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB) {
+                           int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB,
+                           const int* __restrict__ Aang = nullptr) {
     constexpr int RCT = rct_for<NT>();
     constexpr int FPT = RCT * 256 / NT;            // B fragments staged per thread and stage
     static_assert(FPT >= 1 && FPT * NT == RCT * 256, "stage must split evenly over the threads");
@@ -742,8 +767,20 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
             lds_split_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q]);
         }
     };
-    auto tile_at = [&](int kt) { return Atiles[((long long)mt * ktiles + kt) * 64 + l]; };
-    Frag<E> fa[AD + 1];                             // the tile in use and AD requested ahead
+    // A tiles in flight stay raw (phase tiles are expanded only when used)
+    using Raw = std::conditional_t<ANG, AngRaw, Frag<E>>;
+    auto tile_at = [&](int kt) -> Raw {
+        const long long idx = ((long long)mt * ktiles + kt) * 64 + l;
+        if constexpr (ANG) {
+            AngRaw r;
+            r.a0 = *(const intx4*)(Aang + idx * 8);
+            r.a1 = *(const intx4*)(Aang + idx * 8 + 4);
+            return r;
+        } else {
+            return Atiles[idx];
+        }
+    };
+    Raw fa[AD + 1];                                 // the tile in use and AD requested ahead
     if (active) {
 #pragma unroll
         for (int i = 0; i < AD; ++i)
@@ -763,7 +800,9 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
                 const int kt = st * RCT + c;
                 if (kt < ktiles) {
                     if (kt + AD < ktiles) fa[AD] = tile_at(kt + AD);
-                    const Frag<E> a0[1] = {fa[0]};
+                    Frag<E> a0[1];
+                    if constexpr (ANG) a0[0] = angle_frag<E>(fa[0]);
+                    else a0[0] = fa[0];
                     if constexpr (NT >= 768) {
                         // one B fragment at a time (register budget of 12 or 16 waves)
 #pragma unroll
@@ -848,7 +887,7 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
         run(xin + r0, [&](int j, int c) { return (long long)srcrow[j] * A.nrhs + c; });
 }
 
-template <class E, int NT>
+template <class E, int NT, bool ANG>
 __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* tile_off) {
     constexpr int NW = NT / 64;
     __shared__ int crow_in[CROW_MAX];
@@ -884,7 +923,8 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
         const int base = m0 + wave * 16;
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
-        gemm_res16<E, NT, 2>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB);
+        gemm_res16<E, NT, 2, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB,
+                                  ANG ? A.ang + tile_off[bi] * 512 : nullptr);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
@@ -1022,6 +1062,33 @@ struct PackGroupArgs {
     long long g0;                 // first group of this launch
 };
 
+__global__ __launch_bounds__(256) void pack_angle_kernel(PhaseDesc ph, const int* nr_, const int* nc_,
+                                                         const long long* pts_off, const int* pts,
+                                                         const long long* tile_off, int* out, long long b0) {
+    const long long b = b0 + blockIdx.x;
+    const int nr = nr_[b], nc = nc_[b];
+    const int* rp = pts + pts_off[b];
+    const int* cp = rp + nr;
+    const int mtiles = (nr + 15) / 16, ktiles = (nc + KT - 1) / KT;
+    int* o = out + tile_off[b] * 512;
+    const long long n = (long long)mtiles * ktiles * 512;
+    for (long long e = threadIdx.x; e < n; e += blockDim.x) {
+        const int i = (int)(e & 7);
+        const long long lt = e >> 3;
+        const int lane = (int)(lt & 63);
+        const long long tile = lt >> 6;
+        const int mt = (int)(tile / ktiles), kt = (int)(tile - (long long)mt * ktiles);
+        const int row = mt * 16 + (lane & 15), col = kt * KT + (lane >> 4) * 8 + i;
+        int v = 0;
+        if (row < nr && col < nc) {
+            double f = phase_frac(ph, rp[row], cp[col]);      // [0, 1)
+            if (f >= 0.5) f -= 1.0;
+            v = (int)fmax(-2147483648.0, fmin(2147483647.0, rint(f * 4294967296.0)));
+        }
+        o[e] = v;
+    }
+}
+
 constexpr int GROUP_NMAX = BF16_CROW_MAX;
 
 template <class E>
@@ -1085,6 +1152,16 @@ __global__ __launch_bounds__(256) void pack_group_kernel(PackGroupArgs A) {
 
 }  // namespace
 
+void pack_angle_tiles(const PhaseDesc& ph, const int* nr, const int* nc, const long long* pts_off, const int* pts,
+                      const long long* tile_off, long long count, void* out, hipStream_t s) {
+    for (long long b0 = 0; b0 < count; b0 += 65535) {
+        const unsigned cnt = (unsigned)std::min<long long>(65535, count - b0);
+        hipLaunchKernelGGL(pack_angle_kernel, dim3(cnt), dim3(256), 0, s, ph, nr, nc, pts_off, pts, tile_off,
+                           (int*)out, b0);
+        MIDBF_HIP(hipGetLastError());
+    }
+}
+
 void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, const int* perm, void* const* T,
                       const int* nr, const int* nc, const long long* tile_off, long long groups, void* out,
                       hipStream_t s) {
@@ -1111,7 +1188,8 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
         MidArgs a = *(const MidArgs*)args;
         a.mchunks = std::max(1, (a.out_max + NT / 4 - 1) / (NT / 4));
         const dim3 mgrid((unsigned)(count * a.mchunks), grid.y);
-        hipLaunchKernelGGL((middle_res16<E, NT>), mgrid, dim3(NT), 0, s, a, tile_off);
+        if (a.ang) hipLaunchKernelGGL((middle_res16<E, NT, true>), mgrid, dim3(NT), 0, s, a, tile_off);
+        else hipLaunchKernelGGL((middle_res16<E, NT, false>), mgrid, dim3(NT), 0, s, a, tile_off);
     }
     else if (which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT)
         hipLaunchKernelGGL((down_res16<E, NT>), grid, dim3(NT), 0, s, *(const DownArgs*)args, count,

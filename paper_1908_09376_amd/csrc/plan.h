@@ -71,6 +71,8 @@ struct Middle {
     void* S[NPREC] = {};                                // column-major blocks at off (split-16: fragment tiles)
     long long* d_tile_off = nullptr;                    // first bf16 tile of each block
     long long bf16_bytes = 0;
+    void* ang = nullptr;                                // phase tiles of the blocks (split 16-bit applies)
+    long long ang_bytes = 0;
 };
 
 struct Workspace {
