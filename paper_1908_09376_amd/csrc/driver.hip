@@ -291,7 +291,9 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
             D.which = adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle;
             D.grid = dim3((unsigned)cnt, tiles);
             D.smem = (size_t)std::min(width, ab.chunk) * rt * cs;
-            D.bytes = frac * ((double)M.total * cs + (double)M.nblk * 40 + vec);
+            // (split applies with phase tiles read 4 B per entry, padding included)
+            const double fac_bytes = ab.ang ? (double)M.ang_bytes : (double)M.total * cs;
+            D.bytes = frac * (fac_bytes + (double)M.nblk * 40 + vec);
             D.flops = frac * fl * M.total * nrhs;
             D.mfma_count = mfma ? cnt : 0;
             D.level = -1;
