@@ -35,19 +35,19 @@ constexpr int NRHS = MFMA_NRHS;  // columns per workgroup (4 tiles of 16)
 // products per complex product (Gauss): p1 += Ar Br, p2 += Ai Bi,
 // p3 += (Ar + Ai)(Br + Bi); then Cr = p1 - p2 and Ci = p3 - p1 - p2
 // (finish_gauss).  Each sweep issues independent MFMAs back to back.
-template <int MTW>
+template <int MTW, int NTC>
 __device__ inline void kstep(floatx4 (&p1)[MTW][4], floatx4 (&p2)[MTW][4], floatx4 (&p3)[MTW][4],
                              const float2 (&a)[MTW], const float2 (&b)[4], int ntiles) {
     float as[MTW], bs[4];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) as[mt] = a[mt].x + a[mt].y;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) bs[nt] = b[nt].x + b[nt].y;
+    for (int nt = 0; nt < NTC; ++nt) bs[nt] = b[nt].x + b[nt].y;
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
         if (mt < ntiles) {
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
+            for (int nt = 0; nt < NTC; ++nt) {
                 p1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].x, p1[mt][nt], 0, 0, 0);
                 p2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].y, b[nt].y, p2[mt][nt], 0, 0, 0);
                 p3[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[mt], bs[nt], p3[mt][nt], 0, 0, 0);
@@ -56,12 +56,12 @@ __device__ inline void kstep(floatx4 (&p1)[MTW][4], floatx4 (&p2)[MTW][4], float
     }
 }
 
-template <int MTW>
+template <int MTW, int NTC>
 __device__ inline void finish_gauss(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const floatx4 (&p3)[MTW][4]) {
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int nt = 0; nt < NTC; ++nt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float r = cr[mt][nt][v] - ci[mt][nt][v];
@@ -71,14 +71,19 @@ __device__ inline void finish_gauss(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4]
 }
 
 
-template <int MTW_, int KC_, bool PIPE_, int NT_ = MT>
+template <int MTW_, int KC_, bool PIPE_, int NT_ = MT, int NTC_ = 4>
 struct Cfg {
     static constexpr int MTW = MTW_;      // 16-row tiles per wave
     static constexpr int KC = KC_;        // K rows per LDS chunk
     static constexpr bool PIPE = PIPE_;   // chunk-deep register prefetch + double-buffered LDS
     static constexpr int NT = NT_;        // threads per workgroup
+    static constexpr int NTC = NTC_;      // 16-column tiles per workgroup (4: 64 right-hand sides)
+    static constexpr int W = NTC * 16;    // right-hand sides per workgroup
     static constexpr int ROUND = NT / 64 * MTW * 16;
 };
+
+// The same tiling with one 16-column tile (few right-hand sides).
+template <class C> using Narrow = Cfg<C::MTW, C::KC, C::PIPE, C::NT, 1>;
 
 // Rows [base, base + 16 MTW) of C (+)= A B for one wave.  A is column-major
 // with leading dimension M; brow(j, r) returns B[j][r] (j < K, r < nr).
@@ -90,8 +95,8 @@ struct Cfg {
 template <class C, int NT, class BRow>
 __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const float2* __restrict__ A, int M,
                           int K, int base, BRow brow, int nr, float2* sB) {
-    constexpr int MTW = C::MTW, KC = C::KC;
-    constexpr int BPT = KC * NRHS / NT;   // B elements staged per thread and chunk
+    constexpr int MTW = C::MTW, KC = C::KC, W = C::W, NTC = C::NTC;
+    constexpr int BPT = (KC * W + NT - 1) / NT;   // B elements staged per thread and chunk
     const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4;
     const int ntl = base < M ? min(MTW, (M - base + 15) / 16) : 0;
     const int nch = (K + KC - 1) / KC;
@@ -113,13 +118,14 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
     auto loadB = [&](int c0) {
 #pragma unroll
         for (int q = 0; q < BPT; ++q) {
-            const int e = tid + q * NT, jj = e / NRHS, r = e - jj * NRHS, j = c0 + jj;
-            bt[q] = (j < K && r < nr) ? brow(j, r) : make_float2(0.f, 0.f);
+            const int e = tid + q * NT, jj = e / W, r = e - jj * W, j = c0 + jj;
+            bt[q] = (e < KC * W && j < K && r < nr) ? brow(j, r) : make_float2(0.f, 0.f);
         }
     };
     auto storeB = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < BPT; ++q) sB[buf * KC * NRHS + tid + q * NT] = bt[q];
+        for (int q = 0; q < BPT; ++q)
+            if (tid + q * NT < KC * W) sB[buf * KC * W + tid + q * NT] = bt[q];
     };
     if constexpr (C::PIPE) {
         float2 acur[KC / 4][MTW], anext[KC / 4][MTW];
@@ -136,14 +142,14 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
                 for (int ks = 0; ks < KC / 4; ++ks) loadA1((c + 1) * KC + ks * 4 + lk, anext[ks]);
                 loadB((c + 1) * KC);
             }
-            const float2* sb = sB + (c & 1) * KC * NRHS;
+            const float2* sb = sB + (c & 1) * KC * W;
             if (ntl > 0) {
 #pragma unroll
                 for (int ks = 0; ks < KC / 4; ++ks) {
                     float2 bv[4];
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) bv[nt] = sb[(ks * 4 + lk) * NRHS + nt * 16 + lr];
-                    kstep<MTW>(cr, ci, p3, acur[ks], bv, ntl);
+                    for (int nt = 0; nt < NTC; ++nt) bv[nt] = sb[(ks * 4 + lk) * W + nt * 16 + lr];
+                    kstep<MTW, NTC>(cr, ci, p3, acur[ks], bv, ntl);
                 }
             }
             if (more) {
@@ -155,7 +161,7 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
             }
             __syncthreads();
         }
-        finish_gauss<MTW>(cr, ci, p3);
+        finish_gauss<MTW, NTC>(cr, ci, p3);
     } else {
         for (int c = 0; c < nch; ++c) {
             loadB(c * KC);
@@ -173,13 +179,13 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
                     if (ks + 1 < KC / 4) loadA1(c * KC + (ks + 1) * 4 + lk, an);
                     float2 bv[4];
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) bv[nt] = sB[(ks * 4 + lk) * NRHS + nt * 16 + lr];
-                    kstep<MTW>(cr, ci, p3, a, bv, ntl);
+                    for (int nt = 0; nt < NTC; ++nt) bv[nt] = sB[(ks * 4 + lk) * W + nt * 16 + lr];
+                    kstep<MTW, NTC>(cr, ci, p3, a, bv, ntl);
                 }
             }
         }
         __syncthreads();
-        finish_gauss<MTW>(cr, ci, p3);
+        finish_gauss<MTW, NTC>(cr, ci, p3);
     }
 }
 
@@ -239,12 +245,12 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     extern __shared__ int dyn_rows[];          // ncand_max candidate rows, then as many source rows
     int* crow = dyn_rows;
     int* srcrow = dyn_rows + A.ncand_max;
-    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
+    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
-    const int r0 = blockIdx.y * NRHS;
-    const int nr = min(NRHS, A.nrhs - r0);
+    const int r0 = blockIdx.y * C::W;
+    const int nr = min(C::W, A.nrhs - r0);
     candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
     // the leaves read the caller's block, or its row-major copy (A.ext null)
     const bool ext = A.s == 0 && A.ext;
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
                 if (row < k) {
                     const int src = crow[perm[row]];
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
+                    for (int nt = 0; nt < C::NTC; ++nt) {
                         const int r = nt * 16 + lr;
                         if (r < nr) {
                             const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
@@ -292,10 +298,10 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
 template <class C>
 __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, float2* scr) {
     constexpr int MTW = C::MTW;
-    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
+    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
-    const int r0 = blockIdx.y * NRHS;
-    const int nr = min(NRHS, A.nrhs - r0);
+    const int r0 = blockIdx.y * C::W;
+    const int nr = min(C::W, A.nrhs - r0);
     const float2* zin = (const float2*)A.in;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
@@ -303,8 +309,8 @@ __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, fl
     const float2* T = (const float2*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
     float2* w = scr + A.lev.perm_off[id] * A.nrhs;
-    for (int e = tid; e < k * NRHS; e += C::NT) {
-        const int i = e / NRHS, r = e - i * NRHS;
+    for (int e = tid; e < k * C::W; e += C::NT) {
+        const int i = e / C::W, r = e - i * C::W;
         if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
     }
     const float2* z = zin + yo * A.nrhs + r0;
@@ -322,7 +328,7 @@ __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, fl
                 if (row < nred) {
                     float2* d = w + (long long)perm[k + row] * A.nrhs + r0;
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
+                    for (int nt = 0; nt < C::NTC; ++nt) {
                         const int r = nt * 16 + lr;
                         if (r < nr) d[r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
                     }
@@ -380,11 +386,11 @@ __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     extern __shared__ int dyn_rows[];          // in_max input rows, then out_max output rows
     int* crow_in = dyn_rows;
     int* crow_out = dyn_rows + A.in_max;
-    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * NRHS];
+    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
     const long long bi = blockIdx.x / A.mchunks;
     const int chunk = (int)(blockIdx.x - bi * A.mchunks);
-    const int r0 = blockIdx.y * NRHS;
-    const int nr = min(NRHS, A.nrhs - r0);
+    const int r0 = blockIdx.y * C::W;
+    const int nr = min(C::W, A.nrhs - r0);
     const int M = A.nr[bi], K = A.nc[bi];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     middle_rows<C::NT>(crow_in, crow_out, A, bi);
@@ -409,7 +415,7 @@ __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
                 if (row < M) {
                     const long long dst = crow_out[row];
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
+                    for (int nt = 0; nt < C::NTC; ++nt) {
                         const int r = nt * 16 + lr;
                         if (r < nr) zout[dst * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
                     }
@@ -432,7 +438,7 @@ using V9 = Cfg<1, 32, true, 512>;
 
 template <class C>
 void launch_variant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch, hipStream_t s) {
-    const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
+    const dim3 grid((unsigned)count, (nrhs + C::W - 1) / C::W);
     switch (which) {
         case LevelKernel::Up: {
             const UpArgs& a = *(const UpArgs*)args;
@@ -444,7 +450,8 @@ void launch_variant(LevelKernel which, const void* args, long long count, int nr
             break;
         case LevelKernel::DownSum: {
             const DownArgs& a = *(const DownArgs*)args;
-            hipLaunchKernelGGL(down_sum, grid, dim3(MT), sizeof(int) * a.ncand_max, s, a, (const float2*)scratch);
+            const dim3 sgrid((unsigned)count, (nrhs + NRHS - 1) / NRHS);     // its own 64-column tiling
+            hipLaunchKernelGGL(down_sum, sgrid, dim3(MT), sizeof(int) * a.ncand_max, s, a, (const float2*)scratch);
             break;
         }
         case LevelKernel::Middle: {
@@ -531,19 +538,29 @@ void launch_transpose(const TransposeArgs& A, hipStream_t s) {
     MIDBF_HIP(hipGetLastError());
 }
 
+namespace {
+// 64 right-hand sides per workgroup, or one 16-column tile when there are at
+// most 16 (no matrix-core work on empty columns).
+template <class C>
+void launch_width(LevelKernel which, const void* args, long long count, int nrhs, void* scratch, hipStream_t s) {
+    if (nrhs <= 16) launch_variant<Narrow<C>>(which, args, count, nrhs, scratch, s);
+    else launch_variant<C>(which, args, count, nrhs, scratch, s);
+}
+}  // namespace
+
 void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
                         hipStream_t s) {
     switch (variant) {
-        case 0: launch_variant<V0>(which, args, count, nrhs, scratch, s); break;
-        case 1: launch_variant<V1>(which, args, count, nrhs, scratch, s); break;
-        case 2: launch_variant<V2>(which, args, count, nrhs, scratch, s); break;
-        case 3: launch_variant<V3>(which, args, count, nrhs, scratch, s); break;
-        case 4: launch_variant<V4>(which, args, count, nrhs, scratch, s); break;
-        case 5: launch_variant<V5>(which, args, count, nrhs, scratch, s); break;
-        case 6: launch_variant<V6>(which, args, count, nrhs, scratch, s); break;
-        case 7: launch_variant<V7>(which, args, count, nrhs, scratch, s); break;
-        case 8: launch_variant<V8>(which, args, count, nrhs, scratch, s); break;
-        case 9: launch_variant<V9>(which, args, count, nrhs, scratch, s); break;
+        case 0: launch_width<V0>(which, args, count, nrhs, scratch, s); break;
+        case 1: launch_width<V1>(which, args, count, nrhs, scratch, s); break;
+        case 2: launch_width<V2>(which, args, count, nrhs, scratch, s); break;
+        case 3: launch_width<V3>(which, args, count, nrhs, scratch, s); break;
+        case 4: launch_width<V4>(which, args, count, nrhs, scratch, s); break;
+        case 5: launch_width<V5>(which, args, count, nrhs, scratch, s); break;
+        case 6: launch_width<V6>(which, args, count, nrhs, scratch, s); break;
+        case 7: launch_width<V7>(which, args, count, nrhs, scratch, s); break;
+        case 8: launch_width<V8>(which, args, count, nrhs, scratch, s); break;
+        case 9: launch_width<V9>(which, args, count, nrhs, scratch, s); break;
         default: throw Error(MIDBF_ERR_ARG, "unknown matrix-core variant");
     }
 }
