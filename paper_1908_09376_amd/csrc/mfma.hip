@@ -496,7 +496,7 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
 // into LDS and written as whole rows for each of the P partners.
 __global__ __launch_bounds__(256) void up_leaf_copy(UpArgs A) {
     extern __shared__ __align__(16) float2 xs[];      // n0 x (NRHS + 1)
-    __shared__ int crow[4096];
+    __shared__ int crow[64];                          // n0 <= 64 (checked at launch)
     const long long g = blockIdx.x;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(256) void up_leaf_copy(UpArgs A) {
 }  // namespace
 
 void launch_up_leaf_copy(const UpArgs& A, long long groups, int nrhs, hipStream_t s) {
-    MIDBF_CHECK(A.G.n0 <= 4096 && A.ext, MIDBF_ERR_ARG, "leaf copy needs the external block and n0 <= 4096");
+    MIDBF_CHECK(A.G.n0 <= 64 && A.ext, MIDBF_ERR_ARG, "leaf copy needs the external block and n0 <= 64");
     const size_t smem = (size_t)A.G.n0 * (NRHS + 1) * sizeof(float2);
     MIDBF_CHECK(smem <= 64 * 1024, MIDBF_ERR_UNIMPLEMENTED, "leaf block exceeds the copy kernel's LDS");
     const dim3 grid((unsigned)groups, (nrhs + NRHS - 1) / NRHS);
