@@ -64,8 +64,8 @@ def traffic_for(kernel: str, variant, workload: str):
         return None
     with open(path) as fh:
         data = json.load(fh)
-    rec = data.get(kernel)
-    if not rec or rec.get("workload") != workload or rec.get("source_sha") != source_sha(kernel_sources(kernel)):
+    rec = data.get(f"{workload}/{kernel}")
+    if not rec or rec.get("source_sha") != source_sha(kernel_sources(kernel)):
         return None
     if rec.get("variants") is not None and variant not in rec["variants"]:
         return None
