@@ -69,7 +69,12 @@ typedef enum {
                                 and factor entries must stay below 65504 in magnitude    */
 } midbf_precision;
 
-/* Bits of midbf_params.precisions: which factor copies the build keeps. */
+/* Bits of midbf_params.precisions: which factor copies the build keeps.  A
+ * split copy (BF16 or FP16) holds the factors as MFMA fragment tiles, plus,
+ * for the down steps above the leaves, one dense block per group of 2^d
+ * sibling decompositions; the middle factor is also kept once as its phases
+ * (4 bytes per entry, shared by both split types).  Factors are built in FP64
+ * and rounded once into each kept copy. */
 #define MIDBF_KEEP_FP64 1u
 #define MIDBF_KEEP_FP32 2u
 #define MIDBF_KEEP_BF16 4u
