@@ -28,7 +28,7 @@ METRIC = "MIDBF Kf applies/sec (N=512Â², 64 RHS) vs FP64 apply at rel. L2 err â‰
 PEAK = {  # published MI355X figures
     "hbm_GBps": 8000.0,
     "fp32_vector_TF": 157.3,
-    "fp64_vector_TF": 78.6,
+    "fp64_TF": 78.6,          # vector and dense matrix (MFMA) alike
     "fp32_mfma_TF": 157.3,
     "bf16_mfma_TF": 2500.0,
 }
@@ -80,7 +80,7 @@ def roofline(dominant: dict, prec: str, variant=None, workload: str = ""):
     if prec in ("bf16x3", "fp16x3"):
         peak_tf = PEAK["bf16_mfma_TF"]      # dense bf16 and fp16 matrix peaks are equal
     elif prec == "fp64":
-        peak_tf = PEAK["fp64_vector_TF"]
+        peak_tf = PEAK["fp64_TF"]
     else:
         peak_tf = PEAK["fp32_mfma_TF"] if "mfma" in dominant["name"] else PEAK["fp32_vector_TF"]
     ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
@@ -299,7 +299,7 @@ def main() -> int:
 
     variants = None
     tune_s = None
-    if (args.precision == "fp32" and nrhs >= 16) or args.precision in ("bf16x3", "fp16x3"):
+    if (args.precision in ("fp32", "fp64") and nrhs >= 16) or args.precision in ("bf16x3", "fp16x3"):
         t0 = time.perf_counter()
         variants = F.tune(nrhs, args.precision)
         tune_s = time.perf_counter() - t0
@@ -347,9 +347,10 @@ def main() -> int:
     if not args.no_fp64 and args.precision != "fp64":
         f64 = torch.from_numpy(np.ascontiguousarray(f_np.T)).to("cuda:0")
         g64 = torch.empty_like(f64)
+        v64 = F.tune(nrhs, "fp64") if nrhs >= 16 else None
         steps64 = max(2, args.steps // 4)
         wall64, _ = time_applies(F, f64, g64, "fp64", steps64, 1, profile=False)
-        fp64 = {"value": nrhs * steps64 / wall64, "ms_per_step": wall64 / steps64 * 1e3}
+        fp64 = {"value": nrhs * steps64 / wall64, "ms_per_step": wall64 / steps64 * 1e3, "tuned_variants": v64}
         g64_np = g64.cpu().numpy().T
         del f64, g64
         log(f"[bench] fp64: {fp64['ms_per_step']:.3f} ms/step")

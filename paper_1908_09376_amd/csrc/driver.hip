@@ -92,7 +92,7 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
     auto go = [&] {
         if (which == LevelKernel::Transpose) {
-            launch_transpose(*(const TransposeArgs*)args, st);
+            launch_transpose(*(const TransposeArgs*)args, prec == PREC_FP64, st);
             return;
         }
         if (which == LevelKernel::UpLeafCopy) {
@@ -112,7 +112,8 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
                                                                    : h->mid.d_tile_off,
                                    st);
             else
-                launch_mfma_kernel(which, h->mfma_variant[kind][lv], args, mfma_count, nrhs, h->ws[prec].scratch, st);
+                launch_mfma_kernel(which, (prec == PREC_FP64 ? h->mfma64_variant : h->mfma_variant)[kind][lv], args,
+                                   mfma_count, nrhs, h->ws[prec].scratch, st, prec == PREC_FP64);
         }
         else launch_level_kernel(which, prec, rt, args, grid, smem, st);
     };
@@ -242,7 +243,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         D.flops = fl * lv.entries * nrhs;
         D.mfma_count = mfma ? lv.nid : 0;
         D.level = s;
-        if (mfma && s == 0 && lv.entries == 0 && h->n0 <= 64 && !adjoint) {
+        if (mfma && s == 0 && lv.entries == 0 && h->n0 <= 64 && !adjoint && prec != PREC_FP64) {
             // every leaf keeps all its points: a staged copy per leaf (vin read once)
             D.which = LevelKernel::UpLeafCopy;
             D.mfma_count = groups;
@@ -420,7 +421,8 @@ void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long 
     MIDBF_CHECK(!is_split16(prec) || (!adjoint && fits_bf16), MIDBF_ERR_UNIMPLEMENTED,
                 "the split 16-bit applies exist for the forward transform with candidate sets up to 2048");
     // matrix cores: split 16-bit always, FP32 for many right-hand sides
-    const bool mfma = is_split16(prec) || (prec == PREC_FP32 && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
+    const bool mfma = is_split16(prec) ||
+                      ((prec == PREC_FP32 || prec == PREC_FP64) && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
     const bool lat = mfma && nrhs > 1;   // row-major lattice copy around the leaf levels
     ensure_workspace(h, prec, nrhs, mfma, lat);
     const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
@@ -662,13 +664,17 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
         const int pi = prec_index(prec);
         hipStream_t st = (hipStream_t)stream;
         const bool bf = is_split16(pi) && (h->keep & (1u << pi));
-        auto& var = pi == PREC_FP16 ? h->fp16_variant : (pi == PREC_BF16 ? h->bf16_variant : h->mfma_variant);
-        const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
+        auto& var = pi == PREC_FP16   ? h->fp16_variant
+                    : pi == PREC_BF16 ? h->bf16_variant
+                    : pi == PREC_FP64 ? h->mfma64_variant
+                                      : h->mfma_variant;
+        const int nvar = bf ? BF16_VARIANTS : (pi == PREC_FP64 ? MFMA64_VARIANTS : MFMA_VARIANTS);
         constexpr int NL = midbf_plan::VMAXLEV;
-        if (bf || (pi == PREC_FP32 && nrhs >= MFMA_MIN_NRHS && (h->keep & MIDBF_KEEP_FP32))) {
+        const bool cores = (pi == PREC_FP32 || pi == PREC_FP64) && nrhs >= MFMA_MIN_NRHS && (h->keep & (1u << pi));
+        if (bf || cores) {
             void* f = nullptr;
             void* g = nullptr;
-            const size_t bytes = (size_t)h->N * nrhs * 8;
+            const size_t bytes = (size_t)h->N * nrhs * csize(pi);
             MIDBF_HIP(hipMalloc(&f, bytes));
             if (hipMalloc(&g, bytes) != hipSuccess) {
                 (void)hipFree(f);
@@ -735,12 +741,15 @@ midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* st
 midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants) {
     if (!h || !variants) return fail(MIDBF_ERR_ARG, "null argument");
     const bool bf = prec == MIDBF_SPLIT_BF16 || prec == MIDBF_SPLIT_FP16;
-    if (!bf && prec != MIDBF_FP32) return fail(MIDBF_ERR_ARG, "variants exist for FP32 and the split 16-bit applies");
-    const int nvar = bf ? BF16_VARIANTS : MFMA_VARIANTS;
+    const bool f64 = prec == MIDBF_FP64;
+    if (!bf && !f64 && prec != MIDBF_FP32) return fail(MIDBF_ERR_ARG, "unknown precision");
+    const int nvar = bf ? BF16_VARIANTS : (f64 ? MFMA64_VARIANTS : MFMA_VARIANTS);
     for (int q = 0; q < 3; ++q)
         if (variants[q] < 0 || variants[q] >= nvar) return fail(MIDBF_ERR_ARG, "unknown variant");
-    auto& var = prec == MIDBF_SPLIT_FP16 ? h->fp16_variant
-                                          : (prec == MIDBF_SPLIT_BF16 ? h->bf16_variant : h->mfma_variant);
+    auto& var = prec == MIDBF_SPLIT_FP16   ? h->fp16_variant
+                : prec == MIDBF_SPLIT_BF16 ? h->bf16_variant
+                : f64                      ? h->mfma64_variant
+                                           : h->mfma_variant;
     for (int q = 0; q < 3; ++q)
         for (int l = 0; l < midbf_plan::VMAXLEV; ++l) var[q][l] = variants[q];
     return MIDBF_OK;

@@ -11,6 +11,7 @@ constexpr int MFMA_CROW_MAX = 4096;  // FP32: largest candidate vector / middle 
 constexpr int BF16_CROW_MAX = 2048;  // split-bf16: the same
 
 constexpr int MFMA_VARIANTS = 10;     // tile variants (rows per wave, K chunk, pipelining)
+constexpr int MFMA64_VARIANTS = 5;    // the same for FP64 (one row tile per wave)
 
 // One matrix-core level kernel.  count = IDs (up, down), groups (down-sum) or
 // middle blocks (each split over MidArgs::mchunks workgroups).  Going down, each ID writes its
@@ -18,10 +19,10 @@ constexpr int MFMA_VARIANTS = 10;     // tile variants (rows per wave, K chunk, 
 // adds the 2^d contributions of every group into the previous level buffer /
 // external output.
 void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
-                        hipStream_t s);
+                        hipStream_t s, bool fp64 = false);
 
 // The external <-> row-major transposes around a matrix-core apply.
-void launch_transpose(const TransposeArgs& A, hipStream_t s);
+void launch_transpose(const TransposeArgs& A, bool fp64, hipStream_t s);
 // The first up step when every leaf decomposition keeps all its points (no T):
 // per leaf, the caller's block is staged once and copied to the P partners'
 // skeleton rows.  groups = leaves; complex64.

@@ -1,11 +1,13 @@
-// Many-right-hand-side apply on the matrix cores (FP32 in, FP32 accumulate).
+// Many-right-hand-side apply on the matrix cores, FP32 (v_mfma_f32_16x16x4f32)
+// or FP64 (v_mfma_f64_16x16x4f64), accumulating in the same precision.
 //
 // With 64 right-hand sides every factor block becomes a dense complex GEMM,
 // C (rows x 64) = A (rows x K) B (K x 64), computed as three real products
-// per complex product on v_mfma_f32_16x16x4f32 (Gauss's form):
+// per complex product (Gauss's form):
 //     Cr = Ar Br - Ai Bi,   Ci = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi.
 // Lane l of a wave supplies A[l%16][l/16] and B[l/16][l%16] and receives
-// D[4(l/16)+v][l%16], v < 4 (checked on the device).  A (the factor) streams
+// D[4(l/16)+v][l%16] (FP32) or D[l/16+4v][l%16] (FP64), v < 4 (both checked
+// on the device).  A (the factor) streams
 // from HBM exactly once per launch; B (the level vectors, gathered through
 // the candidate permutation) is staged through LDS in chunks of KC rows and
 // shared by the four waves; each wave owns up to MTW 16-row tiles x 64
@@ -25,7 +27,30 @@ namespace midbf {
 
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
+// The real type of a path: its complex element, 4-wide accumulator and MFMA.
+template <class T> struct Real;
+template <> struct Real<float> {
+    typedef float2 C2;
+    typedef float acc4 __attribute__((ext_vector_type(4)));
+    static __device__ acc4 mfma(float a, float b, acc4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // row of the 16 x 16 result held in register v of a lane in row group lk = l/16
+    static __device__ int out_row(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct Real<double> {
+    typedef double2 C2;
+    typedef double acc4 __attribute__((ext_vector_type(4)));
+    static __device__ acc4 mfma(double a, double b, acc4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // the FP64 instruction interleaves the row groups instead
+    static __device__ int out_row(int lk, int v) { return lk + 4 * v; }
+};
+template <class T> __device__ inline typename Real<T>::C2 c2(T x, T y) {
+    typename Real<T>::C2 v;
+    v.x = x;
+    v.y = y;
+    return v;
+}
 
 constexpr int MT = 256;          // threads per workgroup (up, down)
 constexpr int MW = MT / 64;      // waves
@@ -35,10 +60,10 @@ constexpr int NRHS = MFMA_NRHS;  // columns per workgroup (4 tiles of 16)
 // products per complex product (Gauss): p1 += Ar Br, p2 += Ai Bi,
 // p3 += (Ar + Ai)(Br + Bi); then Cr = p1 - p2 and Ci = p3 - p1 - p2
 // (finish_gauss).  Each sweep issues independent MFMAs back to back.
-template <int MTW, int NTC>
-__device__ inline void kstep(floatx4 (&p1)[MTW][4], floatx4 (&p2)[MTW][4], floatx4 (&p3)[MTW][4],
-                             const float2 (&a)[MTW], const float2 (&b)[4], int ntiles) {
-    float as[MTW], bs[4];
+template <class T, int MTW, int NTC, class Acc = typename Real<T>::acc4, class C2 = typename Real<T>::C2>
+__device__ inline void kstep(Acc (&p1)[MTW][4], Acc (&p2)[MTW][4], Acc (&p3)[MTW][4], const C2 (&a)[MTW],
+                             const C2 (&b)[4], int ntiles) {
+    T as[MTW], bs[4];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) as[mt] = a[mt].x + a[mt].y;
 #pragma unroll
@@ -48,31 +73,34 @@ __device__ inline void kstep(floatx4 (&p1)[MTW][4], floatx4 (&p2)[MTW][4], float
         if (mt < ntiles) {
 #pragma unroll
             for (int nt = 0; nt < NTC; ++nt) {
-                p1[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].x, b[nt].x, p1[mt][nt], 0, 0, 0);
-                p2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt].y, b[nt].y, p2[mt][nt], 0, 0, 0);
-                p3[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[mt], bs[nt], p3[mt][nt], 0, 0, 0);
+                p1[mt][nt] = Real<T>::mfma(a[mt].x, b[nt].x, p1[mt][nt]);
+                p2[mt][nt] = Real<T>::mfma(a[mt].y, b[nt].y, p2[mt][nt]);
+                p3[mt][nt] = Real<T>::mfma(as[mt], bs[nt], p3[mt][nt]);
             }
         }
     }
 }
 
-template <int MTW, int NTC>
-__device__ inline void finish_gauss(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4], const floatx4 (&p3)[MTW][4]) {
+template <class Acc, int MTW, int NTC>
+__device__ inline void finish_gauss(Acc (&cr)[MTW][4], Acc (&ci)[MTW][4], const Acc (&p3)[MTW][4]) {
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NTC; ++nt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float r = cr[mt][nt][v] - ci[mt][nt][v];
+                const auto r = cr[mt][nt][v] - ci[mt][nt][v];
                 ci[mt][nt][v] = p3[mt][nt][v] - cr[mt][nt][v] - ci[mt][nt][v];
                 cr[mt][nt][v] = r;
             }
 }
 
 
-template <int MTW_, int KC_, bool PIPE_, int NT_ = MT, int NTC_ = 4>
+template <int MTW_, int KC_, bool PIPE_, int NT_ = MT, int NTC_ = 4, class T_ = float>
 struct Cfg {
+    typedef T_ T;                         // real type (float or double)
+    typedef typename Real<T_>::C2 C2;
+    typedef typename Real<T_>::acc4 Acc;
     static constexpr int MTW = MTW_;      // 16-row tiles per wave
     static constexpr int KC = KC_;        // K rows per LDS chunk
     static constexpr bool PIPE = PIPE_;   // chunk-deep register prefetch + double-buffered LDS
@@ -83,7 +111,7 @@ struct Cfg {
 };
 
 // The same tiling with one 16-column tile (few right-hand sides).
-template <class C> using Narrow = Cfg<C::MTW, C::KC, C::PIPE, C::NT, 1>;
+template <class C> using Narrow = Cfg<C::MTW, C::KC, C::PIPE, C::NT, 1, typename C::T>;
 
 // Rows [base, base + 16 MTW) of C (+)= A B for one wave.  A is column-major
 // with leading dimension M; brow(j, r) returns B[j][r] (j < K, r < nr).
@@ -93,8 +121,12 @@ template <class C> using Narrow = Cfg<C::MTW, C::KC, C::PIPE, C::NT, 1>;
 //   other register set and the other LDS buffer; one barrier per chunk.
 //   otherwise: one LDS buffer, A prefetched one k-step ahead.
 template <class C, int NT, class BRow>
-__device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const float2* __restrict__ A, int M,
-                          int K, int base, BRow brow, int nr, float2* sB) {
+__device__ void gemm_rows(typename C::Acc (&cr)[C::MTW][4], typename C::Acc (&ci)[C::MTW][4],
+                          const typename C::C2* __restrict__ A, int M, int K, int base, BRow brow, int nr,
+                          typename C::C2* sB) {
+    using T = typename C::T;
+    using C2 = typename C::C2;
+    using Acc = typename C::Acc;
     constexpr int MTW = C::MTW, KC = C::KC, W = C::W, NTC = C::NTC;
     constexpr int BPT = (KC * W + NT - 1) / NT;   // B elements staged per thread and chunk
     const int tid = threadIdx.x, l = tid & 63, lr = l & 15, lk = l >> 4;
@@ -102,24 +134,24 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
     const int nch = (K + KC - 1) / KC;
     if (nch == 0) return;
     // cr, ci enter as zero and collect Ar Br and Ai Bi; p3 the sum product
-    floatx4 p3[MTW][4];
+    Acc p3[MTW][4];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) p3[mt][nt] = floatx4{0, 0, 0, 0};
-    auto loadA1 = [&](int col, float2 (&dst)[MTW]) {
+        for (int nt = 0; nt < 4; ++nt) p3[mt][nt] = Acc{0, 0, 0, 0};
+    auto loadA1 = [&](int col, C2 (&dst)[MTW]) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
             const int row = base + mt * 16 + lr;
-            dst[mt] = (mt < ntl && col < K && row < M) ? A[(long long)col * M + row] : make_float2(0.f, 0.f);
+            dst[mt] = (mt < ntl && col < K && row < M) ? A[(long long)col * M + row] : c2<T>(0, 0);
         }
     };
-    float2 bt[BPT];
+    C2 bt[BPT];
     auto loadB = [&](int c0) {
 #pragma unroll
         for (int q = 0; q < BPT; ++q) {
             const int e = tid + q * NT, jj = e / W, r = e - jj * W, j = c0 + jj;
-            bt[q] = (e < KC * W && j < K && r < nr) ? brow(j, r) : make_float2(0.f, 0.f);
+            bt[q] = (e < KC * W && j < K && r < nr) ? brow(j, r) : c2<T>(0, 0);
         }
     };
     auto storeB = [&](int buf) {
@@ -128,7 +160,7 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
             if (tid + q * NT < KC * W) sB[buf * KC * W + tid + q * NT] = bt[q];
     };
     if constexpr (C::PIPE) {
-        float2 acur[KC / 4][MTW], anext[KC / 4][MTW];
+        C2 acur[KC / 4][MTW], anext[KC / 4][MTW];
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ++ks) loadA1(ks * 4 + lk, acur[ks]);
         loadB(0);
@@ -142,14 +174,14 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
                 for (int ks = 0; ks < KC / 4; ++ks) loadA1((c + 1) * KC + ks * 4 + lk, anext[ks]);
                 loadB((c + 1) * KC);
             }
-            const float2* sb = sB + (c & 1) * KC * W;
+            const C2* sb = sB + (c & 1) * KC * W;
             if (ntl > 0) {
 #pragma unroll
                 for (int ks = 0; ks < KC / 4; ++ks) {
-                    float2 bv[4];
+                    C2 bv[4];
 #pragma unroll
                     for (int nt = 0; nt < NTC; ++nt) bv[nt] = sb[(ks * 4 + lk) * W + nt * 16 + lr];
-                    kstep<MTW, NTC>(cr, ci, p3, acur[ks], bv, ntl);
+                    kstep<T, MTW, NTC>(cr, ci, p3, acur[ks], bv, ntl);
                 }
             }
             if (more) {
@@ -161,7 +193,7 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
             }
             __syncthreads();
         }
-        finish_gauss<MTW, NTC>(cr, ci, p3);
+        finish_gauss<Acc, MTW, NTC>(cr, ci, p3);
     } else {
         for (int c = 0; c < nch; ++c) {
             loadB(c * KC);
@@ -169,32 +201,32 @@ __device__ void gemm_rows(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], co
             storeB(0);
             __syncthreads();
             if (ntl > 0) {
-                float2 an[MTW];
+                C2 an[MTW];
                 loadA1(c * KC + lk, an);
 #pragma unroll 2
                 for (int ks = 0; ks < KC / 4; ++ks) {
-                    float2 a[MTW];
+                    C2 a[MTW];
 #pragma unroll
                     for (int mt = 0; mt < MTW; ++mt) a[mt] = an[mt];
                     if (ks + 1 < KC / 4) loadA1(c * KC + (ks + 1) * 4 + lk, an);
-                    float2 bv[4];
+                    C2 bv[4];
 #pragma unroll
                     for (int nt = 0; nt < NTC; ++nt) bv[nt] = sB[(ks * 4 + lk) * W + nt * 16 + lr];
-                    kstep<MTW, NTC>(cr, ci, p3, a, bv, ntl);
+                    kstep<T, MTW, NTC>(cr, ci, p3, a, bv, ntl);
                 }
             }
         }
         __syncthreads();
-        finish_gauss<MTW, NTC>(cr, ci, p3);
+        finish_gauss<Acc, MTW, NTC>(cr, ci, p3);
     }
 }
 
-template <int MTW>
-__device__ inline void zero_acc(floatx4 (&cr)[MTW][4], floatx4 (&ci)[MTW][4]) {
+template <class Acc, int MTW>
+__device__ inline void zero_acc(Acc (&cr)[MTW][4], Acc (&ci)[MTW][4]) {
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = floatx4{0, 0, 0, 0}; ci[mt][nt] = floatx4{0, 0, 0, 0}; }
+        for (int nt = 0; nt < 4; ++nt) { cr[mt][nt] = Acc{0, 0, 0, 0}; ci[mt][nt] = Acc{0, 0, 0, 0}; }
 }
 
 // Row numbers of a group's candidate vector in the previous level buffer
@@ -224,10 +256,10 @@ __device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a,
 
 // element (row, rhs) of a level buffer (row-major, nrhs wide) or of an
 // external column-major block (s == 0)
-__device__ inline float2 load_vec(bool ext, const float2* p, long long ld, int nrhs, int row, int r) {
+template <class C2> __device__ inline C2 load_vec(bool ext, const C2* p, long long ld, int nrhs, int row, int r) {
     return ext ? p[(long long)r * ld + row] : p[(long long)row * nrhs + r];
 }
-__device__ inline float2* vec_ptr(bool ext, float2* p, long long ld, int nrhs, int row, int r) {
+template <class C2> __device__ inline C2* vec_ptr(bool ext, C2* p, long long ld, int nrhs, int row, int r) {
     return ext ? p + (long long)r * ld + row : p + (long long)row * nrhs + r;
 }
 
@@ -242,10 +274,13 @@ __device__ inline long long xcd_group_order(long long b, long long nid, int P) {
 template <class C>
 __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     constexpr int MTW = C::MTW;
+    using T = typename C::T;
+    using C2 = typename C::C2;
+    using Acc = typename C::Acc;
     extern __shared__ int dyn_rows[];          // ncand_max candidate rows, then as many source rows
     int* crow = dyn_rows;
     int* srcrow = dyn_rows + A.ncand_max;
-    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
+    __shared__ C2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const long long g = id / A.G.P;
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
@@ -254,11 +289,11 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
     // the leaves read the caller's block, or its row-major copy (A.ext null)
     const bool ext = A.s == 0 && A.ext;
-    const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
-    float2* out = (float2*)A.out;
+    const C2* xin = ext ? (const C2*)A.ext : (const C2*)A.in;
+    C2* out = (C2*)A.out;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
     const int* perm = A.lev.perm + A.lev.perm_off[id];
-    const float2* T = (const float2*)A.lev.T[id];
+    const C2* Tb = (const C2*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     __syncthreads();
@@ -267,23 +302,23 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     auto brow = [&](int j, int r) { return load_vec(ext, xin, A.ld, A.nrhs, srcrow[j], r0 + r); };
     for (int m0 = 0; m0 < k; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
-        floatx4 cr[MTW][4], ci[MTW][4];
-        zero_acc<MTW>(cr, ci);
-        gemm_rows<C, C::NT>(cr, ci, T, k, nred, base, brow, nr, sB);
+        Acc cr[MTW][4], ci[MTW][4];
+        zero_acc<Acc, MTW>(cr, ci);
+        gemm_rows<C, C::NT>(cr, ci, Tb, k, nred, base, brow, nr, sB);
         // C + skeleton rows of the candidate vector
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = base + mt * 16 + 4 * lk + v;
+                const int row = base + mt * 16 + Real<T>::out_row(lk, v);
                 if (row < k) {
                     const int src = crow[perm[row]];
 #pragma unroll
                     for (int nt = 0; nt < C::NTC; ++nt) {
                         const int r = nt * 16 + lr;
                         if (r < nr) {
-                            const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                            out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
+                            const C2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
+                            out[(yo + row) * A.nrhs + r0 + r] = c2<T>(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
                         }
                     }
                 }
@@ -296,41 +331,44 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
 // candidate row of its group -- z on the skeleton rows, T^T z on the
 // redundant rows -- goes to the scratch block scr[perm_off[id] + position].
 template <class C>
-__global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, float2* scr) {
+__global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, typename C::C2* scr) {
     constexpr int MTW = C::MTW;
-    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
+    using T = typename C::T;
+    using C2 = typename C::C2;
+    using Acc = typename C::Acc;
+    __shared__ C2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
     const int r0 = blockIdx.y * C::W;
     const int nr = min(C::W, A.nrhs - r0);
-    const float2* zin = (const float2*)A.in;
+    const C2* zin = (const C2*)A.in;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
     const int* perm = A.lev.perm + A.lev.perm_off[id];
-    const float2* T = (const float2*)A.lev.T[id];
+    const C2* Tb = (const C2*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
-    float2* w = scr + A.lev.perm_off[id] * A.nrhs;
+    C2* w = scr + A.lev.perm_off[id] * A.nrhs;
     for (int e = tid; e < k * C::W; e += C::NT) {
         const int i = e / C::W, r = e - i * C::W;
         if (r < nr) w[(long long)perm[i] * A.nrhs + r0 + r] = zin[(yo + i) * A.nrhs + r0 + r];
     }
-    const float2* z = zin + yo * A.nrhs + r0;
+    const C2* z = zin + yo * A.nrhs + r0;
     auto brow = [&](int i, int r) { return z[(long long)i * A.nrhs + r]; };
     for (int m0 = 0; m0 < nred; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
-        floatx4 cr[MTW][4], ci[MTW][4];
-        zero_acc<MTW>(cr, ci);
-        gemm_rows<C, C::NT>(cr, ci, T, nred, k, base, brow, nr, sB);
+        Acc cr[MTW][4], ci[MTW][4];
+        zero_acc<Acc, MTW>(cr, ci);
+        gemm_rows<C, C::NT>(cr, ci, Tb, nred, k, base, brow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = base + mt * 16 + 4 * lk + v;
+                const int row = base + mt * 16 + Real<T>::out_row(lk, v);
                 if (row < nred) {
-                    float2* d = w + (long long)perm[k + row] * A.nrhs + r0;
+                    C2* d = w + (long long)perm[k + row] * A.nrhs + r0;
 #pragma unroll
                     for (int nt = 0; nt < C::NTC; ++nt) {
                         const int r = nt * 16 + lr;
-                        if (r < nr) d[r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
+                        if (r < nr) d[r] = c2<T>(cr[mt][nt][v], ci[mt][nt][v]);
                     }
                 }
             }
@@ -340,7 +378,8 @@ __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, fl
 
 // The 2^d contributions of a group summed in a fixed order and written to
 // the candidate rows (previous level buffer, or the leaf's lattice points).
-__global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
+template <class C2>
+__global__ __launch_bounds__(MT) void down_sum(DownArgs A, const C2* scr) {
     extern __shared__ int crow[];               // ncand_max candidate rows
     __shared__ long long base[8];
     const long long g = blockIdx.x;
@@ -351,10 +390,10 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
     if (threadIdx.x < A.G.P) base[threadIdx.x] = A.lev.perm_off[g * A.G.P + threadIdx.x] * A.nrhs + r0;
     __syncthreads();
     const bool ext = A.s == 0 && A.ext;
-    float2* outp = ext ? (float2*)A.ext : (float2*)A.out;
-    // two right-hand sides per thread (16-byte loads) when the row stride allows it
-    const bool pairs = (A.nrhs % 2 == 0) && (nr % 2 == 0) && !ext;
-    if (pairs) {
+    C2* outp = ext ? (C2*)A.ext : (C2*)A.out;
+    // complex64: two right-hand sides per thread (16-byte loads) when the row stride allows it
+    const bool pairs = sizeof(C2) == 8 && (A.nrhs % 2 == 0) && (nr % 2 == 0) && !ext;
+    if constexpr (sizeof(C2) == 8) if (pairs) {
         const int half = nr / 2;
         for (int e = threadIdx.x; e < ncand * half; e += MT) {
             const int p = e / half, r = 2 * (e - p * half);
@@ -370,23 +409,29 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const float2* scr) {
     for (int e = threadIdx.x; e < ncand * NRHS; e += MT) {
         const int p = e / NRHS, r = e - p * NRHS;
         if (r >= nr) continue;
-        float sx = 0.f, sy = 0.f;
+        decltype(C2::x) sx = 0, sy = 0;
         for (int t = 0; t < A.G.P; ++t) {
-            const float2 v = scr[base[t] + (long long)p * A.nrhs + r];
+            const C2 v = scr[base[t] + (long long)p * A.nrhs + r];
             sx += v.x;
             sy += v.y;
         }
-        *vec_ptr(ext, outp, A.ld, A.nrhs, crow[p], r0 + r) = make_float2(sx, sy);
+        C2 o;
+        o.x = sx;
+        o.y = sy;
+        *vec_ptr(ext, outp, A.ld, A.nrhs, crow[p], r0 + r) = o;
     }
 }
 
 template <class C>
 __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     constexpr int MTW = C::MTW;
+    using T = typename C::T;
+    using C2 = typename C::C2;
+    using Acc = typename C::Acc;
     extern __shared__ int dyn_rows[];          // in_max input rows, then out_max output rows
     int* crow_in = dyn_rows;
     int* crow_out = dyn_rows + A.in_max;
-    __shared__ float2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
+    __shared__ C2 sB[(C::PIPE ? 2 : 1) * C::KC * C::W];
     const long long bi = blockIdx.x / A.mchunks;
     const int chunk = (int)(blockIdx.x - bi * A.mchunks);
     const int r0 = blockIdx.y * C::W;
@@ -394,9 +439,9 @@ __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     const int M = A.nr[bi], K = A.nc[bi];
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     middle_rows<C::NT>(crow_in, crow_out, A, bi);
-    const float2* xin = (const float2*)A.in;
-    float2* zout = (float2*)A.out;
-    const float2* S = (const float2*)A.S + A.off[bi];
+    const C2* xin = (const C2*)A.in;
+    C2* zout = (C2*)A.out;
+    const C2* S = (const C2*)A.S + A.off[bi];
     __syncthreads();
     auto brow = [&](int j, int r) { return xin[(long long)crow_in[j] * A.nrhs + r0 + r]; };
     // rows of this workgroup: a run of whole rounds
@@ -404,20 +449,20 @@ __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     const int mlo = chunk * per, mhi = min(M, mlo + per);
     for (int m0 = mlo; m0 < mhi; m0 += C::ROUND) {
         const int base = m0 + wave * MTW * 16;
-        floatx4 cr[MTW][4], ci[MTW][4];
-        zero_acc<MTW>(cr, ci);
+        Acc cr[MTW][4], ci[MTW][4];
+        zero_acc<Acc, MTW>(cr, ci);
         gemm_rows<C, C::NT>(cr, ci, S, M, K, base, brow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = base + mt * 16 + 4 * lk + v;
+                const int row = base + mt * 16 + Real<T>::out_row(lk, v);
                 if (row < M) {
                     const long long dst = crow_out[row];
 #pragma unroll
                     for (int nt = 0; nt < C::NTC; ++nt) {
                         const int r = nt * 16 + lr;
-                        if (r < nr) zout[dst * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
+                        if (r < nr) zout[dst * A.nrhs + r0 + r] = c2<T>(cr[mt][nt][v], ci[mt][nt][v]);
                     }
                 }
             }
@@ -446,12 +491,14 @@ void launch_variant(LevelKernel which, const void* args, long long count, int nr
             break;
         }
         case LevelKernel::Down:
-            hipLaunchKernelGGL(down_mfma<C>, grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count, (float2*)scratch);
+            hipLaunchKernelGGL(down_mfma<C>, grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count,
+                               (typename C::C2*)scratch);
             break;
         case LevelKernel::DownSum: {
             const DownArgs& a = *(const DownArgs*)args;
             const dim3 sgrid((unsigned)count, (nrhs + NRHS - 1) / NRHS);     // its own 64-column tiling
-            hipLaunchKernelGGL(down_sum, sgrid, dim3(MT), sizeof(int) * a.ncand_max, s, a, (const float2*)scratch);
+            hipLaunchKernelGGL(down_sum<typename C::C2>, sgrid, dim3(MT), sizeof(int) * a.ncand_max, s, a,
+                               (const typename C::C2*)scratch);
             break;
         }
         case LevelKernel::Middle: {
@@ -470,13 +517,14 @@ void launch_variant(LevelKernel which, const void* args, long long count, int nr
 // Row-major N x nrhs -> external column-major block, in 64 x 64 tiles through
 // LDS (rows padded to 65 entries: the column reads of each half-wave touch
 // distinct banks); both global sides are coalesced.
+template <class C2>
 __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
-    __shared__ float2 t[64][65];
+    __shared__ C2 t[64][65];
     const long long p0 = (long long)blockIdx.x * 64;
     const int r0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const float2* src = (const float2*)A.src;
-    float2* dst = (float2*)A.dst;
+    const C2* src = (const C2*)A.src;
+    C2* dst = (C2*)A.dst;
     for (int pp = ty; pp < 64; pp += 4) {
         const long long p = p0 + pp;
         const int r = r0 + tx;
@@ -532,13 +580,21 @@ void launch_up_leaf_copy(const UpArgs& A, long long groups, int nrhs, hipStream_
     MIDBF_HIP(hipGetLastError());
 }
 
-void launch_transpose(const TransposeArgs& A, hipStream_t s) {
+void launch_transpose(const TransposeArgs& A, bool fp64, hipStream_t s) {
     const dim3 grid((unsigned)((A.N + 63) / 64), (unsigned)((A.nrhs + 63) / 64));
-    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, A);
+    if (fp64) hipLaunchKernelGGL(transpose_kernel<double2>, grid, dim3(256), 0, s, A);
+    else hipLaunchKernelGGL(transpose_kernel<float2>, grid, dim3(256), 0, s, A);
     MIDBF_HIP(hipGetLastError());
 }
 
 namespace {
+// FP64: one 16-row tile per wave (three 4-wide FP64 accumulators per column tile).
+using D0 = Cfg<1, 16, true, 512, 4, double>;
+using D1 = Cfg<1, 16, false, 512, 4, double>;
+using D2 = Cfg<1, 16, true, 256, 4, double>;
+using D3 = Cfg<1, 32, false, 256, 4, double>;
+using D4 = Cfg<1, 32, true, 256, 4, double>;
+
 // 64 right-hand sides per workgroup, or one 16-column tile when there are at
 // most 16 (no matrix-core work on empty columns).
 template <class C>
@@ -549,7 +605,18 @@ void launch_width(LevelKernel which, const void* args, long long count, int nrhs
 }  // namespace
 
 void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long long count, int nrhs, void* scratch,
-                        hipStream_t s) {
+                        hipStream_t s, bool fp64) {
+    if (fp64) {
+        switch (variant) {
+            case 0: launch_width<D0>(which, args, count, nrhs, scratch, s); break;
+            case 1: launch_width<D1>(which, args, count, nrhs, scratch, s); break;
+            case 2: launch_width<D2>(which, args, count, nrhs, scratch, s); break;
+            case 3: launch_width<D3>(which, args, count, nrhs, scratch, s); break;
+            case 4: launch_width<D4>(which, args, count, nrhs, scratch, s); break;
+            default: throw Error(MIDBF_ERR_ARG, "unknown FP64 matrix-core variant");
+        }
+        return;
+    }
     switch (variant) {
         case 0: launch_width<V0>(which, args, count, nrhs, scratch, s); break;
         case 1: launch_width<V1>(which, args, count, nrhs, scratch, s); break;

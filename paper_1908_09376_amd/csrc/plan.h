@@ -116,6 +116,7 @@ struct midbf_plan {
     // matrix-core tile variant per kernel kind (up, down, middle) and MSCS step (FP32, split-bf16, split-fp16)
     static constexpr int VMAXLEV = 16;
     int mfma_variant[3][VMAXLEV] = {};
+    int mfma64_variant[3][VMAXLEV] = {};
     int bf16_variant[3][VMAXLEV] = {};
     int fp16_variant[3][VMAXLEV] = {};
 };

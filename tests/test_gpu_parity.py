@@ -324,3 +324,36 @@ def test_compressible_leaves_many_rhs(precision, variant):
     rows = W.sample_rows(N, 4, 64)
     gd = direct_sum(Kernel(2, n, ("lowrank", U, V)), f, rows=rows)
     assert rel_l2(g64[rows], gd) < 1e-5
+
+
+# ---- FP64 matrix cores ----------------------------------------------------------
+
+def _single_fp64(F, f, j):
+    return from_dev(F.apply(to_dev(f[:, j:j + 1])[0]).unsqueeze(0))[:, 0]
+
+
+@pytest.mark.parametrize("n,nrhs", [(64, 16), (128, 64), (256, 33)])
+def test_mfma_fp64_equals_single_rhs(n, nrhs):
+    """FP64 with 16 or more RHS runs on v_mfma_f64 (Gauss's three products); each column equals the
+    FP64 VALU apply of that column alone up to FP64 rounding, and the direct sum within the ID error."""
+    F = _build(n, "fio_ellipse")
+    f = W.complex_gaussian(n * n, nrhs, 51, n)
+    many = from_dev(F.apply(to_dev(f)))
+    for j in (0, nrhs // 2, nrhs - 1):
+        one = _single_fp64(F, f, j)
+        assert np.linalg.norm(many[:, j] - one) / np.linalg.norm(one) < 1e-12
+    K = Kernel(2, n, "fio_ellipse")
+    rows = W.sample_rows(K.N, 0, 64)
+    assert rel_l2(many[rows], direct_sum(K, f, rows=rows)) < 1e-5
+
+
+@pytest.mark.parametrize("variant", range(5))
+def test_mfma_fp64_every_variant(variant):
+    F = _build(128, "fio_ellipse")
+    f = W.complex_gaussian(128 * 128, 70, 52)
+    F.set_variants([variant] * 3, precision="fp64")
+    many = from_dev(F.apply(to_dev(f)))
+    for j in (0, 69):
+        one = _single_fp64(F, f, j)
+        assert np.linalg.norm(many[:, j] - one) / np.linalg.norm(one) < 1e-12
+    assert all(v in range(5) for v in F.tune(64, "fp64"))
