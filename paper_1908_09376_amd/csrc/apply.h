@@ -53,6 +53,7 @@ struct UpArgs {
     void* out;               // this level's buffer
     int nrhs;
     int ncand_max;           // largest candidate count of the level (LDS strip size)
+    int nred_max;            // bound on the redundant inputs n - k of the level's decompositions
 };
 
 struct DownArgs {

@@ -231,6 +231,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.nrhs = nrhs;
         const int ncand = s == 0 ? h->n0 : lv.nmax;
         a.ncand_max = ncand;
+        a.nred_max = ncand - lv.kmin;
         // forward VALU up kernel: candidate vector plus one redundant-input strip per wave
         const size_t up_lds = (size_t)ncand * cs * (adjoint || rt > 1 ? rt : 1 + 4);
         const double vin = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;

@@ -481,9 +481,33 @@ static_assert(RES_KT * KT == SPLIT16_RESIDENT_K, "resident rank limit");
 // rows [base, base + 16) (also for K = 0, with zeros).  ONE_B: read one B
 // fragment at a time (fewer registers).  Every thread of the workgroup must
 // call this.
-template <class E, int NT, bool ONE_B, class BOff, class Epi>
+// The first two A tiles a wave of gemm_resident multiplies.  A kernel with
+// table loads and barriers ahead of the GEMM requests them first, so that
+// their latency overlaps that prologue (gemm_resident<..., PRE = true>).
+template <class E>
+struct ResPre {
+    Frag<E> f0, f1;
+};
+
+template <class E, int NT>
+__device__ inline void resident_prefetch(ResPre<E>& p, const Frag<E>* __restrict__ Atiles, int M, int K) {
+    constexpr int NW = NT / 64;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int ktiles = (K + KT - 1) / KT;
+    const int mtiles = (M + 15) / 16;
+    const int mine = mtiles > wave ? (mtiles - wave + NW - 1) / NW : 0;
+    const int total = mine * ktiles;
+    auto tile_at = [&](int q) {
+        const int mt = wave + (q / ktiles) * NW, kt = q - (q / ktiles) * ktiles;
+        return Atiles[((long long)mt * ktiles + kt) * 64 + l];
+    };
+    if (total > 0) p.f0 = tile_at(0);
+    if (total > 1) p.f1 = tile_at(1);
+}
+
+template <class E, int NT, bool ONE_B, bool PRE = false, class BOff, class Epi>
 __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, const float2* __restrict__ src,
-                              BOff boff, int nr, LFrag<E>* sB, Epi epi) {
+                              BOff boff, int nr, LFrag<E>* sB, Epi epi, const ResPre<E>* pre = nullptr) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
     const int ktiles = (K + KT - 1) / KT;
@@ -501,8 +525,13 @@ __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, 
         return Atiles[((long long)mt * ktiles + kt) * 64 + l];
     };
     Frag<E> f0[1], f1, f2;
-    if (total > 0) f0[0] = tile_at(0);
-    if (total > 1) f1 = tile_at(1);
+    if constexpr (PRE) {
+        f0[0] = pre->f0;
+        f1 = pre->f1;
+    } else {
+        if (total > 0) f0[0] = tile_at(0);
+        if (total > 1) f1 = tile_at(1);
+    }
     for (int f = tid; f < ktiles * 256; f += NT) {
         const int kt = f >> 8, rem = f & 255, kb = rem >> 6, col = rem & 63;
         float2 v[8];
@@ -735,10 +764,46 @@ __global__ __launch_bounds__(256) void down_leaf16(DownArgs A) {
 // fragment lanes per stage split evenly over NT threads.
 template <int NT> constexpr int rct_for() { return NT == 768 ? 3 : 4; }
 
+// A tiles in flight stay raw (phase tiles are expanded only when used).
+template <class E, bool ANG> using ARaw = std::conditional_t<ANG, AngRaw, Frag<E>>;
+
+template <class E, bool ANG>
+__device__ inline ARaw<E, ANG> a_tile(const Frag<E>* __restrict__ Atiles, const int* __restrict__ Aang, int mt,
+                                      int ktiles, int kt) {
+    const long long idx = ((long long)mt * ktiles + kt) * 64 + (threadIdx.x & 63);
+    if constexpr (ANG) {
+        AngRaw r;
+        r.a0 = *(const intx4*)(Aang + idx * 8);
+        r.a1 = *(const intx4*)(Aang + idx * 8 + 4);
+        return r;
+    } else {
+        return Atiles[idx];
+    }
+}
+
+// The A tiles of one wave of gemm_res16: the one in use and AD requested
+// ahead.  a_prefetch issues the first AD; a kernel with table loads and
+// barriers ahead of the GEMM calls it first and passes preloaded = true.
+template <class E, int AD, bool ANG>
+struct APipe {
+    ARaw<E, ANG> fa[AD + 1];
+};
+
+template <class E, int AD, bool ANG>
+__device__ inline void a_prefetch(APipe<E, AD, ANG>& p, const Frag<E>* __restrict__ Atiles,
+                                  const int* __restrict__ Aang, int M, int K, int base) {
+    const int ktiles = (K + KT - 1) / KT;
+    if (base < M) {
+#pragma unroll
+        for (int i = 0; i < AD; ++i)
+            if (i < ktiles) p.fa[i] = a_tile<E, ANG>(Atiles, Aang, base / 16, ktiles, i);
+    }
+}
+
 template <class E, int NT, int AD, bool ANG = false, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
                            int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB,
-                           const int* __restrict__ Aang = nullptr) {
+                           const int* __restrict__ Aang, APipe<E, AD, ANG>& pipe, bool preloaded) {
     constexpr int RCT = rct_for<NT>();
     constexpr int FPT = RCT * 256 / NT;            // B fragments staged per thread and stage
     static_assert(FPT >= 1 && FPT * NT == RCT * 256, "stage must split evenly over the threads");
@@ -767,25 +832,9 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
             lds_split_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q]);
         }
     };
-    // A tiles in flight stay raw (phase tiles are expanded only when used)
-    using Raw = std::conditional_t<ANG, AngRaw, Frag<E>>;
-    auto tile_at = [&](int kt) -> Raw {
-        const long long idx = ((long long)mt * ktiles + kt) * 64 + l;
-        if constexpr (ANG) {
-            AngRaw r;
-            r.a0 = *(const intx4*)(Aang + idx * 8);
-            r.a1 = *(const intx4*)(Aang + idx * 8 + 4);
-            return r;
-        } else {
-            return Atiles[idx];
-        }
-    };
-    Raw fa[AD + 1];                                 // the tile in use and AD requested ahead
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < AD; ++i)
-            if (i < ktiles) fa[i] = tile_at(i);
-    }
+    auto tile_at = [&](int kt) { return a_tile<E, ANG>(Atiles, Aang, mt, ktiles, kt); };
+    auto& fa = pipe.fa;
+    if (!preloaded) a_prefetch<E, AD, ANG>(pipe, Atiles, Aang, M, K, base);
     loadB(0);
     __syncthreads();          // the previous user of sB is done
     storeB(0);
@@ -826,7 +875,10 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
     }
 }
 
-template <class E, int NT>
+// RES_ONLY: every decomposition of the level has n - k <= RES_KT * KT, so only
+// the resident path is built, and each wave requests its first two factor
+// tiles before the candidate tables and barriers.
+template <class E, int NT, bool RES_ONLY>
 __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     constexpr int NW = NT / 64;
     __shared__ int crow[CROW_MAX];
@@ -837,15 +889,19 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
-    candidate_rows<NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
-    const bool ext = A.s == 0 && A.ext;   // else the leaves read the row-major copy in A.in
-    const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
-    float2* out = (float2*)A.out;
+    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
     const int* perm = A.lev.perm + A.lev.perm_off[id];
     const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
-    const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const bool resident = RES_ONLY || nred <= RES_KT * KT;
+    APipe<E, 2, false> pipe;
+    ResPre<E> rp;
+    if constexpr (RES_ONLY) resident_prefetch<E, NT>(rp, Tt, k, nred);
+    candidate_rows<NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
+    const bool ext = A.s == 0 && A.ext;   // else the leaves read the row-major copy in A.in
+    const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
+    float2* out = (float2*)A.out;
     __syncthreads();
     for (int j = tid; j < nred; j += NT) srcrow[j] = crow[perm[k + j]];
     __syncthreads();
@@ -867,16 +923,20 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
         }
     };
     auto run = [&](const float2* xb, auto boff) {
-        if (nred <= RES_KT * KT) {       // the redundant inputs fit in LDS: staged once
-            gemm_resident<E, NT, (NT >= 768)>(Tt, k, nred, xb, boff, nr, sB, epi);
-            return;
-        }
-        for (int m0 = 0; m0 < k; m0 += NW * 16) {
-            const int base = m0 + wave * 16;
-            floatx4 cr[1][4], ci[1][4];
-            zero_acc<1>(cr, ci);
-            gemm_res16<E, NT, 2>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB);
-            epi(base, cr, ci);
+        if constexpr (RES_ONLY) {
+            gemm_resident<E, NT, (NT >= 768), true>(Tt, k, nred, xb, boff, nr, sB, epi, &rp);
+        } else {
+            if (resident) {       // the redundant inputs fit in LDS: staged once
+                gemm_resident<E, NT, (NT >= 768)>(Tt, k, nred, xb, boff, nr, sB, epi);
+                return;
+            }
+            for (int m0 = 0; m0 < k; m0 += NW * 16) {
+                const int base = m0 + wave * 16;
+                floatx4 cr[1][4], ci[1][4];
+                zero_acc<1>(cr, ci);
+                gemm_res16<E, NT, 2>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, nullptr, pipe, false);
+                epi(base, cr, ci);
+            }
         }
     };
     // B rows are input rows: at the leaves the caller's column-major input
@@ -913,18 +973,22 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
+    const int* Sang = ANG ? A.ang + tile_off[bi] * 512 : nullptr;
+    // the first factor tiles are requested ahead of the row tables and the barrier
+    APipe<E, 2, ANG> pipe;
+    const int m_first = chunk * NW * 16;
+    a_prefetch<E, 2, ANG>(pipe, St, Sang, M, K, m_first + wave * 16);
     middle_rows<NT>(crow_in, crow_out, A, bi);
     const float2* xin = (const float2*)A.in;
     float2* zout = (float2*)A.out;
-    const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
     __syncthreads();
     auto boff = [&](int j, int c) { return (long long)crow_in[j] * A.nrhs + c; };
-    for (int m0 = chunk * NW * 16; m0 < M; m0 += mc * NW * 16) {
+    for (int m0 = m_first; m0 < M; m0 += mc * NW * 16) {
         const int base = m0 + wave * 16;
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
-        gemm_res16<E, NT, 2, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB,
-                                  ANG ? A.ang + tile_off[bi] * 512 : nullptr);
+        gemm_res16<E, NT, 2, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, Sang, pipe, m0 == m_first);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
@@ -1181,8 +1245,11 @@ template <class E, int NT>
 void launch_res16(LevelKernel which, const void* args, long long count, int nrhs, void* scratch,
                   const long long* tile_off, hipStream_t s) {
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
-    if (which == LevelKernel::Up)
-        hipLaunchKernelGGL((up_res16<E, NT>), grid, dim3(NT), 0, s, *(const UpArgs*)args, count);
+    if (which == LevelKernel::Up) {
+        const UpArgs& a = *(const UpArgs*)args;
+        if (a.nred_max <= RES_KT * KT) hipLaunchKernelGGL((up_res16<E, NT, true>), grid, dim3(NT), 0, s, a, count);
+        else hipLaunchKernelGGL((up_res16<E, NT, false>), grid, dim3(NT), 0, s, a, count);
+    }
     else if (which == LevelKernel::Middle) {
         // one workgroup per chunk of NT / 64 row tiles of a block
         MidArgs a = *(const MidArgs*)args;
