@@ -38,6 +38,7 @@ struct LevelArgs {
     const int* perm;
     const long long* y_off;
     const void* const* T;    // per-ID factor block of the precision in use
+    const int* src;          // split 16-bit up side: input row of every candidate position, or null
 };
 
 struct UpArgs {

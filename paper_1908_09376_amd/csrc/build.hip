@@ -236,6 +236,7 @@ void free_level(LevelSide& lv) {
     for (int q = 0; q < NPREC; ++q) f(lv.d_T[q]);
     for (void* c : lv.chunks) f(c);
     lv.d_k = lv.d_n = nullptr; lv.d_perm_off = lv.d_y_off = nullptr; lv.d_perm = lv.d_skel = nullptr;
+    lv.d_src = nullptr;
     for (int q = 0; q < NPREC; ++q) lv.d_T[q] = nullptr;
     lv.chunks.clear();
 }
@@ -656,6 +657,16 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
                 khat[side] = lv.kmax;
                 if (side == SIDE_ROW && s > 0 && (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)))
                     build_group_dense(h, lv, *prev, st);
+                if (side == SIDE_COL && (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) &&
+                    (s == 0 ? h->n0 : lv.nmax) <= BF16_CROW_MAX) {
+                    // input row of every candidate position, for the split up kernels
+                    lv.d_src = dalloc<int>(std::max<long long>(lv.total_n, 1));
+                    lv.chunks.push_back(lv.d_src);
+                    const ApplyGeom G{h->d, h->n, h->P, h->L, h->leaf, h->n0};
+                    pack_src_rows(G, s, ipow(h->P, s), lv.d_n, lv.d_perm_off, lv.d_perm, prev ? prev->d_k : nullptr,
+                                  prev ? prev->d_y_off : nullptr, lv.nid, lv.d_src, st);
+                    MIDBF_HIP(hipStreamSynchronize(st));
+                }
             }
         }
         build_middle(h, st);

@@ -46,7 +46,7 @@ int prec_index(midbf_precision p) {
 }
 
 LevelArgs level_args(const LevelSide& lv, int prec) {
-    return LevelArgs{lv.d_k, lv.d_n, lv.d_perm_off, lv.d_perm, lv.d_y_off, (const void* const*)lv.d_T[prec]};
+    return LevelArgs{lv.d_k, lv.d_n, lv.d_perm_off, lv.d_perm, lv.d_y_off, (const void* const*)lv.d_T[prec], lv.d_src};
 }
 
 size_t csize(int prec) { return prec == PREC_FP64 ? 16 : 8; }

@@ -50,6 +50,13 @@ void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k
 // Pack the dense candidate-order block of every group of P sibling row
 // decompositions (one step, going down) from the siblings' own tiles; per group
 // nr = n rows, nc = sum of k columns, first tile at tile_off.
+// The input row of every candidate position of the IDs [0, nid) of one up
+// level (LevelSide::d_src): candidate c of ID id is the lattice point c of its
+// leaf at s = 0, else row c of the concatenated child pieces of the previous
+// level; out[perm_off[id] + p] = row of candidate perm[perm_off[id] + p].
+// Candidate sets up to BF16_CROW_MAX.
+void pack_src_rows(const ApplyGeom& G, int s, long long Ps, const int* n, const long long* perm_off, const int* perm,
+                   const int* k_prev, const long long* yoff_prev, long long nid, int* out, hipStream_t st);
 void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, const int* perm, void* const* T,
                       const int* nr, const int* nc, const long long* tile_off, long long groups, void* out,
                       hipStream_t s);

@@ -481,33 +481,9 @@ static_assert(RES_KT * KT == SPLIT16_RESIDENT_K, "resident rank limit");
 // rows [base, base + 16) (also for K = 0, with zeros).  ONE_B: read one B
 // fragment at a time (fewer registers).  Every thread of the workgroup must
 // call this.
-// The first two A tiles a wave of gemm_resident multiplies.  A kernel with
-// table loads and barriers ahead of the GEMM requests them first, so that
-// their latency overlaps that prologue (gemm_resident<..., PRE = true>).
-template <class E>
-struct ResPre {
-    Frag<E> f0, f1;
-};
-
-template <class E, int NT>
-__device__ inline void resident_prefetch(ResPre<E>& p, const Frag<E>* __restrict__ Atiles, int M, int K) {
-    constexpr int NW = NT / 64;
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int ktiles = (K + KT - 1) / KT;
-    const int mtiles = (M + 15) / 16;
-    const int mine = mtiles > wave ? (mtiles - wave + NW - 1) / NW : 0;
-    const int total = mine * ktiles;
-    auto tile_at = [&](int q) {
-        const int mt = wave + (q / ktiles) * NW, kt = q - (q / ktiles) * ktiles;
-        return Atiles[((long long)mt * ktiles + kt) * 64 + l];
-    };
-    if (total > 0) p.f0 = tile_at(0);
-    if (total > 1) p.f1 = tile_at(1);
-}
-
-template <class E, int NT, bool ONE_B, bool PRE = false, class BOff, class Epi>
+template <class E, int NT, bool ONE_B, class BOff, class Epi>
 __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, const float2* __restrict__ src,
-                              BOff boff, int nr, LFrag<E>* sB, Epi epi, const ResPre<E>* pre = nullptr) {
+                              BOff boff, int nr, LFrag<E>* sB, Epi epi) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
     const int ktiles = (K + KT - 1) / KT;
@@ -525,13 +501,8 @@ __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, 
         return Atiles[((long long)mt * ktiles + kt) * 64 + l];
     };
     Frag<E> f0[1], f1, f2;
-    if constexpr (PRE) {
-        f0[0] = pre->f0;
-        f1 = pre->f1;
-    } else {
-        if (total > 0) f0[0] = tile_at(0);
-        if (total > 1) f1 = tile_at(1);
-    }
+    if (total > 0) f0[0] = tile_at(0);
+    if (total > 1) f1 = tile_at(1);
     for (int f = tid; f < ktiles * 256; f += NT) {
         const int kt = f >> 8, rem = f & 255, kb = rem >> 6, col = rem & 63;
         float2 v[8];
@@ -875,42 +846,37 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
     }
 }
 
-// RES_ONLY: every decomposition of the level has n - k <= RES_KT * KT, so only
-// the resident path is built, and each wave requests its first two factor
-// tiles before the candidate tables and barriers.
+// Going up, one workgroup per decomposition.  Input rows come from the level's
+// source-row table (LevelArgs::src, built once per plan): one coalesced copy
+// of the ID's n entries into LDS and one barrier, in place of the child-piece
+// tables, the permutation lookups and their two barriers.  RES_ONLY: every
+// decomposition of the level has n - k <= RES_KT * KT, so only the resident
+// path is built.
 template <class E, int NT, bool RES_ONLY>
 __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     constexpr int NW = NT / 64;
-    __shared__ int crow[CROW_MAX];
-    __shared__ int srcrow[CROW_MAX];
+    __shared__ int srow[CROW_MAX];
     __shared__ LFrag<E> sB[std::max(2 * rct_for<NT>(), RES_KT) * 4];
     const long long id = xcd_group_order(blockIdx.x, nid, A.G.P);
-    const long long g = id / A.G.P;
-    const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
     const int k = A.lev.k[id], nred = A.lev.n[id] - k;
-    const int* perm = A.lev.perm + A.lev.perm_off[id];
     const Frag<E>* Tt = (const Frag<E>*)A.lev.T[id];
     const long long yo = A.lev.y_off[id];
-    const bool resident = RES_ONLY || nred <= RES_KT * KT;
-    APipe<E, 2, false> pipe;
-    ResPre<E> rp;
-    if constexpr (RES_ONLY) resident_prefetch<E, NT>(rp, Tt, k, nred);
-    candidate_rows<NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
     const bool ext = A.s == 0 && A.ext;   // else the leaves read the row-major copy in A.in
     const float2* xin = ext ? (const float2*)A.ext : (const float2*)A.in;
     float2* out = (float2*)A.out;
-    __syncthreads();
-    for (int j = tid; j < nred; j += NT) srcrow[j] = crow[perm[k + j]];
+    // input row of each candidate position p (n <= CROW_MAX, checked at build)
+    const int* src = A.lev.src + A.lev.perm_off[id];
+    for (int p = tid; p < k + nred; p += NT) srow[p] = src[p];
     __syncthreads();
     auto epi = [&](int base, const floatx4 (&cr)[1][4], const floatx4 (&ci)[1][4]) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
             if (row < k) {
-                const int src = crow[perm[row]];
+                const int src = srow[row];
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     const int r = nt * 16 + lr;
@@ -923,13 +889,12 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
         }
     };
     auto run = [&](const float2* xb, auto boff) {
-        if constexpr (RES_ONLY) {
-            gemm_resident<E, NT, (NT >= 768), true>(Tt, k, nred, xb, boff, nr, sB, epi, &rp);
-        } else {
-            if (resident) {       // the redundant inputs fit in LDS: staged once
-                gemm_resident<E, NT, (NT >= 768)>(Tt, k, nred, xb, boff, nr, sB, epi);
-                return;
-            }
+        if (RES_ONLY || nred <= RES_KT * KT) {       // the redundant inputs fit in LDS: staged once
+            gemm_resident<E, NT, (NT >= 768)>(Tt, k, nred, xb, boff, nr, sB, epi);
+            return;
+        }
+        if constexpr (!RES_ONLY) {
+            APipe<E, 2, false> pipe;
             for (int m0 = 0; m0 < k; m0 += NW * 16) {
                 const int base = m0 + wave * 16;
                 floatx4 cr[1][4], ci[1][4];
@@ -942,9 +907,35 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     // B rows are input rows: at the leaves the caller's column-major input
     // (ld apart per right-hand side), above them a level buffer (nrhs wide)
     if (ext)
-        run(xin + (long long)r0 * A.ld, [&](int j, int c) { return (long long)c * A.ld + srcrow[j]; });
+        run(xin + (long long)r0 * A.ld, [&](int j, int c) { return (long long)c * A.ld + srow[k + j]; });
     else
-        run(xin + r0, [&](int j, int c) { return (long long)srcrow[j] * A.nrhs + c; });
+        run(xin + r0, [&](int j, int c) { return (long long)srow[k + j] * A.nrhs + c; });
+}
+
+// The source-row table of one up level: one workgroup per ID.
+struct SrcRowsArgs {
+    ApplyGeom G;
+    int s;
+    long long Ps;
+    const int* n;
+    const long long* perm_off;
+    const int* perm;
+    const int* k_prev;
+    const long long* yoff_prev;
+    int* out;
+    long long id0;
+};
+
+__global__ __launch_bounds__(256) void src_rows_kernel(SrcRowsArgs A) {
+    __shared__ int crow[CROW_MAX];
+    const long long id = A.id0 + blockIdx.x;
+    const long long g = id / A.G.P;
+    const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
+    candidate_rows<256>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
+    __syncthreads();
+    const long long po = A.perm_off[id];
+    const int n = A.n[id];
+    for (int p = threadIdx.x; p < n; p += 256) A.out[po + p] = crow[A.perm[po + p]];
 }
 
 template <class E, int NT, bool ANG>
@@ -1226,6 +1217,16 @@ void pack_angle_tiles(const PhaseDesc& ph, const int* nr, const int* nc, const l
     }
 }
 
+void pack_src_rows(const ApplyGeom& G, int s, long long Ps, const int* n, const long long* perm_off, const int* perm,
+                   const int* k_prev, const long long* yoff_prev, long long nid, int* out, hipStream_t st) {
+    for (long long i0 = 0; i0 < nid; i0 += 65535) {
+        const unsigned cnt = (unsigned)std::min<long long>(65535, nid - i0);
+        SrcRowsArgs A{G, s, Ps, n, perm_off, perm, k_prev, yoff_prev, out, i0};
+        hipLaunchKernelGGL(src_rows_kernel, dim3(cnt), dim3(256), 0, st, A);
+        MIDBF_HIP(hipGetLastError());
+    }
+}
+
 void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, const int* perm, void* const* T,
                       const int* nr, const int* nc, const long long* tile_off, long long groups, void* out,
                       hipStream_t s) {
@@ -1247,6 +1248,7 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
     if (which == LevelKernel::Up) {
         const UpArgs& a = *(const UpArgs*)args;
+        MIDBF_CHECK(a.lev.src != nullptr, MIDBF_ERR_ARG, "the split up kernels need the level's source-row table");
         if (a.nred_max <= RES_KT * KT) hipLaunchKernelGGL((up_res16<E, NT, true>), grid, dim3(NT), 0, s, a, count);
         else hipLaunchKernelGGL((up_res16<E, NT, false>), grid, dim3(NT), 0, s, a, count);
     }

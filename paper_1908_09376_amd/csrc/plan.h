@@ -33,6 +33,10 @@ struct LevelSide {
     long long* d_y_off = nullptr;
     int* d_perm = nullptr;                // candidate positions, skeleton first
     int* d_skel = nullptr;                // skeleton lattice point numbers at y_off
+    // Split 16-bit, column side: for each candidate position p of an ID (perm
+    // order, at perm_off), the row its input comes from: the lattice point at
+    // s = 0, else the row of the previous level buffer.  Null: not built.
+    int* d_src = nullptr;
     void** d_T[NPREC] = {};               // per-ID pointer to its T block
     // Split 16-bit, row side, s >= 1: per group of P siblings (IDs g P + t) the
     // dense candidate-order block [Pi_0 [I; T_0^T] ... Pi_{P-1} [I; T_{P-1}^T]]
