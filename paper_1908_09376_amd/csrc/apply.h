@@ -55,6 +55,8 @@ struct UpArgs {
     int nrhs;
     int ncand_max;           // largest candidate count of the level (LDS strip size)
     int nred_max;            // bound on the redundant inputs n - k of the level's decompositions
+    int lattice_in;          // 1: `in` is the row-major input copy and lev.src holds lattice points
+                             // (only the source-row-table kernels accept it)
 };
 
 struct DownArgs {
@@ -121,11 +123,12 @@ __device__ inline void middle_rows(int* crow_in, int* crow_out, const MidArgs& A
 }
 
 enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum, Transpose, DownGroup, DownDense,
-                         UpLeafCopy, DownLeaf };
+                         UpLeafCopy, DownLeaf, TransposeIn };
 
-// Complex64 block transpose from a row-major N x nrhs copy (element (p, r)
-// at src[p * nrhs + r]) to the external column-major layout (element (p, r)
-// at dst[r * ld + p]).
+// Block transpose between a row-major N x nrhs copy (element (p, r) at
+// [p * nrhs + r]) and the external column-major layout (element (p, r) at
+// [r * ld + p]): Transpose writes the external block from the copy (src
+// row-major), TransposeIn the copy from the external block (src column-major).
 struct TransposeArgs {
     const void* src;
     void* dst;

@@ -237,6 +237,7 @@ void free_level(LevelSide& lv) {
     for (void* c : lv.chunks) f(c);
     lv.d_k = lv.d_n = nullptr; lv.d_perm_off = lv.d_y_off = nullptr; lv.d_perm = lv.d_skel = nullptr;
     lv.d_src = nullptr;
+    lv.d_src_lat = nullptr;
     for (int q = 0; q < NPREC; ++q) lv.d_T[q] = nullptr;
     lv.chunks.clear();
 }
@@ -665,6 +666,11 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
                     const ApplyGeom G{h->d, h->n, h->P, h->L, h->leaf, h->n0};
                     pack_src_rows(G, s, ipow(h->P, s), lv.d_n, lv.d_perm_off, lv.d_perm, prev ? prev->d_k : nullptr,
                                   prev ? prev->d_y_off : nullptr, lv.nid, lv.d_src, st);
+                    if (s == 1 && prev->entries == 0) {
+                        lv.d_src_lat = dalloc<int>(std::max<long long>(lv.total_n, 1));
+                        lv.chunks.push_back(lv.d_src_lat);
+                        pack_src_lattice(prev->d_skel, lv.d_src, lv.total_n, lv.d_src_lat, st);
+                    }
                     MIDBF_HIP(hipStreamSynchronize(st));
                 }
             }

@@ -67,6 +67,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::DownDense: return "down_dense";
         case LevelKernel::UpLeafCopy: return "up_copy";
         case LevelKernel::DownLeaf: return "down_leaf";
+        case LevelKernel::TransposeIn: return "transpose";
     }
     return "?";
 }
@@ -93,6 +94,10 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     auto go = [&] {
         if (which == LevelKernel::Transpose) {
             launch_transpose(*(const TransposeArgs*)args, prec == PREC_FP64, st);
+            return;
+        }
+        if (which == LevelKernel::TransposeIn) {
+            launch_transpose_in(*(const TransposeArgs*)args, st);
             return;
         }
         if (which == LevelKernel::UpLeafCopy) {
@@ -127,9 +132,10 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
                         : prec == PREC_BF16 ? "_bf16x3"
                         : prec == PREC_FP16 ? "_fp16x3"
                                             : "_fp32";
-    if (which == LevelKernel::Transpose) {
+    if (which == LevelKernel::Transpose || which == LevelKernel::TransposeIn) {
         r.name = std::string(kernel_name(which)) + pname;
-        if (P.by_level) r.name += "_out";
+        if (which == LevelKernel::TransposeIn) r.name += "_in";
+        else if (P.by_level) r.name += "_out";
     } else {
         r.name = std::string(kernel_name(which)) + (mfma_count > 0 && !is_split16(prec) ? "_mfma" : "") + pname +
                  (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
@@ -213,10 +219,27 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
     const auto& down = adjoint ? h->cols : h->rows;
     const long long groups = ipow(h->P, h->L);
     std::vector<LaunchDesc> out;
+    // Split 16-bit with a lattice copy, when the first up step keeps every leaf
+    // point: that step only copies input rows, so the input is transposed into
+    // the row-major copy instead and the step above reads it through its
+    // lattice source-row table.
+    // (only the source-row-table up kernels, split variants 7-9, read it)
+    const int v_up1 = (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[0][1];
+    const bool lat_in = is_split16(prec) && mfma && lat && !adjoint && h->b >= 2 && up[0].entries == 0 &&
+                        up[1].d_src_lat != nullptr && v_up1 >= 7 && v_up1 <= 9;
     int o = 0;   // buffer holding the current level's vectors
     for (int s = 0; s < h->b; ++s) {
         const LevelSide& lv = up[s];
         LaunchDesc D{};
+        if (lat_in && s == 0) {
+            D.a.tr = TransposeArgs{in_ext, lat, ld, h->N, nrhs};
+            D.which = LevelKernel::TransposeIn;
+            D.bytes = 2.0 * h->N * nrhs * cs;
+            D.level = 0;
+            out.push_back(D);
+            o ^= 1;
+            continue;
+        }
         UpArgs& a = D.a.up;
         a.G = G;
         a.lev = level_args(lv, prec);
@@ -229,6 +252,11 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.yoff_prev = s ? up[s - 1].d_y_off : nullptr;
         a.out = buf[o];
         a.nrhs = nrhs;
+        if (lat_in && s == 1) {
+            a.in = lat;
+            a.lev.src = lv.d_src_lat;
+            a.lattice_in = 1;
+        }
         const int ncand = s == 0 ? h->n0 : lv.nmax;
         a.ncand_max = ncand;
         a.nred_max = ncand - lv.kmin;

@@ -23,6 +23,8 @@ void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long l
 
 // The external <-> row-major transposes around a matrix-core apply.
 void launch_transpose(const TransposeArgs& A, bool fp64, hipStream_t s);
+// The external column-major complex64 block -> the row-major copy (A.src external, A.dst the copy).
+void launch_transpose_in(const TransposeArgs& A, hipStream_t s);
 // The first up step when every leaf decomposition keeps all its points (no T):
 // per leaf, the caller's block is staged once and copied to the P partners'
 // skeleton rows.  groups = leaves; complex64.
@@ -57,6 +59,9 @@ void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k
 // Candidate sets up to BF16_CROW_MAX.
 void pack_src_rows(const ApplyGeom& G, int s, long long Ps, const int* n, const long long* perm_off, const int* perm,
                    const int* k_prev, const long long* yoff_prev, long long nid, int* out, hipStream_t st);
+// out[i] = skel[src[i]], i < count: a source-row table whose rows are y rows of
+// a first up step that keeps every leaf point, turned into lattice points.
+void pack_src_lattice(const int* skel, const int* src, long long count, int* out, hipStream_t st);
 void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, const int* perm, void* const* T,
                       const int* nr, const int* nc, const long long* tile_off, long long groups, void* out,
                       hipStream_t s);

@@ -517,7 +517,8 @@ void launch_variant(LevelKernel which, const void* args, long long count, int nr
 // Row-major N x nrhs -> external column-major block, in 64 x 64 tiles through
 // LDS (rows padded to 65 entries: the column reads of each half-wave touch
 // distinct banks); both global sides are coalesced.
-template <class C2>
+// TO_EXT: row-major copy -> external column-major block; otherwise the reverse.
+template <class C2, bool TO_EXT = true>
 __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
     __shared__ C2 t[64][65];
     const long long p0 = (long long)blockIdx.x * 64;
@@ -525,16 +526,30 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const C2* src = (const C2*)A.src;
     C2* dst = (C2*)A.dst;
-    for (int pp = ty; pp < 64; pp += 4) {
-        const long long p = p0 + pp;
-        const int r = r0 + tx;
-        if (p < A.N && r < A.nrhs) t[pp][tx] = src[p * A.nrhs + r];
-    }
-    __syncthreads();
-    for (int rr = ty; rr < 64; rr += 4) {
-        const long long p = p0 + tx;
-        const int r = r0 + rr;
-        if (p < A.N && r < A.nrhs) dst[(long long)r * A.ld + p] = t[tx][rr];
+    if constexpr (TO_EXT) {
+        for (int pp = ty; pp < 64; pp += 4) {
+            const long long p = p0 + pp;
+            const int r = r0 + tx;
+            if (p < A.N && r < A.nrhs) t[pp][tx] = src[p * A.nrhs + r];
+        }
+        __syncthreads();
+        for (int rr = ty; rr < 64; rr += 4) {
+            const long long p = p0 + tx;
+            const int r = r0 + rr;
+            if (p < A.N && r < A.nrhs) dst[(long long)r * A.ld + p] = t[tx][rr];
+        }
+    } else {
+        for (int rr = ty; rr < 64; rr += 4) {
+            const long long p = p0 + tx;
+            const int r = r0 + rr;
+            if (p < A.N && r < A.nrhs) t[tx][rr] = src[(long long)r * A.ld + p];
+        }
+        __syncthreads();
+        for (int pp = ty; pp < 64; pp += 4) {
+            const long long p = p0 + pp;
+            const int r = r0 + tx;
+            if (p < A.N && r < A.nrhs) dst[p * A.nrhs + r] = t[pp][tx];
+        }
     }
 }
 
@@ -584,6 +599,12 @@ void launch_transpose(const TransposeArgs& A, bool fp64, hipStream_t s) {
     const dim3 grid((unsigned)((A.N + 63) / 64), (unsigned)((A.nrhs + 63) / 64));
     if (fp64) hipLaunchKernelGGL(transpose_kernel<double2>, grid, dim3(256), 0, s, A);
     else hipLaunchKernelGGL(transpose_kernel<float2>, grid, dim3(256), 0, s, A);
+    MIDBF_HIP(hipGetLastError());
+}
+
+void launch_transpose_in(const TransposeArgs& A, hipStream_t s) {
+    const dim3 grid((unsigned)((A.N + 63) / 64), (unsigned)((A.nrhs + 63) / 64));
+    hipLaunchKernelGGL((transpose_kernel<float2, false>), grid, dim3(256), 0, s, A);
     MIDBF_HIP(hipGetLastError());
 }
 

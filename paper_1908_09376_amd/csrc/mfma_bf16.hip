@@ -926,6 +926,12 @@ struct SrcRowsArgs {
     long long id0;
 };
 
+__global__ __launch_bounds__(256) void src_lattice_kernel(const int* skel, const int* src, long long count,
+                                                         int* out) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) out[i] = skel[src[i]];
+}
+
 __global__ __launch_bounds__(256) void src_rows_kernel(SrcRowsArgs A) {
     __shared__ int crow[CROW_MAX];
     const long long id = A.id0 + blockIdx.x;
@@ -1007,6 +1013,8 @@ void launch_bvariant(LevelKernel which, const void* args, long long count, int n
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
     switch (which) {
         case LevelKernel::Up:
+            MIDBF_CHECK(!((const UpArgs*)args)->lattice_in, MIDBF_ERR_ARG,
+                        "this up kernel does not read the lattice source-row table");
             hipLaunchKernelGGL((up_bf16<C, E>), grid, dim3(C::NT), 0, s, *(const UpArgs*)args, count);
             break;
         case LevelKernel::Down:
@@ -1215,6 +1223,13 @@ void pack_angle_tiles(const PhaseDesc& ph, const int* nr, const int* nc, const l
                            (int*)out, b0);
         MIDBF_HIP(hipGetLastError());
     }
+}
+
+void pack_src_lattice(const int* skel, const int* src, long long count, int* out, hipStream_t st) {
+    if (count <= 0) return;
+    const long long blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(src_lattice_kernel, dim3((unsigned)blocks), dim3(256), 0, st, skel, src, count, out);
+    MIDBF_HIP(hipGetLastError());
 }
 
 void pack_src_rows(const ApplyGeom& G, int s, long long Ps, const int* n, const long long* perm_off, const int* perm,

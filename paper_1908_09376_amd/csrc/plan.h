@@ -37,6 +37,10 @@ struct LevelSide {
     // order, at perm_off), the row its input comes from: the lattice point at
     // s = 0, else the row of the previous level buffer.  Null: not built.
     int* d_src = nullptr;
+    // The same table for s = 1 as lattice points, when the first step keeps
+    // every leaf point (its y rows are copies of the input): the split up
+    // kernels then read a row-major copy of the input directly.
+    int* d_src_lat = nullptr;
     void** d_T[NPREC] = {};               // per-ID pointer to its T block
     // Split 16-bit, row side, s >= 1: per group of P siblings (IDs g P + t) the
     // dense candidate-order block [Pi_0 [I; T_0^T] ... Pi_{P-1} [I; T_{P-1}^T]]
