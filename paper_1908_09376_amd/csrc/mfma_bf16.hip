@@ -681,19 +681,41 @@ __global__ __launch_bounds__(256) void down_leaf16(DownArgs A) {
     }
     __syncthreads();
     const float2* zin = (const float2*)A.in;
-    for (int e = tid; e < n0 * NRHS; e += 256) {
-        const int p = e / NRHS, r = e - p * NRHS;
-        float2 sum = make_float2(0.f, 0.f);
-        if (r < nr) {
+    // Each thread's (point, column) elements in batches of GB.  Every load's
+    // address is formed in range (row 0 of the buffer where a sibling does not
+    // keep the point), so a batch's P * GB loads issue together; the absent
+    // terms are selected away, and the sum keeps sibling order.
+    constexpr int GB = 4;
+    for (int e0 = tid; e0 < n0 * NRHS; e0 += 256 * GB) {
+        float2 v[GB][MAX_P];
+        bool use[GB][MAX_P];
+#pragma unroll
+        for (int b = 0; b < GB; ++b) {
+            const int e = e0 + b * 256;
+            const bool in = e < n0 * NRHS;
+            const int p = in ? e / NRHS : 0, r = in ? e - p * NRHS : 0;
 #pragma unroll
             for (int t = 0; t < MAX_P; ++t) {
-                if (t < P && inv[t][p] < ks[t]) {
-                    const float2 v = zin[(yos[t] + inv[t][p]) * A.nrhs + r0 + r];
-                    sum = make_float2(sum.x + v.x, sum.y + v.y);
+                if (t < P) {
+                    const int i = inv[t][p];
+                    use[b][t] = in && r < nr && i < ks[t];
+                    const long long row = use[b][t] ? yos[t] + i : 0;
+                    v[b][t] = zin[row * A.nrhs + (use[b][t] ? r0 + r : 0)];
                 }
             }
         }
-        acc[p][r] = sum;
+#pragma unroll
+        for (int b = 0; b < GB; ++b) {
+            const int e = e0 + b * 256;
+            if (e < n0 * NRHS) {
+                const int p = e / NRHS, r = e - p * NRHS;
+                float2 sum = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int t = 0; t < MAX_P; ++t)
+                    if (t < P && use[b][t]) sum = make_float2(sum.x + v[b][t].x, sum.y + v[b][t].y);
+                acc[p][r] = sum;
+            }
+        }
     }
     for (int t = 0; t < P; ++t) {
         const long long id = g * P + t;
