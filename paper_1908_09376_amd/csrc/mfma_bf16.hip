@@ -893,19 +893,31 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     const int* src = A.lev.src + A.lev.perm_off[id];
     for (int p = tid; p < k + nred; p += NT) srow[p] = src[p];
     __syncthreads();
+    // The skeleton inputs of a row tile are loaded at in-range addresses (row
+    // 0 / column 0 outside the tile) so that all sixteen loads of a lane issue
+    // together; only the rows and columns inside are stored.
     auto epi = [&](int base, const floatx4 (&cr)[1][4], const floatx4 (&ci)[1][4]) {
+        float2 sv[4][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = base + 4 * lk + v;
+            const int src = srow[row < k ? row : 0];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int r = nt * 16 + lr;
+                sv[v][nt] = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + (r < nr ? r : 0));
+            }
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
             if (row < k) {
-                const int src = srow[row];
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     const int r = nt * 16 + lr;
-                    if (r < nr) {
-                        const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                        out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv.x, ci[0][nt][v] + sv.y);
-                    }
+                    if (r < nr)
+                        out[(yo + row) * A.nrhs + r0 + r] =
+                            make_float2(cr[0][nt][v] + sv[v][nt].x, ci[0][nt][v] + sv[v][nt].y);
                 }
             }
         }
