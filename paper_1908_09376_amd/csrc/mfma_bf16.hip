@@ -470,6 +470,25 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
 // wave streams the fragment tiles of A = T^T row tile by row tile, two tiles
 // ahead, with no barrier in the loop.  The down GEMMs are short in K (k) and
 // long in M (n - k), so the shared B never needs restaging.
+// Eight consecutive K rows j0 .. j0 + 7 of column col of B, B[j][c] =
+// src[boff(j, c)], zero beyond K rows or nr columns (K, nr >= 1).  Every
+// address is formed in range first (row and column clamped), so the eight
+// index reads and the eight loads issue back to back, with no branch around
+// each load; the values outside B are zeroed afterwards.
+template <class BOff>
+__device__ inline void load_b8(float2 (&v)[8], const float2* __restrict__ src, BOff boff, int j0, int col, int K,
+                               int nr) {
+    const int c = col < nr ? col : 0;
+    long long o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = boff(min(j0 + i, K - 1), c);
+    float2 x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = src[o[i]];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (j0 + i < K && col < nr) ? x[i] : make_float2(0.f, 0.f);
+}
+
 constexpr int RES_KT = 8;
 static_assert(RES_KT * KT == SPLIT16_RESIDENT_K, "resident rank limit");
 
@@ -793,7 +812,9 @@ __device__ inline void a_prefetch(APipe<E, AD, ANG>& p, const Frag<E>* __restric
     }
 }
 
-template <class E, int NT, int AD, bool ANG = false, class BOff>
+// BATCH: B stages gathered with load_b8 (measured faster for the up steps,
+// slower for the phase-tile middle).
+template <class E, int NT, int AD, bool ANG = false, bool BATCH = false, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
                            int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB,
                            const int* __restrict__ Aang, APipe<E, AD, ANG>& pipe, bool preloaded) {
@@ -811,10 +832,14 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
 #pragma unroll
         for (int q = 0; q < FPT; ++q) {
             const int f = tid + q * NT, kt = f >> 8, kb = (f & 255) >> 6, col = f & 63;
+            if constexpr (BATCH) {
+                load_b8(bt[q], src, boff, (st * RCT + kt) * KT + kb * 8, col, K, nr);
+            } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int j = (st * RCT + kt) * KT + kb * 8 + i;
-                bt[q][i] = (j < K && col < nr) ? src[boff(j, col)] : make_float2(0.f, 0.f);
+                for (int i = 0; i < 8; ++i) {
+                    const int j = (st * RCT + kt) * KT + kb * 8 + i;
+                    bt[q][i] = (j < K && col < nr) ? src[boff(j, col)] : make_float2(0.f, 0.f);
+                }
             }
         }
     };
@@ -933,7 +958,7 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
                 const int base = m0 + wave * 16;
                 floatx4 cr[1][4], ci[1][4];
                 zero_acc<1>(cr, ci);
-                gemm_res16<E, NT, 2>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, nullptr, pipe, false);
+                gemm_res16<E, NT, 2, false, true>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, nullptr, pipe, false);
                 epi(base, cr, ci);
             }
         }
