@@ -305,21 +305,32 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
         Acc cr[MTW][4], ci[MTW][4];
         zero_acc<Acc, MTW>(cr, ci);
         gemm_rows<C, C::NT>(cr, ci, Tb, k, nred, base, brow, nr, sB);
-        // C + skeleton rows of the candidate vector
+        // C + skeleton rows of the candidate vector.  Per 16-row tile the
+        // skeleton inputs are loaded at in-range addresses (row 0 / column 0
+        // outside the block) so that a lane's loads issue together.
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
+            C2 sv[4][C::NTC];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = base + mt * 16 + Real<T>::out_row(lk, v);
+                const int src = crow[perm[row < k ? row : 0]];
+#pragma unroll
+                for (int nt = 0; nt < C::NTC; ++nt) {
+                    const int r = nt * 16 + lr;
+                    sv[v][nt] = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + (r < nr ? r : 0));
+                }
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = base + mt * 16 + Real<T>::out_row(lk, v);
                 if (row < k) {
-                    const int src = crow[perm[row]];
 #pragma unroll
                     for (int nt = 0; nt < C::NTC; ++nt) {
                         const int r = nt * 16 + lr;
-                        if (r < nr) {
-                            const C2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                            out[(yo + row) * A.nrhs + r0 + r] = c2<T>(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
-                        }
+                        if (r < nr)
+                            out[(yo + row) * A.nrhs + r0 + r] =
+                                c2<T>(cr[mt][nt][v] + sv[v][nt].x, ci[mt][nt][v] + sv[v][nt].y);
                     }
                 }
             }
@@ -398,10 +409,13 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const C2* scr) {
         for (int e = threadIdx.x; e < ncand * half; e += MT) {
             const int p = e / half, r = 2 * (e - p * half);
             float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-            for (int t = 0; t < A.G.P; ++t) {
-                const float4 v = *reinterpret_cast<const float4*>(scr + base[t] + (long long)p * A.nrhs + r);
-                acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
-            }
+            float4 v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)       // P <= 8; the P loads issue together
+                if (t < A.G.P) v[t] = *reinterpret_cast<const float4*>(scr + base[t] + (long long)p * A.nrhs + r);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (t < A.G.P) { acc.x += v[t].x; acc.y += v[t].y; acc.z += v[t].z; acc.w += v[t].w; }
             *reinterpret_cast<float4*>(outp + (long long)crow[p] * A.nrhs + r0 + r) = acc;
         }
         return;
@@ -410,11 +424,16 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const C2* scr) {
         const int p = e / NRHS, r = e - p * NRHS;
         if (r >= nr) continue;
         decltype(C2::x) sx = 0, sy = 0;
-        for (int t = 0; t < A.G.P; ++t) {
-            const C2 v = scr[base[t] + (long long)p * A.nrhs + r];
-            sx += v.x;
-            sy += v.y;
-        }
+        C2 v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)           // P <= 8; the P loads issue together
+            if (t < A.G.P) v[t] = scr[base[t] + (long long)p * A.nrhs + r];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (t < A.G.P) {
+                sx += v[t].x;
+                sy += v[t].y;
+            }
         C2 o;
         o.x = sx;
         o.y = sy;
@@ -526,11 +545,14 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const C2* src = (const C2*)A.src;
     C2* dst = (C2*)A.dst;
+    // loads at in-range addresses (clamped row and column), so that a thread's
+    // sixteen loads issue together; only the stores are guarded
     if constexpr (TO_EXT) {
+#pragma unroll
         for (int pp = ty; pp < 64; pp += 4) {
-            const long long p = p0 + pp;
-            const int r = r0 + tx;
-            if (p < A.N && r < A.nrhs) t[pp][tx] = src[p * A.nrhs + r];
+            const long long p = min(p0 + pp, A.N - 1);
+            const int r = min(r0 + tx, A.nrhs - 1);
+            t[pp][tx] = src[p * A.nrhs + r];
         }
         __syncthreads();
         for (int rr = ty; rr < 64; rr += 4) {
@@ -539,10 +561,11 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
             if (p < A.N && r < A.nrhs) dst[(long long)r * A.ld + p] = t[tx][rr];
         }
     } else {
+#pragma unroll
         for (int rr = ty; rr < 64; rr += 4) {
-            const long long p = p0 + tx;
-            const int r = r0 + rr;
-            if (p < A.N && r < A.nrhs) t[tx][rr] = src[(long long)r * A.ld + p];
+            const long long p = min(p0 + tx, A.N - 1);
+            const int r = min(r0 + rr, A.nrhs - 1);
+            t[tx][rr] = src[(long long)r * A.ld + p];
         }
         __syncthreads();
         for (int pp = ty; pp < 64; pp += 4) {
