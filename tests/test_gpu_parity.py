@@ -290,6 +290,27 @@ def test_fp16x3_every_variant(variant):
     assert F.tune(64, "fp16x3")[0] in range(10)
 
 
+@pytest.mark.parametrize("nrhs", [64, 70])
+def test_fp16x3_lattice_input_path(nrhs):
+    """When the first up step keeps every leaf point (64^2: every leaf decomposition is full rank),
+    the table-driven split kernels (variants 7-9) transpose the input into the row-major copy and
+    the step above reads it through lattice rows; the other variants keep the first-step copy.
+    Both must match the FP64 apply; the profile shows which path ran."""
+    n = 64
+    F = _build(n, "fio_ellipse", precisions=1 | 8)
+    assert int(F.ranks(1, 0).min()) == 64         # no redundant leaf points on the column side
+    f = W.complex_gaussian(n * n, nrhs, 64, n)
+    g64 = from_dev(F.apply(to_dev(f)))
+    for v, lattice in ((9, True), (7, True), (0, False)):
+        F.set_variants([v] * 3, precision="fp16x3")
+        F.profile(True, by_level=True)
+        g = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp16x3"))
+        names = [r["name"] for r in F.profile_read()]
+        F.profile(False)
+        assert ("transpose_fp16x3_in" in names) == lattice, (v, names)
+        assert rel_l2(g, g64) < 5e-6, v
+
+
 def test_split16_precisions_need_their_copy():
     F = _build(64, "fio_ellipse", precisions=1 | 2)
     from paper_1908_09376_amd._lib import MidbfError
