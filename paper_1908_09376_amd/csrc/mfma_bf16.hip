@@ -953,12 +953,13 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
             return;
         }
         if constexpr (!RES_ONLY) {
-            APipe<E, 2, false> pipe;
+            constexpr int UAD = NT >= 1024 ? 1 : 2;   // factor tiles requested ahead (16 waves: register budget)
+            APipe<E, UAD, false> pipe;
             for (int m0 = 0; m0 < k; m0 += NW * 16) {
                 const int base = m0 + wave * 16;
                 floatx4 cr[1][4], ci[1][4];
                 zero_acc<1>(cr, ci);
-                gemm_res16<E, NT, 2, false, true>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, nullptr, pipe, false);
+                gemm_res16<E, NT, UAD, false, true>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, nullptr, pipe, false);
                 epi(base, cr, ci);
             }
         }
@@ -1032,9 +1033,10 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
     const int* Sang = ANG ? A.ang + tile_off[bi] * 512 : nullptr;
     // the first factor tiles are requested ahead of the row tables and the barrier
-    APipe<E, 2, ANG> pipe;
+    constexpr int MAD = NT >= 1024 ? 1 : 2;  // factor tiles requested ahead (16 waves: register budget)
+    APipe<E, MAD, ANG> pipe;
     const int m_first = chunk * NW * 16;
-    a_prefetch<E, 2, ANG>(pipe, St, Sang, M, K, m_first + wave * 16);
+    a_prefetch<E, MAD, ANG>(pipe, St, Sang, M, K, m_first + wave * 16);
     middle_rows<NT>(crow_in, crow_out, A, bi);
     const float2* xin = (const float2*)A.in;
     float2* zout = (float2*)A.out;
@@ -1044,7 +1046,7 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
         const int base = m0 + wave * 16;
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
-        gemm_res16<E, NT, 2, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, Sang, pipe, m0 == m_first);
+        gemm_res16<E, NT, MAD, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, Sang, pipe, m0 == m_first);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
