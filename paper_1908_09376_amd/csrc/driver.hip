@@ -659,7 +659,8 @@ midbf_status midbf_ranks(midbf_handle h, int side, int step, int* out, long long
     if (!h || !out) return fail(MIDBF_ERR_ARG, "null argument");
     if (side < 0 || side > 1 || step < 0 || step >= h->b) return fail(MIDBF_ERR_ARG, "bad side or step");
     const auto& lv = side == 0 ? h->rows[step] : h->cols[step];
-    if (count > (long long)lv.k.size()) return fail(MIDBF_ERR_ARG, "count exceeds the number of IDs");
+    if (count < 0 || count > (long long)lv.k.size())
+        return fail(MIDBF_ERR_ARG, "count must lie in [0, number of IDs]");
     std::memcpy(out, lv.k.data(), count * sizeof(int));
     return MIDBF_OK;
 }

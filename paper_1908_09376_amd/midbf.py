@@ -74,11 +74,21 @@ class MIDBF:
             raise ValueError("expected shape (N,) or (nrhs, N)")
         return (1 if x.dim() == 1 else x.shape[0])
 
+    def _out(self, x: torch.Tensor, out: torch.Tensor | None) -> torch.Tensor:
+        """The output block: a new tensor like x, or the caller's, checked against x before any launch."""
+        if out is None:
+            return torch.empty_like(x)
+        if out.dtype != x.dtype or not out.is_cuda or not out.is_contiguous():
+            raise TypeError(f"out must be a contiguous CUDA {x.dtype} tensor")
+        if out.shape != x.shape or out.device != x.device:
+            raise ValueError("out must have the input's shape and device")
+        return out
+
     def apply(self, f: torch.Tensor, out: torch.Tensor | None = None, precision: str = "fp64",
               stream=None) -> torch.Tensor:
         """g = K f (midbf_apply)."""
         nrhs = self._prep(f, precision)
-        g = torch.empty_like(f) if out is None else out
+        g = self._out(f, out)
         L.check(L.lib.midbf_apply(self._h, f.data_ptr(), g.data_ptr(), nrhs, self.N, _PREC[precision],
                                   _stream_ptr(stream)))
         return g
@@ -87,7 +97,7 @@ class MIDBF:
                       stream=None) -> torch.Tensor:
         """f = K^H g (midbf_apply_adjoint)."""
         nrhs = self._prep(g, precision)
-        f = torch.empty_like(g) if out is None else out
+        f = self._out(g, out)
         L.check(L.lib.midbf_apply_adjoint(self._h, g.data_ptr(), f.data_ptr(), nrhs, self.N,
                                           _PREC[precision], _stream_ptr(stream)))
         return f
@@ -133,8 +143,8 @@ def _batch_arrays(handles, fs, outs, precision):
     if len(fs) != count or len(outs) != count:
         raise ValueError("one input and one output per handle")
     for f, g in zip(fs, outs):
-        if g.shape != f.shape or g.dtype != f.dtype or not g.is_contiguous():
-            raise ValueError("each output must match its input's shape and dtype")
+        if g.shape != f.shape or g.dtype != f.dtype or not g.is_contiguous() or g.device != f.device:
+            raise ValueError("each output must match its input's shape, dtype and device")
     hs = (C.c_void_p * count)(*[h._h for h in handles])
     fp = (C.c_void_p * count)(*[f.data_ptr() for f in fs])
     gp = (C.c_void_p * count)(*[g.data_ptr() for g in outs])

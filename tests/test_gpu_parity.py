@@ -198,6 +198,20 @@ def test_errors_reported():
     F = _build(32, "fio_ellipse", precisions=1)
     with pytest.raises(MidbfError):
         F.apply(torch.zeros(1024, dtype=torch.complex64, device=DEV), precision="fp32")
+    # a caller's output block is checked before any launch
+    f = torch.zeros(1024, dtype=torch.complex128, device=DEV)
+    with pytest.raises(TypeError):
+        F.apply(f, out=torch.zeros(1024, dtype=torch.complex64, device=DEV))
+    with pytest.raises(ValueError):
+        F.apply(f, out=torch.zeros(1000, dtype=torch.complex128, device=DEV))
+    with pytest.raises(ValueError):
+        F.apply_adjoint(f, out=torch.zeros((2, 1024), dtype=torch.complex128, device=DEV))
+    # a negative count is rejected by midbf_ranks
+    import ctypes
+    from paper_1908_09376_amd import _lib
+    buf = (ctypes.c_int * 4)()
+    assert _lib.lib.midbf_ranks(F._h, 0, 0, buf, -1) == -1
+    assert b"count" in _lib.lib.midbf_last_error()
 
 
 # ---- matrix-core path (many right-hand sides, FP32) -------------------------

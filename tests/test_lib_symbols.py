@@ -36,3 +36,17 @@ def test_error_path_without_gpu_work():
     from paper_1908_09376_amd import _lib
     st = _lib.lib.midbf_apply(None, None, None, 1, 16, 0, None)
     assert st == -1 and b"null" in _lib.lib.midbf_last_error()
+
+
+def test_output_block_checked_before_launch():
+    # the binding rejects an output of the wrong dtype or on the host before calling the library
+    import pytest
+    import torch
+    from paper_1908_09376_amd.midbf import MIDBF
+    F = object.__new__(MIDBF)
+    F.N = 16
+    x = torch.zeros(16, dtype=torch.complex64)
+    with pytest.raises(TypeError):
+        F._out(x, torch.zeros(16, dtype=torch.complex128))
+    with pytest.raises(TypeError):
+        F._out(x, torch.zeros(16, dtype=torch.complex64))      # not a CUDA tensor

@@ -71,3 +71,22 @@ def test_direct_adjoint_identity(phase):
     lhs = np.vdot(h, direct_sum(K, f))
     rhs = np.vdot(direct_sum_adjoint(K, h), f)
     assert abs(lhs - rhs) / abs(lhs) < 1e-12
+
+
+def test_lowrank_branch_orientation():
+    """Kernel(("lowrank", U, V)) evaluates Phi = U(I,:) V(J,:)^T: with U = [x, c(x)] and
+    V = [xi, |xi|] it is the 3-D phase x . xi + c(x)|xi| (pinned by hand values above), and
+    with U = x, V = xi the linear phase whose direct sum is the FFT."""
+    n = 8
+    x, xi = x_points(3, n), xi_points(3, n)
+    c = (3.0 + np.prod(np.sin(2 * np.pi * x), axis=1)) / 100.0
+    U = np.c_[x, c]
+    V = np.c_[xi, np.linalg.norm(xi, axis=1)]
+    I = W.index_sample(n ** 3, 50, 81, 0)
+    J = W.index_sample(n ** 3, 60, 81, 1)
+    low = Kernel(3, n, ("lowrank", U, V))
+    assert np.abs(low.phi(I, J) - Kernel(3, n, "iso3d").phi(I, J)).max() < 1e-13
+    assert low.phi(I, J).shape == (50, 60)
+    lin = Kernel(2, 16, ("lowrank", x_points(2, 16), xi_points(2, 16)))
+    f = W.complex_gaussian(256, 2, 81, 2)
+    assert rel_l2(direct_sum(lin, f), fft_linear(2, 16, f)) < 1e-12

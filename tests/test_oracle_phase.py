@@ -244,3 +244,79 @@ def test_max_block_increment_ignores_cut_edges():
     v = np.array([0.0, 0.1, 0.9, 1.0])
     assert abs(max_block_increment(v, P, np.array([0, 0, 0, 0])) - 0.8) < 1e-15
     assert abs(max_block_increment(v, P, np.array([0, 0, 1, 1])) - 0.1) < 1e-15
+
+
+# ---- the tau schedule and Partition2 anchoring, pinned by closed forms ------------------------
+#
+# Phi(x, xi) = x . xi + 0.35 [x1 >= 1/2] + 0.31 [xi2 >= 0.2] on x = a/n and xi = 0.9 (b - n/2)/n
+# (n = 32).  Inside each block every path step of Phi is below 0.03, so Lemma 2.2 holds there;
+# the two jumps are what the schedule (Sec. 2.3.4) and Partition2 (Alg. 6) must handle:
+#   * root column (xi = 0): Phi = 0.35 [x1 >= 1/2].  The comb tree rooted at x = 0 crosses
+#     x1 = 1/2 on one edge only (along the a2 = 0 line), so exactly one row node is flagged for
+#     every tau <= 0.35: node (n/2, 0), which roots the second row block.
+#   * root row (x = 0): Phi = 0.31 [xi2 >= 0.2].  The comb tree rooted at xi = 0 crosses that
+#     line once per xi1 column: n = 32 > 16 flags for every tau <= 0.31, none above.  The
+#     schedule 1/4 + j/40 therefore stops at j = 3, tau = 0.325.
+#   * every block root (s, t) sits where Phi(root_s, root_t) lies in (-1/2, 1/2], so the raw
+#     anchors carry no integer offset and every recovered row and column equals Phi itself.
+
+def _two_jump_phase(n):
+    N = n * n
+    a = np.array(np.unravel_index(np.arange(N), (n, n))).T
+    x = a / n
+    xi = (a - n // 2) / n * 0.9
+
+    def Phi(I, J):
+        I, J = np.atleast_1d(I), np.atleast_1d(J)
+        return x[I] @ xi[J].T + 0.35 * (x[I, 0] >= 0.5)[:, None] + 0.31 * (xi[J, 1] >= 0.2)[None, :]
+    return Phi, x, xi
+
+
+def test_tau_schedule_and_block_anchors_closed_form():
+    from oracle.phase import recovery_matrix2
+    n = 32
+    N = n * n
+    Phi, x, xi = _two_jump_phase(n)
+    kr = lambda i: np.exp(2j * np.pi * Phi([i], np.arange(N))[0])
+    kc = lambda j: np.exp(2j * np.pi * Phi(np.arange(N), [j])[:, 0])
+    P1 = recovery_path_lattice(2, n, (0, 0))
+    P2 = recovery_path_lattice(2, n, (n // 2, n // 2))
+    H = recovery_matrix2(kr, kc, N, P1, P2)
+    assert abs(H.tau - 0.325) < 1e-12
+    assert H.Dr[1:] == [(n // 2) * n] and H.Dc[1:] == []
+    assert [r for r, _ in H.blocks_r] == [0, (n // 2) * n] and len(H.blocks_c) == 1
+    assert np.array_equal(H.owner_r, (x[:, 0] >= 0.5).astype(np.int64))
+    # every recovered row / column is Phi itself (block anchors without offsets)
+    for i in W.index_sample(N, 12, 26, 0):
+        assert np.abs(H.row(int(i)) - Phi([i], np.arange(N))[0]).max() < 1e-12
+    for j in W.index_sample(N, 12, 26, 1):
+        assert np.abs(H.col(int(j)) - Phi(np.arange(N), [j])[:, 0]).max() < 1e-12
+    # Alg. 7 on top: rank(Phi) = 4 (x . xi, two indicator terms) <= r, so U V^T = Phi
+    U, V, _ = low_rank_factorization(kr, kc, N, P1, P2, 8, 2, W.rng(26, 2))
+    S = W.index_sample(N, 150, 26, 3)
+    assert np.abs(U[S] @ V[S].T - Phi(S, S)).max() < 1e-9
+    assert eps_K(np.exp(2j * np.pi * Phi(S, S)), U, V, S) < 1e-12
+
+
+def test_tau_schedule_runs_out_at_one_half():
+    """A phase with no smoothness (iid uniform entries): wrapped path increments are uniform on
+    (-1/2, 1/2], so about (N - 1)(1 - 2 tau) of them reach tau -- about 51 > 16 at the last grid
+    value below 1/2 (tau = 0.475, N = 32^2) -- and the schedule stops at 1/4 + 10/40 = 1/2."""
+    from oracle.phase import recovery_matrix2
+    n = 32
+    N = n * n
+    g = W.rng(27, 0)
+    Phi = g.random((N, N))
+    kr = lambda i: np.exp(2j * np.pi * Phi[i])
+    kc = lambda j: np.exp(2j * np.pi * Phi[:, j])
+    P = recovery_path_lattice(2, n, (0, 0))
+    H = recovery_matrix2(kr, kc, N, P, P)
+    assert abs(H.tau - 0.5) < 1e-12
+    # one grid step earlier the root row and column each carry more than 16 increments >= 0.475:
+    # by the prefix-sum identity of Alg. 4 the increments are wrap(u(ed) - u(bg)) of the raw phases
+    for vec in (Phi[:, 0], Phi[0, :]):
+        u = wrapped_phase(np.exp(2j * np.pi * vec))
+        w = u[P[:, 1]] - u[P[:, 0]]
+        w = w - mround(w)
+        assert (np.abs(w) >= 0.475).sum() > 16
+    assert len(H.Dr) - 1 <= 16 and len(H.Dc) - 1 <= 16
