@@ -129,6 +129,35 @@ midbf_status midbf_build(const midbf_params* p, void* stream, midbf_handle* out)
 midbf_status midbf_apply(midbf_handle h, const void* f_dev, void* g_dev, int nrhs, long long ld,
                          midbf_precision prec, void* stream);
 
+/* Bytes of device scratch behind midbf_apply_noalloc (per GPU, held by the
+ * library from the first such call on that GPU until the process ends). */
+#define MIDBF_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * midbf_apply_noalloc -- midbf_apply for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, layouts, kernels and results as
+ * midbf_apply; the level vectors (and, on the matrix-core paths, the
+ * lattice-order copy and the down pass's contribution block) live in one static
+ * device array of MIDBF_NOALLOC_SCRATCH_BYTES per GPU instead of the handle's
+ * workspace.  No hipMalloc, hipFree or other allocating call is made, and no
+ * profiler events are taken (a handle's profiler records nothing for it).
+ * Nothing in the scratch needs to start at zero: every element a kernel reads
+ * was written earlier in the same call.
+ * Limit: 2 * max_level_rows * nrhs * c, plus N * nrhs * c on the matrix-core
+ * paths with nrhs > 1 (the lattice copy), plus max_candidate_rows * nrhs * c
+ * where the matrix-core down pass writes per-decomposition contributions
+ * (FP32 and FP64 matrix cores, split tile variants 0-4), each part rounded
+ * up to 256, with c = 16 (FP64) or 8; larger applies return MIDBF_ERR_SHAPE
+ * with the size needed (one right-hand side at N = 256^2 needs ~8 MB).
+ * Concurrency: every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (different streams or threads) race; serialize them.
+ * Errors: as midbf_apply, plus MIDBF_ERR_SHAPE beyond the limit and
+ * MIDBF_ERR_HIP if the scratch's device address cannot be obtained.
+ */
+midbf_status midbf_apply_noalloc(midbf_handle h, const void* f_dev, void* g_dev, int nrhs, long long ld,
+                                 midbf_precision prec, void* stream);
+
 /*
  * midbf_apply_adjoint -- f = K~^H g: conjugate-transposed factors in reverse
  * order (the transposed butterfly).  Same layouts as midbf_apply.

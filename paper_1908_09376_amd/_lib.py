@@ -52,6 +52,8 @@ class RecoverInfo(C.Structure):
                 ("shift", (C.c_int * 4) * 64)]
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20   # MIDBF_NOALLOC_SCRATCH_BYTES
+
 SAMPLE_CB = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_longlong, C.POINTER(C.c_double))
 
 
@@ -71,6 +73,7 @@ def _load():
         "midbf_build": (i, [C.POINTER(Params), vp, C.POINTER(vp)]),
         "midbf_apply": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_adjoint": (i, [vp, vp, vp, i, ll, i, vp]),
+        "midbf_apply_noalloc": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_batched": (i, [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(i), i, vp]),
         "midbf_batch_create": (i, [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(i), i, i, vp,
                                    C.POINTER(vp)]),
@@ -105,7 +108,7 @@ def check(status: int) -> None:
         raise MidbfError(status, lib.midbf_last_error().decode())
 
 
-EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_batched",
+EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_noalloc", "midbf_apply_batched",
             "midbf_batch_create", "midbf_batch_run", "midbf_batch_get_stats",
             "midbf_batch_destroy",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",

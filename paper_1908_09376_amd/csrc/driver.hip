@@ -4,12 +4,20 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "apply.h"
 #include "build.h"
 #include "mfma.h"
 #include "recover.h"
+
+// Device scratch of midbf_apply_noalloc: level vectors, the matrix-core down
+// pass's contribution block and the lattice-order copy of one apply.  Each
+// GPU the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (noalloc_scratch below), never through this name.
+static __device__ __align__(256) unsigned char scratch[MIDBF_NOALLOC_SCRATCH_BYTES];
 
 namespace midbf {
 
@@ -86,9 +94,9 @@ hipEvent_t take_event(Profiler& P) {
 // Launch one level kernel; with profiling on, bracket it with events on the
 // same stream and record its algorithmic bytes and flops.  mfma_count > 0
 // selects the matrix-core kernel with that many workgroups in x.
-void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
-                    hipStream_t st, double bytes, double flops, long long mfma_count = 0, int nrhs = 0,
-                    int level = -1) {
+void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int prec, int rt, const void* args,
+                    dim3 grid, size_t smem, hipStream_t st, double bytes, double flops, long long mfma_count = 0,
+                    int nrhs = 0, int level = -1, bool profile = true) {
     MIDBF_CHECK(mfma_count > 0 || smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
     auto go = [&] {
@@ -112,18 +120,18 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
             if (is_split16(prec) && which != LevelKernel::DownSum)
                 launch_bf16_kernel(prec == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, which,
                                    (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[kind][lv], args,
-                                   mfma_count, nrhs, h->ws[prec].scratch,
+                                   mfma_count, nrhs, ws.scratch,
                                    which == LevelKernel::DownDense ? ((const MidArgs*)args)->off
                                                                    : h->mid.d_tile_off,
                                    st);
             else
                 launch_mfma_kernel(which, (prec == PREC_FP64 ? h->mfma64_variant : h->mfma_variant)[kind][lv], args,
-                                   mfma_count, nrhs, h->ws[prec].scratch, st, prec == PREC_FP64);
+                                   mfma_count, nrhs, ws.scratch, st, prec == PREC_FP64);
         }
         else launch_level_kernel(which, prec, rt, args, grid, smem, st);
     };
     Profiler& P = h->prof;
-    if (!P.on) {
+    if (!P.on || !profile) {
         go();
         return;
     }
@@ -151,33 +159,46 @@ void launch_checked(midbf_plan* h, LevelKernel which, int prec, int rt, const vo
     P.recs.push_back(r);
 }
 
+// Bytes of each workspace part an apply of nrhs right-hand sides needs: the
+// two level-vector buffers (each), the matrix-core down pass's contribution
+// block and the N x nrhs lattice-order copy.
+struct WorkspaceNeed {
+    size_t buf, scratch, lat;
+};
+
+WorkspaceNeed workspace_need(const midbf_plan* h, int prec, int nrhs, bool scratch, bool lat) {
+    WorkspaceNeed w;
+    w.buf = (size_t)std::max<long long>(h->max_total_k, 1) * nrhs * csize(prec);
+    w.scratch = scratch ? (size_t)std::max<long long>(h->max_total_n, 1) * nrhs * csize(prec) : 0;
+    w.lat = lat ? (size_t)h->N * nrhs * csize(prec) : 0;
+    return w;
+}
+
 void ensure_workspace(midbf_plan* h, int prec, int nrhs, bool scratch, bool lat) {
     Workspace& w = h->ws[prec];
-    const size_t need = (size_t)std::max<long long>(h->max_total_k, 1) * nrhs * csize(prec);
-    if (w.bytes < need) {
+    const WorkspaceNeed need = workspace_need(h, prec, nrhs, scratch, lat);
+    if (w.bytes < need.buf) {
         if (w.buf[0]) MIDBF_HIP(hipFree(w.buf[0]));
         if (w.buf[1]) MIDBF_HIP(hipFree(w.buf[1]));
         w.buf[0] = w.buf[1] = nullptr;
         w.bytes = 0;
-        MIDBF_HIP(hipMalloc(&w.buf[0], need));
-        MIDBF_HIP(hipMalloc(&w.buf[1], need));
-        w.bytes = need;
+        MIDBF_HIP(hipMalloc(&w.buf[0], need.buf));
+        MIDBF_HIP(hipMalloc(&w.buf[1], need.buf));
+        w.bytes = need.buf;
     }
-    const size_t sneed = (size_t)std::max<long long>(h->max_total_n, 1) * nrhs * csize(prec);
-    if (scratch && w.scratch_bytes < sneed) {
+    if (scratch && w.scratch_bytes < need.scratch) {
         if (w.scratch) MIDBF_HIP(hipFree(w.scratch));
         w.scratch = nullptr;
         w.scratch_bytes = 0;
-        MIDBF_HIP(hipMalloc(&w.scratch, sneed));
-        w.scratch_bytes = sneed;
+        MIDBF_HIP(hipMalloc(&w.scratch, need.scratch));
+        w.scratch_bytes = need.scratch;
     }
-    const size_t lneed = (size_t)h->N * nrhs * csize(prec);
-    if (lat && w.lat_bytes < lneed) {
+    if (lat && w.lat_bytes < need.lat) {
         if (w.lat) MIDBF_HIP(hipFree(w.lat));
         w.lat = nullptr;
         w.lat_bytes = 0;
-        MIDBF_HIP(hipMalloc(&w.lat, lneed));
-        w.lat_bytes = lneed;
+        MIDBF_HIP(hipMalloc(&w.lat, need.lat));
+        w.lat_bytes = need.lat;
     }
 }
 
@@ -441,25 +462,110 @@ void check_apply_args(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs
     MIDBF_CHECK(h->keep & (1u << prec), MIDBF_ERR_ARG, "this precision's factors were not kept by the build");
 }
 
-void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
-               hipStream_t st, bool adjoint) {
-    check_apply_args(h, in_ext, out_ext, nrhs, ld, prec);
+// Which kernels an apply runs: matrix cores (split 16-bit always; FP32 and
+// FP64 for many right-hand sides) and, on matrix cores with several
+// right-hand sides, the row-major lattice copy around the leaf levels.
+struct ApplyMode {
+    bool mfma, lat;
+    int rt;
+};
+
+ApplyMode apply_mode(const midbf_plan* h, int nrhs, int prec, bool adjoint) {
     const bool fits = h->max_n <= MFMA_CROW_MAX && h->mid.nr_max + h->mid.nc_max <= 2 * MFMA_CROW_MAX;
     const bool fits_bf16 =
         h->max_n <= BF16_CROW_MAX && h->mid.nr_max <= BF16_CROW_MAX && h->mid.nc_max <= BF16_CROW_MAX;
     MIDBF_CHECK(!is_split16(prec) || (!adjoint && fits_bf16), MIDBF_ERR_UNIMPLEMENTED,
                 "the split 16-bit applies exist for the forward transform with candidate sets up to 2048");
-    // matrix cores: split 16-bit always, FP32 for many right-hand sides
-    const bool mfma = is_split16(prec) ||
-                      ((prec == PREC_FP32 || prec == PREC_FP64) && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
-    const bool lat = mfma && nrhs > 1;   // row-major lattice copy around the leaf levels
-    ensure_workspace(h, prec, nrhs, mfma, lat);
-    const int rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
-    const auto launches = plan_apply(h, in_ext, out_ext, nrhs, ld, prec, adjoint, mfma, h->ws[prec].buf, true, rt,
-                                     lat ? h->ws[prec].lat : nullptr);
+    ApplyMode m;
+    m.mfma = is_split16(prec) ||
+             ((prec == PREC_FP32 || prec == PREC_FP64) && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
+    m.lat = m.mfma && nrhs > 1;
+    m.rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
+    return m;
+}
+
+// Whether a launch sequence uses the matrix-core down pass's per-ID
+// contribution block (Workspace::scratch).
+bool needs_scratch(const std::vector<LaunchDesc>& launches) {
     for (const LaunchDesc& D : launches)
-        launch_checked(h, D.which, prec, rt, &D.a, D.grid, D.smem, st, D.bytes, D.flops, D.mfma_count, nrhs,
-                       D.level);
+        if (D.mfma_count > 0 && (D.which == LevelKernel::Down || D.which == LevelKernel::DownSum)) return true;
+    return false;
+}
+
+std::vector<LaunchDesc> plan_for(midbf_plan* h, const Workspace& ws, const ApplyMode& m, const void* in_ext,
+                                 void* out_ext, int nrhs, long long ld, int prec, bool adjoint) {
+    return plan_apply(h, in_ext, out_ext, nrhs, ld, prec, adjoint, m.mfma, ws.buf, true, m.rt,
+                      m.lat ? ws.lat : nullptr);
+}
+
+// Launch a planned apply; the contribution block is read from ws at launch.
+// profile = false: no events are taken, even with the handle's profiler on.
+void launch_planned(midbf_plan* h, const Workspace& ws, const ApplyMode& m, const std::vector<LaunchDesc>& launches,
+                    int nrhs, int prec, hipStream_t st, bool profile) {
+    for (const LaunchDesc& D : launches)
+        launch_checked(h, ws, D.which, prec, m.rt, &D.a, D.grid, D.smem, st, D.bytes, D.flops, D.mfma_count, nrhs,
+                       D.level, profile);
+}
+
+void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
+               hipStream_t st, bool adjoint) {
+    check_apply_args(h, in_ext, out_ext, nrhs, ld, prec);
+    const ApplyMode m = apply_mode(h, nrhs, prec, adjoint);
+    ensure_workspace(h, prec, nrhs, false, m.lat);
+    const auto launches = plan_for(h, h->ws[prec], m, in_ext, out_ext, nrhs, ld, prec, adjoint);
+    if (needs_scratch(launches)) ensure_workspace(h, prec, nrhs, true, m.lat);
+    launch_planned(h, h->ws[prec], m, launches, nrhs, prec, st, true);
+}
+
+// Device address of the no-allocation scratch on the current device, looked
+// up once per device with that device current.
+void* noalloc_scratch() {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEVICES] = {};
+    int dev = -1;
+    MIDBF_HIP(hipGetDevice(&dev));
+    MIDBF_CHECK(dev >= 0 && dev < MAX_DEVICES, MIDBF_ERR_HIP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        MIDBF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        MIDBF_CHECK(p != nullptr, MIDBF_ERR_HIP, "no device address for the no-allocation scratch");
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
+// midbf_apply with every workspace part carved out of the static scratch
+// (256-byte aligned pieces: both level buffers, the lattice copy, then the
+// contribution block if the launches use it); no device or profiler
+// allocation.
+void run_apply_noalloc(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
+                       hipStream_t st) {
+    check_apply_args(h, in_ext, out_ext, nrhs, ld, prec);
+    const ApplyMode m = apply_mode(h, nrhs, prec, false);
+    const WorkspaceNeed need = workspace_need(h, prec, nrhs, true, m.lat);
+    auto round_up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b = round_up(need.buf), la = round_up(need.lat), sc = round_up(need.scratch);
+    unsigned char* base = (unsigned char*)noalloc_scratch();
+    Workspace ws;
+    ws.buf[0] = base;
+    ws.buf[1] = base + b;
+    ws.bytes = need.buf;
+    ws.lat = m.lat ? base + 2 * b : nullptr;
+    ws.lat_bytes = need.lat;
+    const auto launches = plan_for(h, ws, m, in_ext, out_ext, nrhs, ld, prec, false);
+    const bool scr = needs_scratch(launches);
+    if (scr) {
+        ws.scratch = base + 2 * b + la;
+        ws.scratch_bytes = need.scratch;
+    }
+    const size_t total = 2 * b + la + (scr ? sc : 0);
+    MIDBF_CHECK(total <= (size_t)MIDBF_NOALLOC_SCRATCH_BYTES, MIDBF_ERR_SHAPE,
+                "this apply needs " + std::to_string(total) + " bytes of workspace; the no-allocation scratch holds " +
+                    std::to_string((size_t)MIDBF_NOALLOC_SCRATCH_BYTES) +
+                    " (use midbf_apply, or fewer right-hand sides per call)");
+    launch_planned(h, ws, m, launches, nrhs, prec, st, false);
 }
 
 }  // namespace
@@ -600,6 +706,12 @@ midbf_status midbf_apply(midbf_handle h, const void* f, void* g, int nrhs, long 
                          void* stream) {
     if (!h) return fail(MIDBF_ERR_ARG, "null handle");
     return guarded([&] { run_apply(h, f, g, nrhs, ld, prec_index(prec), (hipStream_t)stream, false); });
+}
+
+midbf_status midbf_apply_noalloc(midbf_handle h, const void* f, void* g, int nrhs, long long ld,
+                                 midbf_precision prec, void* stream) {
+    if (!h) return fail(MIDBF_ERR_ARG, "null handle");
+    return guarded([&] { run_apply_noalloc(h, f, g, nrhs, ld, prec_index(prec), (hipStream_t)stream); });
 }
 
 midbf_status midbf_apply_adjoint(midbf_handle h, const void* g, void* f, int nrhs, long long ld,

@@ -93,6 +93,15 @@ class MIDBF:
                                   _stream_ptr(stream)))
         return g
 
+    def apply_noalloc(self, f: torch.Tensor, out: torch.Tensor | None = None, precision: str = "fp64",
+                      stream=None) -> torch.Tensor:
+        """g = K f with the library's static device scratch instead of a workspace (midbf_apply_noalloc)."""
+        nrhs = self._prep(f, precision)
+        g = self._out(f, out)
+        L.check(L.lib.midbf_apply_noalloc(self._h, f.data_ptr(), g.data_ptr(), nrhs, self.N, _PREC[precision],
+                                          _stream_ptr(stream)))
+        return g
+
     def apply_adjoint(self, g: torch.Tensor, out: torch.Tensor | None = None, precision: str = "fp64",
                       stream=None) -> torch.Tensor:
         """f = K^H g (midbf_apply_adjoint)."""
