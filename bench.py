@@ -5,9 +5,10 @@ Default workload: the 512^2 ellipse-phase transform (Example 1 shape on the
 integer frequency grid), 64 complex Gaussian right-hand sides in one launch
 sequence, split-fp16 matrix-core apply (fp16 hi + lo, FP32 accumulation;
 its error against the FP64 direct sum is reported next to the result, with
-the FP32 and FP64 applies timed beside it).  A "step" is one full apply of the factor product to
-the 64 right-hand sides (every level kernel, the middle, both permutations);
-inputs are resident in HBM before timing starts.
+the FP32, split-bf16 and FP64 applies timed beside it).  A "step" is one full apply of the factor
+product to the 64 right-hand sides (every level kernel, the middle, both permutations), timed as
+replays of the apply captured in a hipGraph; per-kernel times come from HIP events around eager
+launches.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -72,30 +73,52 @@ def traffic_for(kernel: str, variant, workload: str):
     return rec["hbm_bytes_per_launch"]
 
 
+def compute_peak(prec: str, kernel: str) -> float:
+    """TFLOP/s peak of the arithmetic a kernel runs on."""
+    if prec in ("bf16x3", "fp16x3"):
+        return PEAK["bf16_mfma_TF"]      # dense bf16 and fp16 matrix peaks are equal
+    if prec == "fp64":
+        return PEAK["fp64_TF"]
+    return PEAK["fp32_mfma_TF"] if "mfma" in kernel else PEAK["fp32_vector_TF"]
+
+
 def roofline(dominant: dict, prec: str, variant=None, workload: str = ""):
+    """Both fractions of the dominant kernel: algorithmic bytes / time against HBM, and flops / time
+    against the peak of its arithmetic (split 16-bit: 24 16-bit flops per complex entry and right-hand
+    side on the matrix cores).  `bound` names the larger of the two; neither is reached when both are
+    well below 1 (the kernel is then latency-bound inside its workgroups)."""
     launches = dominant["launches"]
     t = dominant["total_ms"] / 1e3 / launches
     bytes_per = dominant["bytes"] / launches
+    stored_per = dominant.get("stored_bytes", dominant["bytes"]) / launches
     flops_per = dominant["flops"] / launches
-    if prec in ("bf16x3", "fp16x3"):
-        peak_tf = PEAK["bf16_mfma_TF"]      # dense bf16 and fp16 matrix peaks are equal
-    elif prec == "fp64":
-        peak_tf = PEAK["fp64_TF"]
-    else:
-        peak_tf = PEAK["fp32_mfma_TF"] if "mfma" in dominant["name"] else PEAK["fp32_vector_TF"]
-    ridge = peak_tf * 1e12 / (PEAK["hbm_GBps"] * 1e9)
-    if flops_per / max(bytes_per, 1.0) > ridge:
-        bound = "mfma" if ("mfma" in dominant["name"] or prec in ("bf16x3", "fp16x3")) else "alu"
-        ach = flops_per / t / 1e12
-        return {"bound": bound, "achieved": round(ach, 3), "peak": peak_tf, "unit": "TFLOP/s",
-                "frac": round(ach / peak_tf, 4), "traffic": traffic_for(dominant["name"], variant, workload),
-                "kernel": dominant["name"], "avg_ms": round(t * 1e3, 4),
-                "algorithmic_bytes_per_launch": bytes_per, "flops_per_launch": flops_per}
-    ach = bytes_per / t / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
-            "frac": round(ach / PEAK["hbm_GBps"], 4), "traffic": traffic_for(dominant["name"], variant, workload),
-            "kernel": dominant["name"], "avg_ms": round(t * 1e3, 4),
-            "algorithmic_bytes_per_launch": bytes_per, "flops_per_launch": flops_per}
+    peak_tf = compute_peak(prec, dominant["name"])
+    gbps = bytes_per / t / 1e9
+    tfs = flops_per / t / 1e12
+    f_hbm, f_cmp = gbps / PEAK["hbm_GBps"], tfs / peak_tf
+    cmp_bound = "mfma" if ("mfma" in dominant["name"] or prec in ("bf16x3", "fp16x3")) else "alu"
+    common = {"traffic": traffic_for(dominant["name"], variant, workload), "kernel": dominant["name"],
+              "avg_ms": round(t * 1e3, 4), "frac_hbm": round(f_hbm, 4), "frac_" + cmp_bound: round(f_cmp, 4),
+              "achieved_GBps": round(gbps, 1), "achieved_TFLOPs": round(tfs, 3), "peak_TFLOPs": peak_tf,
+              "algorithmic_bytes_per_launch": bytes_per, "stored_bytes_per_launch": stored_per,
+              "flops_per_launch": flops_per}
+    if f_cmp > f_hbm:
+        return {"bound": cmp_bound, "achieved": round(tfs, 3), "peak": peak_tf, "unit": "TFLOP/s",
+                "frac": round(f_cmp, 4), **common}
+    return {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+            "frac": round(f_hbm, 4), **common}
+
+
+def step_roofline(kt: list[dict], steps: int, ms: float, prec: str) -> dict:
+    """The whole step: every kernel's algorithmic bytes and flops over the measured step time."""
+    b = sum(r["bytes"] for r in kt) / steps
+    st = sum(r.get("stored_bytes", r["bytes"]) for r in kt) / steps
+    fl = sum(r["flops"] for r in kt) / steps
+    peak_tf = compute_peak(prec, "mfma" if prec != "fp64" else "")
+    return {"ms": round(ms, 4), "algorithmic_bytes": b, "stored_bytes": st, "flops": fl,
+            "GBps": round(b / ms / 1e6, 1), "frac_hbm": round(b / ms / 1e6 / PEAK["hbm_GBps"], 4),
+            "TFLOPs": round(fl / ms / 1e9, 3), "frac_compute": round(fl / ms / 1e9 / peak_tf, 4),
+            "peak_TFLOPs": peak_tf}
 
 
 def time_applies(F, f, g, prec, steps, warmup, profile: bool):
@@ -117,6 +140,24 @@ def time_applies(F, f, g, prec, steps, warmup, profile: bool):
     return (t1 - t0), kt
 
 
+def time_graph(F, f, g, prec, steps, warmup):
+    """K replays of the apply captured in a hipGraph, between synchronizations."""
+    import torch
+
+    import paper_1908_09376_amd as M
+    G = M.ApplyGraph(F, f, out=g, precision=prec)
+    for _ in range(warmup):
+        G.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        G.launch()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    G.close()
+    return wall
+
+
 def cpu_baseline(w, f_np, rows):
     """The oracle's direct sum (eq. 1) on the sampled rows, timed on this host."""
     import numpy as np
@@ -135,10 +176,23 @@ def cpu_baseline(w, f_np, rows):
     t = float(np.median(times))
     full = t * w.N / len(rows)                 # seconds for all N rows and every RHS
     value = f_np.shape[1] / full
-    return gd, {"value": value, "unit": "applies/s", "cores": threads, "kind": "oracle",
+    # one thread (the paper's timings are single-threaded), on a quarter of the rows
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        r1 = rows[: max(1, len(rows) // 4)]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            direct_sum(K, f_np, rows=r1)
+            t1 = time.perf_counter() - t0
+        one = {"value": f_np.shape[1] / (t1 * w.N / len(r1)), "unit": "RHS-applies/s", "cores": 1,
+               "sample": f"the same on {len(r1)} rows, one BLAS thread ({t1:.2f} s), scaled by N/{len(r1)}"}
+    except Exception as e:  # threadpoolctl missing: report the multi-threaded figure only
+        log(f"[bench] single-thread baseline skipped: {e}")
+    return gd, {"value": value, "unit": "RHS-applies/s", "cores": threads, "kind": "oracle",
                 "sample": f"FP64 direct sum (eq. 1) on {len(rows)} seeded rows x {f_np.shape[1]} RHS "
                           f"(median of 3, {t:.2f} s each), scaled by N/{len(rows)}; BLAS threads={threads}, "
-                          f"host cpus={os.cpu_count()}"}
+                          f"host cpus={os.cpu_count()}", "one_thread": one}
 
 
 def batch_bench(args) -> int:
@@ -235,6 +289,8 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU apply beside the result")
+    ap.add_argument("--no-other-split", action="store_true",
+                    help="skip the other 16-bit split type beside a split result")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -266,6 +322,8 @@ def main() -> int:
     if args.precision == "auto":
         args.precision = "fp16x3" if (nrhs >= 16 and w.d == 2) else "fp32"
     keep = 1 | 2 | {"fp16x3": 8, "bf16x3": 4}.get(args.precision, 0)
+    if args.precision in ("fp16x3", "bf16x3") and not args.no_other_split:
+        keep |= 4 | 8
     log(f"[bench] building {w.name}: d={w.d} n={w.n} tol={w.tol} on {torch.cuda.get_device_name(0)}")
     recover = None
     if w.phase == "iso3d":
@@ -309,10 +367,15 @@ def main() -> int:
     cdt = torch.complex128 if args.precision == "fp64" else torch.complex64
     f = torch.from_numpy(np.ascontiguousarray(f_np.T)).to("cuda:0").to(cdt)
     g = torch.empty_like(f)
-    wall, kt = time_applies(F, f, g, args.precision, args.steps, args.warmup, profile=True)
+    # per-kernel times from eager applies (HIP events on the apply stream), then the timed
+    # steps as replays of the apply captured in a hipGraph
+    ewall, kt = time_applies(F, f, g, args.precision, args.steps, args.warmup, profile=True)
+    eager_ms = ewall / args.steps * 1e3
+    wall = time_graph(F, f, g, args.precision, args.steps, args.warmup)
     ms = wall / args.steps * 1e3
     value = nrhs * args.steps / wall
-    log(f"[bench] {args.precision}: {ms:.3f} ms/step, {value:.1f} RHS-applies/s")
+    log(f"[bench] {args.precision}: {ms:.3f} ms/step (graph replays; eager {eager_ms:.3f}), "
+        f"{value:.1f} RHS-applies/s")
     dominant = max(kt, key=lambda r: r["total_ms"])
     dom_variant = None
     if variants is not None:   # tuned variant of the dominant kernel's kind (up, down at the top step; middle)
@@ -320,7 +383,9 @@ def main() -> int:
         dom_variant = variants[kind]
     roof = roofline(dominant, args.precision, dom_variant, w.name)
     kernels = {r["name"]: {"launches": r["launches"], "avg_ms": round(r["total_ms"] / r["launches"], 4),
-                           "GB": round(r["bytes"] / r["launches"] / 1e9, 4)}
+                           "GB": round(r["bytes"] / r["launches"] / 1e9, 4),
+                           "stored_GB": round(r["stored_bytes"] / r["launches"] / 1e9, 4),
+                           "TFLOP": round(r["flops"] / r["launches"] / 1e12, 4)}
                for r in kt}
     g_np = g.to(torch.complex128).cpu().numpy().T
 
@@ -331,7 +396,8 @@ def main() -> int:
         v32 = F.tune(nrhs, "fp32") if nrhs >= 16 else None
         f32 = f.clone()
         g32 = torch.empty_like(f32)
-        wall32, kt32 = time_applies(F, f32, g32, "fp32", args.steps, args.warmup, profile=True)
+        _, kt32 = time_applies(F, f32, g32, "fp32", args.steps, args.warmup, profile=True)
+        wall32 = time_graph(F, f32, g32, "fp32", args.steps, args.warmup)
         dom32 = max(kt32, key=lambda r: r["total_ms"])
         dv32 = None
         if v32 is not None:
@@ -342,6 +408,25 @@ def main() -> int:
         del f32, g32
         log(f"[bench] fp32 beside: {fp32['ms_per_step']:.3f} ms/step, {fp32['value']:.1f} RHS-applies/s")
 
+    # the other split type beside the headline one (split-bf16 keeps FP32's range, split-fp16 is more accurate)
+    other = None
+    g_other_np = None
+    other_prec = {"fp16x3": "bf16x3", "bf16x3": "fp16x3"}.get(args.precision)
+    if other_prec is not None and not args.no_other_split:
+        vo = F.tune(nrhs, other_prec)
+        fo = f.clone()
+        go = torch.empty_like(fo)
+        _, kto = time_applies(F, fo, go, other_prec, args.steps, args.warmup, profile=True)
+        wallo = time_graph(F, fo, go, other_prec, args.steps, args.warmup)
+        domo = max(kto, key=lambda r: r["total_ms"])
+        other = {"precision": other_prec, "value": round(nrhs * args.steps / wallo, 2),
+                 "ms_per_step": round(wallo / args.steps * 1e3, 4), "tuned_variants": vo,
+                 "roofline": roofline(domo, other_prec, vo[2 if domo["name"].startswith("middle") else
+                                                           (0 if domo["name"].startswith("up") else 1)], w.name)}
+        g_other_np = go.to(torch.complex128).cpu().numpy().T
+        del fo, go
+        log(f"[bench] {other_prec} beside: {other['ms_per_step']:.3f} ms/step, {other['value']:.1f} RHS-applies/s")
+
     fp64 = None
     g64_np = None
     if not args.no_fp64 and args.precision != "fp64":
@@ -349,7 +434,7 @@ def main() -> int:
         g64 = torch.empty_like(f64)
         v64 = F.tune(nrhs, "fp64") if nrhs >= 16 else None
         steps64 = max(2, args.steps // 4)
-        wall64, _ = time_applies(F, f64, g64, "fp64", steps64, 1, profile=False)
+        wall64 = time_graph(F, f64, g64, "fp64", steps64, 1)
         fp64 = {"value": nrhs * steps64 / wall64, "ms_per_step": wall64 / steps64 * 1e3, "tuned_variants": v64}
         g64_np = g64.cpu().numpy().T
         del f64, g64
@@ -369,16 +454,20 @@ def main() -> int:
             fp64["rel_l2_err"] = float(np.linalg.norm((g64_np[rows] - gd).ravel()) / den)
         if fp32 is not None:
             fp32["rel_l2_err"] = float(np.linalg.norm((g32_np[rows] - gd).ravel()) / den)
+        if other is not None:
+            other["rel_l2_err"] = float(np.linalg.norm((g_other_np[rows] - gd).ravel()) / den)
         log(f"[bench] rel L2 error vs direct sum on {len(rows)} rows: {err:.3e} (max per RHS {per_rhs.max():.3e})")
 
     out = {
         "metric": METRIC,
         "value": round(value, 2),
-        "unit": "applies/s",
+        "unit": "RHS-applies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "timing": "hipGraph replays of the whole apply; eager launches beside it",
+        "eager_ms_per_step": round(eager_ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -395,9 +484,11 @@ def main() -> int:
         "ranks": [st["k_min"], st["k_max"]],
         "fp64_gpu": fp64,
         "fp32_gpu": fp32,
+        "other_split_gpu": other,
         "phase_recovery": recover,
         "kernels": kernels,
         "roofline": roof,
+        "step_roofline": step_roofline(kt, args.steps, ms, args.precision),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

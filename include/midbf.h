@@ -36,6 +36,7 @@ extern "C" {
 
 typedef struct midbf_plan* midbf_handle;
 typedef struct midbf_batch_s* midbf_batch;
+typedef struct midbf_graph_s* midbf_graph;
 
 typedef enum {
     MIDBF_OK = 0,
@@ -65,8 +66,12 @@ typedef enum {
     MIDBF_FP32 = 1,          /* FP32 factors, FP32 accumulation                          */
     MIDBF_SPLIT_BF16 = 2,    /* factors and inputs split into bf16 hi + lo, three bf16
                                 products per real product, FP32 accumulation (MFMA)      */
-    MIDBF_SPLIT_FP16 = 3     /* the same with fp16 hi + lo: ~2^-22 per split value; vector
-                                and factor entries must stay below 65504 in magnitude    */
+    MIDBF_SPLIT_FP16 = 3     /* the same with fp16 hi + lo: ~2^-22 per split value.  fp16
+                                holds |x| < 65504: the library keeps every vector it splits
+                                scaled by a power of two per right-hand side (exact), taken
+                                from max |f| of that column and the points behind each entry,
+                                so any finite input works; the build refuses an fp16 copy
+                                whose factor entries reach 2^15 (midbf_stats.t_abs_max)    */
 } midbf_precision;
 
 /* Bits of midbf_params.precisions: which factor copies the build keeps.  A
@@ -104,6 +109,8 @@ typedef struct {
     int k_min, k_max;           /* ranks over all IDs                                  */
     double build_seconds;       /* wall time of midbf_build                            */
     long long bytes_fp16;       /* bytes of the split-fp16 factor copy                 */
+    double t_abs_max;           /* largest |Re| or |Im| of an interpolation coefficient
+                                   (entry of T) in the 16-bit copies; 0 without them   */
 } midbf_stats;
 
 /*
@@ -157,6 +164,25 @@ midbf_status midbf_apply(midbf_handle h, const void* f_dev, void* g_dev, int nrh
  */
 midbf_status midbf_apply_noalloc(midbf_handle h, const void* f_dev, void* g_dev, int nrhs, long long ld,
                                  midbf_precision prec, void* stream);
+
+/*
+ * midbf_apply_graph_create -- capture the launch sequence of
+ * midbf_apply(h, f_dev, g_dev, nrhs, ld, prec) into a hipGraph (the many-RHS
+ * apply of Sec. 3.5's factor product, replayed without host launch overhead).
+ * The handle's workspace for nrhs right-hand sides is allocated before the
+ * capture, and the tile variants in effect now (midbf_tune,
+ * midbf_set_variants) are fixed into the graph.  The graph refers to f_dev,
+ * g_dev and the handle's factors and workspace: they must outlive it, and a
+ * replay must not overlap another apply of the same handle and precision.
+ * Synchronizes `stream`.  Errors: as midbf_apply; MIDBF_ERR_HIP if capture
+ * or instantiation fails.
+ * midbf_graph_launch enqueues one replay on `stream` (asynchronous);
+ * midbf_graph_destroy releases the graph (not the buffers).
+ */
+midbf_status midbf_apply_graph_create(midbf_handle h, const void* f_dev, void* g_dev, int nrhs, long long ld,
+                                      midbf_precision prec, void* stream, midbf_graph* out);
+midbf_status midbf_graph_launch(midbf_graph g, void* stream);
+void midbf_graph_destroy(midbf_graph g);
 
 /*
  * midbf_apply_adjoint -- f = K~^H g: conjugate-transposed factors in reverse
@@ -315,6 +341,8 @@ typedef struct {
     double total_ms;
     double bytes;
     double flops;
+    double stored_bytes;   /* the same traffic as laid out: tile padding and the identity
+                              entries of dense blocks included (>= bytes) */
 } midbf_kernel_time;
 
 midbf_status midbf_profile_enable(midbf_handle h, int on);

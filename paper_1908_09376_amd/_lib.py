@@ -32,12 +32,13 @@ class Stats(C.Structure):
     _fields_ = [("L", C.c_int), ("b", C.c_int), ("hstar", C.c_int), ("ids", C.c_longlong),
                 ("entries", C.c_longlong), ("bytes_fp64", C.c_longlong), ("bytes_fp32", C.c_longlong),
                 ("bytes_bf16", C.c_longlong), ("index_bytes", C.c_longlong), ("k_min", C.c_int),
-                ("k_max", C.c_int), ("build_seconds", C.c_double), ("bytes_fp16", C.c_longlong)]
+                ("k_max", C.c_int), ("build_seconds", C.c_double), ("bytes_fp16", C.c_longlong),
+                ("t_abs_max", C.c_double)]
 
 
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_longlong), ("total_ms", C.c_double),
-                ("bytes", C.c_double), ("flops", C.c_double)]
+                ("bytes", C.c_double), ("flops", C.c_double), ("stored_bytes", C.c_double)]
 
 
 class BatchStats(C.Structure):
@@ -74,6 +75,9 @@ def _load():
         "midbf_apply": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_adjoint": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_noalloc": (i, [vp, vp, vp, i, ll, i, vp]),
+        "midbf_apply_graph_create": (i, [vp, vp, vp, i, ll, i, vp, C.POINTER(vp)]),
+        "midbf_graph_launch": (i, [vp, vp]),
+        "midbf_graph_destroy": (None, [vp]),
         "midbf_apply_batched": (i, [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(i), i, vp]),
         "midbf_batch_create": (i, [i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(i), i, i, vp,
                                    C.POINTER(vp)]),
@@ -109,6 +113,7 @@ def check(status: int) -> None:
 
 
 EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_noalloc", "midbf_apply_batched",
+            "midbf_apply_graph_create", "midbf_graph_launch", "midbf_graph_destroy",
             "midbf_batch_create", "midbf_batch_run", "midbf_batch_get_stats",
             "midbf_batch_destroy",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",

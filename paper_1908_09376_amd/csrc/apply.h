@@ -30,6 +30,45 @@ __device__ inline void child_pieces(int (&len)[MAX_P], long long (&off)[MAX_P], 
     }
 }
 
+// Range guard of the split 16-bit applies.  fp16 holds |x| < 65504 ~ 2^16
+// and keeps a lo part's full precision only for |x| >~ 2^-3 (its normal range
+// starts at 2^-14), so the vectors an apply splits are held in HBM scaled by
+// powers of two, which is exact in both directions:
+//   - every vector v of the apply's chain (the input copy, the up levels' y,
+//     the middle's and down levels' z) stores v * 2^(h_v - cexp[r]) for
+//     right-hand side r, where cexp[r] is the binary exponent of max |f(:, r)|
+//     (max = m 2^cexp, 1/2 <= m < 1), taken from the input once per apply;
+//   - entries of v are (interpolated) sums over the p_v lattice points of the
+//     column node they belong to of unit-modulus kernel entries times f, so
+//     |v| <= p_v max |f(:, r)| up to the decompositions' interpolation growth
+//     (the l1 norms of the up side's composed rows measure below 0.2 p_v),
+//     and h_v <= SPLIT16_HEADROOM - ceil(log2 p_v) keeps the scaled entries
+//     below 2^SPLIT16_HEADROOM, a factor 8 under 65504, while typical entries
+//     (~ sqrt(p_v) max|f| / 5) stay well above 2^-3;
+//   - a kernel whose output copies input rows (up: y = y_skel + T y_red; down:
+//     skeleton rows, sibling sums) keeps its input's scale, so consecutive
+//     vectors joined by such kernels share one h (the smallest bound among
+//     them); the middle kernels (pure products, also the dense down blocks)
+//     change it by a uniform power of two applied while staging
+//     (MidArgs::bscale);
+//   - only the copies at the ends touch per-column scales: the input copy
+//     (TransposeIn or the leaf copy) multiplies by 2^(h - cexp[r]), the output
+//     transpose by 2^(cexp[r] - h).
+// cexp == null: no scaling.
+struct SplitScale {
+    const int* cexp;
+    int hs;
+};
+constexpr int SPLIT16_HEADROOM = 13;
+
+// 2^(hs - cexp[r]) (dir = +1) or its inverse (dir = -1); the exponent is
+// clamped to +-100, so both are normal FP32 values.  1 without scaling.
+__device__ inline float split_scale_of(const SplitScale& sc, int r, int dir) {
+    if (!sc.cexp) return 1.f;
+    const int e = max(-100, min(100, dir * (sc.hs - sc.cexp[r])));
+    return __int_as_float((e + 127) << 23);
+}
+
 // Tables of one level (one step, one side) as seen by a kernel.
 struct LevelArgs {
     const int* k;
@@ -57,6 +96,7 @@ struct UpArgs {
     int nred_max;            // bound on the redundant inputs n - k of the level's decompositions
     int lattice_in;          // 1: `in` is the row-major input copy and lev.src holds lattice points
                              // (only the source-row-table kernels accept it)
+    SplitScale sc;           // split 16-bit leaf copy: scale of the copied input (SplitScale)
 };
 
 struct DownArgs {
@@ -92,6 +132,7 @@ struct MidArgs {
     int chunk;               // VALU path: input entries staged in LDS per pass
     int mchunks;             // matrix-core FP32 path: workgroups splitting the rows of one block
     const int* ang;          // split 16-bit: the blocks' phase tiles (see mfma.h), or null
+    float bscale;            // split 16-bit: power of two applied to the input while staging (SplitScale)
 };
 
 // Input and output row numbers of middle block bi (the concatenations of its
@@ -123,7 +164,19 @@ __device__ inline void middle_rows(int* crow_in, int* crow_out, const MidArgs& A
 }
 
 enum class LevelKernel { Up, Down, Middle, AdjUp, AdjMiddle, AdjDown, DownSum, Transpose, DownGroup, DownDense,
-                         UpLeafCopy, DownLeaf, TransposeIn };
+                         UpLeafCopy, DownLeaf, TransposeIn, ColExp };
+
+// The per right-hand side exponents of SplitScale: blocks (b, r) write the
+// largest |re| or |im| of slice b of column r of the external complex64 block
+// to part[r * S + b]; then one block reduces each column's S slice maxima and
+// writes cexp[r] (0 for a zero or non-finite column).
+struct ColExpArgs {
+    const void* src;
+    long long ld, N;
+    int nrhs, S;
+    float* part;
+    int* cexp;
+};
 
 // Block transpose between a row-major N x nrhs copy (element (p, r) at
 // [p * nrhs + r]) and the external column-major layout (element (p, r) at
@@ -135,6 +188,7 @@ struct TransposeArgs {
     long long ld;
     long long N;
     int nrhs;
+    SplitScale sc;           // complex64: TransposeIn multiplies by 2^(hs - cexp[r]), Transpose by 2^(cexp[r] - hs)
 };
 
 void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,

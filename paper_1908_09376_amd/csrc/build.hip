@@ -3,6 +3,7 @@
 // the middle blocks.
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <cmath>
 #include <vector>
 
@@ -386,7 +387,7 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
                     char* cb = (char*)dalloc<char>((size_t)std::max<long long>(tt, 1) * BF16_TILE_BYTES);
                     lv.chunks.push_back(cb);
                     pack_bf16_slab(q == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, sc.X, sc.xs, sc.k, lv.d_n + id0, cnt,
-                                   lv.side == SIDE_ROW, cb, sc.tile_off, st);
+                                   lv.side == SIDE_ROW, cb, sc.tile_off, h->d_tmax, st);
                     for (int w = 0; w < cnt; ++w) pbf[w] = cb + tile_off[w] * BF16_TILE_BYTES;
                     upload((void**)lv.d_T[q] + id0, pbf, st);
                     MIDBF_HIP(hipStreamSynchronize(st));      // pbf is reused by the next copy
@@ -598,11 +599,13 @@ void destroy_plan(midbf_plan* h) {
     f(M.d_tile_off);
     f(M.ang);
     for (int q = 0; q < NPREC; ++q) f(M.S[q]);
+    f(h->d_tmax);
     for (int q = 0; q < NPREC; ++q) {
         f(h->ws[q].buf[0]);
         f(h->ws[q].buf[1]);
         f(h->ws[q].scratch);
         f(h->ws[q].lat);
+        f(h->ws[q].aux);
     }
     delete h;
 }
@@ -640,6 +643,10 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         h->ph = PhaseDesc{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r};
         h->rows.resize(h->b);
         h->cols.resize(h->b);
+        if (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) {
+            h->d_tmax = dalloc<unsigned>(1);
+            MIDBF_HIP(hipMemsetAsync(h->d_tmax, 0, sizeof(unsigned), st));
+        }
         long long khat[2] = {h->n0, h->n0};
         for (int s = 0; s < h->b; ++s) {
             for (int side = 0; side < 2; ++side) {
@@ -702,6 +709,18 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         S.bytes_bf16 = (h->keep & MIDBF_KEEP_BF16) ? bfb : 0;
         S.bytes_fp16 = (h->keep & MIDBF_KEEP_FP16) ? bfb : 0;
         S.index_bytes = idx;
+        if (h->d_tmax) {
+            unsigned bits = 0;
+            MIDBF_HIP(hipMemcpyAsync(&bits, h->d_tmax, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+            MIDBF_HIP(hipStreamSynchronize(st));
+            float t;
+            std::memcpy(&t, &bits, sizeof t);
+            S.t_abs_max = t;
+            // fp16 holds |x| < 65504; the factor tiles are not rescaled, so their
+            // entries must fit as they are (with a margin for the lo parts)
+            MIDBF_CHECK(!(h->keep & MIDBF_KEEP_FP16) || t < 32768.f, MIDBF_ERR_UNIMPLEMENTED,
+                        "interpolation coefficients beyond the fp16 range: keep the split-bf16 copy instead");
+        }
         S.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     } catch (...) {
         destroy_plan(h);

@@ -76,6 +76,7 @@ const char* kernel_name(LevelKernel k) {
         case LevelKernel::UpLeafCopy: return "up_copy";
         case LevelKernel::DownLeaf: return "down_leaf";
         case LevelKernel::TransposeIn: return "transpose";
+        case LevelKernel::ColExp: return "col_exp";
     }
     return "?";
 }
@@ -96,7 +97,7 @@ hipEvent_t take_event(Profiler& P) {
 // selects the matrix-core kernel with that many workgroups in x.
 void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int prec, int rt, const void* args,
                     dim3 grid, size_t smem, hipStream_t st, double bytes, double flops, long long mfma_count = 0,
-                    int nrhs = 0, int level = -1, bool profile = true) {
+                    int nrhs = 0, int level = -1, bool profile = true, double stored = -1.0) {
     MIDBF_CHECK(mfma_count > 0 || smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
                 "candidate vectors of this factorization exceed the apply kernels' LDS budget");
     auto go = [&] {
@@ -106,6 +107,10 @@ void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int p
         }
         if (which == LevelKernel::TransposeIn) {
             launch_transpose_in(*(const TransposeArgs*)args, st);
+            return;
+        }
+        if (which == LevelKernel::ColExp) {
+            launch_col_exponents(*(const ColExpArgs*)args, st);
             return;
         }
         if (which == LevelKernel::UpLeafCopy) {
@@ -140,10 +145,10 @@ void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int p
                         : prec == PREC_BF16 ? "_bf16x3"
                         : prec == PREC_FP16 ? "_fp16x3"
                                             : "_fp32";
-    if (which == LevelKernel::Transpose || which == LevelKernel::TransposeIn) {
+    if (which == LevelKernel::Transpose || which == LevelKernel::TransposeIn || which == LevelKernel::ColExp) {
         r.name = std::string(kernel_name(which)) + pname;
         if (which == LevelKernel::TransposeIn) r.name += "_in";
-        else if (P.by_level) r.name += "_out";
+        else if (which == LevelKernel::Transpose && P.by_level) r.name += "_out";
     } else {
         r.name = std::string(kernel_name(which)) + (mfma_count > 0 && !is_split16(prec) ? "_mfma" : "") + pname +
                  (mfma_count > 0 ? "" : "_rt" + std::to_string(rt));
@@ -152,6 +157,7 @@ void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int p
     r.a = take_event(P);
     r.b = take_event(P);
     r.bytes = bytes;
+    r.stored = stored < 0.0 ? bytes : stored;
     r.flops = flops;
     MIDBF_HIP(hipEventRecord(r.a, st));
     go();
@@ -163,7 +169,7 @@ void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int p
 // two level-vector buffers (each), the matrix-core down pass's contribution
 // block and the N x nrhs lattice-order copy.
 struct WorkspaceNeed {
-    size_t buf, scratch, lat;
+    size_t buf, scratch, lat, aux;
 };
 
 WorkspaceNeed workspace_need(const midbf_plan* h, int prec, int nrhs, bool scratch, bool lat) {
@@ -171,6 +177,8 @@ WorkspaceNeed workspace_need(const midbf_plan* h, int prec, int nrhs, bool scrat
     w.buf = (size_t)std::max<long long>(h->max_total_k, 1) * nrhs * csize(prec);
     w.scratch = scratch ? (size_t)std::max<long long>(h->max_total_n, 1) * nrhs * csize(prec) : 0;
     w.lat = lat ? (size_t)h->N * nrhs * csize(prec) : 0;
+    // split 16-bit: slice maxima and exponents of the range guard (SplitScale)
+    w.aux = is_split16(prec) ? (size_t)nrhs * (col_exp_slices(h->N) + 1) * 4 : 0;
     return w;
 }
 
@@ -200,6 +208,13 @@ void ensure_workspace(midbf_plan* h, int prec, int nrhs, bool scratch, bool lat)
         MIDBF_HIP(hipMalloc(&w.lat, need.lat));
         w.lat_bytes = need.lat;
     }
+    if (need.aux && w.aux_bytes < need.aux) {
+        if (w.aux) MIDBF_HIP(hipFree(w.aux));
+        w.aux = nullptr;
+        w.aux_bytes = 0;
+        MIDBF_HIP(hipMalloc(&w.aux, need.aux));
+        w.aux_bytes = need.aux;
+    }
 }
 
 // One level launch of an apply: which kernel, its argument block, shape and
@@ -211,10 +226,12 @@ struct LaunchDesc {
         MidArgs mid;
         DownArgs down;
         TransposeArgs tr;
+        ColExpArgs ce;
     } a;
     dim3 grid;
     size_t smem;
     double bytes, flops;
+    double stored;          // bytes as laid out (padded tiles, identity entries), if above `bytes`; else 0
     long long mfma_count;   // > 0: matrix-core kernel with that many workgroups
     int level;
 };
@@ -231,7 +248,7 @@ struct LaunchDesc {
 // in front of them.)
 std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
                                    bool adjoint, bool mfma, void* const* buf, bool chunk_middle, int rt,
-                                   void* lat = nullptr) {
+                                   void* lat = nullptr, void* aux = nullptr) {
     const double fl = is_split16(prec) ? 24.0 : 8.0;   // flops per complex entry and RHS (split-16: three products)
     const int tiles = (nrhs + rt - 1) / rt;
     const size_t cs = csize(prec);
@@ -248,12 +265,39 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
     const int v_up1 = (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[0][1];
     const bool lat_in = is_split16(prec) && mfma && lat && !adjoint && h->b >= 2 && up[0].entries == 0 &&
                         up[1].d_src_lat != nullptr && v_up1 >= 7 && v_up1 <= 9;
+    // Split 16-bit: the exponents of the input's column maxima first; the
+    // vectors of the chain are then held scaled (SplitScale).
+    int* cexp = nullptr;
+    if (is_split16(prec) && aux) {
+        const int S = col_exp_slices(h->N);
+        float* part = (float*)aux;
+        cexp = (int*)(part + (size_t)nrhs * S);
+        LaunchDesc D{};
+        D.a.ce = ColExpArgs{in_ext, ld, h->N, nrhs, S, part, cexp};
+        D.which = LevelKernel::ColExp;
+        D.bytes = (double)h->N * nrhs * cs;
+        D.level = 0;
+        out.push_back(D);
+    }
+    // The scale exponents of the chain's vectors: hU for the input copy and
+    // every up level, hD for every down level and the output.  Both sides
+    // copy rows between levels, so each side keeps one scale, set by its
+    // vectors with the most points behind an entry (the top up step's y, the
+    // leaves' z); the middle moves from one to the other while staging.
+    auto hbound = [&](long long pts) {
+        int lg = 0;
+        while ((1LL << lg) < pts) ++lg;
+        return SPLIT16_HEADROOM - lg;
+    };
+    const int hU = hbound(h->N / ipow(h->P, h->L - h->b + 1)), hD = hbound(h->N / h->P);
+    const SplitScale sc_in{cexp, hU}, sc_out{cexp, hD};
+    auto pow2 = [](int e) { return std::ldexp(1.0f, e); };
     int o = 0;   // buffer holding the current level's vectors
     for (int s = 0; s < h->b; ++s) {
         const LevelSide& lv = up[s];
         LaunchDesc D{};
         if (lat_in && s == 0) {
-            D.a.tr = TransposeArgs{in_ext, lat, ld, h->N, nrhs};
+            D.a.tr = TransposeArgs{in_ext, lat, ld, h->N, nrhs, sc_in};
             D.which = LevelKernel::TransposeIn;
             D.bytes = 2.0 * h->N * nrhs * cs;
             D.level = 0;
@@ -273,6 +317,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.yoff_prev = s ? up[s - 1].d_y_off : nullptr;
         a.out = buf[o];
         a.nrhs = nrhs;
+        a.sc = sc_in;
         if (lat_in && s == 1) {
             a.in = lat;
             a.lev.src = lv.d_src_lat;
@@ -298,6 +343,18 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
             D.which = LevelKernel::UpLeafCopy;
             D.mfma_count = groups;
             D.flops = 0;
+        } else if (s == 0 && cexp) {
+            // split 16-bit leaves with a product: the scaled row-major copy of the
+            // input first, which the leaf kernels then read in place of the input
+            MIDBF_CHECK(lat != nullptr, MIDBF_ERR_ARG, "split 16-bit applies need the lattice copy");
+            LaunchDesc T{};
+            T.a.tr = TransposeArgs{in_ext, lat, ld, h->N, nrhs, sc_in};
+            T.which = LevelKernel::TransposeIn;
+            T.bytes = 2.0 * h->N * nrhs * cs;
+            T.level = 0;
+            out.push_back(T);
+            a.ext = nullptr;
+            a.in = lat;
         }
         out.push_back(D);
         o ^= 1;
@@ -320,6 +377,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.in_max = M.nc_max;
         a.out_max = M.nr_max;
         a.ang = (is_split16(prec) && !adjoint) ? (const int*)M.ang : nullptr;
+        a.bscale = cexp ? pow2(hD - hU) : 1.f;
         // FP32 matrix cores: split the rows of few large blocks over several workgroups
         a.mchunks = (mfma && prec == PREC_FP32)
                         ? (int)std::max<long long>(1, std::min<long long>((2048 + M.nblk - 1) / std::max<long long>(M.nblk, 1),
@@ -342,9 +400,11 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
             D.which = adjoint ? LevelKernel::AdjMiddle : LevelKernel::Middle;
             D.grid = dim3((unsigned)cnt, tiles);
             D.smem = (size_t)std::min(width, ab.chunk) * rt * cs;
-            // (split applies with phase tiles read 4 B per entry, padding included)
-            const double fac_bytes = ab.ang ? (double)M.ang_bytes : (double)M.total * cs;
+            // split applies read the blocks' phase tiles: 4 B per entry (the
+            // padding of partial tiles is counted as stored bytes only)
+            const double fac_bytes = ab.ang ? 4.0 * M.total : (double)M.total * cs;
             D.bytes = frac * (fac_bytes + (double)M.nblk * 40 + vec);
+            if (ab.ang) D.stored = frac * ((double)M.ang_bytes + (double)M.nblk * 40 + vec);
             D.flops = frac * fl * M.total * nrhs;
             D.mfma_count = mfma ? cnt : 0;
             D.level = -1;
@@ -392,11 +452,15 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
             m.in_max = lv.g_nc_max;
             m.out_max = lv.g_nr_max;
             m.mchunks = 1;
+            m.bscale = 1.f;          // z keeps its scale going down
             D.a.mid = m;
             D.which = LevelKernel::DownDense;
             D.grid = dim3();
             D.smem = 0;
-            D.bytes = (double)lv.g_tiles * BF16_TILE_BYTES + (double)lv.groups * 48 + vin + vout;
+            // algorithmic: the T entries (8 B as hi / lo pairs); the group tiles
+            // also hold the skeleton rows' identity entries and tile padding
+            D.bytes = (double)lv.entries * cs + (double)lv.groups * 48 + vin + vout;
+            D.stored = (double)lv.g_tiles * BF16_TILE_BYTES + (double)lv.groups * 48 + vin + vout;
             D.flops = fl * lv.g_entries * nrhs;
             D.mfma_count = lv.groups;
             out.push_back(D);
@@ -446,7 +510,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
     }
     if (lat) {
         LaunchDesc D{};
-        D.a.tr = TransposeArgs{lat, out_ext, ld, h->N, nrhs};
+        D.a.tr = TransposeArgs{lat, out_ext, ld, h->N, nrhs, sc_out};
         D.which = LevelKernel::Transpose;
         D.bytes = 2.0 * h->N * nrhs * cs;
         D.level = 1;
@@ -479,7 +543,7 @@ ApplyMode apply_mode(const midbf_plan* h, int nrhs, int prec, bool adjoint) {
     ApplyMode m;
     m.mfma = is_split16(prec) ||
              ((prec == PREC_FP32 || prec == PREC_FP64) && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
-    m.lat = m.mfma && nrhs > 1;
+    m.lat = m.mfma && (nrhs > 1 || is_split16(prec));
     m.rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     return m;
 }
@@ -495,7 +559,7 @@ bool needs_scratch(const std::vector<LaunchDesc>& launches) {
 std::vector<LaunchDesc> plan_for(midbf_plan* h, const Workspace& ws, const ApplyMode& m, const void* in_ext,
                                  void* out_ext, int nrhs, long long ld, int prec, bool adjoint) {
     return plan_apply(h, in_ext, out_ext, nrhs, ld, prec, adjoint, m.mfma, ws.buf, true, m.rt,
-                      m.lat ? ws.lat : nullptr);
+                      m.lat ? ws.lat : nullptr, ws.aux);
 }
 
 // Launch a planned apply; the contribution block is read from ws at launch.
@@ -504,7 +568,7 @@ void launch_planned(midbf_plan* h, const Workspace& ws, const ApplyMode& m, cons
                     int nrhs, int prec, hipStream_t st, bool profile) {
     for (const LaunchDesc& D : launches)
         launch_checked(h, ws, D.which, prec, m.rt, &D.a, D.grid, D.smem, st, D.bytes, D.flops, D.mfma_count, nrhs,
-                       D.level, profile);
+                       D.level, profile, D.stored > 0.0 ? D.stored : -1.0);
 }
 
 void run_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
@@ -546,7 +610,8 @@ void run_apply_noalloc(midbf_plan* h, const void* in_ext, void* out_ext, int nrh
     const ApplyMode m = apply_mode(h, nrhs, prec, false);
     const WorkspaceNeed need = workspace_need(h, prec, nrhs, true, m.lat);
     auto round_up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t b = round_up(need.buf), la = round_up(need.lat), sc = round_up(need.scratch);
+    const size_t b = round_up(need.buf), la = round_up(need.lat), ax = round_up(need.aux),
+                 sc = round_up(need.scratch);
     unsigned char* base = (unsigned char*)noalloc_scratch();
     Workspace ws;
     ws.buf[0] = base;
@@ -554,13 +619,15 @@ void run_apply_noalloc(midbf_plan* h, const void* in_ext, void* out_ext, int nrh
     ws.bytes = need.buf;
     ws.lat = m.lat ? base + 2 * b : nullptr;
     ws.lat_bytes = need.lat;
+    ws.aux = need.aux ? base + 2 * b + la : nullptr;
+    ws.aux_bytes = need.aux;
     const auto launches = plan_for(h, ws, m, in_ext, out_ext, nrhs, ld, prec, false);
     const bool scr = needs_scratch(launches);
     if (scr) {
-        ws.scratch = base + 2 * b + la;
+        ws.scratch = base + 2 * b + la + ax;
         ws.scratch_bytes = need.scratch;
     }
-    const size_t total = 2 * b + la + (scr ? sc : 0);
+    const size_t total = 2 * b + la + ax + (scr ? sc : 0);
     MIDBF_CHECK(total <= (size_t)MIDBF_NOALLOC_SCRATCH_BYTES, MIDBF_ERR_SHAPE,
                 "this apply needs " + std::to_string(total) + " bytes of workspace; the no-allocation scratch holds " +
                     std::to_string((size_t)MIDBF_NOALLOC_SCRATCH_BYTES) +
@@ -570,6 +637,55 @@ void run_apply_noalloc(midbf_plan* h, const void* in_ext, void* out_ext, int nrh
 
 }  // namespace
 
+}  // namespace midbf
+
+// One apply's launch sequence captured in a hipGraph (midbf_apply_graph_*).
+struct midbf_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace midbf {
+namespace {
+
+void free_graph(midbf_graph_s* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+// Capture the launches of midbf_apply(h, in, out, ...) on a private stream.
+// The handle's workspace for nrhs is reserved (allocated) before the capture,
+// so the graph holds no allocation; profiling events are not captured.
+midbf_graph_s* capture_apply(midbf_plan* h, const void* in_ext, void* out_ext, int nrhs, long long ld, int prec,
+                             hipStream_t st) {
+    check_apply_args(h, in_ext, out_ext, nrhs, ld, prec);
+    const ApplyMode m = apply_mode(h, nrhs, prec, false);
+    ensure_workspace(h, prec, nrhs, false, m.lat);
+    const auto launches = plan_for(h, h->ws[prec], m, in_ext, out_ext, nrhs, ld, prec, false);
+    if (needs_scratch(launches)) ensure_workspace(h, prec, nrhs, true, m.lat);
+    MIDBF_HIP(hipStreamSynchronize(st));
+    std::unique_ptr<midbf_graph_s, void (*)(midbf_graph_s*)> g(new midbf_graph_s, free_graph);
+    hipStream_t cap;
+    MIDBF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    try {
+        MIDBF_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        launch_planned(h, h->ws[prec], m, launches, nrhs, prec, cap, false);
+        MIDBF_HIP(hipStreamEndCapture(cap, &g->graph));
+        MIDBF_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    } catch (...) {
+        hipGraph_t dangling = nullptr;
+        (void)hipStreamEndCapture(cap, &dangling);
+        if (dangling) (void)hipGraphDestroy(dangling);
+        (void)hipStreamDestroy(cap);
+        throw;
+    }
+    MIDBF_HIP(hipStreamDestroy(cap));
+    return g.release();
+}
+
+}  // namespace
 }  // namespace midbf
 
 // A batch of forward transforms (midbf_batch_*): the stage table on the
@@ -713,6 +829,21 @@ midbf_status midbf_apply_noalloc(midbf_handle h, const void* f, void* g, int nrh
     if (!h) return fail(MIDBF_ERR_ARG, "null handle");
     return guarded([&] { run_apply_noalloc(h, f, g, nrhs, ld, prec_index(prec), (hipStream_t)stream); });
 }
+
+midbf_status midbf_apply_graph_create(midbf_handle h, const void* f, void* g, int nrhs, long long ld,
+                                      midbf_precision prec, void* stream, midbf_graph* out) {
+    if (!out) return fail(MIDBF_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (!h) return fail(MIDBF_ERR_ARG, "null handle");
+    return guarded([&] { *out = capture_apply(h, f, g, nrhs, ld, prec_index(prec), (hipStream_t)stream); });
+}
+
+midbf_status midbf_graph_launch(midbf_graph g, void* stream) {
+    if (!g) return fail(MIDBF_ERR_ARG, "null graph");
+    return guarded([&] { MIDBF_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream)); });
+}
+
+void midbf_graph_destroy(midbf_graph g) { free_graph(g); }
 
 midbf_status midbf_apply_adjoint(midbf_handle h, const void* g, void* f, int nrhs, long long ld,
                                  midbf_precision prec, void* stream) {
@@ -924,6 +1055,7 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
             it->launches += 1;
             it->total_ms += ms;
             it->bytes += r.bytes;
+            it->stored_bytes += r.stored;
             it->flops += r.flops;
             P.pool.push_back(r.a);
             P.pool.push_back(r.b);

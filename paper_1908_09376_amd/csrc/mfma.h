@@ -1,6 +1,8 @@
 // Matrix-core (MFMA) level kernels for many right-hand sides.
 #pragma once
 
+#include <algorithm>
+
 #include "apply.h"
 
 namespace midbf {
@@ -25,6 +27,10 @@ void launch_mfma_kernel(LevelKernel which, int variant, const void* args, long l
 void launch_transpose(const TransposeArgs& A, bool fp64, hipStream_t s);
 // The external column-major complex64 block -> the row-major copy (A.src external, A.dst the copy).
 void launch_transpose_in(const TransposeArgs& A, hipStream_t s);
+// SplitScale exponents of the input block (two launches, see ColExpArgs).
+void launch_col_exponents(const ColExpArgs& A, hipStream_t s);
+// Slices per column of the exponent pass (ColExpArgs::S; part holds nrhs * S floats).
+inline int col_exp_slices(long long N) { return (int)std::min<long long>(64, (N + 4095) / 4096); }
 // The first up step when every leaf decomposition keeps all its points (no T):
 // per leaf, the caller's block is staged once and copied to the P partners'
 // skeleton rows.  groups = leaves; complex64.
@@ -47,8 +53,10 @@ long long bf16_tiles(int M, int K);
 constexpr long long BF16_TILE_BYTES = 4096;
 // Pack T of each decomposition of a build wave (FP64 slab) into tiles: the
 // column side stores A = T (k x (n-k)), the row side (transposed = true) A = T^T.
+// tmax (or null): atomic max of the entries' |re| and |im| as FP32 bits (the
+// range of the 16-bit copies; |x| of a non-negative float orders like its bits).
 void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k_w, const int* n_w, int count,
-                    bool transposed, void* out, const long long* tile_off, hipStream_t s);
+                    bool transposed, void* out, const long long* tile_off, unsigned* tmax, hipStream_t s);
 // Pack the dense candidate-order block of every group of P sibling row
 // decompositions (one step, going down) from the siblings' own tiles; per group
 // nr = n rows, nc = sum of k columns, first tile at tile_off.

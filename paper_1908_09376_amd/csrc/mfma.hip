@@ -20,6 +20,8 @@
 //          a scratch block, then the 2^d contributions of a group are summed in
 //          a fixed order (no atomics, bitwise reproducible).
 //   middle: C = z rows, A = S (column-major), B = y rows.
+#include <type_traits>
+
 #include "apply.h"
 #include "mfma.h"
 
@@ -547,6 +549,9 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
     C2* dst = (C2*)A.dst;
     // loads at in-range addresses (clamped row and column), so that a thread's
     // sixteen loads issue together; only the stores are guarded
+    // split 16-bit applies: the copy of the input is scaled, the output
+    // unscaled, per right-hand side (SplitScale; complex64 only)
+    constexpr bool SC = std::is_same_v<C2, float2>;
     if constexpr (TO_EXT) {
 #pragma unroll
         for (int pp = ty; pp < 64; pp += 4) {
@@ -558,7 +563,14 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
         for (int rr = ty; rr < 64; rr += 4) {
             const long long p = p0 + tx;
             const int r = r0 + rr;
-            if (p < A.N && r < A.nrhs) dst[(long long)r * A.ld + p] = t[tx][rr];
+            if (p < A.N && r < A.nrhs) {
+                C2 v = t[tx][rr];
+                if constexpr (SC) {
+                    const float f = split_scale_of(A.sc, r, -1);
+                    v = make_float2(v.x * f, v.y * f);
+                }
+                dst[(long long)r * A.ld + p] = v;
+            }
         }
     } else {
 #pragma unroll
@@ -568,10 +580,16 @@ __global__ __launch_bounds__(256) void transpose_kernel(TransposeArgs A) {
             t[tx][rr] = src[(long long)r * A.ld + p];
         }
         __syncthreads();
+        float f = 1.f;
+        if constexpr (SC) f = split_scale_of(A.sc, min(r0 + tx, A.nrhs - 1), 1);
         for (int pp = ty; pp < 64; pp += 4) {
             const long long p = p0 + pp;
             const int r = r0 + tx;
-            if (p < A.N && r < A.nrhs) dst[p * A.nrhs + r] = t[pp][tx];
+            if (p < A.N && r < A.nrhs) {
+                C2 v = t[pp][tx];
+                if constexpr (SC) v = make_float2(v.x * f, v.y * f);
+                dst[p * A.nrhs + r] = v;
+            }
         }
     }
 }
@@ -591,7 +609,13 @@ __global__ __launch_bounds__(256) void up_leaf_copy(UpArgs A) {
     const float2* x = (const float2*)A.ext;
     for (int e = threadIdx.x; e < n0 * NRHS; e += 256) {
         const int r = e / n0, c = e - r * n0;
-        xs[c * (NRHS + 1) + r] = r < nr ? x[(long long)(r0 + r) * A.ld + crow[c]] : make_float2(0.f, 0.f);
+        float2 v = make_float2(0.f, 0.f);
+        if (r < nr) {
+            v = x[(long long)(r0 + r) * A.ld + crow[c]];
+            const float f = split_scale_of(A.sc, r0 + r, 1);      // split 16-bit: the scaled input copy
+            v = make_float2(v.x * f, v.y * f);
+        }
+        xs[c * (NRHS + 1) + r] = v;
     }
     __syncthreads();
     float2* out = (float2*)A.out;

@@ -72,17 +72,19 @@ template <class E> __device__ inline Frag<E> lds_frag(const LFrag<E>* t, int lan
     return f;
 }
 
-// Split eight complex values (one fragment lane: 8 K rows of one column) into
-// hi/lo planes and store them at lane `lane` of tile t.
-template <class E> __device__ inline void lds_split_store(LFrag<E>* t, int lane, const float2 (&v)[8]) {
+// Split eight complex values (one fragment lane: 8 K rows of one column),
+// times sc (a power of two, see SplitScale), into hi/lo planes and store them
+// at lane `lane` of tile t.
+template <class E> __device__ inline void lds_split_store(LFrag<E>* t, int lane, const float2 (&v)[8], float sc) {
     V8<E> rh, ih, rl, il;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const E xh = (E)v[i].x, yh = (E)v[i].y;
+        const float x = v[i].x * sc, y = v[i].y * sc;
+        const E xh = (E)x, yh = (E)y;
         rh[i] = xh;
         ih[i] = yh;
-        rl[i] = (E)(v[i].x - (float)xh);
-        il[i] = (E)(v[i].y - (float)yh);
+        rl[i] = (E)(x - (float)xh);
+        il[i] = (E)(y - (float)yh);
     }
     t->rh[lane] = rh;
     t->ih[lane] = ih;
@@ -205,7 +207,7 @@ struct BCfg {
 template <class C, class E, class BOff>
 __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4], const Frag<E>* __restrict__ Atiles,
                                int M, int K, int base, const float2* __restrict__ src, BOff boff, int nr,
-                               LFrag<E>* sB) {
+                               LFrag<E>* sB, float bsc) {
     constexpr int MTW = C::MTW, CT = C::CT;
     constexpr int KS = CT * KT;                     // K rows per stage
     const int tid = threadIdx.x, l = tid & 63;
@@ -238,7 +240,7 @@ __device__ void gemm_rows_bf16(floatx4 (&cr)[C::MTW][4], floatx4 (&ci)[C::MTW][4
     auto storeB = [&](int buf) {
         if (!stager) return;
         const int kt = bj / KT, kk = bj % KT;
-        lds_split_store(sB + (buf * CT + kt) * 4 + (br >> 4), (kk >> 3) * 16 + (br & 15), bt);
+        lds_split_store(sB + (buf * CT + kt) * 4 + (br >> 4), (kk >> 3) * 16 + (br & 15), bt, bsc);
     };
     Frag<E> acur[CT][MTW], anext[CT][MTW];
     loadA(0, acur);
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
             const int base = m0 + wave * MTW * 16;
             floatx4 cr[MTW][4], ci[MTW][4];
             zero_acc<MTW>(cr, ci);
-            gemm_rows_bf16<C, E>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB);
+            gemm_rows_bf16<C, E>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, 1.f);
 #pragma unroll
             for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -366,7 +368,8 @@ __global__ __launch_bounds__(C::NT) void up_bf16(UpArgs A, long long nid) {
                             const int r = nt * 16 + lr;
                             if (r < nr) {
                                 const float2 sv = load_vec(ext, xin, A.ld, A.nrhs, src, r0 + r);
-                                out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
+                                out[(yo + row) * A.nrhs + r0 + r] = make_float2(
+                                    cr[mt][nt][v] + sv.x, ci[mt][nt][v] + sv.y);
                             }
                         }
                     }
@@ -406,7 +409,7 @@ __global__ __launch_bounds__(C::NT) void down_bf16(DownArgs A, long long nid, fl
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C, E>(cr, ci, Tt, nred, k, base, z, boff, nr, sB);
+        gemm_rows_bf16<C, E>(cr, ci, Tt, nred, k, base, z, boff, nr, sB, 1.f);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
         const int base = m0 + wave * MTW * 16;
         floatx4 cr[MTW][4], ci[MTW][4];
         zero_acc<MTW>(cr, ci);
-        gemm_rows_bf16<C, E>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB);
+        gemm_rows_bf16<C, E>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, A.bscale);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -457,7 +460,8 @@ __global__ __launch_bounds__(C::NT) void middle_bf16(MidArgs A, const long long*
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) {
                         const int r = nt * 16 + lr;
-                        if (r < nr) zout[dst * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
+                        if (r < nr)
+                            zout[dst * A.nrhs + r0 + r] = make_float2(cr[mt][nt][v], ci[mt][nt][v]);
                     }
                 }
             }
@@ -502,7 +506,7 @@ static_assert(RES_KT * KT == SPLIT16_RESIDENT_K, "resident rank limit");
 // call this.
 template <class E, int NT, bool ONE_B, class BOff, class Epi>
 __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, const float2* __restrict__ src,
-                              BOff boff, int nr, LFrag<E>* sB, Epi epi) {
+                              BOff boff, int nr, LFrag<E>* sB, float bsc, Epi epi) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
     const int ktiles = (K + KT - 1) / KT;
@@ -530,7 +534,7 @@ __device__ void gemm_resident(const Frag<E>* __restrict__ Atiles, int M, int K, 
             const int j = kt * KT + kb * 8 + i;
             v[i] = (j < K && col < nr) ? src[boff(j, col)] : make_float2(0.f, 0.f);
         }
-        lds_split_store(sB + kt * 4 + (col >> 4), kb * 16 + (col & 15), v);
+        lds_split_store(sB + kt * 4 + (col >> 4), kb * 16 + (col & 15), v, bsc);
     }
     __syncthreads();
     for (int q = 0; q < total; ++q) {
@@ -589,7 +593,7 @@ __global__ __launch_bounds__(NT) void down_res16(DownArgs A, long long nid, floa
         }
     };
     gemm_resident<E, NT, (NT >= 1024)>(Tt, nred, k, zin + yo * A.nrhs + r0,
-                                       [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
+                                       [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, 1.f, epi);
 }
 
 // Going down, one workgroup per group of 2^d sibling decompositions (same
@@ -656,14 +660,15 @@ __global__ __launch_bounds__(NT) void down_group16(DownArgs A) {
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
                             const int r = nt * 16 + lr;
-                            if (r < nr) d[r] = make_float2(o[nt].x + cr[0][nt][v], o[nt].y + ci[0][nt][v]);
+                            if (r < nr)
+                                d[r] = make_float2(o[nt].x + cr[0][nt][v], o[nt].y + ci[0][nt][v]);
                         }
                     }
                 }
             }
         };
         gemm_resident<E, NT, (NT >= 768)>(Tt, nred, k, zin + yo * A.nrhs + r0,
-                                          [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
+                                          [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, 1.f, epi);
     }
 }
 
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(256) void down_leaf16(DownArgs A) {
             }
         };
         gemm_resident<E, 256, false>(Tt, nred, k, zin + yo * A.nrhs + r0,
-                                     [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, epi);
+                                     [&](int j, int c) { return (long long)j * A.nrhs + c; }, nr, sB, 1.f, epi);
     }
     __syncthreads();
     float2* outp = A.ext ? (float2*)A.ext : (float2*)A.out;
@@ -817,7 +822,7 @@ __device__ inline void a_prefetch(APipe<E, AD, ANG>& p, const Frag<E>* __restric
 template <class E, int NT, int AD, bool ANG = false, bool BATCH = false, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
                            int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB,
-                           const int* __restrict__ Aang, APipe<E, AD, ANG>& pipe, bool preloaded) {
+                           float bsc, const int* __restrict__ Aang, APipe<E, AD, ANG>& pipe, bool preloaded) {
     constexpr int RCT = rct_for<NT>();
     constexpr int FPT = RCT * 256 / NT;            // B fragments staged per thread and stage
     static_assert(FPT >= 1 && FPT * NT == RCT * 256, "stage must split evenly over the threads");
@@ -847,7 +852,7 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
 #pragma unroll
         for (int q = 0; q < FPT; ++q) {
             const int f = tid + q * NT, kt = f >> 8, kb = (f & 255) >> 6, col = f & 63;
-            lds_split_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q]);
+            lds_split_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q], bsc);
         }
     };
     auto tile_at = [&](int kt) { return a_tile<E, ANG>(Atiles, Aang, mt, ktiles, kt); };
@@ -941,15 +946,15 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
                 for (int nt = 0; nt < 4; ++nt) {
                     const int r = nt * 16 + lr;
                     if (r < nr)
-                        out[(yo + row) * A.nrhs + r0 + r] =
-                            make_float2(cr[0][nt][v] + sv[v][nt].x, ci[0][nt][v] + sv[v][nt].y);
+                        out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv[v][nt].x,
+                                                                        ci[0][nt][v] + sv[v][nt].y);
                 }
             }
         }
     };
     auto run = [&](const float2* xb, auto boff) {
         if (RES_ONLY || nred <= RES_KT * KT) {       // the redundant inputs fit in LDS: staged once
-            gemm_resident<E, NT, (NT >= 768)>(Tt, k, nred, xb, boff, nr, sB, epi);
+            gemm_resident<E, NT, (NT >= 768)>(Tt, k, nred, xb, boff, nr, sB, 1.f, epi);
             return;
         }
         if constexpr (!RES_ONLY) {
@@ -959,7 +964,8 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
                 const int base = m0 + wave * 16;
                 floatx4 cr[1][4], ci[1][4];
                 zero_acc<1>(cr, ci);
-                gemm_res16<E, NT, UAD, false, true>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, nullptr, pipe, false);
+                gemm_res16<E, NT, UAD, false, true>(cr, ci, Tt, k, nred, base, xb, boff, nr, sB, 1.f, nullptr, pipe,
+                                                    false);
                 epi(base, cr, ci);
             }
         }
@@ -1046,7 +1052,9 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
         const int base = m0 + wave * 16;
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
-        gemm_res16<E, NT, MAD, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, Sang, pipe, m0 == m_first);
+        // (only the middle itself, with phase tiles, changes the vectors' scale)
+        gemm_res16<E, NT, MAD, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, ANG ? A.bscale : 1.f, Sang, pipe,
+                                    m0 == m_first);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
@@ -1055,10 +1063,40 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     const int r = nt * 16 + lr;
-                    if (r < nr) zout[dst * A.nrhs + r0 + r] = make_float2(cr[0][nt][v], ci[0][nt][v]);
+                    if (r < nr)
+                        zout[dst * A.nrhs + r0 + r] = make_float2(cr[0][nt][v], ci[0][nt][v]);
                 }
             }
         }
+    }
+}
+
+// Largest |re| or |im| of slice blockIdx.x of column blockIdx.y (ColExpArgs).
+__global__ __launch_bounds__(256) void colmax_kernel(ColExpArgs A) {
+    __shared__ float red[4];
+    const int r = blockIdx.y, b = blockIdx.x;
+    const long long chunk = (A.N + A.S - 1) / A.S;
+    const long long p0 = (long long)b * chunk, p1 = min(A.N, p0 + chunk);
+    const float2* x = (const float2*)A.src + (long long)r * A.ld;
+    float m = 0.f;
+    for (long long p = p0 + threadIdx.x; p < p1; p += 256) {
+        const float2 v = x[p];
+        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) A.part[(long long)r * A.S + b] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void colexp_kernel(ColExpArgs A) {
+    for (int r = threadIdx.x; r < A.nrhs; r += 256) {
+        float m = 0.f;
+        for (int b = 0; b < A.S; ++b) m = fmaxf(m, A.part[(long long)r * A.S + b]);
+        int e = 0;
+        if (m > 0.f && m <= 3.4e38f) (void)frexpf(m, &e);
+        A.cexp[r] = e;
     }
 }
 
@@ -1108,6 +1146,7 @@ struct PackTilesArgs {
     const int* nc;
     void* out;
     const long long* tile_off;  // per block / ID: first tile
+    unsigned* tmax;             // mode 0/1, or null: atomic max of |re|, |im| of the entries (FP32 bits)
 };
 
 template <class E>
@@ -1131,6 +1170,7 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
     const int mtiles = (M + 15) / 16, ktiles = (K + KT - 1) / KT;
     Frag<E>* out = (Frag<E>*)P.out + P.tile_off[b] * 64;
     const long long nfr = (long long)mtiles * ktiles * 64;
+    float amax = 0.f;
     for (long long e = threadIdx.x; e < nfr; e += blockDim.x) {
         const int lane = (int)(e & 63);
         const long long tile = e >> 6;
@@ -1150,6 +1190,7 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
                 } else {
                     const int ti = P.mode == 0 ? row : col, tj = P.mode == 0 ? col : row;
                     const double2 v = X[(long long)ti * n + k + tj];
+                    amax = fmaxf(amax, (float)fmax(fabs(v.x), fabs(v.y)));
                     const float xh = (float)(E)v.x, yh = (float)(E)v.y;
                     f.rh[i] = (E)v.x;
                     f.ih[i] = (E)v.y;
@@ -1165,6 +1206,15 @@ __global__ void pack_tiles_kernel(PackTilesArgs P) {
             f.il[i] = (E)(y - (float)yh);
         }
         out[e] = f;
+    }
+    if (P.tmax) {
+        __shared__ float red[4];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax(P.tmax, __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
     }
 }
 
@@ -1286,6 +1336,15 @@ void pack_angle_tiles(const PhaseDesc& ph, const int* nr, const int* nc, const l
     }
 }
 
+void launch_col_exponents(const ColExpArgs& A, hipStream_t s) {
+    MIDBF_CHECK(A.S >= 1 && A.S <= 65535 && A.nrhs >= 1 && A.nrhs <= 65535, MIDBF_ERR_ARG,
+                "column exponent pass: bad slice or column count");
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)A.S, (unsigned)A.nrhs), dim3(256), 0, s, A);
+    MIDBF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(colexp_kernel, dim3(1), dim3(256), 0, s, A);
+    MIDBF_HIP(hipGetLastError());
+}
+
 void pack_src_lattice(const int* skel, const int* src, long long count, int* out, hipStream_t st) {
     if (count <= 0) return;
     const long long blocks = (count + 255) / 256;
@@ -1331,6 +1390,7 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
     else if (which == LevelKernel::Middle) {
         // one workgroup per chunk of NT / 64 row tiles of a block
         MidArgs a = *(const MidArgs*)args;
+        MIDBF_CHECK(a.ang || a.bscale == 1.f, MIDBF_ERR_ARG, "a scale change needs the middle's phase tiles");
         a.mchunks = std::max(1, (a.out_max + NT / 4 - 1) / (NT / 4));
         const dim3 mgrid((unsigned)(count * a.mchunks), grid.y);
         if (a.ang) hipLaunchKernelGGL((middle_res16<E, NT, true>), mgrid, dim3(NT), 0, s, a, tile_off);
@@ -1417,9 +1477,9 @@ void launch_bf16_kernel(int elem, LevelKernel which, int variant, const void* ar
 long long bf16_tiles(int M, int K) { return (long long)((M + 15) / 16) * ((K + KT - 1) / KT); }
 
 void pack_bf16_slab(int elem, const double2* X, long long x_stride, const int* k_w, const int* n_w, int count,
-                    bool transposed, void* out, const long long* tile_off, hipStream_t s) {
+                    bool transposed, void* out, const long long* tile_off, unsigned* tmax, hipStream_t s) {
     if (count <= 0) return;
-    PackTilesArgs P{transposed ? 1 : 0, X, x_stride, k_w, n_w, nullptr, nullptr, nullptr, nullptr, out, tile_off};
+    PackTilesArgs P{transposed ? 1 : 0, X, x_stride, k_w, n_w, nullptr, nullptr, nullptr, nullptr, out, tile_off, tmax};
     launch_pack(P, elem, (unsigned)count, s);
 }
 
@@ -1427,7 +1487,7 @@ void pack_bf16_blocks(int elem, const float2* S, const long long* s_off, const i
                       long long count, void* out, const long long* tile_off, hipStream_t s) {
     for (long long b0 = 0; b0 < count; b0 += 65535) {
         const long long cnt = std::min<long long>(65535, count - b0);
-        PackTilesArgs P{2, nullptr, 0, nullptr, nullptr, S, s_off + b0, nr + b0, nc + b0, out, tile_off + b0};
+        PackTilesArgs P{2, nullptr, 0, nullptr, nullptr, S, s_off + b0, nr + b0, nc + b0, out, tile_off + b0, nullptr};
         launch_pack(P, elem, (unsigned)cnt, s);
     }
 }

@@ -90,6 +90,8 @@ struct Workspace {
     size_t scratch_bytes = 0;
     void* lat = nullptr;          // N x nrhs row-major copy of the output (matrix-core path)
     size_t lat_bytes = 0;
+    void* aux = nullptr;          // split 16-bit: per right-hand side input maxima and exponents
+    size_t aux_bytes = 0;
 };
 
 // Per-launch HIP-event timing of the apply kernels (midbf_profile_*).
@@ -97,6 +99,7 @@ struct ProfRecord {
     std::string name;
     hipEvent_t a, b;
     double bytes, flops;   // algorithmic bytes moved and flops of the launch
+    double stored;         // bytes as laid out in memory (>= bytes: tile padding, identity entries)
 };
 
 struct Profiler {
@@ -119,6 +122,7 @@ struct midbf_plan {
     midbf_stats stats{};
     unsigned keep = 0;
     long long max_total_k = 0, max_total_n = 0;
+    unsigned* d_tmax = nullptr;   // build only: largest |re|, |im| of the T entries packed into 16-bit tiles
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
     // matrix-core tile variant per kernel kind (up, down, middle) and MSCS step (FP32, split-bf16, split-fp16)

@@ -137,7 +137,8 @@ class MIDBF:
         cnt = C.c_int()
         L.check(L.lib.midbf_profile_read(self._h, buf, 64, C.byref(cnt)))
         return [{"name": buf[i].name.decode(), "launches": buf[i].launches, "total_ms": buf[i].total_ms,
-                 "bytes": buf[i].bytes, "flops": buf[i].flops} for i in range(min(cnt.value, 64))]
+                 "bytes": buf[i].bytes, "flops": buf[i].flops, "stored_bytes": buf[i].stored_bytes}
+                for i in range(min(cnt.value, 64))]
 
     def ranks(self, side: int, step: int) -> np.ndarray:
         st = self.stats()
@@ -171,6 +172,39 @@ def apply_batched(handles: list[MIDBF], fs: list[torch.Tensor], outs: list[torch
     count, hs, fp, gp, nr = _batch_arrays(handles, fs, outs, precision)
     L.check(L.lib.midbf_apply_batched(count, hs, fp, gp, nr, _PREC[precision], _stream_ptr(stream)))
     return outs
+
+
+class ApplyGraph:
+    """g = K f for fixed buffers f, out, captured once in a hipGraph and replayed (midbf_apply_graph_*).
+
+    The factorization and both tensors are referenced here and kept alive; the
+    tile variants in effect at creation are fixed into the graph.
+    """
+
+    def __init__(self, F: MIDBF, f: torch.Tensor, out: torch.Tensor | None = None, precision: str = "fp32",
+                 stream=None):
+        nrhs = F._prep(f, precision)
+        self.out = F._out(f, out)
+        self._keep = (F, f, self.out)
+        g = C.c_void_p()
+        L.check(L.lib.midbf_apply_graph_create(F._h, f.data_ptr(), self.out.data_ptr(), nrhs, F.N,
+                                               _PREC[precision], _stream_ptr(stream), C.byref(g)))
+        self._g = g
+
+    def launch(self, stream=None) -> torch.Tensor:
+        L.check(L.lib.midbf_graph_launch(self._g, _stream_ptr(stream)))
+        return self.out
+
+    def close(self):
+        if getattr(self, "_g", None):
+            L.lib.midbf_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
