@@ -360,10 +360,10 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
  * variant out of range: FP32 0-9, FP64 0-4, split 16-bit 0-9).  nrhs below
  * the matrix-core threshold leaves the choice unchanged.  FP64, FP32,
  * MIDBF_SPLIT_BF16 and MIDBF_SPLIT_FP16 keep separate choices.  For the split
- * applies, variants 7-9 of the up kind read per-level source-row tables built
- * with the plan; with more than one right-hand side and a first up step that
- * keeps every leaf point, they also replace that step by a transpose of the
- * input into the apply's row-major copy.
+ * applies, variants 7-9 of the up kind read per-level source-row tables
+ * built with the plan; when the first up step keeps every leaf point, they
+ * also replace that step by the (scaled) transpose of the input into the
+ * apply's row-major copy.
  */
 midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants);
 midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants);

@@ -264,7 +264,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
     // (only the source-row-table up kernels, split variants 7-9, read it)
     const int v_up1 = (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[0][1];
     const bool lat_in = is_split16(prec) && mfma && lat && !adjoint && h->b >= 2 && up[0].entries == 0 &&
-                        up[1].d_src_lat != nullptr && v_up1 >= 7 && v_up1 <= 9;
+                        up[1].d_src_lat != nullptr && v_up1 >= 7 && v_up1 < BF16_VARIANTS;
     // Split 16-bit: the exponents of the input's column maxima first; the
     // vectors of the chain are then held scaled (SplitScale).
     int* cexp = nullptr;

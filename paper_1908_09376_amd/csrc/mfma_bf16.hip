@@ -72,20 +72,69 @@ template <class E> __device__ inline Frag<E> lds_frag(const LFrag<E>* t, int lan
     return f;
 }
 
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+// fp16 hi and lo parts of two FP32 values a, b, each packed as a pair (a in
+// the low half): hi = fp16(x) (one v_cvt_pk_f16_f32), lo = fp16(x - hi) by one
+// mixed-precision FMA per value (v_fma_mixlo / mixhi_f16: -hi as fp16 source
+// times 1 plus x as FP32 source, rounded once to fp16).  x - hi is exact in
+// FP32, so lo is bit for bit the two-conversion result, in three
+// instructions per pair instead of eight.
+__device__ inline void split_pair_f16(float a, float b, unsigned& hi, unsigned& lo) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    hi = __builtin_bit_cast(unsigned, h2{(_Float16)a, (_Float16)b});
+    unsigned r;
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=&v"(r)
+        : "v"(hi), "v"(a), "v"(b));
+    lo = r;
+}
+
+// The hi / lo planes of eight complex values (re[i], im[i]) as one fragment
+// lane of E.
+template <class E> __device__ inline void split8(const float (&re)[8], const float (&im)[8], V8<E>& rh, V8<E>& ih,
+                                                 V8<E>& rl, V8<E>& il) {
+    if constexpr (std::is_same_v<E, _Float16>) {
+        uintx4 h0, h1, l0, l1;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            unsigned a, b, c, d;
+            split_pair_f16(re[2 * p], re[2 * p + 1], a, b);
+            split_pair_f16(im[2 * p], im[2 * p + 1], c, d);
+            h0[p] = a;
+            l0[p] = b;
+            h1[p] = c;
+            l1[p] = d;
+        }
+        rh = __builtin_bit_cast(V8<E>, h0);
+        ih = __builtin_bit_cast(V8<E>, h1);
+        rl = __builtin_bit_cast(V8<E>, l0);
+        il = __builtin_bit_cast(V8<E>, l1);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const E xh = (E)re[i], yh = (E)im[i];
+            rh[i] = xh;
+            ih[i] = yh;
+            rl[i] = (E)(re[i] - (float)xh);
+            il[i] = (E)(im[i] - (float)yh);
+        }
+    }
+}
+
 // Split eight complex values (one fragment lane: 8 K rows of one column),
 // times sc (a power of two, see SplitScale), into hi/lo planes and store them
 // at lane `lane` of tile t.
 template <class E> __device__ inline void lds_split_store(LFrag<E>* t, int lane, const float2 (&v)[8], float sc) {
-    V8<E> rh, ih, rl, il;
+    float re[8], im[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const float x = v[i].x * sc, y = v[i].y * sc;
-        const E xh = (E)x, yh = (E)y;
-        rh[i] = xh;
-        ih[i] = yh;
-        rl[i] = (E)(x - (float)xh);
-        il[i] = (E)(y - (float)yh);
+        re[i] = v[i].x * sc;
+        im[i] = v[i].y * sc;
     }
+    V8<E> rh, ih, rl, il;
+    split8<E>(re, im, rh, ih, rl, il);
     t->rh[lane] = rh;
     t->ih[lane] = ih;
     t->rl[lane] = rl;
@@ -107,17 +156,15 @@ struct AngRaw {
 
 template <class E> __device__ inline Frag<E> angle_frag(const AngRaw& r) {
     const intx4 a0 = r.a0, a1 = r.a1;
-    Frag<E> f;
+    float c[8], s[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const float t = (float)(i < 4 ? a0[i] : a1[i - 4]) * 0x1p-32f;
-        const float c = __builtin_amdgcn_cosf(t), s = __builtin_amdgcn_sinf(t);
-        const E ch = (E)c, sh = (E)s;
-        f.rh[i] = ch;
-        f.ih[i] = sh;
-        f.rl[i] = (E)(c - (float)ch);
-        f.il[i] = (E)(s - (float)sh);
+        c[i] = __builtin_amdgcn_cosf(t);
+        s[i] = __builtin_amdgcn_sinf(t);
     }
+    Frag<E> f;
+    split8<E>(c, s, f.rh, f.ih, f.rl, f.il);
     return f;
 }
 
@@ -1053,7 +1100,8 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
         // (only the middle itself, with phase tiles, changes the vectors' scale)
-        gemm_res16<E, NT, MAD, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, ANG ? A.bscale : 1.f, Sang, pipe,
+        gemm_res16<E, NT, MAD, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, ANG ? A.bscale : 1.f, Sang,
+                                    pipe,
                                     m0 == m_first);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
