@@ -193,9 +193,9 @@ midbf_status midbf_apply_adjoint(midbf_handle h, const void* g_dev, void* f_dev,
 
 /*
  * midbf_apply_batched -- count independent transforms (different handles,
- * possibly different N): g_j = K~_j f_j as one grouped launch per level
- * round (midbf_batch_create + midbf_batch_run, then destroy; the call
- * therefore synchronizes `stream`).  hs, f_devs, g_devs, nrhs are
+ * possibly different N): g_j = K~_j f_j as one persistent launch
+ * (midbf_batch_create + midbf_batch_run, then destroy; the call therefore
+ * synchronizes `stream`).  hs, f_devs, g_devs, nrhs are
  * host arrays of length count; each f/g block is column-major with ld = N_j.
  * FP64 or FP32.
  */
@@ -207,11 +207,25 @@ midbf_status midbf_apply_batched(int count, const midbf_handle* hs, const void* 
  * Batches of forward transforms of uneven N (the batched apply of many
  * transforms; the factor product of Sec. 3.5 per transform).
  *
- * midbf_batch_create -- prepare g_j = K~_j f_j for j < count.  The level
- * launches of all transforms are grouped by round (every transform's first
- * level, then every second level, ...): one launch per round covers the
- * workgroups of that level of every transform, so a batch of any size takes
- * 2 * max_j(b_j) + 1 launches.  hs, f_devs, g_devs, nrhs: host arrays of
+ * midbf_batch_create -- prepare g_j = K~_j f_j for j < count as ONE
+ * persistent launch per run.  The workgroups of every level launch of every
+ * transform become tasks of one queue, ordered by level (every transform's
+ * first level, then every second level, ...).  As many workgroups as fit on
+ * the device at once take tasks in queue order with an atomic counter; a
+ * task waits until its transform's previous level has completed (a
+ * completion count per level, release / acquire at device scope), runs the
+ * level kernel's body, and counts itself complete.  Tasks depend only on
+ * earlier tasks, so the earliest unfinished one can always proceed: no
+ * deadlock, whatever the number of resident workgroups.  Waits poll with a
+ * bounded count; one that runs out is abandoned and counted
+ * (midbf_batch_stats.timeouts) instead of hanging.  The last workgroup of a
+ * run resets the queue for the next run, so a run is a single kernel node
+ * (graph replays need no reset).  Tasks are handed out in segments of a few
+ * consecutive workgroups; within a level, the segments of transforms given
+ * the same handle are interleaved block by block, so segments that read the
+ * same factor blocks run at about the same time and the repeated reads hit
+ * the caches.  Each output equals midbf_apply of its own transform.
+ * hs, f_devs, g_devs, nrhs: host arrays of
  * length count; f/g blocks column-major with ld = N_j; FP64 (complex128) or
  * FP32 (complex64), through the VALU level kernels.  use_graph != 0 captures
  * the launches in a hipGraph at creation; midbf_batch_run replays it.  The
@@ -222,11 +236,15 @@ midbf_status midbf_apply_batched(int count, const midbf_handle* hs, const void* 
  */
 typedef struct {
     int stages;                 /* level launches folded into the batch              */
-    int rounds;                 /* launches per run                                  */
-    long long items;            /* workgroups over all rounds                        */
+    int rounds;                 /* levels of the deepest transform                   */
+    long long items;            /* tasks (level-launch workgroups) of one run        */
     int graph;                  /* 1 if replayed from a captured hipGraph            */
     long long lds_bytes;        /* dynamic LDS per workgroup                         */
     double bytes, flops;        /* algorithmic bytes and flops of one run            */
+    int launches;               /* kernel launches per run (1)                       */
+    int workgroups;             /* persistent workgroups (resident capacity)         */
+    long long timeouts;         /* dependency waits abandoned at the poll limit, over
+                                   all runs so far (0 in a correct run)              */
 } midbf_batch_stats;
 
 midbf_status midbf_batch_create(int count, const midbf_handle* hs, const void* const* f_devs,
@@ -234,7 +252,24 @@ midbf_status midbf_batch_create(int count, const midbf_handle* hs, const void* c
                                 int use_graph, void* stream, midbf_batch* out);
 /* Enqueue one run of the batch on `stream` (asynchronous). */
 midbf_status midbf_batch_run(midbf_batch b, void* stream);
+/* Synchronizes the device (it reads the timeout count). */
 midbf_status midbf_batch_get_stats(midbf_batch b, midbf_batch_stats* out);
+
+/*
+ * midbf_schedule_simulate -- host check of the persistent batch's queue
+ * protocol (no GPU work): builds the queue of `count` transforms, transform j
+ * having levels[j] level launches with the task counts given in order in
+ * items (sum of levels[] entries) and sharing group share[j] (transforms of
+ * one group are interleaved; NULL: none shared), in segments of `chunk`
+ * tasks, and runs the protocol with `workers` host threads in place of
+ * workgroups (any number, also fewer than segments), each segment pausing at
+ * random.  A dependency wait longer than limit_ms counts as a stall.  Outputs
+ * the tasks completed and the stalls.  Errors: MIDBF_ERR_ARG, MIDBF_ERR_SHAPE
+ * (a level launch without tasks).
+ */
+midbf_status midbf_schedule_simulate(int count, const int* levels, const long long* items, const int* share,
+                                     int workers, int chunk, int limit_ms, unsigned seed, long long* completed,
+                                     long long* stalls);
 /* Free the batch; waits for the device like hipFree. */
 void midbf_batch_destroy(midbf_batch b);
 

@@ -43,7 +43,8 @@ class KernelTime(C.Structure):
 
 class BatchStats(C.Structure):
     _fields_ = [("stages", C.c_int), ("rounds", C.c_int), ("items", C.c_longlong), ("graph", C.c_int),
-                ("lds_bytes", C.c_longlong), ("bytes", C.c_double), ("flops", C.c_double)]
+                ("lds_bytes", C.c_longlong), ("bytes", C.c_double), ("flops", C.c_double),
+                ("launches", C.c_int), ("workgroups", C.c_int), ("timeouts", C.c_longlong)]
 
 
 class RecoverInfo(C.Structure):
@@ -84,6 +85,8 @@ def _load():
         "midbf_batch_run": (i, [vp, vp]),
         "midbf_batch_get_stats": (i, [vp, C.POINTER(BatchStats)]),
         "midbf_batch_destroy": (None, [vp]),
+        "midbf_schedule_simulate": (i, [i, C.POINTER(i), C.POINTER(ll), C.POINTER(i), i, i, i, C.c_uint,
+                                        C.POINTER(ll), C.POINTER(ll)]),
         "midbf_factor_stats": (i, [vp, C.POINTER(Stats)]),
         "midbf_ranks": (i, [vp, i, i, C.POINTER(i), ll]),
         "midbf_kernel_entries": (i, [C.POINTER(Params), vp, i, vp, i, vp, vp]),
@@ -115,7 +118,7 @@ def check(status: int) -> None:
 EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_noalloc", "midbf_apply_batched",
             "midbf_apply_graph_create", "midbf_graph_launch", "midbf_graph_destroy",
             "midbf_batch_create", "midbf_batch_run", "midbf_batch_get_stats",
-            "midbf_batch_destroy",
+            "midbf_batch_destroy", "midbf_schedule_simulate",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",
             "midbf_tune", "midbf_set_variants", "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error",
             "phase_recover"]

@@ -194,16 +194,18 @@ struct TransposeArgs {
 void launch_level_kernel(LevelKernel which, int prec, int rt, const void* args, dim3 grid, size_t smem,
                          hipStream_t s);
 
-// One level launch of one transform inside a grouped batch launch.  The
-// level launches of many transforms are grouped by round (every transform's
-// first level, then every second level, ...); a round's stages are
-// consecutive in the table and its workgroups are numbered through them:
-// stage q owns blocks first .. first + items - 1 of its round's launch.
+// A batch of forward transforms as one persistent launch.  Each level launch
+// of each transform is a stage; its tasks (one per workgroup of that launch)
+// are handed out in segments of up to a chunk of consecutive items, in queue
+// order: level by level, and within a level the transforms that share a
+// factorization item block by item block, so that their segments reading the
+// same factor blocks are handed out together.  A segment waits until its
+// transform's previous level (stage dep) has completed all its items.
 struct BatchStage {
     int kind;                // 0 up, 1 middle, 2 down (forward transform)
     int tiles;               // right-hand-side tiles per group
-    long long items;         // workgroups: groups (or middle blocks) x tiles
-    long long first;         // first block of the stage within its round
+    long long items;         // tasks: groups (or middle blocks) x tiles
+    int dep;                 // stage of the same transform's previous level, or -1
     union {
         UpArgs up;
         MidArgs mid;
@@ -211,9 +213,30 @@ struct BatchStage {
     } a;
 };
 
-// One launch of `items` workgroups over the stages [s0, s0 + ns) of the
-// device table d_st, with `smem` bytes of dynamic LDS.
-void launch_grouped(int prec, int rt, const BatchStage* d_st, int s0, int ns, long long items, size_t smem,
-                    hipStream_t s);
+struct BatchSegment {
+    int stage;
+    int count;               // items item0 .. item0 + count - 1 of the stage
+    long long item0;
+};
+
+// Control block of a persistent run, 32-bit words: next segment to hand out,
+// workgroups finished, waits that hit the spin limit (kept across runs), one
+// spare, then one completion count per stage.  The last workgroup of a run
+// clears every word but the timeout count for the next run.
+constexpr int BATCH_CTL_HEAD = 4;
+
+struct PersistArgs {
+    const BatchStage* st;
+    const BatchSegment* seg;
+    int nseg;
+    unsigned* ctl;
+    int nst;
+    long long spin_limit;    // polls of a dependency before a wait is abandoned (counted as a timeout)
+};
+
+// Workgroups of the persistent kernel that fit on the current device at once
+// (occupancy x compute units) with `smem` bytes of dynamic LDS.
+int persistent_capacity(int prec, int rt, size_t smem);
+void launch_persistent(int prec, int rt, const PersistArgs& P, int grid, size_t smem, hipStream_t s);
 
 }  // namespace midbf

@@ -14,6 +14,8 @@
 // The 2^d-way butterfly permutations are index math on the Z-order numbers,
 // so each workgroup gathers its inputs and scatters its outputs directly and
 // no atomics are needed.
+#include <algorithm>
+
 #include "apply.h"
 
 namespace midbf {
@@ -563,36 +565,104 @@ __global__ __launch_bounds__(AT) void adj_down_kernel(DownArgs A) {
                               A.nrhs, r0, nr);
 }
 
-// ---- grouped batch of forward transforms ----
-// One workgroup per item of the stages of one round: the block index is
-// located among the stages' first blocks, and the item runs the same body as
-// the stage's own level kernel would.  Stages of a round are independent
-// (different transforms); rounds are ordered by the stream.
+// ---- a batch of forward transforms in one persistent launch ----
+// Every workgroup takes one segment at a time from the queue (one atomic
+// add), waits until the segment's dependency stage is complete, runs the same
+// body as that stage's own level kernel on each of its items, and counts the
+// segment's items complete (one release and atomic add per segment).
+// Deadlock freedom: segments are handed out in queue order and depend only on
+// earlier segments, so the earliest unfinished one is either held by a
+// running workgroup whose dependencies are all complete, or not yet handed
+// out while every earlier segment is done; either way some workgroup makes
+// progress, whatever the number of resident workgroups.  Waits poll with
+// s_sleep and give up after spin_limit polls (counted in the control block),
+// so no wait can hang the device.
+__device__ inline unsigned ld_relaxed(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class C, int RT>
-__global__ __launch_bounds__(AT) void grouped_kernel(const BatchStage* __restrict__ st, int s0, int ns) {
+__global__ __launch_bounds__(AT) void persistent_kernel(PersistArgs P) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const long long t = blockIdx.x;
-    int lo = s0, hi = s0 + ns - 1;             // last stage with first <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (st[mid].first <= t) lo = mid;
-        else hi = mid - 1;
+    __shared__ int s_seg;
+    unsigned* next = P.ctl;
+    unsigned* fin = P.ctl + 1;
+    unsigned* timeouts = P.ctl + 2;
+    unsigned* done = P.ctl + BATCH_CTL_HEAD;
+    // The queue's bookkeeping is done by wave 0 as a whole (a branch the compiler
+    // sees as wave-uniform), never by a single lane inside the loop: a lane-divergent
+    // branch there lets the compiler restructure the loop so that the lanes of wave 0
+    // leave it at different iterations, which breaks the barriers.  Only lane 0
+    // contributes to each atomic (the other lanes add 0).
+    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;
+    const unsigned lane0 = threadIdx.x == 0 ? 1u : 0u;
+    for (;;) {
+        if (wave0) {
+            const unsigned v = __hip_atomic_fetch_add(next, lane0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int si = __builtin_amdgcn_readfirstlane((int)v);
+            s_seg = si;
+        }
+        __syncthreads();
+        const int si = __builtin_amdgcn_readfirstlane(s_seg);
+        __syncthreads();               // s_seg is rewritten by the next step
+        if (si >= P.nseg) break;
+        const BatchSegment sg = P.seg[si];
+        const int q = __builtin_amdgcn_readfirstlane(sg.stage);
+        const int cnt = __builtin_amdgcn_readfirstlane(sg.count);
+        const long long item0 = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                                 (int)((unsigned long long)sg.item0 >> 32)) << 32) |
+                                            (unsigned)__builtin_amdgcn_readfirstlane((int)sg.item0));
+        const int dep = P.st[q].dep;
+        if (dep >= 0) {
+            if (wave0) {
+                // poll without cache maintenance; one acquire fence once the count is reached
+                const unsigned need = (unsigned)P.st[dep].items;
+                long long polls = 0;
+                while (__builtin_amdgcn_readfirstlane((int)ld_relaxed(done + dep)) < (int)need) {
+                    if (++polls > P.spin_limit) {
+                        __hip_atomic_fetch_add(timeouts, lane0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            // wave 0's acquire (agent scope) invalidated this CU's L1 and the stale L2
+            // lines; the barrier orders every thread's reads after it
+            __syncthreads();
+        }
+        const int tiles = P.st[q].tiles;
+        const int kind = P.st[q].kind;
+        for (int u = 0; u < cnt; ++u) {
+            const long long item = item0 + u;
+            const long long g = item / tiles;
+            const int tile = (int)(item - g * tiles);
+            if (kind == 0) {
+                const UpArgs A = P.st[q].a.up;
+                up_body<C, RT, (RT == 1 ? 4 : 1)>(A, g, tile, smem_raw);
+            } else if (kind == 1) {
+                const MidArgs A = P.st[q].a.mid;
+                middle_body<C, RT>(A, g, tile, smem_raw);
+            } else {
+                const DownArgs A = P.st[q].a.down;
+                down_body<C, RT>(A, g, tile, smem_raw);
+            }
+            __syncthreads();               // the LDS is free for the next item
+        }
+        // every thread's stores of this segment complete (workgroup scope), then wave 0's
+        // release at agent scope publishes them (the L2 write-back covers all of them)
+        __threadfence_block();
+        __syncthreads();
+        if (wave0) __hip_atomic_fetch_add(done + q, lane0 * (unsigned)cnt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const int q = __builtin_amdgcn_readfirstlane(lo);
-    const long long item = t - st[q].first;
-    const int tiles = st[q].tiles;
-    const long long g = item / tiles;
-    const int tile = (int)(item - g * tiles);
-    const int kind = st[q].kind;
-    if (kind == 0) {
-        const UpArgs A = st[q].a.up;
-        up_body<C, RT, (RT == 1 ? 4 : 1)>(A, g, tile, smem_raw);
-    } else if (kind == 1) {
-        const MidArgs A = st[q].a.mid;
-        middle_body<C, RT>(A, g, tile, smem_raw);
-    } else {
-        const DownArgs A = st[q].a.down;
-        down_body<C, RT>(A, g, tile, smem_raw);
+    // the last workgroup out clears the queue and the counts for the next run
+    if (threadIdx.x == 0) {
+        const unsigned f = __hip_atomic_fetch_add(fin, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (f == gridDim.x - 1) {
+            for (int q = 0; q < P.nst; ++q) __hip_atomic_store(done + q, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(fin, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -624,18 +694,34 @@ void launch_level(LevelKernel which, const void* args, dim3 grid, size_t smem, h
     MIDBF_HIP(hipGetLastError());
 }
 
+template <class C, int RT>
+const void* persistent_fn() {
+    return reinterpret_cast<const void*>(&persistent_kernel<C, RT>);
+}
+
+const void* persistent_for(int prec, int rt) {
+    if (prec == PREC_FP64) return rt == 1 ? persistent_fn<double2, 1>() : persistent_fn<double2, APPLY_RT64>();
+    return rt == 1 ? persistent_fn<float2, 1>() : persistent_fn<float2, APPLY_RT>();
+}
+
 }  // namespace
 
-void launch_grouped(int prec, int rt, const BatchStage* d_st, int s0, int ns, long long items, size_t smem,
-                    hipStream_t s) {
-    MIDBF_CHECK(items >= 1 && items <= 0x7fffffffLL, MIDBF_ERR_SHAPE, "grouped launch size out of range");
-    const dim3 grid((unsigned)items);
+int persistent_capacity(int prec, int rt, size_t smem) {
+    int dev = 0, cus = 0, per = 0;
+    MIDBF_HIP(hipGetDevice(&dev));
+    MIDBF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MIDBF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_for(prec, rt), AT, smem));
+    return std::max(1, per) * std::max(1, cus);
+}
+
+void launch_persistent(int prec, int rt, const PersistArgs& P, int grid, size_t smem, hipStream_t s) {
+    MIDBF_CHECK(grid >= 1 && P.nseg >= 1 && P.nst >= 1, MIDBF_ERR_SHAPE, "persistent batch launch shape out of range");
     if (prec == PREC_FP64) {
-        if (rt == 1) hipLaunchKernelGGL((grouped_kernel<double2, 1>), grid, dim3(AT), smem, s, d_st, s0, ns);
-        else hipLaunchKernelGGL((grouped_kernel<double2, APPLY_RT64>), grid, dim3(AT), smem, s, d_st, s0, ns);
+        if (rt == 1) hipLaunchKernelGGL((persistent_kernel<double2, 1>), dim3(grid), dim3(AT), smem, s, P);
+        else hipLaunchKernelGGL((persistent_kernel<double2, APPLY_RT64>), dim3(grid), dim3(AT), smem, s, P);
     } else {
-        if (rt == 1) hipLaunchKernelGGL((grouped_kernel<float2, 1>), grid, dim3(AT), smem, s, d_st, s0, ns);
-        else hipLaunchKernelGGL((grouped_kernel<float2, APPLY_RT>), grid, dim3(AT), smem, s, d_st, s0, ns);
+        if (rt == 1) hipLaunchKernelGGL((persistent_kernel<float2, 1>), dim3(grid), dim3(AT), smem, s, P);
+        else hipLaunchKernelGGL((persistent_kernel<float2, APPLY_RT>), dim3(grid), dim3(AT), smem, s, P);
     }
     MIDBF_HIP(hipGetLastError());
 }

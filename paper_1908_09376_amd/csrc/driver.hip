@@ -1,11 +1,14 @@
 // Apply orchestration and the C interface (include/midbf.h).
 #include <algorithm>
+#include <atomic>
 #include <cctype>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 
 #include "apply.h"
 #include "build.h"
@@ -689,22 +692,111 @@ midbf_graph_s* capture_apply(midbf_plan* h, const void* in_ext, void* out_ext, i
 }  // namespace midbf
 
 // A batch of forward transforms (midbf_batch_*): the stage table on the
-// device, one pair of level buffers per transform, one grouped launch per
-// round, and optionally the captured graph of those launches.
+// device, one pair of level buffers per transform, and one persistent launch
+// per run (optionally replayed from a captured hipGraph).
 struct midbf_batch_s {
-    int prec = 0, rt = 1, nst = 0;
+    int prec = 0, rt = 1, nst = 0, rounds = 0, grid = 0;
     size_t smem = 0;
     long long items = 0;
-    std::vector<int> round_s0, round_ns;
-    std::vector<long long> round_items;
     std::vector<void*> bufs;
     midbf::BatchStage* d_st = nullptr;
+    midbf::BatchSegment* d_seg = nullptr;
+    unsigned* d_ctl = nullptr;          // control block of the persistent runs (BATCH_CTL_HEAD + nst words)
+    midbf::PersistArgs args{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double bytes = 0, flops = 0;
 };
 
 namespace midbf {
+
+// The queue of a batch.  Stage (j, r) is level launch r of transform j, with
+// items[j][r] tasks; dep = stage (j, r - 1) or -1.  Segments of at most
+// `chunk` consecutive items are handed out level by level (every transform's
+// level r before any level r + 1); within a level, transforms of one sharing
+// group (share[j]: the same factorization) go item block by item block, so
+// the segments of all members that read the same factor blocks are adjacent
+// in the queue and run at about the same time (the later reads hit the
+// caches).  Segments only ever depend on earlier segments.
+struct Schedule {
+    std::vector<int> dep;
+    std::vector<long long> items;
+    std::vector<BatchSegment> seg;
+};
+
+Schedule build_schedule(const std::vector<std::vector<long long>>& items, const std::vector<int>& share, int chunk) {
+    MIDBF_CHECK(chunk >= 1 && share.size() == items.size(), MIDBF_ERR_ARG, "bad batch schedule arguments");
+    Schedule S;
+    const int T = (int)items.size();
+    size_t rounds = 0;
+    for (const auto& v : items) rounds = std::max(rounds, v.size());
+    std::vector<std::vector<int>> stage_of(T);
+    for (size_t r = 0; r < rounds; ++r)           // stages numbered level by level
+        for (int j = 0; j < T; ++j) {
+            if (r >= items[j].size()) continue;
+            MIDBF_CHECK(items[j][r] >= 1, MIDBF_ERR_SHAPE, "a level launch without workgroups");
+            S.dep.push_back(r ? stage_of[j][r - 1] : -1);
+            S.items.push_back(items[j][r]);
+            stage_of[j].push_back((int)S.items.size() - 1);
+        }
+    std::vector<int> groups;                      // sharing groups in order of first appearance
+    for (int j = 0; j < T; ++j)
+        if (std::find(groups.begin(), groups.end(), share[j]) == groups.end()) groups.push_back(share[j]);
+    for (size_t r = 0; r < rounds; ++r)
+        for (int gid : groups) {
+            long long most = 0;
+            for (int j = 0; j < T; ++j)
+                if (share[j] == gid && r < items[j].size()) most = std::max(most, items[j][r]);
+            for (long long i0 = 0; i0 < most; i0 += chunk)
+                for (int j = 0; j < T; ++j) {
+                    if (share[j] != gid || r >= items[j].size() || i0 >= items[j][r]) continue;
+                    S.seg.push_back(BatchSegment{stage_of[j][r], (int)std::min<long long>(chunk, items[j][r] - i0), i0});
+                }
+        }
+    return S;
+}
+
+// The persistent kernel's queue protocol run by host threads in place of
+// workgroups (any number, also far fewer than segments): take one segment per
+// atomic step, wait for its dependency stage to complete, "run" its items (a
+// short random pause), count them complete.  A wait longer than limit_ms
+// counts as a stall.  Returns the items completed and the stalls.
+void simulate_schedule(const Schedule& S, int workers, int limit_ms, unsigned seed, long long& completed,
+                       long long& stalls) {
+    std::atomic<long long> next{0}, comp{0}, stall{0};
+    std::vector<std::atomic<long long>> done(S.items.size());
+    for (auto& d : done) d.store(0);
+    const long long nseg = (long long)S.seg.size();
+    auto worker = [&](int w) {
+        unsigned x = seed * 2654435761u + (unsigned)w * 40503u + 1u;
+        for (;;) {
+            const long long si = next.fetch_add(1);
+            if (si >= nseg) return;
+            const BatchSegment& sg = S.seg[si];
+            const int dep = S.dep[sg.stage];
+            if (dep >= 0) {
+                const auto start = std::chrono::steady_clock::now();
+                while (done[dep].load(std::memory_order_acquire) < S.items[dep]) {
+                    if (std::chrono::steady_clock::now() - start > std::chrono::milliseconds(limit_ms)) {
+                        stall.fetch_add(1);
+                        break;
+                    }
+                    std::this_thread::yield();
+                }
+            }
+            x = x * 1664525u + 1013904223u;
+            if ((x >> 28) == 0) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            done[sg.stage].fetch_add(sg.count, std::memory_order_release);
+            comp.fetch_add(sg.count);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int w = 0; w < workers; ++w) th.emplace_back(worker, w);
+    for (auto& t : th) t.join();
+    completed = comp.load();
+    stalls = stall.load();
+}
+
 namespace {
 
 void free_batch(midbf_batch_s* b) {
@@ -713,12 +805,16 @@ void free_batch(midbf_batch_s* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (void* p : b->bufs) (void)hipFree(p);
     if (b->d_st) (void)hipFree(b->d_st);
+    if (b->d_seg) (void)hipFree(b->d_seg);
+    if (b->d_ctl) (void)hipFree(b->d_ctl);
     delete b;
 }
 
-void launch_rounds(const midbf_batch_s* b, hipStream_t st) {
-    for (size_t r = 0; r < b->round_s0.size(); ++r)
-        launch_grouped(b->prec, b->rt, b->d_st, b->round_s0[r], b->round_ns[r], b->round_items[r], b->smem, st);
+constexpr int BATCH_CHUNK = 8;                    // items per segment of the queue
+constexpr long long BATCH_SPIN_LIMIT = 1LL << 20; // polls (~1-2 us each) before a wait is abandoned
+
+void launch_batch(const midbf_batch_s* b, hipStream_t st) {
+    launch_persistent(b->prec, b->rt, b->args, b->grid, b->smem, st);
 }
 
 midbf_batch_s* create_batch(int count, const midbf_handle* hs, const void* const* f, void* const* g, const int* nrhs,
@@ -726,18 +822,19 @@ midbf_batch_s* create_batch(int count, const midbf_handle* hs, const void* const
     MIDBF_CHECK(count >= 1, MIDBF_ERR_ARG, "empty batch");
     MIDBF_CHECK(prec == PREC_FP64 || prec == PREC_FP32, MIDBF_ERR_UNIMPLEMENTED,
                 "the batched apply runs in FP64 or FP32");
-    bool single = true;
     for (int j = 0; j < count; ++j) {
         MIDBF_CHECK(hs[j], MIDBF_ERR_ARG, "null handle in batch");
         check_apply_args(hs[j], f[j], g[j], nrhs[j], hs[j]->N, prec);
-        single = single && nrhs[j] == 1;
     }
     std::unique_ptr<midbf_batch_s, void (*)(midbf_batch_s*)> b(new midbf_batch_s, free_batch);
     b->prec = prec;
-    b->rt = single ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     const size_t cs = csize(prec);
+    bool single = true;
+    for (int j = 0; j < count; ++j) single = single && nrhs[j] == 1;
+    b->rt = single ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     std::vector<std::vector<LaunchDesc>> seq(count);
-    size_t rounds = 0;
+    std::vector<std::vector<long long>> items(count);
+    std::vector<int> share(count);
     for (int j = 0; j < count; ++j) {
         midbf_plan* h = hs[j];
         void* buf[2] = {nullptr, nullptr};
@@ -747,45 +844,57 @@ midbf_batch_s* create_batch(int count, const midbf_handle* hs, const void* const
             b->bufs.push_back(buf[i]);
         }
         seq[j] = plan_apply(h, f[j], g[j], nrhs[j], h->N, prec, false, false, buf, false, b->rt);
-        rounds = std::max(rounds, seq[j].size());
+        for (const LaunchDesc& D : seq[j]) items[j].push_back((long long)D.grid.x * D.grid.y);
+        b->rounds = std::max(b->rounds, (int)seq[j].size());
+        share[j] = j;                                    // transforms with one handle share its factors
+        for (int i = 0; i < j; ++i)
+            if (hs[i] == h) {
+                share[j] = share[i];
+                break;
+            }
     }
-    // round r groups the r-th level launch of every transform that has one
-    std::vector<BatchStage> stages;
-    for (size_t r = 0; r < rounds; ++r) {
-        long long first = 0;
-        const int s0 = (int)stages.size();
-        for (int j = 0; j < count; ++j) {
-            if (r >= seq[j].size()) continue;
-            const LaunchDesc& D = seq[j][r];
-            MIDBF_CHECK(D.smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
-                        "candidate vectors of this factorization exceed the apply kernels' LDS budget");
-            BatchStage S{};
-            S.kind = D.which == LevelKernel::Up ? 0 : (D.which == LevelKernel::Middle ? 1 : 2);
-            S.tiles = (int)D.grid.y;
-            S.items = (long long)D.grid.x * D.grid.y;
-            S.first = first;
-            std::memcpy(&S.a, &D.a, sizeof(S.a));
-            stages.push_back(S);
-            first += S.items;
-            b->smem = std::max(b->smem, D.smem);
-            b->bytes += D.bytes;
-            b->flops += D.flops;
-        }
-        b->round_s0.push_back(s0);
-        b->round_ns.push_back((int)stages.size() - s0);
-        b->round_items.push_back(first);
-        b->items += first;
+    const Schedule S = build_schedule(items, share, BATCH_CHUNK);
+    MIDBF_CHECK(S.seg.size() < 0x7fffffffULL - 65536, MIDBF_ERR_SHAPE, "batch too large");
+    std::vector<BatchStage> stages(S.items.size());
+    {
+        size_t q = 0;
+        for (int r = 0; r < b->rounds; ++r)              // the schedule's stage numbering
+            for (int j = 0; j < count; ++j) {
+                if (r >= (int)seq[j].size()) continue;
+                const LaunchDesc& D = seq[j][r];
+                MIDBF_CHECK(D.smem <= LDS_LIMIT, MIDBF_ERR_UNIMPLEMENTED,
+                            "candidate vectors of this factorization exceed the apply kernels' LDS budget");
+                BatchStage& B = stages[q];
+                B = BatchStage{};
+                B.kind = D.which == LevelKernel::Up ? 0 : (D.which == LevelKernel::Middle ? 1 : 2);
+                B.tiles = (int)D.grid.y;
+                B.items = S.items[q];
+                B.dep = S.dep[q];
+                std::memcpy(&B.a, &D.a, sizeof(B.a));
+                b->smem = std::max(b->smem, D.smem);
+                b->bytes += D.bytes;
+                b->flops += D.flops;
+                b->items += S.items[q];
+                ++q;
+            }
     }
     b->nst = (int)stages.size();
     MIDBF_HIP(hipMalloc(&b->d_st, stages.size() * sizeof(BatchStage)));
     MIDBF_HIP(hipMemcpyAsync(b->d_st, stages.data(), stages.size() * sizeof(BatchStage), hipMemcpyHostToDevice, st));
+    MIDBF_HIP(hipMalloc(&b->d_seg, S.seg.size() * sizeof(BatchSegment)));
+    MIDBF_HIP(hipMemcpyAsync(b->d_seg, S.seg.data(), S.seg.size() * sizeof(BatchSegment), hipMemcpyHostToDevice, st));
+    const size_t ctl_bytes = (BATCH_CTL_HEAD + stages.size()) * sizeof(unsigned);
+    MIDBF_HIP(hipMalloc(&b->d_ctl, ctl_bytes));
+    MIDBF_HIP(hipMemsetAsync(b->d_ctl, 0, ctl_bytes, st));      // (once, outside any captured graph)
     MIDBF_HIP(hipStreamSynchronize(st));
+    b->grid = (int)std::min<long long>(persistent_capacity(prec, b->rt, b->smem), (long long)S.seg.size());
+    b->args = PersistArgs{b->d_st, b->d_seg, (int)S.seg.size(), b->d_ctl, b->nst, BATCH_SPIN_LIMIT};
     if (use_graph) {
         hipStream_t cap;
         MIDBF_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         try {
             MIDBF_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            launch_rounds(b.get(), cap);
+            launch_batch(b.get(), cap);
             MIDBF_HIP(hipStreamEndCapture(cap, &b->graph));
             MIDBF_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         } catch (...) {
@@ -802,7 +911,7 @@ midbf_batch_s* create_batch(int count, const midbf_handle* hs, const void* const
 
 void run_batch(midbf_batch_s* b, hipStream_t st) {
     if (b->exec) MIDBF_HIP(hipGraphLaunch(b->exec, st));
-    else launch_rounds(b, st);
+    else launch_batch(b, st);
 }
 
 }  // namespace
@@ -880,14 +989,41 @@ midbf_status midbf_batch_run(midbf_batch b, void* stream) {
 
 midbf_status midbf_batch_get_stats(midbf_batch b, midbf_batch_stats* out) {
     if (!b || !out) return fail(MIDBF_ERR_ARG, "null argument");
-    out->stages = b->nst;
-    out->rounds = (int)b->round_s0.size();
-    out->items = b->items;
-    out->graph = b->exec != nullptr;
-    out->lds_bytes = (long long)b->smem;
-    out->bytes = b->bytes;
-    out->flops = b->flops;
-    return MIDBF_OK;
+    return guarded([&] {
+        unsigned timeouts = 0;
+        MIDBF_HIP(hipDeviceSynchronize());
+        MIDBF_HIP(hipMemcpy(&timeouts, b->d_ctl + 2, sizeof(unsigned), hipMemcpyDeviceToHost));
+        out->stages = b->nst;
+        out->rounds = b->rounds;
+        out->items = b->items;
+        out->graph = b->exec != nullptr;
+        out->lds_bytes = (long long)b->smem;
+        out->bytes = b->bytes;
+        out->flops = b->flops;
+        out->launches = 1;
+        out->workgroups = b->grid;
+        out->timeouts = (long long)timeouts;
+    });
+}
+
+midbf_status midbf_schedule_simulate(int count, const int* levels, const long long* items, const int* share,
+                                     int workers, int chunk, int limit_ms, unsigned seed, long long* completed,
+                                     long long* stalls) {
+    if (count < 1 || !levels || !items || !completed || !stalls || workers < 1 || chunk < 1 || limit_ms < 1)
+        return fail(MIDBF_ERR_ARG, "bad schedule simulation arguments");
+    return guarded([&] {
+        std::vector<std::vector<long long>> it(count);
+        std::vector<int> sh(count);
+        long long o = 0;
+        for (int j = 0; j < count; ++j) {
+            MIDBF_CHECK(levels[j] >= 0, MIDBF_ERR_ARG, "negative level count");
+            it[j].assign(items + o, items + o + levels[j]);
+            o += levels[j];
+            sh[j] = share ? share[j] : j;
+        }
+        const Schedule S = build_schedule(it, sh, chunk);
+        simulate_schedule(S, workers, limit_ms, seed, *completed, *stalls);
+    });
 }
 
 void midbf_batch_destroy(midbf_batch b) { free_batch(b); }

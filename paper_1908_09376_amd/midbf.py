@@ -164,7 +164,7 @@ def _batch_arrays(handles, fs, outs, precision):
 
 def apply_batched(handles: list[MIDBF], fs: list[torch.Tensor], outs: list[torch.Tensor] | None = None,
                   precision: str = "fp64", stream=None) -> list[torch.Tensor]:
-    """g_j = K_j f_j for independent transforms, one grouped launch per level round (midbf_apply_batched).
+    """g_j = K_j f_j for independent transforms in one persistent launch (midbf_apply_batched).
 
     Synchronizes the stream.
     """
@@ -210,7 +210,9 @@ class ApplyGraph:
 class Batch:
     """A reusable batch g_j = K_j f_j of uneven transforms (midbf_batch_create / _run).
 
-    One grouped launch per level round covers that level of every transform.
+    One persistent launch per run: every level launch of every transform is a
+    stage of one task queue, ordered by level, consumed by the workgroups that
+    fit on the device at once.
     The handles and the tensors fs, outs are referenced by the batch and kept
     alive here; run() enqueues one replay (of the captured hipGraph when
     graph=True) on the stream.
@@ -231,6 +233,7 @@ class Batch:
         return self.outs
 
     def stats(self) -> dict:
+        """Shape of the batch and the count of abandoned dependency waits (synchronizes the device)."""
         s = L.BatchStats()
         L.check(L.lib.midbf_batch_get_stats(self._b, C.byref(s)))
         return {name: getattr(s, name) for name, _ in L.BatchStats._fields_}

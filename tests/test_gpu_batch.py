@@ -1,9 +1,10 @@
-"""Batched uneven transforms, one grouped launch per level round (needs an MI355X).
+"""Batched uneven transforms in one persistent launch (needs an MI355X).
 
-The batch runs the same level-kernel bodies as a single apply, with the
-workgroups of one level of every transform in one launch; every output is
-compared with the transform's own midbf_apply (bitwise where both use the
-same kernels) and with the oracle's FP64 direct sum (eq. 1).
+The batch runs the same level-kernel bodies as a single apply, as tasks of
+one queue taken by persistent workgroups; every output is compared with the
+transform's own midbf_apply (bitwise: the same bodies on the same data) and
+with the oracle's FP64 direct sum (eq. 1), and every run must finish with no
+abandoned dependency wait.
 """
 import numpy as np
 import pytest
@@ -72,6 +73,19 @@ def test_batch_matches_direct_sum(small):
         assert rel_l2(g.cpu().numpy()[:, None], ref) < 1e-5
 
 
+def test_batch_shared_handle_equals_individual_applies(small):
+    """Transforms given one handle (their segments interleaved in the queue) each equal their own apply."""
+    M = _mod()
+    F = small[3]                                   # 128^2, linear phase
+    n = SMALL[3][0]
+    fs = [to_dev(W.complex_gaussian(n * n, 1, 49, j), torch.complex128).reshape(-1) for j in range(5)]
+    extra = _inputs([1] * 6, torch.complex128, 50)[0]
+    outs = M.apply_batched([F] * 5 + [small[0]], fs + [extra], precision="fp64")
+    for c in range(5):
+        assert torch.equal(outs[c], F.apply(fs[c], precision="fp64")), c
+    assert torch.equal(outs[5], small[0].apply(extra, precision="fp64"))
+
+
 def test_batch_graph_replays_follow_inputs(small):
     """Replays of the captured graph, with eager work between them, each equal the eager applies."""
     M = _mod()
@@ -80,6 +94,7 @@ def test_batch_graph_replays_follow_inputs(small):
     st = B.stats()
     assert st["graph"] == 1 and st["stages"] == sum(2 * F.stats()["b"] + 1 for F in small)
     assert st["rounds"] == max(2 * F.stats()["b"] + 1 for F in small)
+    assert st["launches"] == 1 and st["workgroups"] >= 1
     for rep in range(4):
         for f in fs:
             f.mul_(1.5 - 0.25j)          # eager work on the inputs between replays
@@ -89,6 +104,7 @@ def test_batch_graph_replays_follow_inputs(small):
         for F, f, g in zip(small, fs, outs):
             assert torch.equal(g, F.apply(f, precision="fp32")), rep
         torch.cuda.synchronize()
+    assert B.stats()["timeouts"] == 0
     B.close()
 
 
@@ -131,10 +147,13 @@ def test_uneven_batch_of_32_transforms():
     fs_np = [W.batch_rhs(j, int(n)) for j, n in enumerate(ns)]
     fs = [to_dev(f, torch.complex64).reshape(-1) for f in fs_np]
     B = M.Batch(Fs, fs, precision="fp32", graph=True)
-    outs = B.run()
-    torch.cuda.synchronize()
-    for j, (F, f, g) in enumerate(zip(Fs, fs, outs)):
-        assert torch.equal(g, F.apply(f, precision="fp32")), j
+    for rep in range(3):                 # the queue resets itself between runs
+        outs = B.run()
+        torch.cuda.synchronize()
+        for j, (F, f, g) in enumerate(zip(Fs, fs, outs)):
+            assert torch.equal(g, F.apply(f, precision="fp32")), (rep, j)
+    st = B.stats()
+    assert st["timeouts"] == 0 and st["launches"] == 1
     # against the FP64 definition on seeded sampled rows of three transforms (one per size)
     for n in sorted(cache):
         j = int(np.nonzero(ns == n)[0][0])

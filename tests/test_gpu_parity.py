@@ -33,6 +33,32 @@ def from_dev(t) -> np.ndarray:
 
 # ---- kernel entries -------------------------------------------------------
 
+def _entries_reduced_exactly(d, n, phase, rows, cols):
+    """exp(2 pi i Phi) with the bilinear part x . xi = a . (b - n/2) / n reduced mod 1 in Python
+    integers (exact) and only the smooth part (|.| <~ 70 turns here) rounded in FP64."""
+    grid = np.stack(np.meshgrid(*([np.arange(n)] * d), indexing="ij"), -1).reshape(-1, d)
+    a = grid[rows].astype(object)
+    b = (grid[cols] - n // 2).astype(object)
+    lin = np.array([[int(sum(ai * bi for ai, bi in zip(ar, br))) % n for br in b] for ar in a],
+                   dtype=np.float64) / n
+    x = grid[rows].astype(np.float64) / n
+    xi = (grid[cols] - n // 2).astype(np.float64)
+    tp = 2.0 * np.pi
+    if phase == "linear":
+        smooth = np.zeros((len(rows), len(cols)))
+    elif phase == "fio_ellipse":
+        c1 = (2.0 + np.sin(tp * x[:, 0]) * np.sin(tp * x[:, 1])) / 16.0
+        c2 = (2.0 + np.cos(tp * x[:, 0]) * np.cos(tp * x[:, 1])) / 16.0
+        smooth = np.sqrt(c1[:, None] ** 2 * xi[None, :, 0] ** 2 + c2[:, None] ** 2 * xi[None, :, 1] ** 2)
+    elif phase == "fio_piecewise":
+        c = np.where(x[:, 0] < 0.5, (2.0 + np.sin(tp * x[:, 0])) / 16.0, (3.0 + np.cos(tp * x[:, 1])) / 16.0)
+        smooth = c[:, None] * np.linalg.norm(xi, axis=1)[None, :]
+    else:
+        c = (3.0 + np.prod(np.sin(tp * x), axis=1)) / 100.0
+        smooth = c[:, None] * np.linalg.norm(xi, axis=1)[None, :]
+    return np.exp(2j * np.pi * np.mod(lin + smooth, 1.0))
+
+
 @pytest.mark.parametrize("d,n,phase", [(2, 64, "fio_ellipse"), (2, 512, "fio_ellipse"), (2, 256, "fio_piecewise"),
                                        (2, 128, "linear"), (3, 32, "iso3d")])
 def test_kernel_entries_match_oracle(d, n, phase):
@@ -41,9 +67,14 @@ def test_kernel_entries_match_oracle(d, n, phase):
     rows = W.index_sample(N, 300, 31, n)
     cols = W.index_sample(N, 300, 32, n)
     K = M.kernel_entries(d, n, phase, torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV))
+    got = K.cpu().numpy()
     ref = Kernel(d, n, phase).entries(rows, cols)
     # |Phi| <= ~600 here: the oracle's unreduced FP64 phase carries ~2 pi |Phi| eps ~ 1e-12 of rounding
-    assert np.abs(K.cpu().numpy() - ref).max() < 2e-11
+    assert np.abs(got - ref).max() < 2e-11
+    # against the same phase with its bilinear part reduced exactly: only the smooth part's rounding
+    # (~70 eps turns) and the sine / cosine remain on either side
+    exact = _entries_reduced_exactly(d, n, phase, rows, cols)
+    assert np.abs(got - exact).max() < 2e-13
 
 
 def test_kernel_entries_lowrank():
