@@ -97,7 +97,7 @@ typedef struct {
     const double* V_dev; /* MIDBF_PHASE_LOWRANK: N x r row-major FP64 (xi side)         */
     int r;               /* rank of U V^T                                               */
     unsigned precisions; /* MIDBF_KEEP_* bits; 0 = FP64, FP32 and split-bf16            */
-    size_t build_workspace_bytes; /* cap on transient build memory; 0 = 16 GiB          */
+    size_t build_workspace_bytes; /* cap on transient build memory; 0 = 48 GiB          */
 } midbf_params;
 
 typedef struct {
@@ -111,6 +111,11 @@ typedef struct {
     long long bytes_fp16;       /* bytes of the split-fp16 factor copy                 */
     double t_abs_max;           /* largest |Re| or |Im| of an interpolation coefficient
                                    (entry of T) in the 16-bit copies; 0 without them   */
+    double id_ms;               /* HIP-event time of the batched ID launches            */
+    double id_flops;            /* sum over IDs of 8 m n k (m samples, n candidates,
+                                   k rank): the column-pivoted QR's real flops          */
+    double id_bytes;            /* sum over IDs of 16 m n: each complex FP64 sample
+                                   matrix read once                                     */
 } midbf_stats;
 
 /*

@@ -33,7 +33,8 @@ class Stats(C.Structure):
                 ("entries", C.c_longlong), ("bytes_fp64", C.c_longlong), ("bytes_fp32", C.c_longlong),
                 ("bytes_bf16", C.c_longlong), ("index_bytes", C.c_longlong), ("k_min", C.c_int),
                 ("k_max", C.c_int), ("build_seconds", C.c_double), ("bytes_fp16", C.c_longlong),
-                ("t_abs_max", C.c_double)]
+                ("t_abs_max", C.c_double), ("id_ms", C.c_double), ("id_flops", C.c_double),
+                ("id_bytes", C.c_double)]
 
 
 class KernelTime(C.Structure):

@@ -248,10 +248,13 @@ struct Scratch {
     int* perm = nullptr; int* cand = nullptr; int* k = nullptr; int* n = nullptr; long long* toff = nullptr;
     long long* tile_off = nullptr;
     int* samples = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};   // brackets of the ID launches
     long long wave = 0, xs = 0, vs = 0, ys = 0, nmax = 0;
     void release() {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
         f(X); f(V); f(Y); f(perm); f(cand); f(k); f(n); f(toff); f(samples); f(tile_off);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         *this = Scratch();
     }
 };
@@ -315,6 +318,8 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
     sc.tile_off = dalloc<long long>(wave);
     sc.samples = dalloc<int>(m);
     upload(sc.samples, samples, st);
+    for (hipEvent_t& e : sc.ev) MIDBF_HIP(hipEventCreate(&e));
+    hipEvent_t* ev = sc.ev;
 
     bool saturated = false;
     long long yrun = 0;
@@ -334,10 +339,19 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             MIDBF_HIP(hipGetLastError());
             IdBatch ib{sc.X, sc.xs, sc.V, sc.vs, sc.Y, sc.ys, sc.perm, nmax, sc.k, lv.d_n + id0, 0, (int)m,
                        h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side)};
+            MIDBF_HIP(hipEventRecord(ev[0], st));
             launch_id_batch(ib, cnt, st);
+            MIDBF_HIP(hipEventRecord(ev[1], st));
             std::vector<int> kw(cnt);
             MIDBF_HIP(hipMemcpyAsync(kw.data(), sc.k, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
             MIDBF_HIP(hipStreamSynchronize(st));
+            float id_ms = 0.f;
+            MIDBF_HIP(hipEventElapsedTime(&id_ms, ev[0], ev[1]));
+            h->stats.id_ms += id_ms;
+            for (int w = 0; w < cnt; ++w) {
+                h->stats.id_flops += 8.0 * (double)m * lv.n[id0 + w] * kw[w];
+                h->stats.id_bytes += 16.0 * (double)m * lv.n[id0 + w];
+            }
             std::vector<long long> toff(cnt);
             long long tw = 0;
             for (int w = 0; w < cnt; ++w) {
@@ -631,7 +645,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
     midbf_plan* h = new midbf_plan();
     try {
         h->p = p;
-        if (h->p.build_workspace_bytes == 0) h->p.build_workspace_bytes = (size_t)16 << 30;
+        if (h->p.build_workspace_bytes == 0) h->p.build_workspace_bytes = (size_t)48 << 30;
         h->keep = p.precisions ? p.precisions : (MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16);
         MIDBF_CHECK((h->keep & ~(MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) == 0,
                     MIDBF_ERR_ARG, "unknown precision bits");

@@ -6,6 +6,7 @@
 namespace midbf {
 
 constexpr int ID_THREADS = 256;   // one workgroup per decomposition
+constexpr int ID_WAVES_PER_SIMD = 4;   // occupancy target: four decompositions per CU hide each other's latency
 constexpr int ID_NB = 16;         // pivots per panel
 constexpr int ID_ELL = 24;        // sketch rows (panel width + 8 oversampling)
 constexpr int ID_NMAX = 2048;     // largest candidate count

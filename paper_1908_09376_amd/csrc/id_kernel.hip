@@ -28,7 +28,8 @@ constexpr int NT = ID_THREADS;
 constexpr int NW = NT / 64;
 constexpr int NB = ID_NB;
 constexpr int ELL = ID_ELL;
-constexpr int CHUNK = 64;
+constexpr int CHUNK = 32;       // rows of V (or of the sketch weights) staged in LDS at a time
+constexpr int U = 4;            // rows loaded together per thread (memory-level parallelism)
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -125,7 +126,7 @@ __device__ inline void householder(double2 alpha, double xnorm2, double& beta, d
 
 }  // namespace
 
-__global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
+__global__ __launch_bounds__(NT, ID_WAVES_PER_SIMD) void id_kernel(IdBatch B) {
     const int bid = blockIdx.x;
     const int tid = threadIdx.x;
     const int m = B.m;
@@ -135,9 +136,11 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
     double2* Y = B.Yw + (long long)bid * B.y_stride;
     int* perm = B.perm + (long long)bid * B.p_stride;
 
-    __shared__ double s_ynrm[ID_NMAX];
+    __shared__ float s_ynrm[ID_NMAX];      // sketch column norms: they only choose pivots
     __shared__ double2 s_stage[CHUNK * NB];
     __shared__ double2 s_T[NB * NB];
+    __shared__ double2 s_R11[NB * NB];     // R11 of the panel just factored (upper triangle)
+    __shared__ double2 s_S11[NB * NB];     // R11 of the sketch's own QR for the same pivots (upper triangle)
     __shared__ double2 s_red2[NW * 2 * NB];
     __shared__ double2 s_vec[2 * NB];
     __shared__ double2 s_v[ELL];
@@ -152,13 +155,58 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
         return;
     }
 
-    // column numbering and the reference norm (largest column norm)
+    // (0) sketch Y = Omega X (ELL x n) and the reference norm (largest column norm); the sketch
+    //     rows are formed in two halves (two reads of X, few live accumulators), rows of X are read
+    //     U at a time (in-range addresses, padding rows weighted by zero)
+    constexpr int EH = ELL / 2;
     double cmax = 0.0;
-    for (int c = tid; c < n; c += NT) {
-        perm[c] = c;
-        double acc = 0.0;
-        for (int i = 0; i < m; ++i) acc += cabs2(X[(long long)i * n + c]);
-        cmax = fmax(cmax, acc);
+    for (int c0 = 0; c0 < n; c0 += NT) {
+        const int c = c0 + tid;
+        const bool act = c < n;
+        const int cc = act ? c : n - 1;
+        double yn = 0.0;
+        for (int h = 0; h < 2; ++h) {
+            double2 acc[EH];
+#pragma unroll
+            for (int q = 0; q < EH; ++q) acc[q] = make_double2(0.0, 0.0);
+            double nrm = 0.0;
+            for (int i0 = 0; i0 < m; i0 += CHUNK) {
+                const int rows = min(CHUNK, m - i0);
+                __syncthreads();
+                for (int e = tid; e < EH * CHUNK; e += NT) {
+                    int q = e / CHUNK, ii = e - q * CHUNK;
+                    s_om[e] = (ii < rows) ? omega(B.seed, 0, h * EH + q, i0 + ii) : 0.0;
+                }
+                __syncthreads();
+                for (int ii = 0; ii < rows; ii += U) {
+                    double2 x[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) x[u] = X[(long long)(i0 + min(ii + u, rows - 1)) * n + cc];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        nrm += (ii + u < rows) ? cabs2(x[u]) : 0.0;
+#pragma unroll
+                        for (int q = 0; q < EH; ++q) {
+                            const double w = s_om[q * CHUNK + ii + u];
+                            acc[q].x = fma(w, x[u].x, acc[q].x);
+                            acc[q].y = fma(w, x[u].y, acc[q].y);
+                        }
+                    }
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < EH; ++q) {
+                    Y[(long long)(h * EH + q) * n + c] = acc[q];
+                    yn += cabs2(acc[q]);
+                }
+                if (h == 0) {
+                    perm[c] = c;
+                    cmax = fmax(cmax, nrm);
+                }
+            }
+        }
+        if (act) s_ynrm[c] = (float)yn;
     }
     const double ref2 = block_max(cmax, s_red);
     if (ref2 == 0.0) {
@@ -168,56 +216,17 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
     const double thresh2 = B.tol * B.tol * ref2;
     const int mn = min(m, n);
 
-    int k = -1, j0 = 0, panel = 0;
+    int k = -1, j0 = 0;
     while (k < 0 && j0 < mn) {
         const int nbp = min(NB, mn - j0);
 
-        // (1) sketch Y = Omega X[j0:m, j0:n]
-        for (int c0 = j0; c0 < n; c0 += NT) {
-            const int c = c0 + tid;
-            const bool act = c < n;
-            double2 acc[ELL];
-#pragma unroll
-            for (int q = 0; q < ELL; ++q) acc[q] = make_double2(0.0, 0.0);
-            for (int i0 = j0; i0 < m; i0 += CHUNK) {
-                const int rows = min(CHUNK, m - i0);
-                __syncthreads();
-                for (int e = tid; e < ELL * CHUNK; e += NT) {
-                    int q = e / CHUNK, ii = e - q * CHUNK;
-                    s_om[e] = (ii < rows) ? omega(B.seed, panel, q, i0 + ii) : 0.0;
-                }
-                __syncthreads();
-                if (act) {
-                    for (int ii = 0; ii < rows; ++ii) {
-                        double2 x = X[(long long)(i0 + ii) * n + c];
-#pragma unroll
-                        for (int q = 0; q < ELL; ++q) {
-                            double w = s_om[q * CHUNK + ii];
-                            acc[q].x = fma(w, x.x, acc[q].x);
-                            acc[q].y = fma(w, x.y, acc[q].y);
-                        }
-                    }
-                }
-            }
-            if (act) {
-                double yn = 0.0;
-#pragma unroll
-                for (int q = 0; q < ELL; ++q) {
-                    Y[(long long)q * n + c] = acc[q];
-                    yn += cabs2(acc[q]);
-                }
-                s_ynrm[c] = yn;
-            }
-        }
-        __syncthreads();
-
-        // (2) classical pivoted QR of the sketch: choose nbp pivots
+        // (1) classical pivoted QR of the sketch of the trailing columns: choose nbp pivots
         for (int jj = 0; jj < nbp; ++jj) {
             const int col = j0 + jj;
             double bv = -1.0;
-            int bi = n;
+            int bi = col;                   // a valid column whatever the norms hold
             for (int c = col + tid; c < n; c += NT) {
-                double v = s_ynrm[c];
+                double v = (double)s_ynrm[c];
                 if (v > bv) { bv = v; bi = c; }
             }
             const int p = block_argmax(bv, bi, s_red, s_redi);
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
                     Y[(long long)tid * n + col] = Y[(long long)tid * n + p];
                     Y[(long long)tid * n + p] = t;
                 }
-                if (tid == 0) { double t = s_ynrm[col]; s_ynrm[col] = s_ynrm[p]; s_ynrm[p] = t; }
+                if (tid == 0) { float t = s_ynrm[col]; s_ynrm[col] = s_ynrm[p]; s_ynrm[p] = t; }
             }
             __syncthreads();
             if (tid < 64) {
@@ -241,25 +250,33 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
                 householder(alpha, xs, beta, tau, scal);
                 if (q < ELL) s_v[q] = (q < jj) ? make_double2(0.0, 0.0) : (q == jj ? make_double2(1.0, 0.0) : cmul(yq, scal));
                 if (q == 0) s_tau = tau;
+                if (q == jj) Y[(long long)q * n + col] = make_double2(beta, 0.0);
             }
             __syncthreads();
             const double2 ctau = cconj(s_tau);
             for (int c = col + 1 + tid; c < n; c += NT) {
                 double2 w = make_double2(0.0, 0.0);
+#pragma unroll 4
                 for (int q = jj; q < ELL; ++q) cfmac(w, s_v[q], Y[(long long)q * n + c]);
                 const double2 cw = cmul(ctau, w);
                 double yn = 0.0;
+#pragma unroll 4
                 for (int q = jj; q < ELL; ++q) {
-                    double2 y = csub(Y[(long long)q * n + c], cmul(s_v[q], cw));
+                    const double2 y = csub(Y[(long long)q * n + c], cmul(s_v[q], cw));
                     Y[(long long)q * n + c] = y;
                     if (q > jj) yn += cabs2(y);
                 }
-                s_ynrm[c] = yn;
+                s_ynrm[c] = (float)yn;
             }
             __syncthreads();
         }
+        // the sketch's R11 for these pivots
+        for (int e = tid; e < NB * NB; e += NT) {
+            const int q = e / NB, jj = e - q * NB;
+            s_S11[e] = (q <= jj && jj < nbp) ? Y[(long long)q * n + j0 + jj] : make_double2(0.0, 0.0);
+        }
 
-        // (3) move the chosen columns to the front of the trailing block
+        // (2) move the chosen columns to the front of the trailing block
         for (int i = tid; i < m; i += NT) {
             double2* row = X + (long long)i * n;
             for (int jj = 0; jj < nbp; ++jj) {
@@ -275,7 +292,7 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
         }
         __syncthreads();
 
-        // (4) unpivoted Householder QR of the panel X[j0:m, j0:j0+nbp]
+        // (3) unpivoted Householder QR of the panel X[j0:m, j0:j0+nbp]
         for (int jj = 0; jj < nbp; ++jj) {
             const int col = j0 + jj;
             double xs = 0.0;
@@ -303,29 +320,37 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
                 V[(long long)i * NB + jj] = v;
             }
             __syncthreads();
-            // w_c = v^H X[:, c] for the panel columns right of col, z_q = V[:, q]^H v for q < jj
+            // w_c = v^H X[:, c] for the panel columns right of col, z_q = V[:, q]^H v for q < jj:
+            // thread (g, o) sums output o over the rows col + g + 8 r (one accumulator per thread)
             const int ncw = j0 + nbp - col - 1;
-            double2 part[2 * NB];
+            {
+                const int o = tid & (2 * NB - 1), g = tid >> 5;
+                const bool wcol = o < NB;
+                const bool useful = wcol ? (o < ncw) : (o - NB < jj);
+                const long long off = wcol ? (long long)(col + 1 + o) : (long long)(o - NB);
+                constexpr int RS = NT / (2 * NB);
+                double2 acc = make_double2(0.0, 0.0);
+                if (useful) {       // every address below is in range: o < ncw, or o - NB < jj
+                    for (int i0 = col + g; i0 < m; i0 += 4 * RS) {
+                        double2 vv[4], xx[4];
 #pragma unroll
-            for (int q = 0; q < 2 * NB; ++q) part[q] = make_double2(0.0, 0.0);
-            for (int i = col + tid; i < m; i += NT) {
-                const double2 v = V[(long long)i * NB + jj];
-                const double2* row = X + (long long)i * n + col + 1;
+                        for (int u = 0; u < 4; ++u) {
+                            const int i = min(i0 + u * RS, m - 1);
+                            vv[u] = V[(long long)i * NB + jj];
+                            xx[u] = wcol ? X[(long long)i * n + off] : V[(long long)i * NB + off];
+                        }
 #pragma unroll
-                for (int cc = 0; cc < NB; ++cc)
-                    if (cc < ncw) cfmac(part[cc], v, row[cc]);
-#pragma unroll
-                for (int q = 0; q < NB; ++q)
-                    if (q < jj) cfmac(part[NB + q], V[(long long)i * NB + q], v);
-            }
-#pragma unroll
-            for (int q = 0; q < 2 * NB; ++q) {
-                part[q].x = wave_sum(part[q].x);
-                part[q].y = wave_sum(part[q].y);
-            }
-            if ((tid & 63) == 0) {
-#pragma unroll
-                for (int q = 0; q < 2 * NB; ++q) s_red2[(tid >> 6) * 2 * NB + q] = part[q];
+                        for (int u = 0; u < 4; ++u) {
+                            if (i0 + u * RS < m) {
+                                if (wcol) cfmac(acc, vv[u], xx[u]);
+                                else cfmac(acc, xx[u], vv[u]);
+                            }
+                        }
+                    }
+                }
+                acc.x += __shfl_xor(acc.x, 2 * NB, 64);
+                acc.y += __shfl_xor(acc.y, 2 * NB, 64);
+                if ((tid & 63) < 2 * NB) s_red2[(tid >> 6) * 2 * NB + o] = acc;
             }
             __syncthreads();
             if (tid < 2 * NB) {
@@ -334,31 +359,51 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
                 s_vec[tid] = t;
             }
             __syncthreads();
-            if (tid == 0) {
+            if (tid < NB) {            // column jj of T: thread q computes entry q
+                const int q = tid;
                 const double2 tau = s_tau;
-                for (int q = 0; q < jj; ++q) {
-                    double2 t = make_double2(0.0, 0.0);
-                    for (int l = q; l < jj; ++l) cfma(t, s_T[q * NB + l], s_vec[NB + l]);
-                    s_T[q * NB + jj] = cmul(make_double2(-tau.x, -tau.y), t);
-                }
-                for (int q = jj + 1; q < NB; ++q) s_T[q * NB + jj] = make_double2(0.0, 0.0);
-                s_T[jj * NB + jj] = tau;
+                double2 t = make_double2(0.0, 0.0);
+                for (int l = q; l < jj; ++l) cfma(t, s_T[q * NB + l], s_vec[NB + l]);
+                s_T[q * NB + jj] = q < jj ? cmul(make_double2(-tau.x, -tau.y), t)
+                                          : (q == jj ? tau : make_double2(0.0, 0.0));
             }
             const double2 ctau = cconj(s_tau);
-            for (int i = col + tid; i < m; i += NT) {
-                const double2 v = V[(long long)i * NB + jj];
-                double2* row = X + (long long)i * n + col + 1;
-                for (int cc = 0; cc < ncw; ++cc) row[cc] = csub(row[cc], cmul(v, cmul(ctau, s_vec[cc])));
+            if (ncw > 0) {
+                // thread (column, row) pairs, four rows per thread loaded together
+                const int cc = tid % NB;
+                const double2 coef = cmul(ctau, s_vec[min(cc, ncw - 1)]);
+                const int total = m - col;
+                for (int r0 = tid / NB; r0 < total; r0 += 4 * (NT / NB)) {
+                    double2 xv[4], vv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = col + min(r0 + u * (NT / NB), total - 1);
+                        xv[u] = X[(long long)i * n + col + 1 + min(cc, ncw - 1)];
+                        vv[u] = V[(long long)i * NB + jj];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (cc < ncw && r0 + u * (NT / NB) < total)
+                            X[(long long)(col + r0 + u * (NT / NB)) * n + col + 1 + cc] = csub(xv[u], cmul(vv[u], coef));
+                }
             }
             __syncthreads();
         }
+        // the panel's R11
+        for (int e = tid; e < NB * NB; e += NT) {
+            const int u = e / NB, v = e - u * NB;
+            s_R11[e] = (u <= v && v < nbp) ? X[(long long)(j0 + u) * n + j0 + v] : make_double2(0.0, 0.0);
+        }
 
-        // (5) trailing update X[j0:m, j0+nbp:n] <- (I - V T V^H)^H X, exact residual norms,
-        //     and the first pivot count of this panel that satisfies the rank rule
+        // (4) trailing update X[j0:m, j0+nbp:n] <- (I - V T V^H)^H X with exact residual norms, the
+        //     first pivot count of this panel that satisfies the rank rule, and the sketch of the new
+        //     trailing block from the old one: [S12 - S11 R11^{-1} R12; S22] (Duersch and Gu's update),
+        //     so no pass over X is spent on sketching after the first panel
         int fmax = 0;
         for (int c0 = j0 + nbp; c0 < n; c0 += NT) {
             const int c = c0 + tid;
             const bool act = c < n;
+            const int cc = act ? c : n - 1;
             double2 W[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) W[q] = make_double2(0.0, 0.0);
@@ -370,25 +415,24 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
                     s_stage[e] = (ii < rows && q < nbp) ? V[(long long)(i0 + ii) * NB + q] : make_double2(0.0, 0.0);
                 }
                 __syncthreads();
-                if (act) {
-                    for (int ii = 0; ii < rows; ++ii) {
-                        const double2 x = X[(long long)(i0 + ii) * n + c];
+                for (int ii = 0; ii < rows; ii += U) {
+                    double2 x[U];
 #pragma unroll
-                        for (int q = 0; q < NB; ++q) cfmac(W[q], s_stage[ii * NB + q], x);
-                    }
+                    for (int u = 0; u < U; ++u) x[u] = X[(long long)(i0 + min(ii + u, rows - 1)) * n + cc];
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int q = 0; q < NB; ++q) cfmac(W[q], s_stage[(ii + u) * NB + q], x[u]);
                 }
             }
-            double2 W2[NB];
+            // W <- T^H W in place (row q needs rows l <= q, so go from the last row up)
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
+            for (int q = NB - 1; q >= 0; --q) {
                 double2 t = make_double2(0.0, 0.0);
 #pragma unroll
                 for (int l = 0; l <= q; ++l) cfmac(t, s_T[l * NB + q], W[l]);
-                W2[q] = t;
+                W[q] = t;
             }
-            double r2[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) r2[q] = 0.0;
             double nn = 0.0;
             for (int i0 = j0; i0 < m; i0 += CHUNK) {
                 const int rows = min(CHUNK, m - i0);
@@ -398,32 +442,27 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
                     s_stage[e] = (ii < rows && q < nbp) ? V[(long long)(i0 + ii) * NB + q] : make_double2(0.0, 0.0);
                 }
                 __syncthreads();
-                if (act) {
-                    int ii = 0;
-                    if (i0 == j0) {
+                // rows j0 .. j0+nbp become R12 and stay out of the residual norm
+                const int skip = i0 == j0 ? nbp : 0;
+                for (int ii = 0; ii < rows; ii += U) {
+                    double2 x[U];
 #pragma unroll
-                        for (int u = 0; u < NB; ++u) {
-                            if (u < rows) {
-                                double2* px = X + (long long)(i0 + u) * n + c;
-                                double2 x = *px;
+                    for (int u = 0; u < U; ++u) x[u] = X[(long long)(i0 + min(ii + u, rows - 1)) * n + cc];
 #pragma unroll
-                                for (int q = 0; q < NB; ++q) x = csub(x, cmul(s_stage[u * NB + q], W2[q]));
-                                *px = x;
-                                if (u < nbp) r2[u] = cabs2(x); else nn += cabs2(x);
-                            }
+                    for (int u = 0; u < U; ++u) {
+#pragma unroll
+                        for (int q = 0; q < NB; ++q) x[u] = csub(x[u], cmul(s_stage[(ii + u) * NB + q], W[q]));
+                        if (act && ii + u < rows) {
+                            X[(long long)(i0 + ii + u) * n + c] = x[u];
+                            if (ii + u >= skip) nn += cabs2(x[u]);
                         }
-                        ii = NB;
-                    }
-                    for (; ii < rows; ++ii) {
-                        double2* px = X + (long long)(i0 + ii) * n + c;
-                        double2 x = *px;
-#pragma unroll
-                        for (int q = 0; q < NB; ++q) x = csub(x, cmul(s_stage[ii * NB + q], W2[q]));
-                        *px = x;
-                        nn += cabs2(x);
                     }
                 }
             }
+            double2 r12[NB];        // R12 of this column (rows j0 .. j0+nbp, written above by this thread)
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                r12[u] = (act && u < nbp) ? X[(long long)(j0 + u) * n + c] : make_double2(0.0, 0.0);
             if (act) {
                 double res = nn;
                 int f = nbp;
@@ -431,10 +470,35 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
                 for (int jj = NB - 1; jj >= 0; --jj) {
                     if (jj < nbp) {
                         if (res <= thresh2) f = jj; else break;
-                        res += r2[jj];
+                        res += cabs2(r12[jj]);
                     }
                 }
                 fmax = max(fmax, f);
+                // z = R11^{-1} R12 (in r12), then the sketch rows 0..nbp of this column lose S11 z
+#pragma unroll
+                for (int u = NB - 1; u >= 0; --u) {
+                    if (u < nbp) {
+                        double2 t = r12[u];
+#pragma unroll
+                        for (int v = u + 1; v < NB; ++v)
+                            if (v < nbp) t = csub(t, cmul(s_R11[u * NB + v], r12[v]));
+                        const double d = s_R11[u * NB + u].x;
+                        r12[u] = d != 0.0 ? make_double2(t.x / d, t.y / d) : make_double2(0.0, 0.0);
+                    }
+                }
+                double yn = 0.0;
+#pragma unroll
+                for (int q = 0; q < ELL; ++q) {
+                    double2 y = Y[(long long)q * n + c];
+                    if (q < nbp) {
+#pragma unroll
+                        for (int u = 0; u < NB; ++u)
+                            if (u >= q && u < nbp) y = csub(y, cmul(s_S11[q * NB + u], r12[u]));
+                        Y[(long long)q * n + c] = y;
+                    }
+                    yn += cabs2(y);
+                }
+                s_ynrm[c] = (float)yn;
             }
         }
         // panel columns: column j0+cc is excluded once cc pivots are taken
@@ -451,13 +515,12 @@ __global__ __launch_bounds__(NT) void id_kernel(IdBatch B) {
         const int F = block_max_int(fmax, s_redi);
         if (F < nbp) k = j0 + F + 1;
         j0 += nbp;
-        ++panel;
     }
     if (k < 0) k = mn;
     if (B.kcap > 0 && k > B.kcap) k = B.kcap;
     __syncthreads();
 
-    // (6) T = R11^{-1} R12 in place over X[0:k, k:n] (back substitution, one column per thread)
+    // (5) T = R11^{-1} R12 in place over X[0:k, k:n] (back substitution, one column per thread)
     for (int c0 = k; c0 < n; c0 += NT) {
         const int c = c0 + tid;
         const bool act = c < n;
