@@ -98,6 +98,10 @@ typedef struct {
     int r;               /* rank of U V^T                                               */
     unsigned precisions; /* MIDBF_KEEP_* bits; 0 = FP64, FP32 and split-bf16            */
     size_t build_workspace_bytes; /* cap on transient build memory; 0 = 48 GiB          */
+    int fixed_rank;      /* > 0: the fixed-rank variant (Sec. 3.5, closing paragraph):
+                            every ID keeps min(fixed_rank, samples, candidates) columns
+                            whatever tol says, so each level's ranks are known before
+                            the build; 0: the adaptive rank rule with tol                */
 } midbf_params;
 
 typedef struct {

@@ -15,7 +15,7 @@ Follows Section 3 of the paper:
     rows of S^{L-s+1} restricted to the block).  The column side is
     symmetric.  The middle factor S is K restricted to the last skeletons.
 
-Readings (listed in the design doc): b = ceil(L/2) steps (odd L allowed); the
+Readings of the paper taken here: b = ceil(L/2) steps (odd L allowed); the
 sample pool of an ID is the paired box's lattice points; rank k = number of
 pivots with |R_jj| > tol |R_11|; if the samples limit the rank, the sample
 count is doubled and the ID redone.
@@ -113,9 +113,11 @@ class ID:
         return self.cand[self.piv[:self.k]]
 
 
-def column_id(X: np.ndarray, tol: float, kcap: int | None = None):
+def column_id(X: np.ndarray, tol: float, kcap: int | None = None, rank: int | None = None):
     """CPQR X[:, piv] = Q R; k = #{j : |R_jj| > tol |R_11|}; T = R11^{-1} R12.
 
+    rank: the fixed-rank form the paper starts from (Sec. 3.5, closing paragraph):
+    k = min(rank, m, n) whatever tol says.
     Returns (k, piv, T, |diag R|).  Pinned by the CPQR residual bound
     ||X - X[:,skel][I T]Pi^T||_F = ||R22||_F <= sqrt(n-k) |R_{k+1,k+1}| and
     by the dense brute-force tests.
@@ -123,7 +125,9 @@ def column_id(X: np.ndarray, tol: float, kcap: int | None = None):
     R, piv = sla.qr(X, mode="r", pivoting=True)
     m, n = X.shape
     diag = np.abs(np.diag(R))
-    if diag.size == 0 or diag[0] == 0.0:
+    if rank is not None:
+        k = min(rank, m, n)
+    elif diag.size == 0 or diag[0] == 0.0:
         k = 0
     else:
         small = np.nonzero(diag <= tol * diag[0])[0]
@@ -143,8 +147,8 @@ class MIDBF:
     """
 
     def __init__(self, K: Kernel, tol: float = 1e-6, leaf_box: int = 8, t: int = 5,
-                 kcap: int | None = None):
-        self.K, self.tol, self.t, self.kcap = K, tol, t, kcap
+                 kcap: int | None = None, rank: int | None = None):
+        self.K, self.tol, self.t, self.kcap, self.rank = K, tol, t, kcap, rank
         self.tree = Tree(K.d, K.n, leaf_box)
         tr = self.tree
         self.L, self.P = tr.L, tr.P
@@ -187,7 +191,7 @@ class MIDBF:
                         X = K.entries(cand, smp).T
                     else:                      # columns of K(:, cand) -> CPQR of K(smp, cand)
                         X = K.entries(smp, cand)
-                    k, piv, T, diag = column_id(X, self.tol, self.kcap)
+                    k, piv, T, diag = column_id(X, self.tol, self.kcap, self.rank)
                     box_pts = (tr.n >> lb) ** tr.d
                     if k >= X.shape[0] and X.shape[0] < min(box_pts, len(cand)):
                         want *= 2              # rank limited by the samples: enlarge (Sec. 3.2)

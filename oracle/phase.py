@@ -9,7 +9,7 @@ Section 2 of the paper, in its order:
   * Partition2 (Sec. 2.3.4, Fig. 5) and Alg. 6 RecoveryMatrix2;
   * Alg. 7   LowRankFactorization (Sec. 2.3.5).
 
-Readings (listed in the design doc): the phase representative is
+Readings of the paper taken here: the phase representative is
 u = angle(K)/(2 pi) in (-1/2, 1/2]; round is half-away-from-zero; D starts
 with the path root; on lattices the recovery path is the dimension-ordered
 comb tree (an MST of axis edges, BFS order = Manhattan distance from the

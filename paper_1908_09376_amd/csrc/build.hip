@@ -338,7 +338,7 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             hipLaunchKernelGGL(gen_kernel, dim3(gx, cnt), dim3(BT), 0, st, ga);
             MIDBF_HIP(hipGetLastError());
             IdBatch ib{sc.X, sc.xs, sc.V, sc.vs, sc.Y, sc.ys, sc.perm, nmax, sc.k, lv.d_n + id0, 0, (int)m,
-                       h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side)};
+                       h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side), h->p.fixed_rank};
             MIDBF_HIP(hipEventRecord(ev[0], st));
             launch_id_batch(ib, cnt, st);
             MIDBF_HIP(hipEventRecord(ev[1], st));
@@ -635,6 +635,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
     MIDBF_CHECK(p.n % 2 == 0, MIDBF_ERR_SHAPE, "n must be even");
     MIDBF_CHECK(p.tol > 0.0 && p.tol < 1.0, MIDBF_ERR_ARG, "tol must be in (0, 1)");
     MIDBF_CHECK(p.oversample_t >= 1, MIDBF_ERR_ARG, "oversample_t must be >= 1");
+    MIDBF_CHECK(p.fixed_rank >= 0, MIDBF_ERR_ARG, "fixed_rank must be >= 0");
     if (p.phase == MIDBF_PHASE_LOWRANK)
         MIDBF_CHECK(p.U_dev && p.V_dev && p.r >= 1, MIDBF_ERR_ARG, "low-rank phase needs U, V and r");
     if (p.phase == MIDBF_PHASE_FIO_ELLIPSE || p.phase == MIDBF_PHASE_FIO_PIECEWISE)

@@ -28,6 +28,7 @@ struct IdBatch {
     double tol;
     int kcap;            // 0: none
     unsigned seed;
+    int kfixed;          // > 0: keep exactly min(kfixed, m, n) pivots (the rank rule is not used)
 };
 
 void launch_id_batch(const IdBatch& B, int batch, hipStream_t s);

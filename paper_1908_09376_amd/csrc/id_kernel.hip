@@ -214,11 +214,13 @@ __global__ __launch_bounds__(NT, ID_WAVES_PER_SIMD) void id_kernel(IdBatch B) {
         return;
     }
     const double thresh2 = B.tol * B.tol * ref2;
+    // the fixed-rank variant factors exactly kstop pivots; the adaptive one stops by the rank rule
     const int mn = min(m, n);
+    const int kstop = B.kfixed > 0 ? min(B.kfixed, mn) : mn;
 
     int k = -1, j0 = 0;
-    while (k < 0 && j0 < mn) {
-        const int nbp = min(NB, mn - j0);
+    while (k < 0 && j0 < kstop) {
+        const int nbp = min(NB, kstop - j0);
 
         // (1) classical pivoted QR of the sketch of the trailing columns: choose nbp pivots
         for (int jj = 0; jj < nbp; ++jj) {
@@ -513,10 +515,10 @@ __global__ __launch_bounds__(NT, ID_WAVES_PER_SIMD) void id_kernel(IdBatch B) {
             fmax = max(fmax, f);
         }
         const int F = block_max_int(fmax, s_redi);
-        if (F < nbp) k = j0 + F + 1;
+        if (B.kfixed <= 0 && F < nbp) k = j0 + F + 1;
         j0 += nbp;
     }
-    if (k < 0) k = mn;
+    if (k < 0) k = kstop;
     if (B.kcap > 0 && k > B.kcap) k = B.kcap;
     __syncthreads();
 

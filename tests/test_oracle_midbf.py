@@ -132,3 +132,36 @@ def test_three_dimensional_lattice():
     f = W.complex_gaussian(K.N, 1, 15)
     rows = W.sample_rows(K.N, 3, 128)
     assert rel_l2(F.apply(f)[rows], direct_sum(K, f, rows=rows)) < 1e-5
+
+
+# ---- the fixed-rank variant (Sec. 3.5, closing paragraph) ---------------------
+
+def test_fixed_rank_keeps_the_given_rank_everywhere():
+    # every ID keeps min(rank, samples, candidates) columns: n0 = 64 leaf candidates, then 4 * rank
+    K = Kernel(2, 64, "fio_ellipse")
+    F = MIDBF(K, rank=20)
+    for side in F.rank_table().values():
+        for lev in side:
+            assert set(lev) == {20}
+    # the stored T blocks follow from the ranks alone: 4 * 20 candidates, 20 kept, at every ID of step 1;
+    # 64 candidates at step 0
+    nid = 4 ** (F.L + 1)
+    t_entries = 2 * nid * (20 * (64 - 20) + 20 * (80 - 20))
+    assert F.entry_count() - sum(S.size for S in F.mid.values()) == t_entries
+
+
+def test_fixed_rank_full_rank_is_exact():
+    # at 32^2 a rank of 64 keeps every leaf point: the factorization reproduces K
+    K = Kernel(2, 32, "fio_ellipse")
+    F = MIDBF(K, rank=64)
+    assert rel_l2(F.dense(), K.dense()) < 1e-13
+
+
+def test_fixed_rank_error_falls_with_the_rank():
+    # 32^2 (one MSCS step, 64 leaf candidates): the error against the direct sum falls with the rank
+    K = Kernel(2, 32, "fio_ellipse")
+    f = W.complex_gaussian(K.N, 1, 16)
+    gd = direct_sum(K, f)
+    errs = [rel_l2(MIDBF(K, rank=r).apply(f), gd) for r in (24, 40, 56)]
+    assert errs[0] > errs[1] > errs[2] > 0.0
+    assert errs[2] < 1e-2

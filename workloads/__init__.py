@@ -6,7 +6,8 @@ Both the CPU oracle and the HIP path receive exactly these arrays.
 
 Workloads follow the shapes of the paper's Example 1 (Section 4, the 2-D
 generalized Radon transform) on integer frequency grids, plus a 3-D lattice
-and a piecewise-smooth 2-D phase (see the design doc for the recipe).
+and a piecewise-smooth 2-D phase.  Inputs are complex Gaussian with real parts drawn
+before imaginary parts from numpy's default_rng seeded by [9376, workload, j].
 """
 from __future__ import annotations
 
