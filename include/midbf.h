@@ -46,7 +46,8 @@ typedef enum {
     MIDBF_ERR_RANK_SATURATED = -4,  /* an ID kept as many pivots as samples        */
     MIDBF_ERR_RECOVERY = -5,        /* phase recovery failed (tau schedule ran out) */
     MIDBF_ERR_HIP = -6,             /* a HIP runtime call failed                   */
-    MIDBF_ERR_UNIMPLEMENTED = -7
+    MIDBF_ERR_UNIMPLEMENTED = -7,
+    MIDBF_ERR_IO = -8          /* a factor file could not be written or read, or is not one */
 } midbf_status;
 
 /* Phase functions (Scenario 1 of Table 1: O(1) entry access). */
@@ -134,6 +135,32 @@ typedef struct {
  * doubling the samples could not lift a saturated ID, _HIP.
  */
 midbf_status midbf_build(const midbf_params* p, void* stream, midbf_handle* out);
+
+/*
+ * midbf_save -- write the factorization to `path` so that a later run skips the build
+ * (the build costs far more than an apply: T_fac against T_app in Table 2).  The file holds
+ * the parameters, for the low-rank phase U and V, and per step and side the sample count,
+ * the candidate count, rank and pivot order of every decomposition and its FP64 T block
+ * (Sec. 3.2: V = [I T] Pi^T); the middle factor and every other precision are derived from
+ * these on loading.  Needs the FP64 copy (MIDBF_KEEP_FP64).  Synchronizes `stream`.
+ * Little-endian binary; not portable across format versions (the magic carries the version).
+ * Errors: MIDBF_ERR_ARG (null argument, no FP64 copy), MIDBF_ERR_IO (cannot write), _HIP.
+ */
+midbf_status midbf_save(midbf_handle h, const char* path, void* stream);
+
+/*
+ * midbf_load -- rebuild a factorization from a file written by midbf_save, keeping the
+ * `precisions` copies (MIDBF_KEEP_* bits, 0 = the midbf_build default).  The decompositions
+ * are read instead of computed; the packing, the middle factor and the split tiles are made
+ * as in midbf_build, so every apply equals the saved handle's bit for bit.  params_out
+ * (may be null) receives the parameters (U_dev, V_dev then point at the handle's own copies).
+ * The whole header is checked before the device is touched, and every record before it is
+ * used (counts, ranks, pivot orders are permutations).
+ * Errors: MIDBF_ERR_IO (cannot open, not a factor file, truncated or inconsistent), the
+ * midbf_build errors.
+ */
+midbf_status midbf_load(const char* path, unsigned precisions, void* stream, midbf_params* params_out,
+                        midbf_handle* out);
 
 /*
  * midbf_apply -- g = K~ f for nrhs right-hand sides (the factor product of

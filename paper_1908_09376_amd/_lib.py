@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmidbf.so")
 
 MIDBF_OK = 0
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_OOM", -4: "ERR_RANK_SATURATED",
-          -5: "ERR_RECOVERY", -6: "ERR_HIP", -7: "ERR_UNIMPLEMENTED"}
+          -5: "ERR_RECOVERY", -6: "ERR_HIP", -7: "ERR_UNIMPLEMENTED", -8: "ERR_IO"}
 
 PHASES = {"linear": 0, "fio_ellipse": 1, "fio_piecewise": 2, "iso3d": 3, "lowrank": 4}
 FP64, FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2, 3
@@ -74,6 +74,8 @@ def _load():
     vp, i, ll = C.c_void_p, C.c_int, C.c_longlong
     sig = {
         "midbf_build": (i, [C.POINTER(Params), vp, C.POINTER(vp)]),
+        "midbf_save": (i, [vp, C.c_char_p, vp]),
+        "midbf_load": (i, [C.c_char_p, C.c_uint, vp, C.POINTER(Params), C.POINTER(vp)]),
         "midbf_apply": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_adjoint": (i, [vp, vp, vp, i, ll, i, vp]),
         "midbf_apply_noalloc": (i, [vp, vp, vp, i, ll, i, vp]),
@@ -116,7 +118,7 @@ def check(status: int) -> None:
         raise MidbfError(status, lib.midbf_last_error().decode())
 
 
-EXPORTED = ["midbf_build", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_noalloc", "midbf_apply_batched",
+EXPORTED = ["midbf_build", "midbf_save", "midbf_load", "midbf_apply", "midbf_apply_adjoint", "midbf_apply_noalloc", "midbf_apply_batched",
             "midbf_apply_graph_create", "midbf_graph_launch", "midbf_graph_destroy",
             "midbf_batch_create", "midbf_batch_run", "midbf_batch_get_stats",
             "midbf_batch_destroy", "midbf_schedule_simulate",

@@ -3,8 +3,10 @@
 // the middle blocks.
 #include <algorithm>
 #include <chrono>
-#include <cstring>
 #include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "build.h"
@@ -137,6 +139,32 @@ __global__ void pack_kernel(PackArgs A) {
     }
 }
 
+// The inverse of pack_kernel's T mapping: a T block in the stored order back into the
+// decomposition slab (X[i][k + j]), for factors read from a file.
+struct UnpackArgs {
+    int side;
+    const int* k_w;
+    const int* n_w;
+    double2* X;
+    long long x_stride;
+    const long long* toff_w;
+    const double2* T;
+};
+
+__global__ void unpack_kernel(UnpackArgs A) {
+    const int w = blockIdx.x;
+    const int k = A.k_w[w], n = A.n_w[w], nred = n - k;
+    double2* X = A.X + (long long)w * A.x_stride;
+    const long long to = A.toff_w[w];
+    const long long tot = (long long)k * nred;
+    for (long long e = threadIdx.x; e < tot; e += BT) {
+        int i, j;
+        if (A.side == SIDE_COL) { j = (int)(e / k); i = (int)(e - (long long)j * k); }
+        else { i = (int)(e / nred); j = (int)(e - (long long)i * nred); }
+        X[(long long)i * n + k + j] = A.T[to + e];
+    }
+}
+
 struct MidGenArgs {
     PhaseDesc ph;
     const int* nr;
@@ -241,6 +269,7 @@ void free_level(LevelSide& lv) {
     lv.d_src_lat = nullptr;
     for (int q = 0; q < NPREC; ++q) lv.d_T[q] = nullptr;
     lv.chunks.clear();
+    lv.t64.clear();
 }
 
 struct Scratch {
@@ -259,13 +288,28 @@ struct Scratch {
     }
 };
 
+// The decompositions of one step and side as read from a factor file: sample
+// count, candidate count and rank per ID, pivot orders (concatenated) and the
+// FP64 T blocks in pack_kernel's stored order (concatenated).
+struct ReplayLevel {
+    int m = 0;
+    std::vector<int> n, k, perm;
+    std::vector<double2> T;
+};
+
 // Decompositions of one step and side.  Returns false if some ID kept as
-// many pivots as it had samples while more samples were available.
-bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long want, hipStream_t st) {
+// many pivots as it had samples while more samples were available.  With rl,
+// the decompositions come from a factor file instead of samples and pivoted QR.
+bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long want, hipStream_t st,
+                 const ReplayLevel* rl = nullptr) {
     const int P = h->P, d = h->d;
     const int side_len = h->n >> lv.lb;
-    std::vector<int> samples = mock_chebyshev_local(d, side_len, want);
-    lv.m = (int)samples.size();
+    std::vector<int> samples;
+    if (rl) lv.m = rl->m;
+    else {
+        samples = mock_chebyshev_local(d, side_len, want);
+        lv.m = (int)samples.size();
+    }
     MIDBF_CHECK(lv.m <= ID_MMAX, MIDBF_ERR_SHAPE, "too many samples per decomposition");
     const long long nid = lv.nid;
     const long long nB = ipow(P, lv.lb);
@@ -281,6 +325,7 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
     }
     lv.nmax = *std::max_element(lv.n.begin(), lv.n.end());
     MIDBF_CHECK(lv.nmax <= ID_NMAX, MIDBF_ERR_SHAPE, "too many candidates per decomposition (rank too large)");
+    if (rl) MIDBF_CHECK(rl->n == lv.n, MIDBF_ERR_IO, "factor file: candidate counts do not follow from its ranks");
     lv.perm_off.assign(nid + 1, 0);
     for (long long id = 0; id < nid; ++id) lv.perm_off[id + 1] = lv.perm_off[id] + lv.n[id];
     lv.total_n = lv.perm_off[nid];
@@ -316,9 +361,12 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
     sc.k = dalloc<int>(wave);
     sc.toff = dalloc<long long>(wave);
     sc.tile_off = dalloc<long long>(wave);
-    sc.samples = dalloc<int>(m);
-    upload(sc.samples, samples, st);
+    if (!rl) {
+        sc.samples = dalloc<int>(m);
+        upload(sc.samples, samples, st);
+    }
     for (hipEvent_t& e : sc.ev) MIDBF_HIP(hipEventCreate(&e));
+    long long t_read = 0;      // replay: T entries of the waves done
     hipEvent_t* ev = sc.ev;
 
     bool saturated = false;
@@ -332,32 +380,65 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
                         sc.cand, (int)nmax};
             hipLaunchKernelGGL(cand_kernel, dim3(cnt), dim3(BT), 0, st, ca);
             MIDBF_HIP(hipGetLastError());
-            GenArgs ga{h->ph, lv.side, lv.lb, id0, nB, (int)m, sc.samples, side_len, lv.d_n + id0, sc.cand,
-                       (int)nmax, sc.X, sc.xs};
-            const int gx = (int)std::min<long long>((m * nmax + BT - 1) / BT, 64);
-            hipLaunchKernelGGL(gen_kernel, dim3(gx, cnt), dim3(BT), 0, st, ga);
-            MIDBF_HIP(hipGetLastError());
-            IdBatch ib{sc.X, sc.xs, sc.V, sc.vs, sc.Y, sc.ys, sc.perm, nmax, sc.k, lv.d_n + id0, 0, (int)m,
-                       h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side), h->p.fixed_rank};
-            MIDBF_HIP(hipEventRecord(ev[0], st));
-            launch_id_batch(ib, cnt, st);
-            MIDBF_HIP(hipEventRecord(ev[1], st));
             std::vector<int> kw(cnt);
-            MIDBF_HIP(hipMemcpyAsync(kw.data(), sc.k, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
-            MIDBF_HIP(hipStreamSynchronize(st));
-            float id_ms = 0.f;
-            MIDBF_HIP(hipEventElapsedTime(&id_ms, ev[0], ev[1]));
-            h->stats.id_ms += id_ms;
-            for (int w = 0; w < cnt; ++w) {
-                h->stats.id_flops += 8.0 * (double)m * lv.n[id0 + w] * kw[w];
-                h->stats.id_bytes += 16.0 * (double)m * lv.n[id0 + w];
+            if (!rl) {
+                GenArgs ga{h->ph, lv.side, lv.lb, id0, nB, (int)m, sc.samples, side_len, lv.d_n + id0, sc.cand,
+                           (int)nmax, sc.X, sc.xs};
+                const int gx = (int)std::min<long long>((m * nmax + BT - 1) / BT, 64);
+                hipLaunchKernelGGL(gen_kernel, dim3(gx, cnt), dim3(BT), 0, st, ga);
+                MIDBF_HIP(hipGetLastError());
+                IdBatch ib{sc.X, sc.xs, sc.V, sc.vs, sc.Y, sc.ys, sc.perm, nmax, sc.k, lv.d_n + id0, 0, (int)m,
+                           h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side), h->p.fixed_rank};
+                MIDBF_HIP(hipEventRecord(ev[0], st));
+                launch_id_batch(ib, cnt, st);
+                MIDBF_HIP(hipEventRecord(ev[1], st));
+                MIDBF_HIP(hipMemcpyAsync(kw.data(), sc.k, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+                MIDBF_HIP(hipStreamSynchronize(st));
+                float id_ms = 0.f;
+                MIDBF_HIP(hipEventElapsedTime(&id_ms, ev[0], ev[1]));
+                h->stats.id_ms += id_ms;
+                for (int w = 0; w < cnt; ++w) {
+                    h->stats.id_flops += 8.0 * (double)m * lv.n[id0 + w] * kw[w];
+                    h->stats.id_bytes += 16.0 * (double)m * lv.n[id0 + w];
+                }
+            } else {
+                // ranks, pivot orders and T blocks of this wave from the file, into the slab layout
+                // the packing below reads (T at X[i][k + j], pivots at perm + w * nmax)
+                std::copy(rl->k.begin() + id0, rl->k.begin() + id0 + cnt, kw.begin());
+                std::vector<int> pw((size_t)cnt * nmax, 0);
+                std::vector<long long> tof(cnt);
+                long long tsum = 0;
+                for (int w = 0; w < cnt; ++w) {
+                    const long long id = id0 + w;
+                    std::copy(rl->perm.begin() + lv.perm_off[id], rl->perm.begin() + lv.perm_off[id] + lv.n[id],
+                              pw.begin() + (size_t)w * nmax);
+                    tof[w] = tsum;
+                    tsum += (long long)kw[w] * (lv.n[id] - kw[w]);
+                }
+                upload(sc.k, kw, st);
+                upload(sc.perm, pw, st);
+                upload(sc.toff, tof, st);
+                double2* stage = dalloc<double2>(std::max<long long>(tsum, 1));
+                try {
+                    MIDBF_HIP(hipMemcpyAsync(stage, rl->T.data() + t_read, tsum * sizeof(double2),
+                                             hipMemcpyHostToDevice, st));
+                    UnpackArgs ua{lv.side, sc.k, lv.d_n + id0, sc.X, sc.xs, sc.toff, stage};
+                    hipLaunchKernelGGL(unpack_kernel, dim3(cnt), dim3(BT), 0, st, ua);
+                    MIDBF_HIP(hipGetLastError());
+                    MIDBF_HIP(hipStreamSynchronize(st));
+                } catch (...) {
+                    (void)hipFree(stage);
+                    throw;
+                }
+                (void)hipFree(stage);
+                t_read += tsum;
             }
             std::vector<long long> toff(cnt);
             long long tw = 0;
             for (int w = 0; w < cnt; ++w) {
                 const long long id = id0 + w;
                 const int k = kw[w], nn = lv.n[id];
-                if (k >= m && m < box_pts && m < nn) saturated = true;
+                if (!rl && k >= m && m < box_pts && m < nn) saturated = true;
                 lv.k[id] = k;
                 lv.y_off[id] = yrun;
                 yrun += k;
@@ -370,7 +451,11 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             upload(sc.toff, toff, st);
             double2* c64 = nullptr;
             float2* c32 = nullptr;
-            if (h->keep & MIDBF_KEEP_FP64) { c64 = dalloc<double2>(tw); lv.chunks.push_back(c64); }
+            if (h->keep & MIDBF_KEEP_FP64) {
+                c64 = dalloc<double2>(tw);
+                lv.chunks.push_back(c64);
+                lv.t64.push_back({c64, tw});
+            }
             if (h->keep & MIDBF_KEEP_FP32) { c32 = dalloc<float2>(tw); lv.chunks.push_back(c32); }
             PackArgs pa{lv.side, id0, sc.k, lv.d_n + id0, sc.X, sc.xs, sc.perm, nmax, sc.cand, (int)nmax, sc.toff,
                         c64, c32, lv.d_perm_off, lv.d_y_off, lv.d_perm, lv.d_skel};
@@ -614,6 +699,8 @@ void destroy_plan(midbf_plan* h) {
     f(M.ang);
     for (int q = 0; q < NPREC; ++q) f(M.S[q]);
     f(h->d_tmax);
+    f(h->own_U);
+    f(h->own_V);
     for (int q = 0; q < NPREC; ++q) {
         f(h->ws[q].buf[0]);
         f(h->ws[q].buf[1]);
@@ -624,8 +711,82 @@ void destroy_plan(midbf_plan* h) {
     delete h;
 }
 
-midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
+namespace {
+
+// ---- factor files --------------------------------------------------------------------------
+// Little-endian binary: FileHead; for the low-rank phase U then V (N x r FP64 each); then for
+// every step s = 0..b-1, the row side then the column side: int64 nid, int32 m, int32 0,
+// int32 n[nid], int32 k[nid], int32 pivot orders (sum n), complex FP64 T blocks in pack_kernel's
+// stored order (sum k (n - k)); then the magic again.
+constexpr char FILE_MAGIC[8] = {'M', 'I', 'D', 'B', 'F', 'f', '1', '\n'};
+
+struct FileHead {
+    char magic[8];
+    int32_t d, n, leaf_box, oversample_t, k_cap, phase, r, fixed_rank;
+    double tol;
+    int32_t L, b;
+    int64_t N;
+};
+
+struct File {
+    FILE* f = nullptr;
+    File(const char* path, const char* mode) : f(std::fopen(path, mode)) {
+        MIDBF_CHECK(f, MIDBF_ERR_IO, "cannot open the factor file");
+    }
+    ~File() { if (f) std::fclose(f); }
+    void read(void* dst, size_t bytes) {
+        MIDBF_CHECK(std::fread(dst, 1, bytes, f) == bytes, MIDBF_ERR_IO, "factor file truncated");
+    }
+    void write(const void* src, size_t bytes) {
+        MIDBF_CHECK(std::fwrite(src, 1, bytes, f) == bytes, MIDBF_ERR_IO, "cannot write the factor file");
+    }
+    template <class T> void read_vec(std::vector<T>& v, long long count) {
+        MIDBF_CHECK(count >= 0 && count < (1LL << 40), MIDBF_ERR_IO, "factor file: bad array size");
+        v.resize((size_t)count);
+        if (count) read(v.data(), (size_t)count * sizeof(T));
+    }
+};
+
+// One level record, checked against the geometry before anything reaches the device.
+void read_level(File& F, long long nid_expect, ReplayLevel& rl) {
+    int64_t nid = 0;
+    int32_t mz[2] = {0, 0};
+    F.read(&nid, sizeof nid);
+    F.read(mz, sizeof mz);
+    MIDBF_CHECK(nid == nid_expect, MIDBF_ERR_IO, "factor file: decomposition count does not match its tree");
+    rl.m = mz[0];
+    MIDBF_CHECK(rl.m >= 1 && rl.m <= ID_MMAX, MIDBF_ERR_IO, "factor file: bad sample count");
+    F.read_vec(rl.n, nid);
+    F.read_vec(rl.k, nid);
+    long long sn = 0, st = 0;
+    for (long long i = 0; i < nid; ++i) {
+        const int n = rl.n[i], k = rl.k[i];
+        MIDBF_CHECK(n >= 1 && n <= ID_NMAX && k >= 0 && k <= n && k <= rl.m, MIDBF_ERR_IO,
+                    "factor file: bad rank or candidate count");
+        sn += n;
+        st += (long long)k * (n - k);
+    }
+    F.read_vec(rl.perm, sn);
+    std::vector<char> seen;
+    long long off = 0;
+    for (long long i = 0; i < nid; ++i) {
+        const int n = rl.n[i];
+        seen.assign(n, 0);
+        for (int j = 0; j < n; ++j) {
+            const int v = rl.perm[off + j];
+            MIDBF_CHECK(v >= 0 && v < n && !seen[v], MIDBF_ERR_IO, "factor file: a pivot order is not a permutation");
+            seen[v] = 1;
+        }
+        off += n;
+    }
+    F.read_vec(rl.T, st);
+}
+
+}  // namespace
+
+midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file) {
     auto t0 = std::chrono::steady_clock::now();
+    File* rf = (File*)replay_file;
     MIDBF_CHECK(p.d == 2 || p.d == 3, MIDBF_ERR_ARG, "d must be 2 or 3");
     MIDBF_CHECK(p.leaf_box >= 1 && p.n >= 2 * p.leaf_box && p.n % p.leaf_box == 0, MIDBF_ERR_SHAPE,
                 "n must be a multiple of leaf_box and at least 2*leaf_box");
@@ -637,7 +798,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
     MIDBF_CHECK(p.oversample_t >= 1, MIDBF_ERR_ARG, "oversample_t must be >= 1");
     MIDBF_CHECK(p.fixed_rank >= 0, MIDBF_ERR_ARG, "fixed_rank must be >= 0");
     if (p.phase == MIDBF_PHASE_LOWRANK)
-        MIDBF_CHECK(p.U_dev && p.V_dev && p.r >= 1, MIDBF_ERR_ARG, "low-rank phase needs U, V and r");
+        MIDBF_CHECK((rf || (p.U_dev && p.V_dev)) && p.r >= 1, MIDBF_ERR_ARG, "low-rank phase needs U, V and r");
     if (p.phase == MIDBF_PHASE_FIO_ELLIPSE || p.phase == MIDBF_PHASE_FIO_PIECEWISE)
         MIDBF_CHECK(p.d == 2, MIDBF_ERR_ARG, "this phase is two-dimensional");
     if (p.phase == MIDBF_PHASE_ISO3D) MIDBF_CHECK(p.d == 3, MIDBF_ERR_ARG, "this phase is three-dimensional");
@@ -655,7 +816,25 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         h->N = ipow(p.n, p.d);
         h->b = (L + 1) / 2;
         h->hstar = L - h->b + 1;
-        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r};
+        if (p.phase == MIDBF_PHASE_LOWRANK) {
+            // the plan keeps its own U and V: a factor file carries them, and the caller may free theirs
+            const size_t cnt = (size_t)h->N * p.r;
+            h->own_U = dalloc<double>(cnt);
+            h->own_V = dalloc<double>(cnt);
+            if (rf) {
+                std::vector<double> hv;
+                rf->read_vec(hv, (long long)cnt);
+                MIDBF_HIP(hipMemcpy(h->own_U, hv.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+                rf->read_vec(hv, (long long)cnt);
+                MIDBF_HIP(hipMemcpy(h->own_V, hv.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+            } else {
+                MIDBF_HIP(hipMemcpyAsync(h->own_U, p.U_dev, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+                MIDBF_HIP(hipMemcpyAsync(h->own_V, p.V_dev, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+            }
+            h->p.U_dev = h->own_U;
+            h->p.V_dev = h->own_V;
+        }
+        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, h->p.U_dev, h->p.V_dev, p.r};
         h->rows.resize(h->b);
         h->cols.resize(h->b);
         if (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) {
@@ -668,7 +847,15 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
                 LevelSide& lv = side == SIDE_ROW ? h->rows[s] : h->cols[s];
                 const LevelSide* prev = s == 0 ? nullptr : (side == SIDE_ROW ? &h->rows[s - 1] : &h->cols[s - 1]);
                 long long want = (long long)p.oversample_t * khat[side];
-                for (int attempt = 0;; ++attempt) {
+                if (rf) {
+                    ReplayLevel rl;
+                    read_level(*rf, ipow(h->P, L + 1), rl);
+                    lv = LevelSide();
+                    lv.s = s; lv.side = side; lv.la = L - s; lv.lb = s + 1;
+                    lv.nid = ipow(h->P, L + 1);
+                    build_level(h, lv, prev, want, st, &rl);
+                }
+                for (int attempt = 0; !rf; ++attempt) {
                     lv = LevelSide();
                     lv.s = s; lv.side = side; lv.la = L - s; lv.lb = s + 1;
                     lv.nid = ipow(h->P, L + 1);
@@ -741,6 +928,81 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st) {
         destroy_plan(h);
         throw;
     }
+    return h;
+}
+
+void save_plan(midbf_plan* h, const char* path, hipStream_t st) {
+    MIDBF_CHECK(path, MIDBF_ERR_ARG, "null path");
+    MIDBF_CHECK(h->keep & MIDBF_KEEP_FP64, MIDBF_ERR_ARG, "saving needs the FP64 factor copy (MIDBF_KEEP_FP64)");
+    MIDBF_HIP(hipStreamSynchronize(st));
+    File F(path, "wb");
+    FileHead H{};
+    std::memcpy(H.magic, FILE_MAGIC, sizeof FILE_MAGIC);
+    H.d = h->d; H.n = h->n; H.leaf_box = h->leaf; H.oversample_t = h->p.oversample_t; H.k_cap = h->p.k_cap;
+    H.phase = h->p.phase; H.r = h->p.phase == MIDBF_PHASE_LOWRANK ? h->p.r : 0; H.fixed_rank = h->p.fixed_rank;
+    H.tol = h->p.tol; H.L = h->L; H.b = h->b; H.N = h->N;
+    F.write(&H, sizeof H);
+    if (h->p.phase == MIDBF_PHASE_LOWRANK) {
+        std::vector<double> hv((size_t)h->N * h->p.r);
+        for (const double* src : {h->own_U, h->own_V}) {
+            MIDBF_HIP(hipMemcpy(hv.data(), src, hv.size() * sizeof(double), hipMemcpyDeviceToHost));
+            F.write(hv.data(), hv.size() * sizeof(double));
+        }
+    }
+    std::vector<double2> buf;
+    for (int s = 0; s < h->b; ++s)
+        for (LevelSide* lv : {&h->rows[s], &h->cols[s]}) {
+            const int64_t nid = lv->nid;
+            const int32_t mz[2] = {lv->m, 0};
+            F.write(&nid, sizeof nid);
+            F.write(mz, sizeof mz);
+            F.write(lv->n.data(), lv->n.size() * sizeof(int));
+            F.write(lv->k.data(), lv->k.size() * sizeof(int));
+            std::vector<int> perm((size_t)lv->total_n);
+            if (!perm.empty())
+                MIDBF_HIP(hipMemcpy(perm.data(), lv->d_perm, perm.size() * sizeof(int), hipMemcpyDeviceToHost));
+            F.write(perm.data(), perm.size() * sizeof(int));
+            long long want = 0, have = 0;
+            for (long long i = 0; i < lv->nid; ++i) want += (long long)lv->k[i] * (lv->n[i] - lv->k[i]);
+            for (const auto& c : lv->t64) {
+                constexpr long long piece = 1LL << 24;      // 256 MB of complex FP64 at a time
+                for (long long o = 0; o < c.second; o += piece) {
+                    const long long cnt = std::min(piece, c.second - o);
+                    buf.resize((size_t)cnt);
+                    MIDBF_HIP(hipMemcpy(buf.data(), c.first + o, cnt * sizeof(double2), hipMemcpyDeviceToHost));
+                    F.write(buf.data(), cnt * sizeof(double2));
+                }
+                have += c.second;
+            }
+            MIDBF_CHECK(have == want, MIDBF_ERR_IO, "internal: T chunks do not cover the level");
+        }
+    F.write(FILE_MAGIC, sizeof FILE_MAGIC);
+}
+
+midbf_plan* load_plan(const char* path, unsigned precisions, hipStream_t st, midbf_params* params_out) {
+    MIDBF_CHECK(path, MIDBF_ERR_ARG, "null path");
+    File F(path, "rb");
+    FileHead H{};
+    F.read(&H, sizeof H);
+    MIDBF_CHECK(std::memcmp(H.magic, FILE_MAGIC, sizeof FILE_MAGIC) == 0, MIDBF_ERR_IO, "not a MIDBF factor file");
+    midbf_params p{};
+    p.d = H.d; p.n = H.n; p.tol = H.tol; p.leaf_box = H.leaf_box; p.oversample_t = H.oversample_t;
+    p.k_cap = H.k_cap; p.phase = (midbf_phase_kind)H.phase; p.r = H.r; p.fixed_rank = H.fixed_rank;
+    p.precisions = precisions;
+    int L = 0;
+    while (p.leaf_box >= 1 && (p.leaf_box << L) < p.n && L < 30) ++L;
+    MIDBF_CHECK(H.L == L && H.b == (L + 1) / 2 && H.N == ipow(p.n, p.d) && p.d >= 2 && p.d <= 3, MIDBF_ERR_IO,
+                "factor file: header does not describe a factorization");
+    midbf_plan* h = build_plan(p, st, &F);
+    try {
+        char tail[sizeof FILE_MAGIC];
+        F.read(tail, sizeof tail);
+        MIDBF_CHECK(std::memcmp(tail, FILE_MAGIC, sizeof FILE_MAGIC) == 0, MIDBF_ERR_IO, "factor file: bad ending");
+    } catch (...) {
+        destroy_plan(h);
+        throw;
+    }
+    if (params_out) *params_out = h->p;
     return h;
 }
 

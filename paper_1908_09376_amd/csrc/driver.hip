@@ -927,6 +927,18 @@ midbf_status midbf_build(const midbf_params* p, void* stream, midbf_handle* out)
     return guarded([&] { *out = build_plan(*p, (hipStream_t)stream); });
 }
 
+midbf_status midbf_save(midbf_handle h, const char* path, void* stream) {
+    if (!h || !path) return fail(MIDBF_ERR_ARG, "null argument");
+    return guarded([&] { save_plan(h, path, (hipStream_t)stream); });
+}
+
+midbf_status midbf_load(const char* path, unsigned precisions, void* stream, midbf_params* params_out,
+                        midbf_handle* out) {
+    if (!path || !out) return fail(MIDBF_ERR_ARG, "null argument");
+    *out = nullptr;
+    return guarded([&] { *out = load_plan(path, precisions, (hipStream_t)stream, params_out); });
+}
+
 midbf_status midbf_apply(midbf_handle h, const void* f, void* g, int nrhs, long long ld, midbf_precision prec,
                          void* stream) {
     if (!h) return fail(MIDBF_ERR_ARG, "null handle");

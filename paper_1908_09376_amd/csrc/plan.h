@@ -3,6 +3,7 @@
 #pragma once
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -58,6 +59,8 @@ struct LevelSide {
     int* d_g_out_len = nullptr;
     void* g_T[NPREC] = {};
     std::vector<void*> chunks;            // device allocations owned by this level
+    // the FP64 T chunks (one per build wave, IDs in order) and their entry counts
+    std::vector<std::pair<double2*, long long>> t64;
 };
 
 // Middle factor: one dense block per (row group, column group) pair.
@@ -123,6 +126,8 @@ struct midbf_plan {
     unsigned keep = 0;
     long long max_total_k = 0, max_total_n = 0;
     unsigned* d_tmax = nullptr;   // build only: largest |re|, |im| of the T entries packed into 16-bit tiles
+    double* own_U = nullptr;      // low-rank phase: the plan's own copies of U and V (N x r)
+    double* own_V = nullptr;
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
     // matrix-core tile variant per kernel kind (up, down, middle) and MSCS step (FP32, split-bf16, split-fp16)

@@ -7,6 +7,7 @@ FP64 apply, complex64 for FP32 and split-BF16.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 import torch
@@ -54,6 +55,23 @@ class MIDBF:
         h = C.c_void_p()
         L.check(L.lib.midbf_build(C.byref(self._p), _stream_ptr(stream), C.byref(h)))
         self._h = h
+
+    def save(self, path: str, stream=None) -> None:
+        """Write the factorization to a file (midbf_save; needs the FP64 copy)."""
+        L.check(L.lib.midbf_save(self._h, os.fsencode(path), _stream_ptr(stream)))
+
+    @classmethod
+    def load(cls, path: str, precisions: int = 0, stream=None) -> "MIDBF":
+        """A factorization read from a file written by save (midbf_load), keeping `precisions`."""
+        p = L.Params()
+        h = C.c_void_p()
+        L.check(L.lib.midbf_load(os.fsencode(path), precisions, _stream_ptr(stream), C.byref(p), C.byref(h)))
+        self = cls.__new__(cls)
+        self.d, self.n, self.N = p.d, p.n, p.n ** p.d
+        self._UV = (None, None)
+        self._p = p
+        self._h = h
+        return self
 
     def close(self):
         if getattr(self, "_h", None):

@@ -50,3 +50,22 @@ def test_output_block_checked_before_launch():
         F._out(x, torch.zeros(16, dtype=torch.complex128))
     with pytest.raises(TypeError):
         F._out(x, torch.zeros(16, dtype=torch.complex64))      # not a CUDA tensor
+
+
+def test_factor_file_errors_without_gpu_work(tmp_path):
+    # a missing file, a file that is not a factor file and a truncated header are refused on the
+    # host, before any device call
+    import ctypes as C
+    from paper_1908_09376_amd import _lib
+    h = C.c_void_p()
+    st = _lib.lib.midbf_load(str(tmp_path / "absent.midbf").encode(), 0, None, None, C.byref(h))
+    assert st == -8 and not h.value
+    bad = tmp_path / "bad.midbf"
+    bad.write_bytes(b"NOTMIDBF" + bytes(64))
+    assert _lib.lib.midbf_load(str(bad).encode(), 0, None, None, C.byref(h)) == -8
+    assert b"not a MIDBF factor file" in _lib.lib.midbf_last_error()
+    short = tmp_path / "short.midbf"
+    short.write_bytes(b"MIDBFf1\n" + bytes(8))
+    assert _lib.lib.midbf_load(str(short).encode(), 0, None, None, C.byref(h)) == -8
+    assert b"truncated" in _lib.lib.midbf_last_error()
+    assert _lib.lib.midbf_save(None, b"x", None) == -1
