@@ -121,7 +121,9 @@ void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int p
             return;
         }
         if (mfma_count > 0) {
-            const int kind = which == LevelKernel::Up ? 0 : (which == LevelKernel::Middle ? 2 : 1);
+            const int kind = (which == LevelKernel::Up || which == LevelKernel::AdjUp)           ? 0
+                             : (which == LevelKernel::Middle || which == LevelKernel::AdjMiddle) ? 2
+                                                                                                 : 1;
             const int lv = std::max(0, std::min(level, midbf_plan::VMAXLEV - 1));
             // (DownGroup and DownDense are split-16 only; DownDense runs the middle
             // kernels on the group blocks, whose first-tile table travels in MidArgs::off)
@@ -381,10 +383,20 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.out_max = M.nr_max;
         a.ang = (is_split16(prec) && !adjoint) ? (const int*)M.ang : nullptr;
         a.bscale = cexp ? pow2(hD - hU) : 1.f;
+        if (adjoint && mfma) {
+            // x = S^H z on the matrix cores: the blocks seen transposed (rows = columns of S),
+            // inputs from the row pieces, outputs to the column pieces
+            std::swap(a.nr, a.nc);
+            std::swap(a.in_off, a.out_off);
+            std::swap(a.in_len, a.out_len);
+            a.in_max = M.nr_max;
+            a.out_max = M.nc_max;
+        }
         // FP32 matrix cores: split the rows of few large blocks over several workgroups
+        const int rows_max = adjoint ? M.nc_max : M.nr_max;
         a.mchunks = (mfma && prec == PREC_FP32)
                         ? (int)std::max<long long>(1, std::min<long long>((2048 + M.nblk - 1) / std::max<long long>(M.nblk, 1),
-                                                                          (M.nr_max + 127) / 128))
+                                                                          (rows_max + 127) / 128))
                         : 1;
         const int width = adjoint ? M.nr_max : M.nc_max;
         // VALU path: entries of the staged vector per LDS pass
@@ -488,7 +500,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         } else if (mfma) {
             // per-ID contributions to the scratch block, then the ordered group sums
             const double scr = (double)lv.total_n * nrhs * cs;
-            D.which = LevelKernel::Down;
+            D.which = adjoint ? LevelKernel::AdjDown : LevelKernel::Down;
             D.grid = dim3();
             D.smem = 0;
             D.bytes = fac + vin + scr;
@@ -544,8 +556,7 @@ ApplyMode apply_mode(const midbf_plan* h, int nrhs, int prec, bool adjoint) {
     MIDBF_CHECK(!is_split16(prec) || (!adjoint && fits_bf16), MIDBF_ERR_UNIMPLEMENTED,
                 "the split 16-bit applies exist for the forward transform with candidate sets up to 2048");
     ApplyMode m;
-    m.mfma = is_split16(prec) ||
-             ((prec == PREC_FP32 || prec == PREC_FP64) && !adjoint && nrhs >= MFMA_MIN_NRHS && fits);
+    m.mfma = is_split16(prec) || ((prec == PREC_FP32 || prec == PREC_FP64) && nrhs >= MFMA_MIN_NRHS && fits);
     m.lat = m.mfma && (nrhs > 1 || is_split16(prec));
     m.rt = nrhs == 1 ? 1 : (prec == PREC_FP64 ? APPLY_RT64 : APPLY_RT);
     return m;
@@ -555,7 +566,9 @@ ApplyMode apply_mode(const midbf_plan* h, int nrhs, int prec, bool adjoint) {
 // contribution block (Workspace::scratch).
 bool needs_scratch(const std::vector<LaunchDesc>& launches) {
     for (const LaunchDesc& D : launches)
-        if (D.mfma_count > 0 && (D.which == LevelKernel::Down || D.which == LevelKernel::DownSum)) return true;
+        if (D.mfma_count > 0 && (D.which == LevelKernel::Down || D.which == LevelKernel::AdjDown ||
+                                 D.which == LevelKernel::DownSum))
+            return true;
     return false;
 }
 

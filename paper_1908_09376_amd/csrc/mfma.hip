@@ -116,13 +116,15 @@ struct Cfg {
 template <class C> using Narrow = Cfg<C::MTW, C::KC, C::PIPE, C::NT, 1, typename C::T>;
 
 // Rows [base, base + 16 MTW) of C (+)= A B for one wave.  A is column-major
-// with leading dimension M; brow(j, r) returns B[j][r] (j < K, r < nr).
+// with leading dimension M, or with ADJ the conjugate of a row-major block with
+// leading dimension K (A[row][col] = conj(F[row K + col]): the adjoint passes
+// read the forward factors this way); brow(j, r) returns B[j][r] (j < K, r < nr).
 // Every thread of the workgroup must call this (it synchronizes).
 //   PIPE: the wave's A fragments of chunk c+1 and this thread's B elements of
 //   chunk c+1 are loaded into registers while chunk c is multiplied from the
 //   other register set and the other LDS buffer; one barrier per chunk.
 //   otherwise: one LDS buffer, A prefetched one k-step ahead.
-template <class C, int NT, class BRow>
+template <class C, int NT, bool ADJ = false, class BRow>
 __device__ void gemm_rows(typename C::Acc (&cr)[C::MTW][4], typename C::Acc (&ci)[C::MTW][4],
                           const typename C::C2* __restrict__ A, int M, int K, int base, BRow brow, int nr,
                           typename C::C2* sB) {
@@ -145,7 +147,12 @@ __device__ void gemm_rows(typename C::Acc (&cr)[C::MTW][4], typename C::Acc (&ci
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
             const int row = base + mt * 16 + lr;
-            dst[mt] = (mt < ntl && col < K && row < M) ? A[(long long)col * M + row] : c2<T>(0, 0);
+            if constexpr (ADJ) {
+                const C2 v = (mt < ntl && col < K && row < M) ? A[(long long)row * K + col] : c2<T>(0, 0);
+                dst[mt] = c2<T>(v.x, -v.y);
+            } else {
+                dst[mt] = (mt < ntl && col < K && row < M) ? A[(long long)col * M + row] : c2<T>(0, 0);
+            }
         }
     };
     C2 bt[BPT];
@@ -273,7 +280,8 @@ __device__ inline long long xcd_group_order(long long b, long long nid, int P) {
     return ((q << 3) + x) * 4 + t;
 }
 
-template <class C>
+// ADJ: the adjoint going up (row side, A = conj(T) with T row-major k x (n-k)).
+template <class C, bool ADJ = false>
 __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     constexpr int MTW = C::MTW;
     using T = typename C::T;
@@ -306,7 +314,7 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
         const int base = m0 + wave * MTW * 16;
         Acc cr[MTW][4], ci[MTW][4];
         zero_acc<Acc, MTW>(cr, ci);
-        gemm_rows<C, C::NT>(cr, ci, Tb, k, nred, base, brow, nr, sB);
+        gemm_rows<C, C::NT, ADJ>(cr, ci, Tb, k, nred, base, brow, nr, sB);
         // C + skeleton rows of the candidate vector.  Per 16-row tile the
         // skeleton inputs are loaded at in-range addresses (row 0 / column 0
         // outside the block) so that a lane's loads issue together.
@@ -343,7 +351,8 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
 // Going down, one workgroup per decomposition: its contribution to every
 // candidate row of its group -- z on the skeleton rows, T^T z on the
 // redundant rows -- goes to the scratch block scr[perm_off[id] + position].
-template <class C>
+// ADJ: the adjoint going down (column side, A = T^H with T column-major k x (n-k)).
+template <class C, bool ADJ = false>
 __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, typename C::C2* scr) {
     constexpr int MTW = C::MTW;
     using T = typename C::T;
@@ -370,7 +379,7 @@ __global__ __launch_bounds__(C::NT) void down_mfma(DownArgs A, long long nid, ty
         const int base = m0 + wave * MTW * 16;
         Acc cr[MTW][4], ci[MTW][4];
         zero_acc<Acc, MTW>(cr, ci);
-        gemm_rows<C, C::NT>(cr, ci, Tb, nred, k, base, brow, nr, sB);
+        gemm_rows<C, C::NT, ADJ>(cr, ci, Tb, nred, k, base, brow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -443,7 +452,9 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const C2* scr) {
     }
 }
 
-template <class C>
+// ADJ: x = S^H z; the caller swaps the block shapes (nr <-> nc) and the input and
+// output piece tables, so M = columns of S and K = its rows.
+template <class C, bool ADJ = false>
 __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
     constexpr int MTW = C::MTW;
     using T = typename C::T;
@@ -472,7 +483,7 @@ __global__ __launch_bounds__(C::NT) void middle_mfma(MidArgs A) {
         const int base = m0 + wave * MTW * 16;
         Acc cr[MTW][4], ci[MTW][4];
         zero_acc<Acc, MTW>(cr, ci);
-        gemm_rows<C, C::NT>(cr, ci, S, M, K, base, brow, nr, sB);
+        gemm_rows<C, C::NT, ADJ>(cr, ci, S, M, K, base, brow, nr, sB);
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -506,13 +517,21 @@ template <class C>
 void launch_variant(LevelKernel which, const void* args, long long count, int nrhs, void* scratch, hipStream_t s) {
     const dim3 grid((unsigned)count, (nrhs + C::W - 1) / C::W);
     switch (which) {
-        case LevelKernel::Up: {
+        case LevelKernel::Up:
+        case LevelKernel::AdjUp: {
             const UpArgs& a = *(const UpArgs*)args;
-            hipLaunchKernelGGL(up_mfma<C>, grid, dim3(C::NT), 2 * sizeof(int) * a.ncand_max, s, a, count);
+            if (which == LevelKernel::AdjUp)
+                hipLaunchKernelGGL((up_mfma<C, true>), grid, dim3(C::NT), 2 * sizeof(int) * a.ncand_max, s, a, count);
+            else
+                hipLaunchKernelGGL(up_mfma<C>, grid, dim3(C::NT), 2 * sizeof(int) * a.ncand_max, s, a, count);
             break;
         }
         case LevelKernel::Down:
             hipLaunchKernelGGL(down_mfma<C>, grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count,
+                               (typename C::C2*)scratch);
+            break;
+        case LevelKernel::AdjDown:
+            hipLaunchKernelGGL((down_mfma<C, true>), grid, dim3(C::NT), 0, s, *(const DownArgs*)args, count,
                                (typename C::C2*)scratch);
             break;
         case LevelKernel::DownSum: {
@@ -522,11 +541,16 @@ void launch_variant(LevelKernel which, const void* args, long long count, int nr
                                (const typename C::C2*)scratch);
             break;
         }
-        case LevelKernel::Middle: {
+        case LevelKernel::Middle:
+        case LevelKernel::AdjMiddle: {
             const MidArgs& a = *(const MidArgs*)args;
             MIDBF_CHECK(a.mchunks >= 1, MIDBF_ERR_ARG, "middle row split must be >= 1");
             const dim3 mgrid((unsigned)(count * a.mchunks), grid.y);
-            hipLaunchKernelGGL(middle_mfma<C>, mgrid, dim3(C::NT), sizeof(int) * (a.in_max + a.out_max), s, a);
+            if (which == LevelKernel::AdjMiddle)
+                hipLaunchKernelGGL((middle_mfma<C, true>), mgrid, dim3(C::NT), sizeof(int) * (a.in_max + a.out_max),
+                                   s, a);
+            else
+                hipLaunchKernelGGL(middle_mfma<C>, mgrid, dim3(C::NT), sizeof(int) * (a.in_max + a.out_max), s, a);
             break;
         }
         default:
