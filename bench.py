@@ -154,6 +154,24 @@ def time_applies(F, f, g, prec, steps, warmup, profile: bool):
     return (t1 - t0), kt
 
 
+def time_adjoint(F, g, f, prec, steps, warmup):
+    """Eager adjoint applies f = K^H g with per-kernel HIP-event records."""
+    import torch
+    for _ in range(warmup):
+        F.apply_adjoint(g, out=f, precision=prec)
+    torch.cuda.synchronize()
+    F.profile_read()
+    F.profile(True, by_level=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F.apply_adjoint(g, out=f, precision=prec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = F.profile_read()
+    F.profile(False)
+    return wall, kt
+
+
 def time_graph(F, f, g, prec, steps, warmup):
     """K replays of the apply captured in a hipGraph, between synchronizations."""
     import torch
@@ -439,6 +457,25 @@ def main() -> int:
         del f32, g32
         log(f"[bench] fp32 beside: {fp32['ms_per_step']:.3f} ms/step, {fp32['value']:.1f} RHS-applies/s")
 
+    # the adjoint (K^H, the backward of a linear layer) on the same block, FP64 when the headline is
+    # FP64 and FP32 otherwise: matrix cores from 16 RHS
+    adjoint = None
+    if nrhs >= 16 and w.d == 2:
+        aprec = "fp64" if args.precision == "fp64" else "fp32"
+        ga = f.clone() if aprec == "fp64" else f.to(torch.complex64)
+        fa = torch.empty_like(ga)
+        walla, kta = time_adjoint(F, ga, fa, aprec, args.steps, args.warmup)
+        doma = max(kta, key=lambda r: r["total_ms"])
+        va = F.tune(nrhs, aprec)
+        kinda = doma["name"].removeprefix("adj_")
+        adjoint = {"precision": aprec, "value": round(nrhs * args.steps / walla, 2),
+                   "ms_per_step": round(walla / args.steps * 1e3, 4), "timing": "eager launches",
+                   "roofline": roofline(doma, aprec, va[2 if kinda.startswith("middle") else
+                                                          (0 if kinda.startswith("up") else 1)], w.name),
+                   "kernels": {r["name"]: round(r["total_ms"] / r["launches"], 4) for r in kta}}
+        del ga, fa
+        log(f"[bench] {aprec} adjoint: {adjoint['ms_per_step']:.3f} ms/step, {adjoint['value']:.1f} RHS-applies/s")
+
     # the other split type beside the headline one (split-bf16 keeps FP32's range, split-fp16 is more accurate)
     other = None
     g_other_np = None
@@ -517,6 +554,7 @@ def main() -> int:
         "fp64_gpu": fp64,
         "fp32_gpu": fp32,
         "other_split_gpu": other,
+        "adjoint_gpu": adjoint,
         "phase_recovery": recover,
         "kernels": kernels,
         "roofline": roof,
