@@ -73,14 +73,23 @@ class Kernel:
     """Entry access K(I, J) = exp(2 pi i Phi(x_I, xi_J)) (Scenario 1, Table 1).
 
     ``phase`` is a kind name from PHASES, or ("lowrank", U, V) for a phase
-    given as Phi = U V^T (the output of Alg. 7).
+    given as Phi = U V^T (the output of Alg. 7).  ``points`` = (x, xi) replaces
+    the lattices by given point sets (N x d each; Sec. 3.5, closing paragraph:
+    non-uniform points), x in [0, 1)^d and xi in [-n/2, n/2)^d.
     """
 
-    def __init__(self, d: int, n: int, phase):
+    def __init__(self, d: int, n: int, phase, points=None):
         self.d, self.n = d, n
-        self.N = n ** d
-        self.x = x_points(d, n)
-        self.xi = xi_points(d, n)
+        if points is None:
+            self.x = x_points(d, n)
+            self.xi = xi_points(d, n)
+        else:
+            self.x = np.asarray(points[0], dtype=np.float64)
+            self.xi = np.asarray(points[1], dtype=np.float64)
+            if self.x.shape != self.xi.shape or self.x.shape[1] != d:
+                raise ValueError("points: two N x d arrays")
+        self.points = points is not None
+        self.N = len(self.x)
         if isinstance(phase, tuple) and phase[0] == "lowrank":
             U, V = phase[1], phase[2]
             self._phi = lambda I, J: U[I] @ V[J].T

@@ -75,6 +75,86 @@ class Tree:
     def parent(self, idx: int) -> int:
         return idx // self.P
 
+    def size(self, level: int, idx: int) -> int:
+        return (self.n >> level) ** self.d
+
+    def samples(self, level: int, idx: int, count: int) -> np.ndarray:
+        return mock_chebyshev_points(self, level, idx, count)
+
+
+class PointTree:
+    """Z-ordered 2^d-ary tree over a point set in [0, 1)^d (Sec. 3.5, closing paragraph).
+
+    Node i at level l is the box of its Z-order digits, as in the lattice tree (Fig. 4): digit j
+    (root first) holds bit l-1-j of every box coordinate, coordinate 1 the most significant bit.
+    A node holds the points inside its box, listed leaf by leaf in Z order and by increasing point
+    number inside a leaf; an empty node keeps its number and holds no point (its decompositions
+    have nothing to compress).
+    """
+
+    def __init__(self, pts: np.ndarray, L: int):
+        self.pts = np.asarray(pts, dtype=np.float64)
+        self.d = self.pts.shape[1]
+        self.L, self.P = L, 1 << self.d
+        side = 1 << L
+        cells = np.clip(np.floor(self.pts * side).astype(np.int64), 0, side - 1)
+        leaf = np.zeros(len(self.pts), dtype=np.int64)
+        for j in range(L):
+            bit = L - 1 - j
+            digit = np.zeros(len(self.pts), dtype=np.int64)
+            for q in range(self.d):
+                digit |= ((cells[:, q] >> bit) & 1) << (self.d - 1 - q)
+            leaf = leaf * self.P + digit
+        self.leaf_of = leaf
+        self.order = np.lexsort((np.arange(len(self.pts)), leaf))
+        counts = np.bincount(leaf, minlength=self.P ** L)
+        self.start = np.concatenate([[0], np.cumsum(counts)])
+
+    def count(self, level: int) -> int:
+        return self.P ** level
+
+    def points(self, level: int, idx: int) -> np.ndarray:
+        w = self.P ** (self.L - level)
+        return self.order[self.start[idx * w]:self.start[(idx + 1) * w]]
+
+    def size(self, level: int, idx: int) -> int:
+        return len(self.points(level, idx))
+
+    def child(self, idx: int, t: int) -> int:
+        return self.P * idx + t
+
+    def parent(self, idx: int) -> int:
+        return idx // self.P
+
+    def samples(self, level: int, idx: int, count: int) -> np.ndarray:
+        """Mock-Chebyshev samples of a node (Sec. 3.2) for scattered points.
+
+        q = ceil(count^(1/d)) Chebyshev-Lobatto nodes per dimension over the bounding box of the
+        node's points; for every node of the tensor grid (C order) the nearest point of the node
+        (Euclidean; ties go to the larger point number), duplicates removed in first-seen order.
+        A node with no more than q^d points is taken whole.
+        """
+        pts = self.points(level, idx)
+        q = 1
+        while q ** self.d < count:
+            q += 1
+        if len(pts) <= q ** self.d:
+            return pts
+        xyz = self.pts[pts]
+        lo, hi = xyz.min(axis=0), xyz.max(axis=0)
+        if q == 1:
+            nodes = [0.5 * (lo[qd] + hi[qd]) * np.ones(1) for qd in range(self.d)]
+        else:
+            c = 0.5 * (1.0 - np.cos(np.pi * np.arange(q) / (q - 1)))
+            nodes = [lo[qd] + (hi[qd] - lo[qd]) * c for qd in range(self.d)]
+        grids = np.meshgrid(*nodes, indexing="ij")
+        g = np.stack([gr.ravel() for gr in grids], axis=1)
+        d2 = ((g[:, None, :] - xyz[None, :, :]) ** 2).sum(axis=2)         # grid nodes x points
+        best = d2.min(axis=1, keepdims=True)
+        pick = np.where(d2 == best, pts[None, :], -1).max(axis=1)          # ties: larger point number
+        _, first = np.unique(pick, return_index=True)
+        return pick[np.sort(first)]
+
 
 def mock_chebyshev_points(tree: Tree, level: int, idx: int, count: int) -> np.ndarray:
     """About `count` lattice points of a box nearest to a tensor Chebyshev grid.
@@ -122,8 +202,10 @@ def column_id(X: np.ndarray, tol: float, kcap: int | None = None, rank: int | No
     ||X - X[:,skel][I T]Pi^T||_F = ||R22||_F <= sqrt(n-k) |R_{k+1,k+1}| and
     by the dense brute-force tests.
     """
-    R, piv = sla.qr(X, mode="r", pivoting=True)
     m, n = X.shape
+    if m == 0 or n == 0:       # an empty node on either side: nothing to compress
+        return 0, np.arange(n), np.zeros((0, n), complex), np.zeros(0)
+    R, piv = sla.qr(X, mode="r", pivoting=True)
     diag = np.abs(np.diag(R))
     if rank is not None:
         k = min(rank, m, n)
@@ -150,6 +232,14 @@ class MIDBF:
                  kcap: int | None = None, rank: int | None = None):
         self.K, self.tol, self.t, self.kcap, self.rank = K, tol, t, kcap, rank
         self.tree = Tree(K.d, K.n, leaf_box)
+        if getattr(K, "points", False):
+            # scattered points: the same box hierarchy over x in [0, 1)^d and over xi mapped from
+            # [-n/2, n/2)^d to [0, 1)^d
+            L = self.tree.L
+            self.tree_x = PointTree(K.x, L)
+            self.tree_xi = PointTree((K.xi + K.n / 2) / K.n, L)
+        else:
+            self.tree_x = self.tree_xi = self.tree
         tr = self.tree
         self.L, self.P = tr.L, tr.P
         if self.L < 1:
@@ -173,11 +263,13 @@ class MIDBF:
         tr, K = self.tree, self.K
         la, lb = self.L - s, s + 1
         prev = None if s == 0 else (self.rows[s - 1] if side == "row" else self.cols[s - 1])
+        # row side: candidates are x points, samples xi points; column side the reverse
+        ctree, stree = (self.tree_x, self.tree_xi) if side == "row" else (self.tree_xi, self.tree_x)
         out = {}
         kmax = 0
         for a in range(tr.count(la)):
             if s == 0:
-                cand_base = tr.points(la, a)
+                cand_base = ctree.points(la, a)
             for bb in range(tr.count(lb)):
                 if s == 0:
                     cand = cand_base
@@ -186,13 +278,13 @@ class MIDBF:
                     cand = np.concatenate([prev[(tr.child(a, t), pb)].skel for t in range(self.P)])
                 want = self.t * khat
                 while True:
-                    smp = mock_chebyshev_points(tr, lb, bb, want)
+                    smp = stree.samples(lb, bb, want)
                     if side == "row":          # rows of K(cand, :) -> CPQR of K(cand, smp)^T
                         X = K.entries(cand, smp).T
                     else:                      # columns of K(:, cand) -> CPQR of K(smp, cand)
                         X = K.entries(smp, cand)
                     k, piv, T, diag = column_id(X, self.tol, self.kcap, self.rank)
-                    box_pts = (tr.n >> lb) ** tr.d
+                    box_pts = stree.size(lb, bb)
                     if k >= X.shape[0] and X.shape[0] < min(box_pts, len(cand)):
                         want *= 2              # rank limited by the samples: enlarge (Sec. 3.2)
                         continue
@@ -230,6 +322,8 @@ class MIDBF:
         v2 = v.reshape(self.K.N, -1).astype(np.complex128)
         up = self.rows if adjoint else self.cols      # factors used going up
         down = self.cols if adjoint else self.rows    # factors used going down
+        tree_up = self.tree_x if adjoint else self.tree_xi      # candidates of the up side's leaves
+        tree_down = self.tree_xi if adjoint else self.tree_x
         # going up: y[(node at L-s, partner at s+1)] = (interp)^op y_cand
         y = None
         for s in range(self.b):
@@ -239,7 +333,7 @@ class MIDBF:
                 for bb in range(tr.count(lb)):
                     idd = up[s][(a, bb)]
                     if s == 0:
-                        yc = v2[tr.points(la, a)]
+                        yc = v2[tree_up.points(la, a)]
                     else:
                         pb = tr.parent(bb)
                         yc = np.concatenate([y[(tr.child(a, t), pb)] for t in range(P)])
@@ -290,7 +384,7 @@ class MIDBF:
                     w[piv[:k]] = zz
                     w[piv[k:]] = Top @ zz
                     if s == 0:
-                        out[tr.points(la, a)] += w
+                        out[tree_down.points(la, a)] += w
                     else:
                         pb = tr.parent(bb)
                         sizes = [down[s - 1][(tr.child(a, t), pb)].k for t in range(P)]

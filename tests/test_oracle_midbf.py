@@ -165,3 +165,60 @@ def test_fixed_rank_error_falls_with_the_rank():
     errs = [rel_l2(MIDBF(K, rank=r).apply(f), gd) for r in (24, 40, 56)]
     assert errs[0] > errs[1] > errs[2] > 0.0
     assert errs[2] < 1e-2
+
+
+# ---- scattered points (Sec. 3.5, closing paragraph; Example 2 of Sec. 4) -------------------
+
+def test_point_tree_on_the_lattice_is_the_lattice_tree():
+    from oracle.kernel import x_points
+    from oracle.midbf import PointTree
+    lat = Tree(2, 32, 8)
+    pt = PointTree(x_points(2, 32), lat.L)
+    for level in range(lat.L + 1):
+        for i in range(lat.count(level)):
+            a, b = np.sort(lat.points(level, i)), np.sort(pt.points(level, i))
+            assert np.array_equal(a, b), (level, i)
+    for i in range(lat.count(lat.L)):        # leaves list their points by increasing number
+        assert np.array_equal(lat.points(lat.L, i), pt.points(lat.L, i))
+
+
+def test_point_samples_are_node_points():
+    from oracle.midbf import PointTree
+    x, _ = W.random_points(2, 32, 40)
+    pt = PointTree(x, 2)
+    for level in (1, 2):
+        for i in range(pt.count(level)):
+            pts = pt.points(level, i)
+            for want in (9, 40, 400):
+                s = pt.samples(level, i, want)
+                q = int(np.ceil(want ** 0.5 - 1e-9))
+                assert len(np.unique(s)) == len(s) and set(s) <= set(pts)
+                if len(pts) <= q * q:
+                    assert np.array_equal(s, pts)
+                else:
+                    assert len(s) <= q * q
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_scattered_points_dense_brute_force(half):
+    # 2-D, N = 16^2 random points (half: x only in x_1 < 1/2, so half the nodes are empty); the
+    # factor product against K itself
+    x, xi = W.random_points(2, 16, 41, half=half)
+    K = Kernel(2, 16, "linear", points=(x, xi))
+    F = MIDBF(K, tol=1e-6, leaf_box=4)
+    assert F.L == 2
+    assert rel_l2(F.dense(), K.dense()) < 1e-5
+
+
+def test_scattered_points_3d_nuft_and_adjoint():
+    # Example 2 at N = 16^3: random x in [0,1)^3 and xi in [-8, 8)^3, Phi = x . xi
+    x, xi = W.random_points(3, 16, 42)
+    K = Kernel(3, 16, "linear", points=(x, xi))
+    F = MIDBF(K, tol=1e-6, leaf_box=4)
+    f = W.complex_gaussian(K.N, 2, 43)
+    rows = W.sample_rows(K.N, 5, 128)
+    assert rel_l2(F.apply(f)[rows], direct_sum(K, f, rows=rows)) < 1e-5
+    h = W.complex_gaussian(K.N, 2, 44)
+    lhs = np.vdot(h, F.apply(f))
+    rhs = np.vdot(F.apply_adjoint(h), f)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-13

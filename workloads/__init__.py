@@ -108,3 +108,16 @@ def random_lowrank_factors(N: int, r: int, *key: int) -> tuple[np.ndarray, np.nd
 def index_sample(N: int, count: int, *key: int) -> np.ndarray:
     """Random distinct indices (without replacement) in [0, N)."""
     return rng(*key).choice(N, min(count, N), replace=False)
+
+
+def random_points(d: int, n: int, *key: int, half: bool = False) -> tuple[np.ndarray, np.ndarray]:
+    """Scattered point sets of Example 2 (Section 4): N = n^d points x uniform in [0, 1)^d and N
+    frequencies xi = n (u - 1/2) with u uniform in [0, 1)^d (so xi spans the lattice's frequency box
+    [-n/2, n/2)^d).  half: x confined to x_1 < 1/2, leaving half of every level's nodes empty."""
+    g = rng(*key)
+    N = n ** d
+    x = g.random((N, d))
+    if half:
+        x[:, 0] *= 0.5
+    xi = n * (g.random((N, d)) - 0.5)
+    return x, xi
