@@ -103,6 +103,16 @@ typedef struct {
                             every ID keeps min(fixed_rank, samples, candidates) columns
                             whatever tol says, so each level's ranks are known before
                             the build; 0: the adaptive rank rule with tol                */
+    const double* x_points;  /* scattered points (Sec. 3.5, closing paragraph; Sec. 4 Ex. 2):
+                                N = n^d points x in [0, 1)^d, N x d row-major FP64, device  */
+    const double* xi_points; /* and N frequencies xi in [-n/2, n/2)^d, the same layout.  Both
+                                set: the trees partition these sets on the boxes of the
+                                n^d lattice's trees (leaf side leaf_box / n); a node without
+                                points holds none, leaves hold uneven counts.  Phase
+                                MIDBF_PHASE_LINEAR (Phi = x . xi on the given coordinates)
+                                or MIDBF_PHASE_LOWRANK (U, V rows per point).  Vectors are
+                                indexed by point number.  FP64 and FP32 copies only.  Both
+                                null: the lattices {0..n-1}^d / n and {0..n-1}^d - n/2      */
 } midbf_params;
 
 typedef struct {

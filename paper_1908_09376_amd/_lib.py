@@ -25,7 +25,8 @@ class Params(C.Structure):
     _fields_ = [("d", C.c_int), ("n", C.c_int), ("tol", C.c_double), ("leaf_box", C.c_int),
                 ("oversample_t", C.c_int), ("k_cap", C.c_int), ("phase", C.c_int),
                 ("U_dev", C.c_void_p), ("V_dev", C.c_void_p), ("r", C.c_int),
-                ("precisions", C.c_uint), ("build_workspace_bytes", C.c_size_t), ("fixed_rank", C.c_int)]
+                ("precisions", C.c_uint), ("build_workspace_bytes", C.c_size_t), ("fixed_rank", C.c_int),
+                ("x_points", C.c_void_p), ("xi_points", C.c_void_p)]
 
 
 class Stats(C.Structure):

@@ -78,6 +78,7 @@ struct LevelArgs {
     const long long* y_off;
     const void* const* T;    // per-ID factor block of the precision in use
     const int* src;          // split 16-bit up side: input row of every candidate position, or null
+    const int* slot;         // scattered points: leaf slot table of this side's tree (point or -1), or null
 };
 
 struct UpArgs {

@@ -53,13 +53,20 @@ template <class C> __device__ inline C wave_sum_c(C v) {
     return v;
 }
 
+// Point number of slot c of leaf a: the lattice point of the box, or with a
+// slot table (scattered points) the table's entry (-1 past the leaf's points).
+__device__ inline long long leaf_slot_point(const ApplyGeom& G, const int* slot, const int* origin, long long a,
+                                            int c) {
+    return slot ? (long long)slot[a * G.n0 + c] : box_point(origin, G.leaf, c, G.d, G.n);
+}
+
 // Gather the candidate vector of group (a, partner) into LDS: either the
 // leaf's points from an external column-major block or the P child pieces
 // of the previous level buffer.
 template <class C, int RT>
 __device__ int gather_candidates(C* s_x, const ApplyGeom& G, int s, long long a, long long partner, long long Ps,
                                  const C* ext, long long ld, const C* prev_buf, const int* k_prev,
-                                 const long long* yoff_prev, int nrhs, int r0, int nr) {
+                                 const long long* yoff_prev, int nrhs, int r0, int nr, const int* slot) {
     const int tid = threadIdx.x;
     if (s == 0) {
         int origin[3];
@@ -67,7 +74,8 @@ __device__ int gather_candidates(C* s_x, const ApplyGeom& G, int s, long long a,
         for (int e = tid; e < G.n0 * RT; e += AT) {
             const int c = e / RT, r = e - c * RT;
             C v = czero<C>();
-            if (r < nr) v = ext[(long long)(r0 + r) * ld + box_point(origin, G.leaf, c, G.d, G.n)];
+            const long long p = leaf_slot_point(G, slot, origin, a, c);
+            if (r < nr && p >= 0) v = ext[(long long)(r0 + r) * ld + p];
             s_x[e] = v;
         }
         return G.n0;
@@ -94,14 +102,15 @@ __device__ int gather_candidates(C* s_x, const ApplyGeom& G, int s, long long a,
 template <class C, int RT>
 __device__ void scatter_candidates(const C* s_w, const ApplyGeom& G, int s, long long a, long long partner,
                                    long long Ps, C* ext, long long ld, C* prev_buf, const int* k_prev,
-                                   const long long* yoff_prev, int nrhs, int r0, int nr) {
+                                   const long long* yoff_prev, int nrhs, int r0, int nr, const int* slot) {
     const int tid = threadIdx.x;
     if (s == 0) {
         int origin[3];
         node_origin(a, G.L, G.d, G.n, origin);
         for (int e = tid; e < G.n0 * RT; e += AT) {
             const int c = e / RT, r = e - c * RT;
-            if (r < nr) ext[(long long)(r0 + r) * ld + box_point(origin, G.leaf, c, G.d, G.n)] = s_w[e];
+            const long long p = leaf_slot_point(G, slot, origin, a, c);
+            if (r < nr && p >= 0) ext[(long long)(r0 + r) * ld + p] = s_w[e];
         }
         return;
     }
@@ -165,7 +174,7 @@ __device__ __forceinline__ void up_body(const UpArgs& A, long long g, int tile, 
     const int nr = min(RT, A.nrhs - r0);
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
     const int ncand = gather_candidates<C, RT>(s_x, A.G, A.s, a, ap, A.Ps, (const C*)A.ext, A.ld, (const C*)A.in,
-                                               A.k_prev, A.yoff_prev, A.nrhs, r0, nr);
+                                               A.k_prev, A.yoff_prev, A.nrhs, r0, nr, A.lev.slot);
     C* s_red = s_x + (size_t)A.ncand_max * RT;     // single RHS: AW strips of ncand_max values
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -301,7 +310,7 @@ __device__ __forceinline__ void down_body(const DownArgs& A, long long g, int ti
     }
     __syncthreads();
     scatter_candidates<C, RT>(s_w, A.G, A.s, a, bp, A.Ps, (C*)A.ext, A.ld, (C*)A.out, A.k_prev, A.yoff_prev,
-                              A.nrhs, r0, nr);
+                              A.nrhs, r0, nr, A.lev.slot);
 }
 
 template <class C, int RT>
@@ -429,7 +438,7 @@ __global__ __launch_bounds__(AT) void adj_up_kernel(UpArgs A) {
     const int nr = min(RT, A.nrhs - r0);
     const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
     gather_candidates<C, RT>(s_x, A.G, A.s, a, bp, A.Ps, (const C*)A.ext, A.ld, (const C*)A.in, A.k_prev,
-                             A.yoff_prev, A.nrhs, r0, nr);
+                             A.yoff_prev, A.nrhs, r0, nr, A.lev.slot);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     C* out = (C*)A.out;
@@ -562,7 +571,7 @@ __global__ __launch_bounds__(AT) void adj_down_kernel(DownArgs A) {
     }
     __syncthreads();
     scatter_candidates<C, RT>(s_w, A.G, A.s, a, ap, A.Ps, (C*)A.ext, A.ld, (C*)A.out, A.k_prev, A.yoff_prev,
-                              A.nrhs, r0, nr);
+                              A.nrhs, r0, nr, A.lev.slot);
 }
 
 // ---- a batch of forward transforms in one persistent launch ----

@@ -31,10 +31,12 @@ struct CandArgs {
     const int* skel_prev;
     int* cand;                  // wave x nmax
     int nmax;
+    const int* slot;            // scattered points: leaf slot table of the candidate tree, or null
+    int n0;                     // slots per leaf
 };
 
-// Candidate lattice points of each decomposition: the points of the leaf
-// (s = 0) or the children's skeletons against the partner's parent.
+// Candidate points of each decomposition: the points of the leaf (s = 0) or
+// the children's skeletons against the partner's parent.
 __global__ void cand_kernel(CandArgs A) {
     const int w = blockIdx.x;
     const long long id = A.id0 + w;
@@ -42,6 +44,10 @@ __global__ void cand_kernel(CandArgs A) {
     const int ncand = A.n_arr[w];
     int* out = A.cand + (long long)w * A.nmax;
     if (A.s == 0) {
+        if (A.slot) {
+            for (int c = threadIdx.x; c < ncand; c += BT) out[c] = A.slot[a * A.n0 + c];
+            return;
+        }
         int origin[3];
         node_origin(a, A.L, A.d, A.n, origin);
         for (int c = threadIdx.x; c < ncand; c += BT) out[c] = (int)box_point(origin, A.leaf, c, A.d, A.n);
@@ -70,9 +76,10 @@ struct GenArgs {
     int nmax;
     double2* X;
     long long x_stride;
+    const int* samp_tab;        // scattered points: per partner node m sample point numbers (-1: none), or null
 };
 
-// Sample matrix of decomposition w, row-major m x n:
+// Sample matrix of decomposition w, row-major m x n (rows of missing samples zero):
 //   row side:    X[i][c] = K(x = cand_c, xi = sample_i)   (X = K(cand, samples)^T)
 //   column side: X[i][c] = K(x = sample_i, xi = cand_c)   (X = K(samples, cand))
 __global__ void gen_kernel(GenArgs A) {
@@ -87,9 +94,11 @@ __global__ void gen_kernel(GenArgs A) {
     const long long total = (long long)A.m * n;
     for (long long e = (long long)blockIdx.x * BT + threadIdx.x; e < total; e += (long long)gridDim.x * BT) {
         const int i = (int)(e / n), c = (int)(e - (e / n) * n);
-        const long long sp = box_point(origin, A.box_side, A.samples[i], A.ph.d, A.ph.n);
+        const long long sp = A.samp_tab ? (long long)A.samp_tab[bb * A.m + i]
+                                        : box_point(origin, A.box_side, A.samples[i], A.ph.d, A.ph.n);
         const long long cp = cand[c];
-        X[e] = (A.side == SIDE_ROW) ? kernel_entry(A.ph, cp, sp) : kernel_entry(A.ph, sp, cp);
+        if (sp < 0) X[e] = make_double2(0.0, 0.0);
+        else X[e] = (A.side == SIDE_ROW) ? kernel_entry(A.ph, cp, sp) : kernel_entry(A.ph, sp, cp);
     }
 }
 
@@ -277,16 +286,109 @@ struct Scratch {
     int* perm = nullptr; int* cand = nullptr; int* k = nullptr; int* n = nullptr; long long* toff = nullptr;
     long long* tile_off = nullptr;
     int* samples = nullptr;
+    int* samp_tab = nullptr;                 // scattered points: per partner node sample lists
+    int* m_arr = nullptr;                    // scattered points: samples of each ID of a wave
     hipEvent_t ev[2] = {nullptr, nullptr};   // brackets of the ID launches
     long long wave = 0, xs = 0, vs = 0, ys = 0, nmax = 0;
     void release() {
         auto f = [](void* p) { if (p) (void)hipFree(p); };
-        f(X); f(V); f(Y); f(perm); f(cand); f(k); f(n); f(toff); f(samples); f(tile_off);
+        f(X); f(V); f(Y); f(perm); f(cand); f(k); f(n); f(toff); f(samples); f(tile_off); f(samp_tab); f(m_arr);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
         *this = Scratch();
     }
 };
+
+// ---- scattered points (Sec. 3.5, closing paragraph) ----------------------------------------
+// A point tree uses the boxes of the lattice tree: leaf of a point = the Z-order number of its box
+// at level L (digit j, root first, holds bit L-1-j of every box coordinate; coordinate 1 is the
+// most significant bit, Fig. 4).  Points are listed leaf by leaf and by increasing number inside a
+// leaf, so node (level, i) holds one contiguous run of the list; an empty node holds none.
+
+// Points leaf by leaf (order) and the start of every leaf's run (P^L + 1 entries).
+void point_tree(const std::vector<double>& pts, int d, int L, std::vector<int>& order,
+                std::vector<long long>& start) {
+    const long long N = (long long)pts.size() / d;
+    const int P = 1 << d, side = 1 << L;
+    const long long nleaf = ipow(P, L);
+    std::vector<long long> leaf(N);
+    for (long long i = 0; i < N; ++i) {
+        long long cell[3];
+        for (int q = 0; q < d; ++q)
+            cell[q] = std::min<long long>(side - 1, std::max<long long>(0, (long long)std::floor(pts[i * d + q] * side)));
+        long long lf = 0;
+        for (int j = 0; j < L; ++j) {
+            const int bit = L - 1 - j;
+            long long digit = 0;
+            for (int q = 0; q < d; ++q) digit |= ((cell[q] >> bit) & 1) << (d - 1 - q);
+            lf = lf * P + digit;
+        }
+        leaf[i] = lf;
+    }
+    start.assign(nleaf + 1, 0);
+    for (long long i = 0; i < N; ++i) ++start[leaf[i] + 1];
+    for (long long l = 0; l < nleaf; ++l) start[l + 1] += start[l];
+    order.assign(N, 0);
+    std::vector<long long> fill(start.begin(), start.end() - 1);
+    for (long long i = 0; i < N; ++i) order[fill[leaf[i]]++] = (int)i;     // counting sort, stable in i
+}
+
+// Mock-Chebyshev samples of node (level, idx) for scattered points (Sec. 3.2): q = ceil(want^(1/d))
+// Chebyshev-Lobatto nodes per dimension over the bounding box of the node's points; for every node
+// of the tensor grid (C order) the nearest point (ties: the larger point number), duplicates
+// removed in first-seen order.  A node with at most q^d points is taken whole.
+std::vector<int> point_samples(const std::vector<double>& pts, int d, int L, const std::vector<int>& order,
+                               const std::vector<long long>& start, int level, long long idx, long long want) {
+    const long long w = ipow(1 << d, L - level);
+    const long long a = start[idx * w], e = start[(idx + 1) * w];
+    int q = 1;
+    while (ipow(q, d) < want) ++q;
+    std::vector<int> out;
+    if (e - a <= ipow(q, d)) {
+        out.assign(order.begin() + a, order.begin() + e);
+        return out;
+    }
+    double lo[3], hi[3];
+    for (int k = 0; k < d; ++k) { lo[k] = 1e300; hi[k] = -1e300; }
+    for (long long t = a; t < e; ++t)
+        for (int k = 0; k < d; ++k) {
+            const double v = pts[(long long)order[t] * d + k];
+            lo[k] = std::min(lo[k], v);
+            hi[k] = std::max(hi[k], v);
+        }
+    std::vector<double> c(q);
+    for (int j = 0; j < q; ++j) c[j] = q == 1 ? 0.5 : 0.5 * (1.0 - std::cos(M_PI * j / (q - 1)));
+    const long long G = ipow(q, d);
+    std::vector<char> seen;
+    std::vector<int> picked;
+    picked.reserve(G);
+    for (long long gi = 0; gi < G; ++gi) {
+        double g[3];
+        long long r = gi;
+        for (int k = d - 1; k >= 0; --k) { g[k] = lo[k] + (hi[k] - lo[k]) * c[r % q]; r /= q; }
+        double best = 1e300;
+        int bp = -1;
+        for (long long t = a; t < e; ++t) {
+            const int p = order[t];
+            double s = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double dv = g[k] - pts[(long long)p * d + k];
+                s += dv * dv;
+            }
+            if (s < best || (s == best && p > bp)) { best = s; bp = p; }
+        }
+        picked.push_back(bp);
+    }
+    std::vector<int> sorted(picked);
+    std::sort(sorted.begin(), sorted.end());
+    sorted.erase(std::unique(sorted.begin(), sorted.end()), sorted.end());
+    seen.assign(sorted.size(), 0);
+    for (int p : picked) {
+        const size_t pos = std::lower_bound(sorted.begin(), sorted.end(), p) - sorted.begin();
+        if (!seen[pos]) { seen[pos] = 1; out.push_back(p); }
+    }
+    return out;
+}
 
 // The decompositions of one step and side as read from a factor file: sample
 // count, candidate count and rank per ID, pivot orders (concatenated) and the
@@ -304,26 +406,50 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
                  const ReplayLevel* rl = nullptr) {
     const int P = h->P, d = h->d;
     const int side_len = h->n >> lv.lb;
+    const long long nid = lv.nid;
+    const long long nB = ipow(P, lv.lb);
+    const long long Ps = ipow(P, lv.s);
+    // the candidate tree is this side's (rows: x, columns: xi), the samples come from the other
+    const int ct = lv.side == SIDE_ROW ? 0 : 1, stt = 1 - ct;
     std::vector<int> samples;
+    std::vector<int> m_part, size_part, samp_tab;      // scattered points, per partner node
     if (rl) lv.m = rl->m;
-    else {
+    else if (h->points) {
+        std::vector<std::vector<int>> lists(nB);
+        m_part.assign(nB, 0);
+        size_part.assign(nB, 0);
+        int mm = 1;
+        const long long w = ipow(P, h->L - lv.lb);
+        for (long long bb = 0; bb < nB; ++bb) {
+            lists[bb] = point_samples(h->tree_pts[stt], d, h->L, h->tree_order[stt], h->tree_start[stt], lv.lb, bb,
+                                      want);
+            m_part[bb] = (int)lists[bb].size();
+            size_part[bb] = (int)(h->tree_start[stt][(bb + 1) * w] - h->tree_start[stt][bb * w]);
+            mm = std::max(mm, m_part[bb]);
+        }
+        lv.m = mm;
+        samp_tab.assign((size_t)nB * mm, -1);
+        for (long long bb = 0; bb < nB; ++bb)
+            std::copy(lists[bb].begin(), lists[bb].end(), samp_tab.begin() + bb * mm);
+    } else {
         samples = mock_chebyshev_local(d, side_len, want);
         lv.m = (int)samples.size();
     }
     MIDBF_CHECK(lv.m <= ID_MMAX, MIDBF_ERR_SHAPE, "too many samples per decomposition");
-    const long long nid = lv.nid;
-    const long long nB = ipow(P, lv.lb);
-    const long long Ps = ipow(P, lv.s);
     // candidate counts
     lv.n.assign(nid, 0);
     for (long long id = 0; id < nid; ++id) {
-        if (lv.s == 0) { lv.n[id] = h->n0; continue; }
+        if (lv.s == 0) {
+            const long long a = id / nB;
+            lv.n[id] = h->points ? (int)(h->tree_start[ct][a + 1] - h->tree_start[ct][a]) : h->n0;
+            continue;
+        }
         const long long a = id / nB, pb = (id % nB) / P;
         int c = 0;
         for (int t = 0; t < P; ++t) c += prev->k[((long long)P * a + t) * Ps + pb];
         lv.n[id] = c;
     }
-    lv.nmax = *std::max_element(lv.n.begin(), lv.n.end());
+    lv.nmax = std::max(1, *std::max_element(lv.n.begin(), lv.n.end()));
     MIDBF_CHECK(lv.nmax <= ID_NMAX, MIDBF_ERR_SHAPE, "too many candidates per decomposition (rank too large)");
     if (rl) MIDBF_CHECK(rl->n == lv.n, MIDBF_ERR_IO, "factor file: candidate counts do not follow from its ranks");
     lv.perm_off.assign(nid + 1, 0);
@@ -361,9 +487,14 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
     sc.k = dalloc<int>(wave);
     sc.toff = dalloc<long long>(wave);
     sc.tile_off = dalloc<long long>(wave);
-    if (!rl) {
+    if (!rl && !h->points) {
         sc.samples = dalloc<int>(m);
         upload(sc.samples, samples, st);
+    }
+    if (!rl && h->points) {
+        sc.samp_tab = dalloc<int>(samp_tab.size());
+        upload(sc.samp_tab, samp_tab, st);
+        sc.m_arr = dalloc<int>(wave);
     }
     for (hipEvent_t& e : sc.ev) MIDBF_HIP(hipEventCreate(&e));
     long long t_read = 0;      // replay: T entries of the waves done
@@ -377,18 +508,24 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             const int cnt = (int)std::min<long long>(wave, nid - id0);
             CandArgs ca{lv.s, P, d, h->n, h->L, h->leaf, lv.la, lv.lb, id0, Ps, nB, lv.d_n + id0,
                         prev ? prev->d_k : nullptr, prev ? prev->d_y_off : nullptr, prev ? prev->d_skel : nullptr,
-                        sc.cand, (int)nmax};
+                        sc.cand, (int)nmax, h->points ? h->d_slot[ct] : nullptr, h->n0};
             hipLaunchKernelGGL(cand_kernel, dim3(cnt), dim3(BT), 0, st, ca);
             MIDBF_HIP(hipGetLastError());
             std::vector<int> kw(cnt);
             if (!rl) {
                 GenArgs ga{h->ph, lv.side, lv.lb, id0, nB, (int)m, sc.samples, side_len, lv.d_n + id0, sc.cand,
-                           (int)nmax, sc.X, sc.xs};
+                           (int)nmax, sc.X, sc.xs, sc.samp_tab};
+                if (h->points) {
+                    std::vector<int> mw(cnt);
+                    for (int w = 0; w < cnt; ++w) mw[w] = m_part[(id0 + w) % nB];
+                    upload(sc.m_arr, mw, st);
+                    MIDBF_HIP(hipStreamSynchronize(st));
+                }
                 const int gx = (int)std::min<long long>((m * nmax + BT - 1) / BT, 64);
                 hipLaunchKernelGGL(gen_kernel, dim3(gx, cnt), dim3(BT), 0, st, ga);
                 MIDBF_HIP(hipGetLastError());
                 IdBatch ib{sc.X, sc.xs, sc.V, sc.vs, sc.Y, sc.ys, sc.perm, nmax, sc.k, lv.d_n + id0, 0, (int)m,
-                           h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side), h->p.fixed_rank};
+                           h->p.tol, h->p.k_cap, 0x5eedu + (unsigned)(lv.s * 2 + lv.side), h->p.fixed_rank, sc.m_arr};
                 MIDBF_HIP(hipEventRecord(ev[0], st));
                 launch_id_batch(ib, cnt, st);
                 MIDBF_HIP(hipEventRecord(ev[1], st));
@@ -438,7 +575,11 @@ bool build_level(midbf_plan* h, LevelSide& lv, const LevelSide* prev, long long 
             for (int w = 0; w < cnt; ++w) {
                 const long long id = id0 + w;
                 const int k = kw[w], nn = lv.n[id];
-                if (!rl && k >= m && m < box_pts && m < nn) saturated = true;
+                if (!rl && !h->points && k >= m && m < box_pts && m < nn) saturated = true;
+                if (!rl && h->points) {
+                    const int mp = m_part[id % nB];
+                    if (k >= mp && mp < size_part[id % nB] && mp < nn) saturated = true;
+                }
                 lv.k[id] = k;
                 lv.y_off[id] = yrun;
                 yrun += k;
@@ -701,6 +842,10 @@ void destroy_plan(midbf_plan* h) {
     f(h->d_tmax);
     f(h->own_U);
     f(h->own_V);
+    f(h->own_xp);
+    f(h->own_wp);
+    f(h->d_slot[0]);
+    f(h->d_slot[1]);
     for (int q = 0; q < NPREC; ++q) {
         f(h->ws[q].buf[0]);
         f(h->ws[q].buf[1]);
@@ -803,12 +948,22 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
         MIDBF_CHECK(p.d == 2, MIDBF_ERR_ARG, "this phase is two-dimensional");
     if (p.phase == MIDBF_PHASE_ISO3D) MIDBF_CHECK(p.d == 3, MIDBF_ERR_ARG, "this phase is three-dimensional");
     MIDBF_CHECK(p.phase >= MIDBF_PHASE_LINEAR && p.phase <= MIDBF_PHASE_LOWRANK, MIDBF_ERR_ARG, "unknown phase");
+    const bool points = p.x_points || p.xi_points;
+    if (points) {
+        MIDBF_CHECK(p.x_points && p.xi_points, MIDBF_ERR_ARG, "scattered points need both x_points and xi_points");
+        MIDBF_CHECK(p.phase == MIDBF_PHASE_LINEAR || p.phase == MIDBF_PHASE_LOWRANK, MIDBF_ERR_ARG,
+                    "scattered points take the linear phase (x . xi) or the low-rank phase");
+        MIDBF_CHECK(!rf, MIDBF_ERR_UNIMPLEMENTED, "factor files hold lattice factorizations");
+        MIDBF_CHECK(!(p.precisions & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)), MIDBF_ERR_UNIMPLEMENTED,
+                    "scattered points keep the FP64 and FP32 copies only");
+    }
 
     midbf_plan* h = new midbf_plan();
     try {
         h->p = p;
         if (h->p.build_workspace_bytes == 0) h->p.build_workspace_bytes = (size_t)48 << 30;
-        h->keep = p.precisions ? p.precisions : (MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16);
+        h->keep = p.precisions ? p.precisions
+                               : (MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | (points ? 0u : (unsigned)MIDBF_KEEP_BF16));
         MIDBF_CHECK((h->keep & ~(MIDBF_KEEP_FP64 | MIDBF_KEEP_FP32 | MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) == 0,
                     MIDBF_ERR_ARG, "unknown precision bits");
         h->d = p.d; h->n = p.n; h->P = 1 << p.d; h->L = L; h->leaf = p.leaf_box;
@@ -834,14 +989,50 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
             h->p.U_dev = h->own_U;
             h->p.V_dev = h->own_V;
         }
-        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, h->p.U_dev, h->p.V_dev, p.r};
+        if (points) {
+            // own copies of the coordinates, host copies for the trees (xi mapped to [0, 1)^d), and
+            // per side the leaf slot tables, n0 slots per leaf (the fullest leaf of either tree)
+            h->points = true;
+            const size_t cnt = (size_t)h->N * p.d;
+            h->own_xp = dalloc<double>(cnt);
+            h->own_wp = dalloc<double>(cnt);
+            MIDBF_HIP(hipMemcpyAsync(h->own_xp, p.x_points, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+            MIDBF_HIP(hipMemcpyAsync(h->own_wp, p.xi_points, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+            MIDBF_HIP(hipStreamSynchronize(st));
+            h->tree_pts[0].resize(cnt);
+            h->tree_pts[1].resize(cnt);
+            MIDBF_HIP(hipMemcpy(h->tree_pts[0].data(), h->own_xp, cnt * sizeof(double), hipMemcpyDeviceToHost));
+            MIDBF_HIP(hipMemcpy(h->tree_pts[1].data(), h->own_wp, cnt * sizeof(double), hipMemcpyDeviceToHost));
+            for (double& v : h->tree_pts[1]) v = (v + 0.5 * p.n) / p.n;
+            int n0 = 1;
+            const long long nleaf = ipow(h->P, L);
+            for (int t = 0; t < 2; ++t) {
+                point_tree(h->tree_pts[t], p.d, L, h->tree_order[t], h->tree_start[t]);
+                for (long long l = 0; l < nleaf; ++l)
+                    n0 = std::max<int>(n0, (int)(h->tree_start[t][l + 1] - h->tree_start[t][l]));
+            }
+            MIDBF_CHECK(n0 <= ID_NMAX, MIDBF_ERR_SHAPE, "a leaf holds more points than a decomposition takes");
+            h->n0 = n0;
+            for (int t = 0; t < 2; ++t) {
+                std::vector<int> slot((size_t)nleaf * n0, -1);
+                for (long long l = 0; l < nleaf; ++l)
+                    for (long long c = h->tree_start[t][l]; c < h->tree_start[t][l + 1]; ++c)
+                        slot[l * n0 + (c - h->tree_start[t][l])] = h->tree_order[t][c];
+                h->d_slot[t] = dalloc<int>(slot.size());
+                upload(h->d_slot[t], slot, st);
+                MIDBF_HIP(hipStreamSynchronize(st));
+            }
+            h->p.x_points = h->own_xp;
+            h->p.xi_points = h->own_wp;
+        }
+        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, h->p.U_dev, h->p.V_dev, p.r, h->own_xp, h->own_wp};
         h->rows.resize(h->b);
         h->cols.resize(h->b);
         if (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) {
             h->d_tmax = dalloc<unsigned>(1);
             MIDBF_HIP(hipMemsetAsync(h->d_tmax, 0, sizeof(unsigned), st));
         }
-        long long khat[2] = {h->n0, h->n0};
+        long long khat[2] = {ipow(p.leaf_box, p.d), ipow(p.leaf_box, p.d)};
         for (int s = 0; s < h->b; ++s) {
             for (int side = 0; side < 2; ++side) {
                 LevelSide& lv = side == SIDE_ROW ? h->rows[s] : h->cols[s];
@@ -934,6 +1125,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
 void save_plan(midbf_plan* h, const char* path, hipStream_t st) {
     MIDBF_CHECK(path, MIDBF_ERR_ARG, "null path");
     MIDBF_CHECK(h->keep & MIDBF_KEEP_FP64, MIDBF_ERR_ARG, "saving needs the FP64 factor copy (MIDBF_KEEP_FP64)");
+    MIDBF_CHECK(!h->points, MIDBF_ERR_UNIMPLEMENTED, "factor files hold lattice factorizations");
     MIDBF_HIP(hipStreamSynchronize(st));
     File F(path, "wb");
     FileHead H{};
@@ -1008,7 +1200,7 @@ midbf_plan* load_plan(const char* path, unsigned precisions, hipStream_t st, mid
 
 void kernel_entries(const midbf_params& p, const int* rows, int nrows, const int* cols, int ncols, void* out,
                     hipStream_t st) {
-    PhaseDesc ph{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r};
+    PhaseDesc ph{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r, p.x_points, p.xi_points};
     const long long tot = (long long)nrows * ncols;
     if (tot == 0) return;
     const int gx = (int)std::min<long long>((tot + BT - 1) / BT, 4096);

@@ -57,7 +57,14 @@ int prec_index(midbf_precision p) {
 }
 
 LevelArgs level_args(const LevelSide& lv, int prec) {
-    return LevelArgs{lv.d_k, lv.d_n, lv.d_perm_off, lv.d_perm, lv.d_y_off, (const void* const*)lv.d_T[prec], lv.d_src};
+    return LevelArgs{lv.d_k, lv.d_n, lv.d_perm_off, lv.d_perm, lv.d_y_off, (const void* const*)lv.d_T[prec], lv.d_src,
+                     nullptr};
+}
+
+LevelArgs level_args(const midbf_plan* h, const LevelSide& lv, int prec) {
+    LevelArgs a = level_args(lv, prec);
+    if (h->points) a.slot = h->d_slot[lv.side];
+    return a;
 }
 
 size_t csize(int prec) { return prec == PREC_FP64 ? 16 : 8; }
@@ -312,7 +319,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         }
         UpArgs& a = D.a.up;
         a.G = G;
-        a.lev = level_args(lv, prec);
+        a.lev = level_args(h, lv, prec);
         a.s = s;
         a.Ps = ipow(h->P, s);
         a.ext = in_ext;
@@ -343,7 +350,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         D.flops = fl * lv.entries * nrhs;
         D.mfma_count = mfma ? lv.nid : 0;
         D.level = s;
-        if (mfma && s == 0 && lv.entries == 0 && h->n0 <= 64 && !adjoint && prec != PREC_FP64) {
+        if (mfma && s == 0 && lv.entries == 0 && h->n0 <= 64 && !adjoint && prec != PREC_FP64 && !h->points) {
             // every leaf keeps all its points: a staged copy per leaf (vin read once)
             D.which = LevelKernel::UpLeafCopy;
             D.mfma_count = groups;
@@ -432,7 +439,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         LaunchDesc D{};
         DownArgs& a = D.a.down;
         a.G = G;
-        a.lev = level_args(lv, prec);
+        a.lev = level_args(h, lv, prec);
         a.s = s;
         a.Ps = ipow(h->P, s);
         a.in = buf[o ^ 1];
@@ -555,6 +562,8 @@ ApplyMode apply_mode(const midbf_plan* h, int nrhs, int prec, bool adjoint) {
         h->max_n <= BF16_CROW_MAX && h->mid.nr_max <= BF16_CROW_MAX && h->mid.nc_max <= BF16_CROW_MAX;
     MIDBF_CHECK(!is_split16(prec) || (!adjoint && fits_bf16), MIDBF_ERR_UNIMPLEMENTED,
                 "the split 16-bit applies exist for the forward transform with candidate sets up to 2048");
+    MIDBF_CHECK(!is_split16(prec) || !h->points, MIDBF_ERR_UNIMPLEMENTED,
+                "scattered points are applied in FP64 and FP32");
     ApplyMode m;
     m.mfma = is_split16(prec) || ((prec == PREC_FP32 || prec == PREC_FP64) && nrhs >= MFMA_MIN_NRHS && fits);
     m.lat = m.mfma && (nrhs > 1 || is_split16(prec));

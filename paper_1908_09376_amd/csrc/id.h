@@ -29,6 +29,7 @@ struct IdBatch {
     int kcap;            // 0: none
     unsigned seed;
     int kfixed;          // > 0: keep exactly min(kfixed, m, n) pivots (the rank rule is not used)
+    const int* m_arr;    // per-decomposition count of real sample rows (rows beyond are zero), or null: m
 };
 
 void launch_id_batch(const IdBatch& B, int batch, hipStream_t s);

@@ -214,8 +214,9 @@ __global__ __launch_bounds__(NT, ID_WAVES_PER_SIMD) void id_kernel(IdBatch B) {
         return;
     }
     const double thresh2 = B.tol * B.tol * ref2;
-    // the fixed-rank variant factors exactly kstop pivots; the adaptive one stops by the rank rule
-    const int mn = min(m, n);
+    // the fixed-rank variant factors exactly kstop pivots; the adaptive one stops by the rank rule.
+    // Rows past a decomposition's own sample count are zero and add no rank.
+    const int mn = min(B.m_arr ? min(B.m_arr[bid], m) : m, n);
     const int kstop = B.kfixed > 0 ? min(B.kfixed, mn) : mn;
 
     int k = -1, j0 = 0;

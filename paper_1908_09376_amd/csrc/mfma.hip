@@ -239,11 +239,17 @@ __device__ inline void zero_acc(Acc (&cr)[MTW][4], Acc (&ci)[MTW][4]) {
 }
 
 // Row numbers of a group's candidate vector in the previous level buffer
-// (or lattice points of the leaf when s == 0).
+// (or points of the leaf when s == 0: the lattice box's, or with a slot table
+// the leaf's first nleaf slots).
 template <int NT>
 __device__ int candidate_rows(int* crow, const ApplyGeom& G, int s, long long a, long long partner, long long Ps,
-                              const int* k_prev, const long long* yoff_prev) {
+                              const int* k_prev, const long long* yoff_prev, const int* slot = nullptr,
+                              int nleaf = 0) {
     if (s == 0) {
+        if (slot) {
+            for (int c = threadIdx.x; c < nleaf; c += NT) crow[c] = slot[a * G.n0 + c];
+            return nleaf;
+        }
         int origin[3];
         node_origin(a, G.L, G.d, G.n, origin);
         for (int c = threadIdx.x; c < G.n0; c += NT) crow[c] = (int)box_point(origin, G.leaf, c, G.d, G.n);
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(C::NT) void up_mfma(UpArgs A, long long nid) {
     const long long a = g / A.Ps, ap = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * C::W;
     const int nr = min(C::W, A.nrhs - r0);
-    candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev);
+    candidate_rows<C::NT>(crow, A.G, A.s, a, ap, A.Ps, A.k_prev, A.yoff_prev, A.lev.slot, A.lev.n[g * A.G.P]);
     // the leaves read the caller's block, or its row-major copy (A.ext null)
     const bool ext = A.s == 0 && A.ext;
     const C2* xin = ext ? (const C2*)A.ext : (const C2*)A.in;
@@ -408,7 +414,8 @@ __global__ __launch_bounds__(MT) void down_sum(DownArgs A, const C2* scr) {
     const long long a = g / A.Ps, bp = g - (g / A.Ps) * A.Ps;
     const int r0 = blockIdx.y * NRHS;
     const int nr = min(NRHS, A.nrhs - r0);
-    const int ncand = candidate_rows<MT>(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev);
+    const int ncand = candidate_rows<MT>(crow, A.G, A.s, a, bp, A.Ps, A.k_prev, A.yoff_prev, A.lev.slot,
+                                         A.lev.n[g * A.G.P]);
     if (threadIdx.x < A.G.P) base[threadIdx.x] = A.lev.perm_off[g * A.G.P + threadIdx.x] * A.nrhs + r0;
     __syncthreads();
     const bool ext = A.s == 0 && A.ext;

@@ -14,6 +14,8 @@ struct PhaseDesc {
     const double* U;      // MIDBF_PHASE_LOWRANK: N x r row-major
     const double* V;
     int r;
+    const double* xp;     // scattered points: x and xi coordinates (N x d row-major), or null
+    const double* wp;
 };
 
 // Smooth (non-bilinear) part of the phase at x = a/n, xi = b - n/2.
@@ -50,13 +52,20 @@ __device__ inline double phase_smooth(const PhaseDesc& ph, const int* a, const i
     }
 }
 
-// frac(Phi(x_p, xi_q)) in [0, 1) for lattice point numbers p (x side), q (xi side).
+// frac(Phi(x_p, xi_q)) in [0, 1) for point numbers p (x side), q (xi side).
 __device__ inline double phase_frac(const PhaseDesc& ph, long long p, long long q) {
     if (ph.kind == MIDBF_PHASE_LOWRANK) {
         const double* u = ph.U + p * ph.r;
         const double* v = ph.V + q * ph.r;
         double s = 0.0;
         for (int l = 0; l < ph.r; ++l) s = fma(u[l], v[l], s);
+        return s - floor(s);
+    }
+    if (ph.xp) {            // Phi = x . xi on given point sets, in FP64
+        const double* x = ph.xp + p * ph.d;
+        const double* w = ph.wp + q * ph.d;
+        double s = 0.0;
+        for (int l = 0; l < ph.d; ++l) s = fma(x[l], w[l], s);
         return s - floor(s);
     }
     int a[3], b[3];

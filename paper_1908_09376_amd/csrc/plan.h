@@ -128,6 +128,16 @@ struct midbf_plan {
     unsigned* d_tmax = nullptr;   // build only: largest |re|, |im| of the T entries packed into 16-bit tiles
     double* own_U = nullptr;      // low-rank phase: the plan's own copies of U and V (N x r)
     double* own_V = nullptr;
+    // scattered points: own coordinate copies (x, xi; N x d) and, per side (row: the x tree,
+    // column: the xi tree), the leaves' slot tables (leaf a, slot c < n0 -> point number, or -1
+    // past the leaf's points) and the host trees (points leaf by leaf, leaf starts)
+    bool points = false;
+    double* own_xp = nullptr;
+    double* own_wp = nullptr;
+    int* d_slot[2] = {nullptr, nullptr};
+    std::vector<double> tree_pts[2];      // coordinates in [0, 1)^d
+    std::vector<int> tree_order[2];
+    std::vector<long long> tree_start[2];
     int max_n = 0, max_k = 0;
     midbf::Profiler prof;
     // matrix-core tile variant per kernel kind (up, down, middle) and MSCS step (FP32, split-bf16, split-fp16)

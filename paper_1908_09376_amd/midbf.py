@@ -21,7 +21,7 @@ def _stream_ptr(stream) -> int:
 
 
 def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, precisions=0,
-            workspace_bytes=0, fixed_rank=0) -> L.Params:
+            workspace_bytes=0, fixed_rank=0, points=None) -> L.Params:
     p = L.Params()
     p.d, p.n, p.tol = d, n, tol
     p.leaf_box, p.oversample_t, p.k_cap = leaf_box, oversample_t, k_cap
@@ -32,6 +32,9 @@ def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, pre
     p.precisions = precisions
     p.build_workspace_bytes = workspace_bytes
     p.fixed_rank = fixed_rank
+    if points is not None:
+        p.x_points = points[0].data_ptr()
+        p.xi_points = points[1].data_ptr()
     return p
 
 
@@ -44,14 +47,20 @@ class MIDBF:
     def __init__(self, d: int, n: int, phase: str, tol: float = 1e-6, leaf_box: int = 8,
                  oversample_t: int = 5, k_cap: int = 0, U: torch.Tensor | None = None,
                  V: torch.Tensor | None = None, precisions: int = 0, workspace_bytes: int = 0,
-                 fixed_rank: int = 0, stream=None):
+                 fixed_rank: int = 0, points=None, stream=None):
         self.d, self.n, self.N = d, n, n ** d
         if phase == "lowrank":
             U = U.to(torch.float64).contiguous()
             V = V.to(torch.float64).contiguous()
-        self._UV = (U, V)       # kept alive: the library reads them during the build
+        if points is not None:
+            # scattered points (N = n^d each): x in [0, 1)^d and xi in [-n/2, n/2)^d, N x d FP64
+            points = tuple(t.to(torch.float64).contiguous() for t in points)
+            for t in points:
+                if not t.is_cuda or t.shape != (self.N, d):
+                    raise ValueError("points: two CUDA tensors of shape (n^d, d)")
+        self._UV = (U, V, points)    # kept alive: the library reads them during the build
         self._p = _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U, V, precisions,
-                          workspace_bytes, fixed_rank)
+                          workspace_bytes, fixed_rank, points)
         h = C.c_void_p()
         L.check(L.lib.midbf_build(C.byref(self._p), _stream_ptr(stream), C.byref(h)))
         self._h = h
