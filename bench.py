@@ -199,7 +199,8 @@ def cpu_baseline(w, f_np, rows):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count()
-    K = Kernel(w.d, w.n, w.phase)
+    import workloads as W
+    K = Kernel(w.d, w.n, w.phase, points=W.workload_points(w))
     times, gd = [], None
     for _ in range(3):
         t0 = time.perf_counter()
@@ -398,7 +399,11 @@ def main() -> int:
         F = M.MIDBF(w.d, w.n, "lowrank", tol=w.tol, leaf_box=w.leaf_box, U=U, V=V, precisions=keep)
     else:
         t0 = time.perf_counter()
-        F = M.MIDBF(w.d, w.n, w.phase, tol=w.tol, leaf_box=w.leaf_box, precisions=keep)
+        pts = W.workload_points(w)
+        if pts is not None:      # scattered points: FP64 and FP32 copies only
+            keep &= 1 | 2
+            pts = tuple(torch.from_numpy(a).to("cuda:0") for a in pts)
+        F = M.MIDBF(w.d, w.n, w.phase, tol=w.tol, leaf_box=w.leaf_box, precisions=keep, points=pts)
     build_s = time.perf_counter() - t0
     st = F.stats()
     log(f"[bench] built in {build_s:.2f} s: L={st['L']} ranks {st['k_min']}..{st['k_max']} "

@@ -104,11 +104,12 @@ typedef struct {
                             whatever tol says, so each level's ranks are known before
                             the build; 0: the adaptive rank rule with tol                */
     const double* x_points;  /* scattered points (Sec. 3.5, closing paragraph; Sec. 4 Ex. 2):
-                                N = n^d points x in [0, 1)^d, N x d row-major FP64, device  */
-    const double* xi_points; /* and N frequencies xi in [-n/2, n/2)^d, the same layout.  Both
-                                set: the trees partition these sets on the boxes of the
-                                n^d lattice's trees (leaf side leaf_box / n); a node without
-                                points holds none, leaves hold uneven counts.  Phase
+                                N = n^d points x, N x d row-major FP64, device            */
+    const double* xi_points; /* and N frequencies xi, the same layout.  Both set: each set
+                                is moved and scaled uniformly into [0, 1]^d by its bounding
+                                cube and partitioned on the boxes of the n^d lattice's tree
+                                (depth log2(n / leaf_box)); a node without points holds
+                                none, leaves hold uneven counts.  Phase
                                 MIDBF_PHASE_LINEAR (Phi = x . xi on the given coordinates)
                                 or MIDBF_PHASE_LOWRANK (U, V rows per point).  Vectors are
                                 indexed by point number.  FP64 and FP32 copies only.  Both
@@ -372,6 +373,30 @@ typedef struct {
 midbf_status phase_recover(int d, int n, const double* X1, const double* X2, midbf_sample_cb cb, void* user,
                            int r, int q, double tau, uint64_t seed, void* stream, double* U_dev,
                            double* V_dev, phase_recover_info* info);
+
+/*
+ * phase_recover_points -- phase_recover for scattered point sets (Sec. 3.5,
+ * closing paragraph; Sec. 4 Example 2): X1 and X2 are the host N x d row-major
+ * coordinates of the x and xi points (both required).  The recovery paths are
+ * those of midbf_recovery_path rooted at point 0 of each set; flagged nodes are
+ * taken in path order; everything else is phase_recover's.
+ * Errors: as phase_recover.
+ */
+midbf_status phase_recover_points(int d, long long N, const double* X1, const double* X2, midbf_sample_cb cb,
+                                  void* user, int r, int q, double tau, uint64_t seed, void* stream, double* U_dev,
+                                  double* V_dev, phase_recover_info* info);
+
+/*
+ * midbf_recovery_path -- the recovery path of a point set (Alg. 5, Def. 2.3):
+ * the minimum spanning tree of the Euclidean distances (the Delaunay graph
+ * the paper builds first holds every edge of it, so the tree is the same),
+ * computed on the device by Prim's algorithm (ties to the smaller point
+ * number), then a breadth-first order from `root` with neighbours visited by
+ * increasing number.  pts: host N x d row-major coordinates (d = 2 or 3);
+ * P_out: host (N - 1) x 2 int32, row t = (predecessor, node), in
+ * non-decreasing depth.  Synchronizes `stream`.  Errors: _ARG, _OOM, _HIP.
+ */
+midbf_status midbf_recovery_path(const double* pts, long long N, int d, long long root, int* P_out, void* stream);
 
 /* Sizes and ranks of a built factorization. */
 midbf_status midbf_factor_stats(midbf_handle h, midbf_stats* out);

@@ -82,6 +82,14 @@ class Tree:
         return mock_chebyshev_points(self, level, idx, count)
 
 
+def unit_cube(pts: np.ndarray) -> np.ndarray:
+    """A point set moved and scaled uniformly into [0, 1]^d: (p - min) / (largest extent)."""
+    p = np.asarray(pts, dtype=np.float64)
+    lo = p.min(axis=0)
+    s = float((p.max(axis=0) - lo).max())
+    return (p - lo) / (s if s > 0 else 1.0)
+
+
 class PointTree:
     """Z-ordered 2^d-ary tree over a point set in [0, 1)^d (Sec. 3.5, closing paragraph).
 
@@ -233,11 +241,10 @@ class MIDBF:
         self.K, self.tol, self.t, self.kcap, self.rank = K, tol, t, kcap, rank
         self.tree = Tree(K.d, K.n, leaf_box)
         if getattr(K, "points", False):
-            # scattered points: the same box hierarchy over x in [0, 1)^d and over xi mapped from
-            # [-n/2, n/2)^d to [0, 1)^d
+            # scattered points: the lattice tree's box hierarchy over each set's bounding cube
             L = self.tree.L
-            self.tree_x = PointTree(K.x, L)
-            self.tree_xi = PointTree((K.xi + K.n / 2) / K.n, L)
+            self.tree_x = PointTree(unit_cube(K.x), L)
+            self.tree_xi = PointTree(unit_cube(K.xi), L)
         else:
             self.tree_x = self.tree_xi = self.tree
         tr = self.tree

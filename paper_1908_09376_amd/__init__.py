@@ -8,7 +8,8 @@ decompositions) and applies g = K f and f = K^H g level by level.
 The binding is loaded on first use, so that `build_lib` can run before the
 library exists.
 """
-_EXPORTS = ("MIDBF", "ApplyGraph", "Batch", "apply_batched", "id_batch", "kernel_entries", "phase_recover")
+_EXPORTS = ("MIDBF", "ApplyGraph", "Batch", "apply_batched", "id_batch", "kernel_entries", "phase_recover",
+            "recovery_path")
 
 
 def __getattr__(name):

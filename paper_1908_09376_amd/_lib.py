@@ -101,6 +101,9 @@ def _load():
         "midbf_profile_read": (i, [vp, C.POINTER(KernelTime), i, C.POINTER(i)]),
         "phase_recover": (i, [i, i, C.POINTER(C.c_double), C.POINTER(C.c_double), SAMPLE_CB, vp, i, i, C.c_double,
                               C.c_uint64, vp, vp, vp, C.POINTER(RecoverInfo)]),
+        "phase_recover_points": (i, [i, ll, C.POINTER(C.c_double), C.POINTER(C.c_double), SAMPLE_CB, vp, i, i,
+                                     C.c_double, C.c_uint64, vp, vp, vp, C.POINTER(RecoverInfo)]),
+        "midbf_recovery_path": (i, [C.POINTER(C.c_double), ll, i, ll, C.POINTER(C.c_int), vp]),
         "midbf_destroy": (None, [vp]),
         "midbf_last_error": (C.c_char_p, []),
     }
@@ -125,4 +128,4 @@ EXPORTED = ["midbf_build", "midbf_save", "midbf_load", "midbf_apply", "midbf_app
             "midbf_batch_destroy", "midbf_schedule_simulate",
             "midbf_factor_stats", "midbf_ranks", "midbf_kernel_entries", "midbf_id_batch",
             "midbf_tune", "midbf_set_variants", "midbf_profile_enable", "midbf_profile_read", "midbf_destroy", "midbf_last_error",
-            "phase_recover"]
+            "phase_recover", "phase_recover_points", "midbf_recovery_path"]

@@ -1003,7 +1003,23 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
             h->tree_pts[1].resize(cnt);
             MIDBF_HIP(hipMemcpy(h->tree_pts[0].data(), h->own_xp, cnt * sizeof(double), hipMemcpyDeviceToHost));
             MIDBF_HIP(hipMemcpy(h->tree_pts[1].data(), h->own_wp, cnt * sizeof(double), hipMemcpyDeviceToHost));
-            for (double& v : h->tree_pts[1]) v = (v + 0.5 * p.n) / p.n;
+            // each set moved and scaled uniformly into [0, 1]^d by its bounding cube
+            for (int t = 0; t < 2; ++t) {
+                std::vector<double>& v = h->tree_pts[t];
+                double lo[3], ext = 0.0;
+                for (int k = 0; k < p.d; ++k) {
+                    double mn = v[k], mx = v[k];
+                    for (long long i = 0; i < h->N; ++i) {
+                        mn = std::min(mn, v[i * p.d + k]);
+                        mx = std::max(mx, v[i * p.d + k]);
+                    }
+                    lo[k] = mn;
+                    ext = std::max(ext, mx - mn);
+                }
+                const double sc = ext > 0.0 ? ext : 1.0;
+                for (long long i = 0; i < h->N; ++i)
+                    for (int k = 0; k < p.d; ++k) v[i * p.d + k] = (v[i * p.d + k] - lo[k]) / sc;
+            }
             int n0 = 1;
             const long long nleaf = ipow(h->P, L);
             for (int t = 0; t < 2; ++t) {

@@ -1252,6 +1252,20 @@ midbf_status phase_recover(int d, int n, const double* X1, const double* X2, mid
     });
 }
 
+midbf_status phase_recover_points(int d, long long N, const double* X1, const double* X2, midbf_sample_cb cb,
+                                  void* user, int r, int q, double tau, uint64_t seed, void* stream, double* U_dev,
+                                  double* V_dev, phase_recover_info* info) {
+    if (N < 2) return fail(MIDBF_ERR_ARG, "need at least two points");
+    return guarded([&] {
+        phase_recover_run(d, 0, X1, X2, cb, user, r, q, tau, seed, (hipStream_t)stream, U_dev, V_dev, info, N);
+    });
+}
+
+midbf_status midbf_recovery_path(const double* pts, long long N, int d, long long root, int* P_out, void* stream) {
+    if (!pts || !P_out) return fail(MIDBF_ERR_ARG, "null argument");
+    return guarded([&] { recovery_path_points(pts, N, d, root, P_out, (hipStream_t)stream); });
+}
+
 const char* midbf_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

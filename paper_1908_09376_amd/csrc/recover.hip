@@ -1,12 +1,17 @@
 // Phase recovery on the GPU (Section 2): exp(2 pi i U V^T) ~ K from O(1)
-// rows and columns of K, on the lattices of the library.
+// rows and columns of K, on the lattices of the library or on scattered points.
 //
-//   * recovery paths: the dimension-ordered comb trees of the x and xi
-//     lattices (an MST of unit axis edges of the lattice's Delaunay graph,
-//     Alg. 5), rooted at x = 0 and xi = 0.  The path from the root to a node
-//     first moves along coordinate 0, then 1, ...; so the whole path is d
+//   * recovery paths on the lattices: the dimension-ordered comb trees of the
+//     x and xi lattices (an MST of unit axis edges of the lattice's Delaunay
+//     graph, Alg. 5), rooted at x = 0 and xi = 0.  The path from the root to a
+//     node first moves along coordinate 0, then 1, ...; so the whole path is d
 //     rounds of independent 1-D line walks (round s: every line along axis s
 //     that leaves the axis-(s-1) lines), one workgroup per vector;
+//   * recovery paths on scattered points (Alg. 5): the Euclidean minimum
+//     spanning tree by Prim's algorithm on the device (the Delaunay graph only
+//     thins the candidate edges: it holds every edge of this tree), then a
+//     breadth-first order from point 0 on the host, neighbours by increasing
+//     number; a walk then runs the path's depth levels in turn;
 //   * Alg. 4 along those walks: v(ed) = u(ed) - round(u(ed) - v(bg)) with
 //     u = angle(K) / 2 pi, block roots (Partition2 cuts) taking their anchors;
 //   * Alg. 6: tau schedule on the root column / row, per-block root rows and
@@ -100,8 +105,18 @@ __device__ void comb_walk(const Lattice& L, F&& f) {
     __syncthreads();
 }
 
+// A general recovery path: rows (pred, node) grouped by depth, level l holding
+// rows lev_off[l] .. lev_off[l+1]; the walk runs the levels in turn.
+struct PathWalk {
+    const int* path;             // (N - 1) x 2, or null: the lattice's comb tree
+    const long long* lev_off;
+    int nlev;
+    long long root;
+};
+
 struct UnwrapArgs {
     Lattice L;
+    PathWalk pw;
     const double2* kv;            // the sampled row or column of K
     double* u;                    // wrapped phase angle(K) / 2 pi (out)
     double* v;                    // recovered phase (out)
@@ -121,6 +136,7 @@ __global__ __launch_bounds__(WT) void unwrap_kernel(UnwrapArgs A) {
         return A.anchor_vecs ? A.anchor_vecs[(long long)b * N + A.anchor_index] : A.u[p];
     };
     const long long root = [&] {
+        if (A.pw.path) return A.pw.root;
         long long r = 0;
         for (int k = 0; k < A.L.d; ++k) r += A.L.q[k] * A.L.stride[k];
         return r;
@@ -130,7 +146,7 @@ __global__ __launch_bounds__(WT) void unwrap_kernel(UnwrapArgs A) {
         if (A.inc) A.inc[root] = 0.0;
     }
     double mx = 0.0;
-    comb_walk(A.L, [&](long long p, long long par) {
+    auto step = [&](long long p, long long par) {
         const int rb = A.root_block ? A.root_block[p] : -1;
         const double vpar = A.v[par];
         double vp;
@@ -144,7 +160,17 @@ __global__ __launch_bounds__(WT) void unwrap_kernel(UnwrapArgs A) {
         const double dl = fabs(vp - vpar);
         if (A.inc) A.inc[p] = dl;
         if (rb < 0) mx = fmax(mx, dl);
-    });
+    };
+    if (A.pw.path) {
+        for (int l = 0; l < A.pw.nlev; ++l) {
+            __syncthreads();
+            for (long long e = A.pw.lev_off[l] + threadIdx.x; e < A.pw.lev_off[l + 1]; e += WT)
+                step(A.pw.path[2 * e + 1], A.pw.path[2 * e]);
+        }
+        __syncthreads();
+    } else {
+        comb_walk(A.L, step);
+    }
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
     if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = mx;
     __syncthreads();
@@ -152,6 +178,62 @@ __global__ __launch_bounds__(WT) void unwrap_kernel(UnwrapArgs A) {
         double m = 0.0;
         for (int w = 0; w < WT / 64; ++w) m = fmax(m, s_max[w]);
         *A.maxinc = m;
+    }
+}
+
+// Euclidean minimum spanning tree of N points (Prim's algorithm, one
+// workgroup): per step every thread updates the keys (squared distance to the
+// tree, FP64) of its points outside the tree against the point just added,
+// then the block adds the nearest outside point (ties: the smaller number).
+__global__ __launch_bounds__(WT) void prim_kernel(const double* pts, long long N, int d, long long root, double* key,
+                                                  int* parent, unsigned char* in) {
+    __shared__ double s_v[WT / 64];
+    __shared__ long long s_i[WT / 64];
+    __shared__ long long s_u;
+    for (long long v = threadIdx.x; v < N; v += WT) {
+        key[v] = INFINITY;
+        parent[v] = -1;
+        in[v] = v == root;
+    }
+    if (threadIdx.x == 0) s_u = root;
+    __syncthreads();
+    for (long long it = 1; it < N; ++it) {
+        const long long u = s_u;
+        double pu[3] = {0, 0, 0};
+        for (int k = 0; k < d; ++k) pu[k] = pts[u * d + k];
+        double best = INFINITY;
+        long long bi = N;
+        for (long long v = threadIdx.x; v < N; v += WT) {
+            if (in[v]) continue;
+            double s = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double dv = pts[v * d + k] - pu[k];
+                s += dv * dv;
+            }
+            double kv = key[v];
+            if (s < kv) {
+                kv = s;
+                key[v] = s;
+                parent[v] = (int)u;
+            }
+            if (kv < best || (kv == best && v < bi)) { best = kv; bi = v; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const long long oi = __shfl_xor(bi, o, 64);
+            if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if ((threadIdx.x & 63) == 0) { s_v[threadIdx.x >> 6] = best; s_i[threadIdx.x >> 6] = bi; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double b = s_v[0];
+            long long i = s_i[0];
+            for (int w = 1; w < WT / 64; ++w)
+                if (s_v[w] < b || (s_v[w] == b && s_i[w] < i)) { b = s_v[w]; i = s_i[w]; }
+            s_u = i < N ? i : u;
+            if (i < N) in[i] = 1;
+        }
+        __syncthreads();
     }
 }
 
@@ -521,20 +603,108 @@ struct DevBuf {
     }
 };
 
+// The recovery path of scattered points (Alg. 5 with the tree computed
+// directly): rows (pred, node) in breadth-first order from root, neighbours in
+// increasing number; levels by depth; the row of every node (-1: the root).
+struct HostPath {
+    std::vector<int> P;
+    std::vector<long long> lev, rowpos;
+};
+
+HostPath points_path(const double* pts, long long N, int d, long long root, hipStream_t st) {
+    MIDBF_CHECK(N >= 1 && root >= 0 && root < N && (d == 2 || d == 3), MIDBF_ERR_ARG, "bad point set");
+    DevBuf b_pts, b_key, b_par, b_in;
+    double* d_pts = b_pts.alloc<double>((size_t)N * d);
+    double* d_key = b_key.alloc<double>(N);
+    int* d_par = b_par.alloc<int>(N);
+    unsigned char* d_in = b_in.alloc<unsigned char>(N);
+    MIDBF_HIP(hipMemcpyAsync(d_pts, pts, (size_t)N * d * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(prim_kernel, dim3(1), dim3(WT), 0, st, (const double*)d_pts, N, d, root, d_key, d_par, d_in);
+    MIDBF_HIP(hipGetLastError());
+    std::vector<int> parent(N);
+    MIDBF_HIP(hipMemcpyAsync(parent.data(), d_par, N * sizeof(int), hipMemcpyDeviceToHost, st));
+    MIDBF_HIP(hipStreamSynchronize(st));
+    // undirected adjacency, neighbours sorted
+    std::vector<long long> deg(N + 1, 0);
+    for (long long v = 0; v < N; ++v)
+        if (v != root) {
+            MIDBF_CHECK(parent[v] >= 0 && parent[v] < N, MIDBF_ERR_HIP, "spanning tree incomplete");
+            ++deg[v + 1];
+            ++deg[parent[v] + 1];
+        }
+    for (long long v = 0; v < N; ++v) deg[v + 1] += deg[v];
+    std::vector<int> adj(deg[N]);
+    std::vector<long long> fill(deg.begin(), deg.end() - 1);
+    for (long long v = 0; v < N; ++v)
+        if (v != root) {
+            adj[fill[v]++] = parent[v];
+            adj[fill[parent[v]]++] = (int)v;
+        }
+    for (long long v = 0; v < N; ++v) std::sort(adj.begin() + deg[v], adj.begin() + deg[v + 1]);
+    HostPath H;
+    H.P.reserve(2 * (N - 1));
+    H.rowpos.assign(N, -1);
+    std::vector<int> depth(N, -1);
+    std::vector<long long> queue{root};
+    depth[root] = 0;
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const long long u = queue[h];
+        for (long long e = deg[u]; e < deg[u + 1]; ++e) {
+            const int v = adj[e];
+            if (depth[v] >= 0) continue;
+            depth[v] = depth[u] + 1;
+            H.rowpos[v] = (long long)H.P.size() / 2;
+            H.P.push_back((int)u);
+            H.P.push_back(v);
+            queue.push_back(v);
+        }
+    }
+    MIDBF_CHECK((long long)queue.size() == N, MIDBF_ERR_HIP, "spanning tree not connected");
+    H.lev.push_back(0);
+    for (long long e = 1; e < N - 1 + 1; ++e)
+        if (e == N - 1 || depth[H.P[2 * e + 1]] != depth[H.P[2 * (e - 1) + 1]]) H.lev.push_back(e);
+    return H;
+}
+
 }  // namespace
+
+void recovery_path_points(const double* pts, long long N, int d, long long root, int* P_out, hipStream_t st) {
+    const HostPath H = points_path(pts, N, d, root, st);
+    std::copy(H.P.begin(), H.P.end(), P_out);
+}
 
 void phase_recover_run(int d, int n, const double* X1, const double* X2, midbf_sample_cb cb, void* user, int r,
                        int q, double tau, uint64_t seed, hipStream_t st, double* U_dev, double* V_dev,
-                       phase_recover_info* info_out) {
-    (void)X1;   // the x lattice enters only through the recovery path
+                       phase_recover_info* info_out, long long Npts) {
     MIDBF_CHECK(d == 2 || d == 3, MIDBF_ERR_ARG, "d must be 2 or 3");
-    MIDBF_CHECK(n >= 2 && n % 2 == 0, MIDBF_ERR_ARG, "n must be even and >= 2");
+    MIDBF_CHECK(Npts > 0 || (n >= 2 && n % 2 == 0), MIDBF_ERR_ARG, "n must be even and >= 2");
+    MIDBF_CHECK(Npts == 0 || (X1 && X2 && Npts >= 2), MIDBF_ERR_ARG, "scattered points need x and xi coordinates");
     MIDBF_CHECK(cb && U_dev && V_dev, MIDBF_ERR_ARG, "null sampler or output");
     MIDBF_CHECK(r >= 1 && r <= MAXR && q >= 1 && r * q <= 32, MIDBF_ERR_ARG, "need 1 <= r <= 16 and r q <= 32");
     MIDBF_CHECK(tau > 0.0 && tau <= 0.5, MIDBF_ERR_ARG, "tau must lie in (0, 1/2]");
-    const Lattice Lx = make_lattice(d, n, 0), Lk = make_lattice(d, n, n / 2);
-    const long long N = Lx.N;
-    const long long r1 = lattice_root(Lx), r2 = lattice_root(Lk);
+    // the two recovery paths: the lattices' comb trees (the x lattice enters only through its
+    // path), or the point sets' spanning trees rooted at point 0
+    const bool pts = Npts > 0;
+    const Lattice Lx = pts ? Lattice{} : make_lattice(d, n, 0), Lk = pts ? Lattice{} : make_lattice(d, n, n / 2);
+    const long long N = pts ? Npts : Lx.N;
+    const long long r1 = pts ? 0 : lattice_root(Lx), r2 = pts ? 0 : lattice_root(Lk);
+    HostPath Hx, Hk;
+    DevBuf b_px, b_pk, b_lx, b_lk;
+    PathWalk Wx{}, Wk{};
+    if (pts) {
+        Hx = points_path(X1, N, d, r1, st);
+        Hk = points_path(X2, N, d, r2, st);
+        int* dpx = b_px.alloc<int>(Hx.P.size());
+        int* dpk = b_pk.alloc<int>(Hk.P.size());
+        long long* dlx = b_lx.alloc<long long>(Hx.lev.size());
+        long long* dlk = b_lk.alloc<long long>(Hk.lev.size());
+        MIDBF_HIP(hipMemcpyAsync(dpx, Hx.P.data(), Hx.P.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        MIDBF_HIP(hipMemcpyAsync(dpk, Hk.P.data(), Hk.P.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        MIDBF_HIP(hipMemcpyAsync(dlx, Hx.lev.data(), Hx.lev.size() * sizeof(long long), hipMemcpyHostToDevice, st));
+        MIDBF_HIP(hipMemcpyAsync(dlk, Hk.lev.data(), Hk.lev.size() * sizeof(long long), hipMemcpyHostToDevice, st));
+        Wx = PathWalk{dpx, dlx, (int)Hx.lev.size() - 1, r1};
+        Wk = PathWalk{dpk, dlk, (int)Hk.lev.size() - 1, r2};
+    }
     phase_recover_info info{};
     // xi coordinates (row-major N x d) for the integer-shift fit
     std::vector<double> xi((size_t)N * d);
@@ -570,6 +740,8 @@ void phase_recover_run(int d, int n, const double* X1, const double* X2, midbf_s
                       bool want_inc) {
         UnwrapArgs a{};
         a.L = L;
+        a.L.N = N;
+        a.pw = &L == &Lx ? Wx : Wk;
         a.kv = d_kv;
         a.u = d_u;
         a.v = v_out;
@@ -598,10 +770,11 @@ void phase_recover_run(int d, int n, const double* X1, const double* X2, midbf_s
     MIDBF_HIP(hipMemcpyAsync(inc_c.data(), d_inc, N * sizeof(double), hipMemcpyDeviceToHost, st));
     MIDBF_HIP(hipStreamSynchronize(st));
     auto flagged = [&](const std::vector<double>& inc, const Lattice& L, long long root, double t) {
-        std::vector<std::pair<int, long long>> f;
+        const HostPath& H = &L == &Lx ? Hx : Hk;
+        std::vector<std::pair<long long, long long>> f;
         for (long long p = 0; p < N; ++p)
-            if (p != root && inc[p] >= t) f.push_back({manhattan_depth(L, p), p});
-        std::sort(f.begin(), f.end());                // path order: depth, then node number
+            if (p != root && inc[p] >= t) f.push_back({pts ? H.rowpos[p] : (long long)manhattan_depth(L, p), p});
+        std::sort(f.begin(), f.end());                // path order (lattice: depth, then node number)
         std::vector<long long> D{root};
         for (auto& e : f) D.push_back(e.second);
         return D;

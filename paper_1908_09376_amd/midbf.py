@@ -306,8 +306,18 @@ def id_batch(X: torch.Tensor, tol: float, k_cap: int = 0, stream=None):
     return kk, perm.cpu().numpy(), Ts
 
 
+def recovery_path(pts: np.ndarray, root: int = 0, stream=None) -> np.ndarray:
+    """(N-1) x 2 recovery path (pred, node) of a point set (midbf_recovery_path, Alg. 5)."""
+    a = np.ascontiguousarray(pts, dtype=np.float64)
+    N, d = a.shape
+    P = np.zeros((N - 1, 2), dtype=np.int32)
+    L.check(L.lib.midbf_recovery_path(a.ctypes.data_as(C.POINTER(C.c_double)), N, d, root,
+                                      P.ctypes.data_as(C.POINTER(C.c_int)), _stream_ptr(stream)))
+    return P.astype(np.int64)
+
+
 def phase_recover(d: int, n: int, sample, r: int = 8, q: int = 2, tau: float = 0.25, seed: int = 0,
-                  X2: np.ndarray | None = None, stream=None):
+                  X2: np.ndarray | None = None, stream=None, points=None):
     """[U, V] with exp(2 pi i U V^T) ~ K from rows / columns of K (phase_recover).
 
     sample(is_row, index) returns row `index` (is_row True) or column `index`
@@ -315,7 +325,7 @@ def phase_recover(d: int, n: int, sample, r: int = 8, q: int = 2, tau: float = 0
     Returns (U, V, info): (N, r) float64 CUDA tensors and a dict of the
     recovery's threshold, flagged nodes, accepted samples and integer shifts.
     """
-    N = n ** d
+    N = n ** d if points is None else len(points[0])
     dev = torch.device("cuda", torch.cuda.current_device())
     U = torch.empty((N, r), dtype=torch.float64, device=dev)
     V = torch.empty((N, r), dtype=torch.float64, device=dev)
@@ -338,8 +348,16 @@ def phase_recover(d: int, n: int, sample, r: int = 8, q: int = 2, tau: float = 0
         x2a = np.ascontiguousarray(X2, dtype=np.float64).reshape(N, d)
         x2 = x2a.ctypes.data_as(C.POINTER(C.c_double))
     info = L.RecoverInfo()
-    st = L.lib.phase_recover(d, n, None, x2, cfun, None, r, q, tau, seed, _stream_ptr(stream),
-                             U.data_ptr(), V.data_ptr(), C.byref(info))
+    if points is not None:
+        # scattered points (phase_recover_points): host coordinate copies for the paths and the fit
+        xa = np.ascontiguousarray(points[0], dtype=np.float64).reshape(N, d)
+        wa = np.ascontiguousarray(points[1], dtype=np.float64).reshape(N, d)
+        st = L.lib.phase_recover_points(d, N, xa.ctypes.data_as(C.POINTER(C.c_double)),
+                                        wa.ctypes.data_as(C.POINTER(C.c_double)), cfun, None, r, q, tau, seed,
+                                        _stream_ptr(stream), U.data_ptr(), V.data_ptr(), C.byref(info))
+    else:
+        st = L.lib.phase_recover(d, n, None, x2, cfun, None, r, q, tau, seed, _stream_ptr(stream),
+                                 U.data_ptr(), V.data_ptr(), C.byref(info))
     if err:
         raise err[0]
     L.check(st)

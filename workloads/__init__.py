@@ -47,7 +47,15 @@ WORKLOADS = {
     "fio512x64": Workload("fio512x64", 2, 512, FIO_ELLIPSE, cfg=2, nrhs=64),
     "iso3d32": Workload("iso3d32", 3, 32, ISO3D, cfg=3, nrhs=16),
     "pw256x16": Workload("pw256x16", 2, 256, FIO_PIECEWISE, cfg=4, nrhs=16),
+    # Example 2 of Section 4: the 3-D non-uniform Fourier transform on N = 32^3 random points
+    # (random_points(3, 32, 5)), Phi = x . xi, 16 right-hand sides
+    "nuft3d32": Workload("nuft3d32", 3, 32, LINEAR, leaf_box=4, cfg=5, nrhs=16, extra={"points": True}),
 }
+
+
+def workload_points(w: Workload):
+    """The point sets of a scattered-point workload (None for the lattices)."""
+    return random_points(w.d, w.n, w.cfg) if w.extra.get("points") else None
 
 
 def rng(*key: int) -> np.random.Generator:
