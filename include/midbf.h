@@ -59,7 +59,9 @@ typedef enum {
     MIDBF_PHASE_FIO_PIECEWISE = 2, /* x.xi + c(x)|xi|, c = (2 + sin 2pi x1)/16 if x1 < 1/2,
                                       else (3 + cos 2pi x2)/16  (d = 2)                    */
     MIDBF_PHASE_ISO3D = 3,         /* x.xi + c(x)|xi|, c = (3 + prod_q sin 2pi x_q)/100 (d = 3) */
-    MIDBF_PHASE_LOWRANK = 4        /* Phi = U V^T from phase_recover (Section 2.3.5, Alg. 7) */
+    MIDBF_PHASE_LOWRANK = 4,       /* Phi = U V^T from phase_recover (Section 2.3.5, Alg. 7) */
+    MIDBF_PHASE_HELMHOLTZ = 5      /* Phi = h |x - xi|_2, scattered points only (Sec. 4, Example 3:
+                                      the oscillatory part of the Helmholtz Green's function)     */
 } midbf_phase_kind;
 
 typedef enum {
@@ -110,10 +112,14 @@ typedef struct {
                                 cube and partitioned on the boxes of the n^d lattice's tree
                                 (depth log2(n / leaf_box)); a node without points holds
                                 none, leaves hold uneven counts.  Phase
-                                MIDBF_PHASE_LINEAR (Phi = x . xi on the given coordinates)
-                                or MIDBF_PHASE_LOWRANK (U, V rows per point).  Vectors are
+                                MIDBF_PHASE_LINEAR (Phi = x . xi on the given coordinates),
+                                MIDBF_PHASE_HELMHOLTZ or MIDBF_PHASE_LOWRANK (U, V rows per
+                                point).  Vectors are
                                 indexed by point number.  FP64 and FP32 copies only.  Both
                                 null: the lattices {0..n-1}^d / n and {0..n-1}^d - n/2      */
+    long long n_points;      /* scattered points: N, the size of each set (0: n^d); n then
+                                only sets the tree depth log2(n / leaf_box)                */
+    double helmholtz_h;      /* MIDBF_PHASE_HELMHOLTZ: h                                    */
 } midbf_params;
 
 typedef struct {

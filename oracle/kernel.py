@@ -72,8 +72,9 @@ PHASES = {
 class Kernel:
     """Entry access K(I, J) = exp(2 pi i Phi(x_I, xi_J)) (Scenario 1, Table 1).
 
-    ``phase`` is a kind name from PHASES, or ("lowrank", U, V) for a phase
-    given as Phi = U V^T (the output of Alg. 7).  ``points`` = (x, xi) replaces
+    ``phase`` is a kind name from PHASES, ("lowrank", U, V) for a phase
+    given as Phi = U V^T (the output of Alg. 7), or ("helmholtz", h) for
+    Phi = h |x - xi| on point sets.  ``points`` = (x, xi) replaces
     the lattices by given point sets (N x d each; Sec. 3.5, closing paragraph:
     non-uniform points), x in [0, 1)^d and xi in [-n/2, n/2)^d.
     """
@@ -93,6 +94,10 @@ class Kernel:
         if isinstance(phase, tuple) and phase[0] == "lowrank":
             U, V = phase[1], phase[2]
             self._phi = lambda I, J: U[I] @ V[J].T
+        elif isinstance(phase, tuple) and phase[0] == "helmholtz":
+            # Phi = h |x - xi|_2 (Sec. 4, Example 3)
+            h = float(phase[1])
+            self._phi = lambda I, J: h * np.sqrt(((self.x[I][:, None, :] - self.xi[J][None, :, :]) ** 2).sum(axis=2))
         else:
             f = PHASES[phase]
             self._phi = lambda I, J: f(self.x[I], self.xi[J])

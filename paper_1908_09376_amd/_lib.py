@@ -16,7 +16,7 @@ MIDBF_OK = 0
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_OOM", -4: "ERR_RANK_SATURATED",
           -5: "ERR_RECOVERY", -6: "ERR_HIP", -7: "ERR_UNIMPLEMENTED", -8: "ERR_IO"}
 
-PHASES = {"linear": 0, "fio_ellipse": 1, "fio_piecewise": 2, "iso3d": 3, "lowrank": 4}
+PHASES = {"linear": 0, "fio_ellipse": 1, "fio_piecewise": 2, "iso3d": 3, "lowrank": 4, "helmholtz": 5}
 FP64, FP32, SPLIT_BF16, SPLIT_FP16 = 0, 1, 2, 3
 KEEP_FP64, KEEP_FP32, KEEP_BF16, KEEP_FP16 = 1, 2, 4, 8
 
@@ -26,7 +26,8 @@ class Params(C.Structure):
                 ("oversample_t", C.c_int), ("k_cap", C.c_int), ("phase", C.c_int),
                 ("U_dev", C.c_void_p), ("V_dev", C.c_void_p), ("r", C.c_int),
                 ("precisions", C.c_uint), ("build_workspace_bytes", C.c_size_t), ("fixed_rank", C.c_int),
-                ("x_points", C.c_void_p), ("xi_points", C.c_void_p)]
+                ("x_points", C.c_void_p), ("xi_points", C.c_void_p), ("n_points", C.c_longlong),
+                ("helmholtz_h", C.c_double)]
 
 
 class Stats(C.Structure):

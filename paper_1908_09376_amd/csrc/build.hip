@@ -947,12 +947,16 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
     if (p.phase == MIDBF_PHASE_FIO_ELLIPSE || p.phase == MIDBF_PHASE_FIO_PIECEWISE)
         MIDBF_CHECK(p.d == 2, MIDBF_ERR_ARG, "this phase is two-dimensional");
     if (p.phase == MIDBF_PHASE_ISO3D) MIDBF_CHECK(p.d == 3, MIDBF_ERR_ARG, "this phase is three-dimensional");
-    MIDBF_CHECK(p.phase >= MIDBF_PHASE_LINEAR && p.phase <= MIDBF_PHASE_LOWRANK, MIDBF_ERR_ARG, "unknown phase");
+    MIDBF_CHECK(p.phase >= MIDBF_PHASE_LINEAR && p.phase <= MIDBF_PHASE_HELMHOLTZ, MIDBF_ERR_ARG, "unknown phase");
     const bool points = p.x_points || p.xi_points;
+    MIDBF_CHECK(points || p.phase != MIDBF_PHASE_HELMHOLTZ, MIDBF_ERR_ARG, "the Helmholtz phase is for point sets");
+    MIDBF_CHECK(points || p.n_points == 0, MIDBF_ERR_ARG, "n_points is for point sets");
     if (points) {
         MIDBF_CHECK(p.x_points && p.xi_points, MIDBF_ERR_ARG, "scattered points need both x_points and xi_points");
-        MIDBF_CHECK(p.phase == MIDBF_PHASE_LINEAR || p.phase == MIDBF_PHASE_LOWRANK, MIDBF_ERR_ARG,
-                    "scattered points take the linear phase (x . xi) or the low-rank phase");
+        MIDBF_CHECK(p.phase == MIDBF_PHASE_LINEAR || p.phase == MIDBF_PHASE_LOWRANK ||
+                        p.phase == MIDBF_PHASE_HELMHOLTZ,
+                    MIDBF_ERR_ARG, "scattered points take the linear, Helmholtz or low-rank phase");
+        MIDBF_CHECK(p.n_points >= 0, MIDBF_ERR_ARG, "n_points must be >= 0");
         MIDBF_CHECK(!rf, MIDBF_ERR_UNIMPLEMENTED, "factor files hold lattice factorizations");
         MIDBF_CHECK(!(p.precisions & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)), MIDBF_ERR_UNIMPLEMENTED,
                     "scattered points keep the FP64 and FP32 copies only");
@@ -968,7 +972,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
                     MIDBF_ERR_ARG, "unknown precision bits");
         h->d = p.d; h->n = p.n; h->P = 1 << p.d; h->L = L; h->leaf = p.leaf_box;
         h->n0 = (int)ipow(p.leaf_box, p.d);
-        h->N = ipow(p.n, p.d);
+        h->N = points && p.n_points > 0 ? p.n_points : ipow(p.n, p.d);
         h->b = (L + 1) / 2;
         h->hstar = L - h->b + 1;
         if (p.phase == MIDBF_PHASE_LOWRANK) {
@@ -1041,7 +1045,7 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
             h->p.x_points = h->own_xp;
             h->p.xi_points = h->own_wp;
         }
-        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, h->p.U_dev, h->p.V_dev, p.r, h->own_xp, h->own_wp};
+        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, h->p.U_dev, h->p.V_dev, p.r, h->own_xp, h->own_wp, p.helmholtz_h};
         h->rows.resize(h->b);
         h->cols.resize(h->b);
         if (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) {
@@ -1216,7 +1220,7 @@ midbf_plan* load_plan(const char* path, unsigned precisions, hipStream_t st, mid
 
 void kernel_entries(const midbf_params& p, const int* rows, int nrows, const int* cols, int ncols, void* out,
                     hipStream_t st) {
-    PhaseDesc ph{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r, p.x_points, p.xi_points};
+    PhaseDesc ph{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r, p.x_points, p.xi_points, p.helmholtz_h};
     const long long tot = (long long)nrows * ncols;
     if (tot == 0) return;
     const int gx = (int)std::min<long long>((tot + BT - 1) / BT, 4096);

@@ -16,6 +16,7 @@ struct PhaseDesc {
     int r;
     const double* xp;     // scattered points: x and xi coordinates (N x d row-major), or null
     const double* wp;
+    double hh;            // MIDBF_PHASE_HELMHOLTZ: h
 };
 
 // Smooth (non-bilinear) part of the phase at x = a/n, xi = b - n/2.
@@ -61,11 +62,19 @@ __device__ inline double phase_frac(const PhaseDesc& ph, long long p, long long 
         for (int l = 0; l < ph.r; ++l) s = fma(u[l], v[l], s);
         return s - floor(s);
     }
-    if (ph.xp) {            // Phi = x . xi on given point sets, in FP64
+    if (ph.xp) {            // given point sets, in FP64: Phi = x . xi, or h |x - xi|
         const double* x = ph.xp + p * ph.d;
         const double* w = ph.wp + q * ph.d;
         double s = 0.0;
-        for (int l = 0; l < ph.d; ++l) s = fma(x[l], w[l], s);
+        if (ph.kind == MIDBF_PHASE_HELMHOLTZ) {
+            for (int l = 0; l < ph.d; ++l) {
+                const double dl = x[l] - w[l];
+                s = fma(dl, dl, s);
+            }
+            s = ph.hh * sqrt(s);
+        } else {
+            for (int l = 0; l < ph.d; ++l) s = fma(x[l], w[l], s);
+        }
         return s - floor(s);
     }
     int a[3], b[3];

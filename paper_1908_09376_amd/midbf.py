@@ -21,7 +21,7 @@ def _stream_ptr(stream) -> int:
 
 
 def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, precisions=0,
-            workspace_bytes=0, fixed_rank=0, points=None) -> L.Params:
+            workspace_bytes=0, fixed_rank=0, points=None, helmholtz_h=0.0) -> L.Params:
     p = L.Params()
     p.d, p.n, p.tol = d, n, tol
     p.leaf_box, p.oversample_t, p.k_cap = leaf_box, oversample_t, k_cap
@@ -35,6 +35,8 @@ def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, pre
     if points is not None:
         p.x_points = points[0].data_ptr()
         p.xi_points = points[1].data_ptr()
+        p.n_points = points[0].shape[0]
+    p.helmholtz_h = helmholtz_h
     return p
 
 
@@ -47,20 +49,22 @@ class MIDBF:
     def __init__(self, d: int, n: int, phase: str, tol: float = 1e-6, leaf_box: int = 8,
                  oversample_t: int = 5, k_cap: int = 0, U: torch.Tensor | None = None,
                  V: torch.Tensor | None = None, precisions: int = 0, workspace_bytes: int = 0,
-                 fixed_rank: int = 0, points=None, stream=None):
+                 fixed_rank: int = 0, points=None, helmholtz_h: float = 0.0, stream=None):
         self.d, self.n, self.N = d, n, n ** d
         if phase == "lowrank":
             U = U.to(torch.float64).contiguous()
             V = V.to(torch.float64).contiguous()
         if points is not None:
-            # scattered points (N = n^d each): x in [0, 1)^d and xi in [-n/2, n/2)^d, N x d FP64
+            # scattered points: two N x d FP64 sets (N = n^d unless given by their length); n then
+            # only sets the tree depth
             points = tuple(t.to(torch.float64).contiguous() for t in points)
+            self.N = points[0].shape[0]
             for t in points:
-                if not t.is_cuda or t.shape != (self.N, d):
-                    raise ValueError("points: two CUDA tensors of shape (n^d, d)")
+                if not t.is_cuda or t.dim() != 2 or t.shape != (self.N, d):
+                    raise ValueError("points: two CUDA tensors of the same shape (N, d)")
         self._UV = (U, V, points)    # kept alive: the library reads them during the build
         self._p = _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U, V, precisions,
-                          workspace_bytes, fixed_rank, points)
+                          workspace_bytes, fixed_rank, points, helmholtz_h)
         h = C.c_void_p()
         L.check(L.lib.midbf_build(C.byref(self._p), _stream_ptr(stream), C.byref(h)))
         self._h = h

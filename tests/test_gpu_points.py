@@ -161,3 +161,32 @@ def test_points_refusals():
     with pytest.raises(MidbfError, match="ERR_UNIMPLEMENTED"):
         F.save("/tmp/points.midbf")
     F.close()
+
+
+@pytest.mark.parametrize("refine,n", [(4, 32), (5, 32), (6, 64)])
+def test_example3_helmholtz_sphere_halves(refine, n):
+    """Example 3: Phi = h |x - xi|, h = sqrt(N)/10, X and Omega the two halves of an icosphere refined
+    `refine` times (N = 5 * 4^refine + 1 nodes each); octree depth log2(n / 4) over each half's
+    bounding cube."""
+    M = _mod()
+    X, O = W.icosphere_halves(refine)
+    N = len(X)
+    hh = np.sqrt(N) / 10
+    K = Kernel(3, n, ("helmholtz", hh), points=(X, O))
+    print(f"[points] Example 3, refinement {refine}, N = {N}", flush=True)
+    F = M.MIDBF(3, n, "helmholtz", leaf_box=4, points=_pts(X, O), helmholtz_h=hh, precisions=1 | 2)
+    st = F.stats()
+    f = W.complex_gaussian(N, 2, 59)
+    rows = W.sample_rows(N, 9, 256)
+    gd = direct_sum(K, f, rows=rows)
+    g = from_dev(F.apply(to_dev(f)))
+    err = rel_l2(g[rows], gd)
+    print(f"[points] Example 3 N = {N}: ranks {st['k_min']}..{st['k_max']}, FP64 {err:.2e}", flush=True)
+    assert err < 1e-5
+    if refine == 4:
+        O_ = OracleMIDBF(K, tol=1e-6, leaf_box=4)
+        e_or = rel_l2(O_.apply(f)[rows], gd)
+        assert err < 3.0 * e_or + 1e-13
+    g32 = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp32"))
+    assert rel_l2(g32[rows], gd) < 1e-5
+    F.close()

@@ -222,3 +222,14 @@ def test_scattered_points_3d_nuft_and_adjoint():
     lhs = np.vdot(h, F.apply(f))
     rhs = np.vdot(F.apply_adjoint(h), f)
     assert abs(lhs - rhs) / abs(lhs) < 1e-13
+
+
+def test_helmholtz_sphere_halves_dense():
+    # Example 3 at refinement 3: 321 nodes on each half of the icosphere, Phi = h |x - xi| with
+    # h = sqrt(N) / 10; the octree leaves are mostly empty (the points lie on a surface)
+    X, O = W.icosphere_halves(3)
+    N = len(X)
+    K = Kernel(3, 16, ("helmholtz", np.sqrt(N) / 10), points=(X, O))
+    F = MIDBF(K, tol=1e-6, leaf_box=4)
+    assert F.L == 2
+    assert rel_l2(F.dense(), K.dense()) < 1e-5

@@ -129,3 +129,38 @@ def random_points(d: int, n: int, *key: int, half: bool = False) -> tuple[np.nda
         x[:, 0] *= 0.5
     xi = n * (g.random((N, d)) - 0.5)
     return x, xi
+
+
+def icosphere_halves(refine: int) -> tuple[np.ndarray, np.ndarray]:
+    """The point sets of Example 3 (Section 4): the nodes of a triangular mesh of the unit sphere made
+    by refining an icosahedron `refine` times (every edge's midpoint becomes a node, projected onto
+    the sphere), split into two halves by the sign of a fixed generic direction.  The mesh is
+    centrally symmetric, so each half holds (10 * 4^refine + 2) / 2 nodes.  Returns (X, Omega)."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+             (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(refine):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                mid[key] = len(verts) - 1
+            return mid[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    P = np.array(verts)
+    side = P @ np.array([0.2113248654, 0.5773502692, 0.7886751346])
+    if np.any(side == 0.0):
+        raise ValueError("a node lies on the splitting plane")
+    return P[side > 0], P[side < 0]
