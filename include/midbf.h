@@ -346,6 +346,8 @@ typedef struct {
     long long callbacks;           /* rows and columns fetched through the sampler           */
     long long rows[PHASE_RECOVER_MAX_SAMPLES], cols[PHASE_RECOVER_MAX_SAMPLES];
     int shift[PHASE_RECOVER_MAX_SAMPLES][4];   /* per accepted row: integer m (d entries), a  */
+    int disc_rows_initial, disc_cols_initial;  /* flagged nodes at the initial tau, before the
+                                                  schedule raises it (Table 4's counts)        */
 } phase_recover_info;
 
 /*

@@ -54,7 +54,7 @@ class RecoverInfo(C.Structure):
     _fields_ = [("tau", C.c_double), ("disc_rows", C.c_int), ("disc_cols", C.c_int), ("n_rows", C.c_int),
                 ("n_cols", C.c_int), ("rejected_rows", C.c_int), ("rejected_cols", C.c_int),
                 ("callbacks", C.c_longlong), ("rows", C.c_longlong * 64), ("cols", C.c_longlong * 64),
-                ("shift", (C.c_int * 4) * 64)]
+                ("shift", (C.c_int * 4) * 64), ("disc_rows_initial", C.c_int), ("disc_cols_initial", C.c_int)]
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # MIDBF_NOALLOC_SCRATCH_BYTES

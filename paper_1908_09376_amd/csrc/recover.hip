@@ -784,6 +784,10 @@ void phase_recover_run(int d, int n, const double* X1, const double* X2, midbf_s
     for (;;) {
         Dr = flagged(inc_r, Lx, r1, t_cur);
         Dc = flagged(inc_c, Lk, r2, t_cur);
+        if (t_cur == tau) {
+            info.disc_rows_initial = (int)Dr.size() - 1;
+            info.disc_cols_initial = (int)Dc.size() - 1;
+        }
         if (((int)Dr.size() - 1 <= DMAX && (int)Dc.size() - 1 <= DMAX) || t_cur >= 0.5) break;
         t_cur += 1.0 / 40.0;
     }

@@ -367,6 +367,7 @@ def phase_recover(d: int, n: int, sample, r: int = 8, q: int = 2, tau: float = 0
     L.check(st)
     nr, nc = info.n_rows, info.n_cols
     out = {"tau": info.tau, "disc_rows": info.disc_rows, "disc_cols": info.disc_cols,
+           "disc_rows_initial": info.disc_rows_initial, "disc_cols_initial": info.disc_cols_initial,
            "rejected_rows": info.rejected_rows, "rejected_cols": info.rejected_cols,
            "callbacks": info.callbacks,
            "R": np.array(info.rows[:nr], dtype=np.int64), "C": np.array(info.cols[:nc], dtype=np.int64),

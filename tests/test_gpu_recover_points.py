@@ -91,3 +91,28 @@ def test_example2_recovered_phase_through_midbf():
           flush=True)
     assert err < 1e-5
     F.close()
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_table4_flag_counts_against_oracle(n):
+    """Table 4's quantity: nodes flagged as discontinuities along the root column (N_Dr) and root row
+    (N_Dc) of Example 2 at a fixed threshold tau, for tau = 1/4, 1/6, 1/8, 1/10; equal to the oracle's
+    counts on the same paths.  At tau = 1/4 nothing is flagged (the paper's choice for this example)."""
+    from oracle.phase import RecoveredPhase
+    M = _mod()
+    x, xi = _example2_unit(n, (59, n))
+    N = len(x)
+    K = Kernel(3, n, "linear", points=(x, xi))
+    sample = lambda is_row, i: (K.entries([i], np.arange(N))[0] if is_row else K.entries(np.arange(N), [i])[:, 0])
+    kr = lambda i: K.entries([i], np.arange(N))[0]
+    kc = lambda j: K.entries(np.arange(N), [j])[:, 0]
+    P1, P2 = recovery_path_general(x, 0), recovery_path_general(xi, 0)
+    counts = []
+    for tau in (1 / 4, 1 / 6, 1 / 8, 1 / 10):
+        _, _, info = M.phase_recover(3, n, sample, r=2, q=2, seed=590, tau=tau, points=(x, xi))
+        H = RecoveredPhase(kr, kc, N, P1, 0, P2, 0, tau)
+        got = (info["disc_rows_initial"], info["disc_cols_initial"])
+        assert got == (len(H.Dr) - 1, len(H.Dc) - 1), (tau, got)
+        counts.append(got)
+    print(f"[rec-points] Table 4, n = {n}: (N_Dr, N_Dc) at tau = 1/4, 1/6, 1/8, 1/10: {counts}", flush=True)
+    assert counts[0] == (0, 0)
