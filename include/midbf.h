@@ -471,10 +471,10 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
  * variants != NULL, writes the choice for the top step of up and down and
  * for the middle to variants[0..3).  midbf_set_variants installs one variant
  * per kind for every step (MIDBF_ERR_ARG for an unknown precision or a
- * variant out of range: FP32 0-9, FP64 0-4, split 16-bit 0-9).  nrhs below
+ * variant out of range: FP32 0-9, FP64 0-4, split 16-bit 0-10).  nrhs below
  * the matrix-core threshold leaves the choice unchanged.  FP64, FP32,
  * MIDBF_SPLIT_BF16 and MIDBF_SPLIT_FP16 keep separate choices.  For the split
- * applies, variants 7-9 of the up kind read per-level source-row tables
+ * applies, variants 7-10 of the up kind read per-level source-row tables
  * built with the plan; when the first up step keeps every leaf point, they
  * also replace that step by the (scaled) transpose of the input into the
  * apply's row-major copy.

@@ -273,7 +273,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
     // point: that step only copies input rows, so the input is transposed into
     // the row-major copy instead and the step above reads it through its
     // lattice source-row table.
-    // (only the source-row-table up kernels, split variants 7-9, read it)
+    // (only the source-row-table up kernels, split variants 7-10, read it)
     const int v_up1 = (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[0][1];
     const bool lat_in = is_split16(prec) && mfma && lat && !adjoint && h->b >= 2 && up[0].entries == 0 &&
                         up[1].d_src_lat != nullptr && v_up1 >= 7 && v_up1 < BF16_VARIANTS;

@@ -40,7 +40,7 @@ void launch_up_leaf_copy(const UpArgs& A, long long groups, int nrhs, hipStream_
 // MFMA fragment tiles; tile_off gives each middle block's first tile), for
 // elem = SPLIT16_BF16 or SPLIT16_FP16.  DownDense runs the middle kernels on
 // the group blocks of a down step (MidArgs; tile_off = their first tiles).
-constexpr int BF16_VARIANTS = 10;
+constexpr int BF16_VARIANTS = 11;
 // Ranks up to which the split down kernels keep z in LDS (variants 5-9 then
 // run the grouped down pass, LevelKernel::DownGroup).
 constexpr int SPLIT16_RESIDENT_K = 256;

@@ -865,12 +865,13 @@ __device__ inline void a_prefetch(APipe<E, AD, ANG>& p, const Frag<E>* __restric
 }
 
 // BATCH: B stages gathered with load_b8 (measured faster for the up steps,
-// slower for the phase-tile middle).
-template <class E, int NT, int AD, bool ANG = false, bool BATCH = false, class BOff>
+// slower for the phase-tile middle).  RCT_ > 0: K tiles per B stage (else
+// rct_for<NT>), with one B fragment in registers at a time.
+template <class E, int NT, int AD, bool ANG = false, bool BATCH = false, int RCT_ = 0, class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
                            int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB,
                            float bsc, const int* __restrict__ Aang, APipe<E, AD, ANG>& pipe, bool preloaded) {
-    constexpr int RCT = rct_for<NT>();
+    constexpr int RCT = RCT_ > 0 ? RCT_ : rct_for<NT>();
     constexpr int FPT = RCT * 256 / NT;            // B fragments staged per thread and stage
     static_assert(FPT >= 1 && FPT * NT == RCT * 256, "stage must split evenly over the threads");
     const int tid = threadIdx.x, l = tid & 63;
@@ -922,8 +923,8 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
                     Frag<E> a0[1];
                     if constexpr (ANG) a0[0] = angle_frag<E>(fa[0]);
                     else a0[0] = fa[0];
-                    if constexpr (NT >= 768) {
-                        // one B fragment at a time (register budget of 12 or 16 waves)
+                    if constexpr (NT >= 768 || RCT_ > 0) {
+                        // one B fragment at a time (register budget of 12 or 16 waves per CU)
 #pragma unroll
                         for (int nt = 0; nt < 4; ++nt) {
                             const Frag<E> b = lds_frag(sb + c * 4 + nt, l);
@@ -1057,12 +1058,16 @@ __global__ __launch_bounds__(256) void src_rows_kernel(SrcRowsArgs A) {
     for (int p = threadIdx.x; p < n; p += 256) A.out[po + p] = crow[A.perm[po + p]];
 }
 
-template <class E, int NT, bool ANG>
-__global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* tile_off) {
+// TWO: two-tile B stages and at most 128 registers, so that two workgroups
+// share a CU (LDS 80 KB each at 512 threads) and one's table loads, first
+// gather and barriers overlap the other's products.
+template <class E, int NT, bool ANG, bool TWO = false>
+__global__ __launch_bounds__(NT, TWO ? NT / 128 : 1) void middle_res16(MidArgs A, const long long* tile_off) {
     constexpr int NW = NT / 64;
+    constexpr int RCT = TWO ? 2 : rct_for<NT>();
     __shared__ int crow_in[CROW_MAX];
     __shared__ int crow_out[CROW_MAX];
-    __shared__ LFrag<E> sB[2 * rct_for<NT>() * 4];
+    __shared__ LFrag<E> sB[2 * RCT * 4];
     // workgroup -> (block, chunk of NW row tiles).  Workgroups are dealt to the
     // eight XCDs in turn, so the chunks of a block are numbered eight apart:
     // they run on one XCD at about the same time and share its input rows in L2.
@@ -1086,7 +1091,7 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
     const Frag<E>* St = (const Frag<E>*)A.S + tile_off[bi] * 64;
     const int* Sang = ANG ? A.ang + tile_off[bi] * 512 : nullptr;
     // the first factor tiles are requested ahead of the row tables and the barrier
-    constexpr int MAD = NT >= 1024 ? 1 : 2;  // factor tiles requested ahead (16 waves: register budget)
+    constexpr int MAD = (NT >= 1024 || TWO) ? 1 : 2;  // factor tiles requested ahead (16 waves: register budget)
     APipe<E, MAD, ANG> pipe;
     const int m_first = chunk * NW * 16;
     a_prefetch<E, MAD, ANG>(pipe, St, Sang, M, K, m_first + wave * 16);
@@ -1100,9 +1105,8 @@ __global__ __launch_bounds__(NT) void middle_res16(MidArgs A, const long long* t
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
         // (only the middle itself, with phase tiles, changes the vectors' scale)
-        gemm_res16<E, NT, MAD, ANG>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB, ANG ? A.bscale : 1.f, Sang,
-                                    pipe,
-                                    m0 == m_first);
+        gemm_res16<E, NT, MAD, ANG, false, TWO ? RCT : 0>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB,
+                                                         ANG ? A.bscale : 1.f, Sang, pipe, m0 == m_first);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
@@ -1425,7 +1429,9 @@ void pack_group_tiles(int elem, int P, const int* k, const long long* perm_off, 
 namespace {
 // Up and middle with multi-tile B stages and streamed A; down with z resident
 // (ranks beyond the resident capacity run W0).  NT = 512, 768 or 1024 threads.
-template <class E, int NT>
+// TWO: the middle kinds (phase-tile middle, dense group down) in the form
+// that puts two workgroups on a CU.
+template <class E, int NT, bool TWO = false>
 void launch_res16(LevelKernel which, const void* args, long long count, int nrhs, void* scratch,
                   const long long* tile_off, hipStream_t s) {
     const dim3 grid((unsigned)count, (nrhs + NRHS - 1) / NRHS);
@@ -1441,8 +1447,8 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
         MIDBF_CHECK(a.ang || a.bscale == 1.f, MIDBF_ERR_ARG, "a scale change needs the middle's phase tiles");
         a.mchunks = std::max(1, (a.out_max + NT / 4 - 1) / (NT / 4));
         const dim3 mgrid((unsigned)(count * a.mchunks), grid.y);
-        if (a.ang) hipLaunchKernelGGL((middle_res16<E, NT, true>), mgrid, dim3(NT), 0, s, a, tile_off);
-        else hipLaunchKernelGGL((middle_res16<E, NT, false>), mgrid, dim3(NT), 0, s, a, tile_off);
+        if (a.ang) hipLaunchKernelGGL((middle_res16<E, NT, true, TWO>), mgrid, dim3(NT), 0, s, a, tile_off);
+        else hipLaunchKernelGGL((middle_res16<E, NT, false, TWO>), mgrid, dim3(NT), 0, s, a, tile_off);
     }
     else if (which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT)
         hipLaunchKernelGGL((down_res16<E, NT>), grid, dim3(NT), 0, s, *(const DownArgs*)args, count,
@@ -1470,6 +1476,11 @@ void launch_split16(LevelKernel which, int variant, const void* args, long long 
         case 7: launch_res16<E, 512>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 8: launch_res16<E, 1024>(which, args, count, nrhs, scratch, tile_off, s); break;
         case 9: launch_res16<E, 768>(which, args, count, nrhs, scratch, tile_off, s); break;
+        case 10:
+            // the middle kinds with two workgroups per CU; the other kinds as variant 9
+            if (which == LevelKernel::Middle) launch_res16<E, 512, true>(which, args, count, nrhs, scratch, tile_off, s);
+            else launch_res16<E, 768>(which, args, count, nrhs, scratch, tile_off, s);
+            break;
         case 5:
         case 6: {
             // down with z resident in LDS (variant 5: 512 threads, 6: 1024); other kinds, or ranks

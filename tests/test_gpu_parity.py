@@ -297,7 +297,7 @@ def test_bf16x3_apply(n, nrhs):
     assert rel_l2(gb[rows], direct_sum(K, f, rows=rows)) < 1e-3
 
 
-@pytest.mark.parametrize("variant", range(10))
+@pytest.mark.parametrize("variant", range(11))
 def test_bf16x3_every_variant(variant):
     F = _build(128, "fio_ellipse")
     f = W.complex_gaussian(128 * 128, 64, 46)
@@ -305,7 +305,7 @@ def test_bf16x3_every_variant(variant):
     F.set_variants([variant] * 3, precision="bf16x3")
     gb = from_dev(F.apply(to_dev(f, torch.complex64), precision="bf16x3"))
     assert rel_l2(gb, g64) < 1e-4
-    assert F.tune(64, "bf16x3")[0] in range(10)
+    assert F.tune(64, "bf16x3")[0] in range(11)
 
 
 # ---- split-fp16 matrix-core path ---------------------------------------------
@@ -324,7 +324,7 @@ def test_fp16x3_apply(n, nrhs):
     assert F.stats()["bytes_fp16"] > 0
 
 
-@pytest.mark.parametrize("variant", range(10))
+@pytest.mark.parametrize("variant", range(11))
 def test_fp16x3_every_variant(variant):
     F = _build(128, "fio_ellipse", precisions=1 | 8)
     f = W.complex_gaussian(128 * 128, 64, 48)
@@ -332,13 +332,13 @@ def test_fp16x3_every_variant(variant):
     F.set_variants([variant] * 3, precision="fp16x3")
     gh = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp16x3"))
     assert rel_l2(gh, g64) < 5e-6
-    assert F.tune(64, "fp16x3")[0] in range(10)
+    assert F.tune(64, "fp16x3")[0] in range(11)
 
 
 @pytest.mark.parametrize("nrhs", [64, 70])
 def test_fp16x3_lattice_input_path(nrhs):
     """When the first up step keeps every leaf point (64^2: every leaf decomposition is full rank),
-    the table-driven split kernels (variants 7-9) transpose the input into the row-major copy and
+    the table-driven split kernels (variants 7-10) transpose the input into the row-major copy and
     the step above reads it through lattice rows; the other variants keep the first-step copy.
     Both must match the FP64 apply; the profile shows which path ran."""
     n = 64
