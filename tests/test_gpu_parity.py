@@ -346,7 +346,7 @@ def test_fp16x3_lattice_input_path(nrhs):
     assert int(F.ranks(1, 0).min()) == 64         # no redundant leaf points on the column side
     f = W.complex_gaussian(n * n, nrhs, 64, n)
     g64 = from_dev(F.apply(to_dev(f)))
-    for v, lattice in ((9, True), (7, True), (0, False)):
+    for v, lattice in ((9, True), (10, True), (7, True), (0, False)):
         F.set_variants([v] * 3, precision="fp16x3")
         F.profile(True, by_level=True)
         g = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp16x3"))
