@@ -109,18 +109,28 @@ def roofline(dominant: dict, prec: str, variant=None, workload: str = ""):
             "frac": round(f_hbm, 4), **common}
 
 
-def id_roofline(st: dict) -> dict:
+def id_roofline(st: dict, workload: str = "") -> dict:
     """The build's batched FP64 interpolative decompositions (id_kernel): HIP-event time of their
     launches, 8 m n k real flops per decomposition against the FP64 peak, and one read of every
-    sample matrix against HBM."""
+    sample matrix against HBM.  With a committed counter record of this workload and kernel source,
+    also the HBM bytes all of the build's id_kernel launches moved (FETCH_SIZE + WRITE_SIZE)."""
     ms = st["id_ms"]
     if ms <= 0:
         return None
     tf = st["id_flops"] / ms / 1e9
     gbps = st["id_bytes"] / ms / 1e6
-    return {"kernel": "id_kernel", "ms": round(ms, 1), "flops": st["id_flops"], "bytes": st["id_bytes"],
-            "TFLOPs": round(tf, 3), "frac_fp64": round(tf / PEAK["fp64_TF"], 4),
-            "GBps": round(gbps, 1), "frac_hbm": round(gbps / PEAK["hbm_GBps"], 4)}
+    out = {"kernel": "id_kernel", "ms": round(ms, 1), "flops": st["id_flops"], "bytes": st["id_bytes"],
+           "TFLOPs": round(tf, 3), "frac_fp64": round(tf / PEAK["fp64_TF"], 4),
+           "GBps": round(gbps, 1), "frac_hbm": round(gbps / PEAK["hbm_GBps"], 4), "traffic": None}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(path):
+        with open(path) as fh:
+            rec = json.load(fh).get(f"{workload}/id_kernel")
+        if rec and rec.get("source_sha") == source_sha(rec["source_files"]):
+            t = rec["hbm_bytes_per_build"]
+            out.update({"traffic": t, "traffic_GBps": round(t / ms / 1e6, 1),
+                        "traffic_frac_hbm": round(t / ms / 1e6 / PEAK["hbm_GBps"], 4)})
+    return out
 
 
 def step_roofline(kt: list[dict], steps: int, ms: float, prec: str) -> dict:
@@ -557,7 +567,7 @@ def main() -> int:
         "rel_l2_err": err,
         "launches_per_s": round(args.steps / wall, 3),
         "build_s": round(build_s, 2), "init_s": round(init_s, 2),
-        "build_id": id_roofline(st),
+        "build_id": id_roofline(st, w.name),
         "tuned_variants": variants,
         "tune_s": None if tune_s is None else round(tune_s, 2),
         "factor_entries": st["entries"],
