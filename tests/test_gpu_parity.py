@@ -335,6 +335,20 @@ def test_fp16x3_every_variant(variant):
     assert F.tune(64, "fp16x3")[0] in range(11)
 
 
+@pytest.mark.parametrize("n,nrhs", [(64, 70), (256, 64), (256, 20)])
+@pytest.mark.parametrize("variant", [9, 10])
+def test_fp16x3_two_workgroup_middle_odd_levels(n, nrhs, variant):
+    """Split variant 10 runs the middle kinds with two 512-thread workgroups per CU (two-tile B
+    stages).  L odd (64^2: L = 3, 256^2: L = 5) gives single-piece middle blocks and ragged right-hand
+    side tiles (70 = 64 + 6, 20); the result must match the FP64 apply as variant 9's does."""
+    F = _build(n, "fio_ellipse", precisions=1 | 8)
+    f = W.complex_gaussian(n * n, nrhs, 49, n)
+    g64 = from_dev(F.apply(to_dev(f)))
+    F.set_variants([variant] * 3, precision="fp16x3")
+    gh = from_dev(F.apply(to_dev(f, torch.complex64), precision="fp16x3"))
+    assert rel_l2(gh, g64) < 5e-6, (n, nrhs, variant)
+
+
 @pytest.mark.parametrize("nrhs", [64, 70])
 def test_fp16x3_lattice_input_path(nrhs):
     """When the first up step keeps every leaf point (64^2: every leaf decomposition is full rank),
