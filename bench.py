@@ -57,9 +57,9 @@ def source_sha(files: list[str]) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, variant, workload: str):
-    """HBM bytes per launch from the committed counter summary, if taken on this workload, kernel source
-    and variant."""
+def counter_record(kernel: str, variant, workload: str):
+    """The committed counter record of a kernel (profiles/traffic.json), if taken on this workload,
+    kernel source and variant."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -70,7 +70,13 @@ def traffic_for(kernel: str, variant, workload: str):
         return None
     if rec.get("variants") is not None and variant not in rec["variants"]:
         return None
-    return rec["hbm_bytes_per_launch"]
+    return rec
+
+
+def traffic_for(kernel: str, variant, workload: str):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE), or None."""
+    rec = counter_record(kernel, variant, workload)
+    return None if rec is None else rec["hbm_bytes_per_launch"]
 
 
 def compute_peak(prec: str, kernel: str) -> float:
@@ -102,6 +108,12 @@ def roofline(dominant: dict, prec: str, variant=None, workload: str = ""):
               "achieved_GBps": round(gbps, 1), "achieved_TFLOPs": round(tfs, 3), "peak_TFLOPs": peak_tf,
               "algorithmic_bytes_per_launch": bytes_per, "stored_bytes_per_launch": stored_per,
               "flops_per_launch": flops_per}
+    rec = counter_record(dominant["name"], variant, workload)
+    if rec and "mfma_util" in rec:
+        # the matrix cores' own view (MfmaUtil, MfmaFlops* counters), flops over this run's time
+        hw = rec["mfma_flops_per_launch"] / t / 1e12
+        common.update({"mfma_util_counters": rec["mfma_util"], "mfma_TFLOPs_counters": round(hw, 3),
+                       "frac_mfma_counters": round(hw / peak_tf, 4)})
     if f_cmp > f_hbm:
         return {"bound": cmp_bound, "achieved": round(tfs, 3), "peak": peak_tf, "unit": "TFLOP/s",
                 "frac": round(f_cmp, 4), **common}
