@@ -133,6 +133,50 @@ def test_id_batch_exact_low_rank():
         assert rel_l2(rec, A[b]) < 1e-11
 
 
+def _low_rank(rng, b, m, n, r):
+    A = (rng.standard_normal((b, m, r)) + 1j * rng.standard_normal((b, m, r))) @ \
+        (rng.standard_normal((b, r, n)) + 1j * rng.standard_normal((b, r, n)))
+    return A
+
+
+@pytest.mark.parametrize("m,n,r", [(64, 2048, 12), (4096, 32, 7), (37, 301, 5), (5, 40, 9), (1, 17, 1),
+                                   (33, 1, 1)])
+def test_id_batch_edge_shapes(m, n, r):
+    """The largest candidate count (2048) and sample count (4096) the kernel takes, sizes off every
+    block (rows not a multiple of the 32-row staging or the 4-row loads, columns not a multiple of the
+    256 threads or the 16-pivot panels), fewer rows than the rank (wide: rank m), one row, one column.
+    Exact low-rank inputs: the rank is min(r, m, n) and the ID reproduces the matrix."""
+    M = _mod()
+    A = _low_rank(W.rng(38, m + n), 2, m, n, r)
+    k, perm, T = M.id_batch(torch.from_numpy(A.copy()).to(DEV), 1e-10)
+    want = min(r, m, n)
+    for b in range(2):
+        assert int(k[b]) == want, (m, n, r, k)
+        assert sorted(perm[b].tolist()) == list(range(n))
+        kb = int(k[b])
+        rec = np.zeros_like(A[b])
+        rec[:, perm[b]] = A[b][:, perm[b][:kb]] @ np.hstack([np.eye(kb), T[b].cpu().numpy()])
+        assert rel_l2(rec, A[b]) < 1e-10, (m, n, r)
+
+
+def test_id_batch_zero_and_mixed_matrices():
+    """A zero matrix has rank 0 (T empty, every column redundant); it may share a batch with others."""
+    M = _mod()
+    A = _low_rank(W.rng(39, 0), 3, 50, 40, 6)
+    A[1] = 0.0
+    k, perm, T = M.id_batch(torch.from_numpy(A.copy()).to(DEV), 1e-10)
+    assert int(k[1]) == 0 and tuple(T[1].shape) == (0, 40)
+    assert int(k[0]) == 6 and int(k[2]) == 6
+
+
+def test_id_batch_refuses_beyond_its_sizes():
+    M = _mod()
+    for m, n in ((8, 2049), (4097, 8)):
+        X = torch.zeros((1, m, n), dtype=torch.complex128, device=DEV)
+        with pytest.raises(Exception):
+            M.id_batch(X, 1e-6)
+
+
 # ---- whole-transform parity ------------------------------------------------
 
 def _build(n, phase, d=2, **kw):
