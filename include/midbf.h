@@ -184,7 +184,9 @@ midbf_status midbf_load(const char* path, unsigned precisions, void* stream, mid
  * Sec. 3.5 applied right to left).  f_dev, g_dev: N x nrhs column-major with
  * leading dimension ld (complex128 for MIDBF_FP64, complex64 otherwise).
  * The precision's factor copy must have been kept.  Workspace for nrhs is
- * allocated on the first call with that many right-hand sides.
+ * allocated on the first call with that many right-hand sides.  Errors:
+ * MIDBF_ERR_ARG for a null handle or vector, nrhs < 1, ld < N, or a
+ * precision whose copy was not kept; nothing is launched then.
  */
 midbf_status midbf_apply(midbf_handle h, const void* f_dev, void* g_dev, int nrhs, long long ld,
                          midbf_precision prec, void* stream);

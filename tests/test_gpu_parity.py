@@ -265,6 +265,18 @@ def test_fio256_sampled_rows_fp64_fp32():
     assert rel_l2(g32[rows], gd) < 1e-5
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp16x3", 5e-6), ("bf16x3", 1e-4)])
+def test_many_rhs_tiles(precision, tol):
+    """257 right-hand sides: five 64-column tiles on the matrix cores, the last holding one column."""
+    F = _build(64, "fio_ellipse", precisions=1 | 2 | 4 | 8)
+    f = W.complex_gaussian(64 * 64, 257, 50, 64)
+    g64 = from_dev(F.apply(to_dev(f)))
+    g = from_dev(F.apply(to_dev(f, torch.complex64), precision=precision))
+    assert g.shape == g64.shape and np.isfinite(g).all()
+    assert rel_l2(g, g64) < tol
+    assert rel_l2(g[:, -1:], g64[:, -1:]) < 2 * tol
+
+
 def test_errors_reported():
     M = _mod()
     from paper_1908_09376_amd._lib import MidbfError
@@ -287,6 +299,15 @@ def test_errors_reported():
     buf = (ctypes.c_int * 4)()
     assert _lib.lib.midbf_ranks(F._h, 0, 0, buf, -1) == -1
     assert b"count" in _lib.lib.midbf_last_error()
+    # the C ABI refuses an empty block, a short leading dimension and null vectors before any launch
+    g = torch.empty_like(f)
+    fp, gp = ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(g.data_ptr())
+    assert _lib.lib.midbf_apply(F._h, fp, gp, 0, 1024, 0, None) == -1
+    assert b"nrhs" in _lib.lib.midbf_last_error()
+    assert _lib.lib.midbf_apply(F._h, fp, gp, 1, 1000, 0, None) == -1
+    assert b"ld" in _lib.lib.midbf_last_error()
+    assert _lib.lib.midbf_apply(F._h, None, gp, 1, 1024, 0, None) == -1
+    assert _lib.lib.midbf_apply(F._h, fp, gp, 1, 1024, 0, None) == 0          # the same call, well formed
 
 
 # ---- matrix-core path (many right-hand sides, FP32) -------------------------
