@@ -277,6 +277,18 @@ def test_many_rhs_tiles(precision, tol):
     assert rel_l2(g[:, -1:], g64[:, -1:]) < 2 * tol
 
 
+def test_split_adjoint_refused():
+    """The split 16-bit copies serve the forward transform only: an adjoint in them is refused with
+    MIDBF_ERR_UNIMPLEMENTED, and the FP32 adjoint of the same handle still runs."""
+    M = _mod()
+    from paper_1908_09376_amd._lib import MidbfError
+    F = _build(64, "fio_ellipse", precisions=1 | 2 | 8)
+    g = torch.zeros((64, 64 * 64), dtype=torch.complex64, device=DEV)
+    with pytest.raises(MidbfError, match="UNIMPLEMENTED"):
+        F.apply_adjoint(g, precision="fp16x3")
+    assert torch.isfinite(F.apply_adjoint(g, precision="fp32").abs()).all()
+
+
 def test_errors_reported():
     M = _mod()
     from paper_1908_09376_amd._lib import MidbfError
