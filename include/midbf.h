@@ -120,6 +120,15 @@ typedef struct {
     long long n_points;      /* scattered points: N, the size of each set (0: n^d); n then
                                 only sets the tree depth log2(n / leaf_box)                */
     double helmholtz_h;      /* MIDBF_PHASE_HELMHOLTZ: h                                    */
+    int adjoint;             /* nonzero: factor K^H instead of K, i.e. the kernel
+                                conj(K(x, xi)) with the xi points as rows and the x points
+                                as columns (the same trees, the phase negated and its
+                                arguments swapped), so that midbf_apply computes K^H g in
+                                every kept precision, the split 16-bit ones included.  This
+                                is a factorization of K^H to the tolerance, not the exact
+                                conjugate transpose of a forward factorization (that is
+                                midbf_apply_adjoint, FP64 and FP32).  Factor files hold
+                                forward factorizations only.                                */
 } midbf_params;
 
 typedef struct {
@@ -422,7 +431,8 @@ midbf_status midbf_ranks(midbf_handle h, int side, int step, int* out, long long
  * midbf_kernel_entries -- out_dev[i * ncols + j] = K(x_rows[i], xi_cols[j])
  * (complex128) for point numbers rows_dev[0..nrows) and cols_dev[0..ncols),
  * with the phase of p (Sec. 3 preamble: entry evaluation from Phi in FP64,
- * reduced mod 1 before the exponential).
+ * reduced mod 1 before the exponential); with p->adjoint set, the entries of
+ * K^H instead, conj(K(x_cols[j], xi_rows[i])).
  */
 midbf_status midbf_kernel_entries(const midbf_params* p, const int* rows_dev, int nrows,
                                   const int* cols_dev, int ncols, void* out_dev, void* stream);

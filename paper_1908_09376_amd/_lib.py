@@ -27,7 +27,7 @@ class Params(C.Structure):
                 ("U_dev", C.c_void_p), ("V_dev", C.c_void_p), ("r", C.c_int),
                 ("precisions", C.c_uint), ("build_workspace_bytes", C.c_size_t), ("fixed_rank", C.c_int),
                 ("x_points", C.c_void_p), ("xi_points", C.c_void_p), ("n_points", C.c_longlong),
-                ("helmholtz_h", C.c_double)]
+                ("helmholtz_h", C.c_double), ("adjoint", C.c_int)]
 
 
 class Stats(C.Structure):

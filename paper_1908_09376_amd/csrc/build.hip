@@ -995,8 +995,10 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
         }
         if (points) {
             // own copies of the coordinates, host copies for the trees (xi mapped to [0, 1)^d), and
-            // per side the leaf slot tables, n0 slots per leaf (the fullest leaf of either tree)
+            // per side the leaf slot tables, n0 slots per leaf (the fullest leaf of either tree).
+            // The row tree holds the x points, or for K^H the xi points.
             h->points = true;
+            const bool adj = p.adjoint != 0;
             const size_t cnt = (size_t)h->N * p.d;
             h->own_xp = dalloc<double>(cnt);
             h->own_wp = dalloc<double>(cnt);
@@ -1005,8 +1007,10 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
             MIDBF_HIP(hipStreamSynchronize(st));
             h->tree_pts[0].resize(cnt);
             h->tree_pts[1].resize(cnt);
-            MIDBF_HIP(hipMemcpy(h->tree_pts[0].data(), h->own_xp, cnt * sizeof(double), hipMemcpyDeviceToHost));
-            MIDBF_HIP(hipMemcpy(h->tree_pts[1].data(), h->own_wp, cnt * sizeof(double), hipMemcpyDeviceToHost));
+            MIDBF_HIP(hipMemcpy(h->tree_pts[adj ? 1 : 0].data(), h->own_xp, cnt * sizeof(double),
+                                hipMemcpyDeviceToHost));
+            MIDBF_HIP(hipMemcpy(h->tree_pts[adj ? 0 : 1].data(), h->own_wp, cnt * sizeof(double),
+                                hipMemcpyDeviceToHost));
             // each set moved and scaled uniformly into [0, 1]^d by its bounding cube
             for (int t = 0; t < 2; ++t) {
                 std::vector<double>& v = h->tree_pts[t];
@@ -1045,7 +1049,8 @@ midbf_plan* build_plan(const midbf_params& p, hipStream_t st, void* replay_file)
             h->p.x_points = h->own_xp;
             h->p.xi_points = h->own_wp;
         }
-        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, h->p.U_dev, h->p.V_dev, p.r, h->own_xp, h->own_wp, p.helmholtz_h};
+        h->ph = PhaseDesc{(int)p.phase, p.d, p.n, h->p.U_dev, h->p.V_dev, p.r, h->own_xp, h->own_wp, p.helmholtz_h,
+                          p.adjoint != 0};
         h->rows.resize(h->b);
         h->cols.resize(h->b);
         if (h->keep & (MIDBF_KEEP_BF16 | MIDBF_KEEP_FP16)) {
@@ -1146,6 +1151,7 @@ void save_plan(midbf_plan* h, const char* path, hipStream_t st) {
     MIDBF_CHECK(path, MIDBF_ERR_ARG, "null path");
     MIDBF_CHECK(h->keep & MIDBF_KEEP_FP64, MIDBF_ERR_ARG, "saving needs the FP64 factor copy (MIDBF_KEEP_FP64)");
     MIDBF_CHECK(!h->points, MIDBF_ERR_UNIMPLEMENTED, "factor files hold lattice factorizations");
+    MIDBF_CHECK(!h->p.adjoint, MIDBF_ERR_UNIMPLEMENTED, "factor files hold forward factorizations");
     MIDBF_HIP(hipStreamSynchronize(st));
     File F(path, "wb");
     FileHead H{};
@@ -1220,7 +1226,8 @@ midbf_plan* load_plan(const char* path, unsigned precisions, hipStream_t st, mid
 
 void kernel_entries(const midbf_params& p, const int* rows, int nrows, const int* cols, int ncols, void* out,
                     hipStream_t st) {
-    PhaseDesc ph{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r, p.x_points, p.xi_points, p.helmholtz_h};
+    PhaseDesc ph{(int)p.phase, p.d, p.n, p.U_dev, p.V_dev, p.r, p.x_points, p.xi_points, p.helmholtz_h,
+                 p.adjoint != 0};
     const long long tot = (long long)nrows * ncols;
     if (tot == 0) return;
     const int gx = (int)std::min<long long>((tot + BT - 1) / BT, 4096);

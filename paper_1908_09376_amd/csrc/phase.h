@@ -17,6 +17,7 @@ struct PhaseDesc {
     const double* xp;     // scattered points: x and xi coordinates (N x d row-major), or null
     const double* wp;
     double hh;            // MIDBF_PHASE_HELMHOLTZ: h
+    int transpose;        // nonzero: the kernel of K^H, conj(K(x_q, xi_p)) (rows p are xi points)
 };
 
 // Smooth (non-bilinear) part of the phase at x = a/n, xi = b - n/2.
@@ -54,7 +55,7 @@ __device__ inline double phase_smooth(const PhaseDesc& ph, const int* a, const i
 }
 
 // frac(Phi(x_p, xi_q)) in [0, 1) for point numbers p (x side), q (xi side).
-__device__ inline double phase_frac(const PhaseDesc& ph, long long p, long long q) {
+__device__ inline double phase_frac_xxi(const PhaseDesc& ph, long long p, long long q) {
     if (ph.kind == MIDBF_PHASE_LOWRANK) {
         const double* u = ph.U + p * ph.r;
         const double* v = ph.V + q * ph.r;
@@ -87,6 +88,14 @@ __device__ inline double phase_frac(const PhaseDesc& ph, long long p, long long 
     if (md < 0) md += ph.n;
     double t = (double)md / (double)ph.n + phase_smooth(ph, a, b);
     return t - floor(t);
+}
+
+// The phase of entry (p, q) of the factored kernel, as frac in [0, 1): Phi(x_p, xi_q), or for
+// K^H the phase of conj(K(x_q, xi_p)), frac(-Phi(x_q, xi_p)).
+__device__ inline double phase_frac(const PhaseDesc& ph, long long p, long long q) {
+    if (!ph.transpose) return phase_frac_xxi(ph, p, q);
+    const double f = phase_frac_xxi(ph, q, p);
+    return f > 0.0 ? 1.0 - f : 0.0;
 }
 
 __device__ inline double2 kernel_entry(const PhaseDesc& ph, long long p, long long q) {

@@ -21,7 +21,7 @@ def _stream_ptr(stream) -> int:
 
 
 def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, precisions=0,
-            workspace_bytes=0, fixed_rank=0, points=None, helmholtz_h=0.0) -> L.Params:
+            workspace_bytes=0, fixed_rank=0, points=None, helmholtz_h=0.0, adjoint=False) -> L.Params:
     p = L.Params()
     p.d, p.n, p.tol = d, n, tol
     p.leaf_box, p.oversample_t, p.k_cap = leaf_box, oversample_t, k_cap
@@ -37,6 +37,7 @@ def _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U=None, V=None, pre
         p.xi_points = points[1].data_ptr()
         p.n_points = points[0].shape[0]
     p.helmholtz_h = helmholtz_h
+    p.adjoint = 1 if adjoint else 0
     return p
 
 
@@ -44,12 +45,14 @@ _PREC = {"fp64": L.FP64, "fp32": L.FP32, "bf16x3": L.SPLIT_BF16, "fp16x3": L.SPL
 
 
 class MIDBF:
-    """A built factorization K ~ U^L...U^h S V^h...V^L (midbf_build)."""
+    """A built factorization K ~ U^L...U^h S V^h...V^L (midbf_build); with adjoint=True a factorization
+    of K^H, whose apply computes K^H g in every kept precision."""
 
     def __init__(self, d: int, n: int, phase: str, tol: float = 1e-6, leaf_box: int = 8,
                  oversample_t: int = 5, k_cap: int = 0, U: torch.Tensor | None = None,
                  V: torch.Tensor | None = None, precisions: int = 0, workspace_bytes: int = 0,
-                 fixed_rank: int = 0, points=None, helmholtz_h: float = 0.0, stream=None):
+                 fixed_rank: int = 0, points=None, helmholtz_h: float = 0.0, adjoint: bool = False,
+                 stream=None):
         self.d, self.n, self.N = d, n, n ** d
         if phase == "lowrank":
             U = U.to(torch.float64).contiguous()
@@ -64,7 +67,7 @@ class MIDBF:
                     raise ValueError("points: two CUDA tensors of the same shape (N, d)")
         self._UV = (U, V, points)    # kept alive: the library reads them during the build
         self._p = _params(d, n, phase, tol, leaf_box, oversample_t, k_cap, U, V, precisions,
-                          workspace_bytes, fixed_rank, points, helmholtz_h)
+                          workspace_bytes, fixed_rank, points, helmholtz_h, adjoint)
         h = C.c_void_p()
         L.check(L.lib.midbf_build(C.byref(self._p), _stream_ptr(stream), C.byref(h)))
         self._h = h
@@ -283,9 +286,11 @@ class Batch:
 
 
 def kernel_entries(d: int, n: int, phase: str, rows: torch.Tensor, cols: torch.Tensor,
-                   U: torch.Tensor | None = None, V: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """K(rows, cols) as a complex128 (len(rows), len(cols)) tensor (midbf_kernel_entries)."""
-    p = _params(d, n, phase, 1e-6, 1, 1, 0, U, V)
+                   U: torch.Tensor | None = None, V: torch.Tensor | None = None, adjoint: bool = False,
+                   stream=None) -> torch.Tensor:
+    """K(rows, cols) (or K^H(rows, cols) with adjoint) as a complex128 (len(rows), len(cols)) tensor
+    (midbf_kernel_entries)."""
+    p = _params(d, n, phase, 1e-6, 1, 1, 0, U, V, adjoint=adjoint)
     rows = rows.to(torch.int32).contiguous()
     cols = cols.to(torch.int32).contiguous()
     out = torch.empty((rows.numel(), cols.numel()), dtype=torch.complex128, device=rows.device)

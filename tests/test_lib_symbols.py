@@ -69,3 +69,32 @@ def test_factor_file_errors_without_gpu_work(tmp_path):
     assert _lib.lib.midbf_load(str(short).encode(), 0, None, None, C.byref(h)) == -8
     assert b"truncated" in _lib.lib.midbf_last_error()
     assert _lib.lib.midbf_save(None, b"x", None) == -1
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets that a C compiler gives the
+    header's struct of the same role (a field added on one side only would shift the others)."""
+    import shutil
+    import subprocess
+    from paper_1908_09376_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        import pytest
+        pytest.skip("no C compiler")
+    pairs = [(_lib.Params, "midbf_params"), (_lib.Stats, "midbf_stats"), (_lib.KernelTime, "midbf_kernel_time"),
+             (_lib.BatchStats, "midbf_batch_stats"), (_lib.RecoverInfo, "phase_recover_info")]
+    lines = ['#include "midbf.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    want = []
+    for cls, cname in pairs:
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for f in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f[0]}));')
+            want.append(getattr(cls, f[0]).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == want
