@@ -92,6 +92,21 @@ def test_adjoint_build_256_split16_sampled():
     F.close()
 
 
+def test_adjoint_build_3d():
+    """3-D lattice, the iso3d phase at 16^3: FP64 and 16-RHS FP32 matrix-core applies of the K^H
+    factorization against the direct adjoint sum on seeded rows."""
+    M = _mod()
+    n = 16
+    K = Kernel(3, n, "iso3d")
+    F = M.MIDBF(3, n, "iso3d", tol=1e-6, adjoint=True, precisions=1 | 2)
+    g = W.complex_gaussian(K.N, 16, 79)
+    rows = W.sample_rows(K.N, 3, 64)
+    fd = direct_sum_adjoint(K, g, rows=rows)
+    assert rel_l2(from_dev(F.apply(to_dev(g)))[rows], fd) < 1e-5
+    assert rel_l2(from_dev(F.apply(to_dev(g, torch.complex64), precision="fp32"))[rows], fd) < 1e-5
+    F.close()
+
+
 def test_adjoint_build_lowrank_phase():
     M = _mod()
     n = 32
