@@ -92,6 +92,28 @@ def test_adjoint_build_256_split16_sampled():
     F.close()
 
 
+def test_adjoint_build_512x64_split16():
+    """The metric's size, 512^2 with 64 right-hand sides: the autotuned split-FP16 apply of the K^H
+    factorization (even L) against the direct adjoint sum on 64 seeded rows."""
+    M = _mod()
+    w = W.WORKLOADS["fio512x64"]
+    K = Kernel(2, w.n, w.phase)
+    print("[adj-build] 512^2 ellipse, fp16x3 x 64", flush=True)
+    FH = M.MIDBF(2, w.n, w.phase, tol=w.tol, adjoint=True, precisions=8)
+    st = FH.stats()
+    print(f"[adj-build] ranks {st['k_min']}..{st['k_max']}", flush=True)
+    assert st["L"] == 6
+    FH.tune(64, "fp16x3")
+    g = W.complex_gaussian(K.N, 64, 80)
+    f16 = from_dev(FH.apply(to_dev(g, torch.complex64), precision="fp16x3"))
+    rows = W.sample_rows(K.N, w.cfg, 64)
+    fd = direct_sum_adjoint(K, g, rows=rows)
+    err = rel_l2(f16[rows], fd)
+    print(f"[adj-build] 512^2 x 64 fp16x3: rel L2 vs direct adjoint sum {err:.3e}", flush=True)
+    assert err < 1e-5
+    FH.close()
+
+
 def test_adjoint_build_3d():
     """3-D lattice, the iso3d phase at 16^3: FP64 and 16-RHS FP32 matrix-core applies of the K^H
     factorization against the direct adjoint sum on seeded rows."""
