@@ -54,6 +54,7 @@ class MIDBF:
                  fixed_rank: int = 0, points=None, helmholtz_h: float = 0.0, adjoint: bool = False,
                  stream=None):
         self.d, self.n, self.N = d, n, n ** d
+        self.adjoint = bool(adjoint)
         if phase == "lowrank":
             U = U.to(torch.float64).contiguous()
             V = V.to(torch.float64).contiguous()
@@ -84,6 +85,7 @@ class MIDBF:
         L.check(L.lib.midbf_load(os.fsencode(path), precisions, _stream_ptr(stream), C.byref(p), C.byref(h)))
         self = cls.__new__(cls)
         self.d, self.n, self.N = p.d, p.n, p.n ** p.d
+        self.adjoint = False                  # factor files hold forward factorizations
         self._UV = (None, None)
         self._p = p
         self._h = h

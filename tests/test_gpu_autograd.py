@@ -74,3 +74,32 @@ def test_gradient_piecewise_256_16rhs():
     assert rel_l2(grad[rows], exact) < 1e-5
     # the forward itself vs the direct sum
     assert rel_l2(Kf[rows[:32]], direct_sum(K, f0, rows=rows[:32])) < 1e-5
+
+
+def test_gradient_through_a_factorization_of_the_adjoint():
+    """The backward through a factorization of K^H (adjoint=True) in split FP16, 256^2 x 64 piecewise
+    phase: the gradient 2 K^H (K f - y) against the direct adjoint sum of the same residual on seeded
+    rows, and against the FP64 backward of the forward factors."""
+    import paper_1908_09376_amd as M
+    w = W.WORKLOADS["pw256x16"]
+    F = M.MIDBF(2, w.n, w.phase, tol=w.tol, precisions=1 | 8)
+    FH = M.MIDBF(2, w.n, w.phase, tol=w.tol, precisions=8, adjoint=True)
+    F.tune(64, "fp16x3")
+    FH.tune(64, "fp16x3")
+    f0 = W.complex_gaussian(w.N, 64, 81)
+    y = W.complex_gaussian(w.N, 64, 82)
+    f = _dev(f0).to(torch.complex64).requires_grad_(True)
+    yd = _dev(y).to(torch.complex64)
+    g = M.midbf_matvec(f, F, "fp16x3", adjoint_factor=FH)
+    (g - yd).abs().pow(2).sum().backward()
+    grad = f.grad.to(torch.complex128).cpu().numpy().T
+    r = g.detach().to(torch.complex128).cpu().numpy().T - y
+    rows = W.sample_rows(w.N, w.cfg, 64)
+    exact = 2.0 * direct_sum_adjoint(Kernel(2, w.n, w.phase), r, rows=rows)
+    assert rel_l2(grad[rows], exact) < 1e-5
+    ref = 2.0 * F.apply_adjoint(_dev(r)).cpu().numpy().T
+    assert rel_l2(grad, ref) < 1e-5
+    with pytest.raises(ValueError):
+        M.midbf_matvec(f, F, "fp16x3", adjoint_factor=F)
+    FH.close()
+    F.close()
