@@ -250,7 +250,10 @@ void midbf_graph_destroy(midbf_graph g);
 
 /*
  * midbf_apply_adjoint -- f = K~^H g: conjugate-transposed factors in reverse
- * order (the transposed butterfly).  Same layouts as midbf_apply.
+ * order (the transposed butterfly).  Same layouts as midbf_apply.  FP64 and
+ * FP32 (matrix cores from 16 right-hand sides); a split 16-bit precision is
+ * refused with MIDBF_ERR_UNIMPLEMENTED (K^H in those comes from a handle
+ * built with midbf_params.adjoint, applied with midbf_apply).
  */
 midbf_status midbf_apply_adjoint(midbf_handle h, const void* g_dev, void* f_dev, int nrhs, long long ld,
                                  midbf_precision prec, void* stream);
