@@ -361,8 +361,8 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU apply beside the result")
-    ap.add_argument("--no-adjoint-build", action="store_true",
-                    help="skip the split apply of K^H through a factorization of K^H")
+    ap.add_argument("--adjoint-build", action="store_true",
+                    help="also time K^H in the split precision through a factorization of K^H")
     ap.add_argument("--no-other-split", action="store_true",
                     help="skip the other 16-bit split type beside a split result")
     ap.add_argument("--copy-probe", action="store_true",
@@ -548,7 +548,7 @@ def main() -> int:
     # K^H is factored itself (the adjoint build) and applied like K, against the forward handle's
     # FP64 adjoint of the same block
     adjoint_build = None
-    if args.precision in ("bf16x3", "fp16x3") and pts is None and not args.no_adjoint_build:
+    if args.precision in ("bf16x3", "fp16x3") and pts is None and args.adjoint_build:
         gh = torch.from_numpy(np.ascontiguousarray(W.complex_gaussian(w.N, nrhs, w.cfg, 1).T)).to("cuda:0")
         fh64 = F.apply_adjoint(gh, precision="fp64").cpu().numpy()
         F.close()
