@@ -98,6 +98,8 @@ struct UpArgs {
     int lattice_in;          // 1: `in` is the row-major input copy and lev.src holds lattice points
                              // (only the source-row-table kernels accept it)
     SplitScale sc;           // split 16-bit leaf copy: scale of the copied input (SplitScale)
+    float presplit;          // split 16-bit top up step: > 0 writes its output already split, times
+                             // this power of two, for the middle (MidArgs::presplit); 0: FP32 pairs
 };
 
 struct DownArgs {
@@ -134,6 +136,9 @@ struct MidArgs {
     int mchunks;             // matrix-core FP32 path: workgroups splitting the rows of one block
     const int* ang;          // split 16-bit: the blocks' phase tiles (see mfma.h), or null
     float bscale;            // split 16-bit: power of two applied to the input while staging (SplitScale)
+    int presplit;            // split 16-bit: the input was written already split and scaled by the top
+                             // up step (per entry hi(re) | hi(im) << 16, then lo(re) | lo(im) << 16,
+                             // in the 8 bytes of an FP32 pair), so staging only moves halves
 };
 
 // Input and output row numbers of middle block bi (the concatenations of its

@@ -134,13 +134,31 @@ void launch_checked(midbf_plan* h, const Workspace& ws, LevelKernel which, int p
             const int lv = std::max(0, std::min(level, midbf_plan::VMAXLEV - 1));
             // (DownGroup and DownDense are split-16 only; DownDense runs the middle
             // kernels on the group blocks, whose first-tile table travels in MidArgs::off)
-            if (is_split16(prec) && which != LevelKernel::DownSum)
-                launch_bf16_kernel(prec == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, which,
-                                   (prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant)[kind][lv], args,
+            if (is_split16(prec) && which != LevelKernel::DownSum) {
+                const auto& var = prec == PREC_FP16 ? h->fp16_variant : h->bf16_variant;
+                // the top up step and the middle exchange split vectors only when both run
+                // source-table kernels (split variants 7-10); else both keep FP32 pairs
+                const int top = std::max(0, std::min(h->b - 1, midbf_plan::VMAXLEV - 1));
+                const bool xv = var[0][top] >= 7 && var[0][top] <= 10 && var[2][0] >= 7 && var[2][0] <= 10;
+                const void* ka = args;
+                UpArgs ua;
+                MidArgs ma;
+                if (which == LevelKernel::Up && ((const UpArgs*)args)->presplit > 0.f && !xv) {
+                    ua = *(const UpArgs*)args;
+                    ua.presplit = 0.f;
+                    ka = &ua;
+                }
+                if (which == LevelKernel::Middle && ((const MidArgs*)args)->presplit && !xv) {
+                    ma = *(const MidArgs*)args;
+                    ma.presplit = 0;
+                    ka = &ma;
+                }
+                launch_bf16_kernel(prec == PREC_FP16 ? SPLIT16_FP16 : SPLIT16_BF16, which, var[kind][lv], ka,
                                    mfma_count, nrhs, ws.scratch,
                                    which == LevelKernel::DownDense ? ((const MidArgs*)args)->off
                                                                    : h->mid.d_tile_off,
                                    st);
+            }
             else
                 launch_mfma_kernel(which, (prec == PREC_FP64 ? h->mfma64_variant : h->mfma_variant)[kind][lv], args,
                                    mfma_count, nrhs, ws.scratch, st, prec == PREC_FP64);
@@ -304,6 +322,10 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
     const int hU = hbound(h->N / ipow(h->P, h->L - h->b + 1)), hD = hbound(h->N / h->P);
     const SplitScale sc_in{cexp, hU}, sc_out{cexp, hD};
     auto pow2 = [](int e) { return std::ldexp(1.0f, e); };
+    // The top up step may hand the middle its vectors already split (UpArgs::presplit); whether it
+    // does is settled at launch from the two kernels' variants (launch_checked)
+    const char* xenv = std::getenv("MIDBF_SPLIT_EXCHANGE");
+    const bool exch = mfma && is_split16(prec) && !adjoint && h->b >= 2 && !(xenv && xenv[0] == '0');
     int o = 0;   // buffer holding the current level's vectors
     for (int s = 0; s < h->b; ++s) {
         const LevelSide& lv = up[s];
@@ -338,6 +360,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         const int ncand = s == 0 ? h->n0 : lv.nmax;
         a.ncand_max = ncand;
         a.nred_max = ncand - lv.kmin;
+        a.presplit = exch && s == h->b - 1 ? (cexp ? pow2(hD - hU) : 1.f) : 0.f;
         // forward VALU up kernel: candidate vector plus one redundant-input strip per wave
         const size_t up_lds = (size_t)ncand * cs * (adjoint || rt > 1 ? rt : 1 + 4);
         const double vin = (s == 0 ? (double)h->N : (double)lv.total_n / h->P) * nrhs * cs;
@@ -390,6 +413,7 @@ std::vector<LaunchDesc> plan_apply(midbf_plan* h, const void* in_ext, void* out_
         a.out_max = M.nr_max;
         a.ang = (is_split16(prec) && !adjoint) ? (const int*)M.ang : nullptr;
         a.bscale = cexp ? pow2(hD - hU) : 1.f;
+        a.presplit = exch ? 1 : 0;
         if (adjoint && mfma) {
             // x = S^H z on the matrix cores: the blocks seen transposed (rows = columns of S),
             // inputs from the row pieces, outputs to the column pieces

@@ -141,6 +141,43 @@ template <class E> __device__ inline void lds_split_store(LFrag<E>* t, int lane,
     t->il[lane] = il;
 }
 
+// One complex value split into hi / lo halves of E, in the exchange form of
+// the top up step's output: x = hi(re) | hi(im) << 16, y = lo(re) | lo(im) << 16
+// (the same conversions as split8, so the planes built from it are the same).
+template <class E> __device__ inline uint2 split_one(float re, float im) {
+    unsigned hw, lw;
+    if constexpr (std::is_same_v<E, _Float16>) {
+        split_pair_f16(re, im, hw, lw);
+    } else {
+        const E xh = (E)re, yh = (E)im;
+        const E xl = (E)(re - (float)xh), yl = (E)(im - (float)yh);
+        hw = (unsigned)__builtin_bit_cast(unsigned short, xh) | ((unsigned)__builtin_bit_cast(unsigned short, yh) << 16);
+        lw = (unsigned)__builtin_bit_cast(unsigned short, xl) | ((unsigned)__builtin_bit_cast(unsigned short, yl) << 16);
+    }
+    return make_uint2(hw, lw);
+}
+
+// Eight values of one fragment lane (8 K rows of one column) already in the
+// exchange form (carried in float2 registers, bits untouched) moved into the
+// four planes of tile t: only 16-bit halves are regrouped.
+template <class E> __device__ inline void lds_presplit_store(LFrag<E>* t, int lane, const float2 (&v)[8]) {
+    uintx4 rh, ih, rl, il;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const unsigned h0 = __builtin_bit_cast(unsigned, v[2 * p].x), h1 = __builtin_bit_cast(unsigned, v[2 * p + 1].x);
+        const unsigned l0 = __builtin_bit_cast(unsigned, v[2 * p].y), l1 = __builtin_bit_cast(unsigned, v[2 * p + 1].y);
+        // v_perm_b32 picks bytes of {src0 : src1} (src1 = bytes 0-3): low halves, then high halves
+        rh[p] = __builtin_amdgcn_perm(h1, h0, 0x05040100u);
+        ih[p] = __builtin_amdgcn_perm(h1, h0, 0x07060302u);
+        rl[p] = __builtin_amdgcn_perm(l1, l0, 0x05040100u);
+        il[p] = __builtin_amdgcn_perm(l1, l0, 0x07060302u);
+    }
+    t->rh[lane] = __builtin_bit_cast(V8<E>, rh);
+    t->ih[lane] = __builtin_bit_cast(V8<E>, ih);
+    t->rl[lane] = __builtin_bit_cast(V8<E>, rl);
+    t->il[lane] = __builtin_bit_cast(V8<E>, il);
+}
+
 template <class V> __device__ inline V neg8(V v) {     // sign flip of eight 16-bit values
     intx4 x = __builtin_bit_cast(intx4, v);
     x ^= (int)0x80008000;
@@ -866,8 +903,10 @@ __device__ inline void a_prefetch(APipe<E, AD, ANG>& p, const Frag<E>* __restric
 
 // BATCH: B stages gathered with load_b8 (measured faster for the up steps,
 // slower for the phase-tile middle).  RCT_ > 0: K tiles per B stage (else
-// rct_for<NT>), with one B fragment in registers at a time.
-template <class E, int NT, int AD, bool ANG = false, bool BATCH = false, int RCT_ = 0, class BOff>
+// rct_for<NT>), with one B fragment in registers at a time.  PRE: B arrives
+// in the exchange form (split_one; bsc is then already applied).
+template <class E, int NT, int AD, bool ANG = false, bool BATCH = false, int RCT_ = 0, bool PRE = false,
+          class BOff>
 __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<E>* __restrict__ Atiles, int M,
                            int K, int base, const float2* __restrict__ src, BOff boff, int nr, LFrag<E>* sB,
                            float bsc, const int* __restrict__ Aang, APipe<E, AD, ANG>& pipe, bool preloaded) {
@@ -900,7 +939,8 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
 #pragma unroll
         for (int q = 0; q < FPT; ++q) {
             const int f = tid + q * NT, kt = f >> 8, kb = (f & 255) >> 6, col = f & 63;
-            lds_split_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q], bsc);
+            if constexpr (PRE) lds_presplit_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q]);
+            else lds_split_store(sB + (buf * RCT + kt) * 4 + (col >> 4), kb * 16 + (col & 15), bt[q], bsc);
         }
     };
     auto tile_at = [&](int kt) { return a_tile<E, ANG>(Atiles, Aang, mt, ktiles, kt); };
@@ -952,7 +992,9 @@ __device__ void gemm_res16(floatx4 (&cr)[1][4], floatx4 (&ci)[1][4], const Frag<
 // tables, the permutation lookups and their two barriers.  RES_ONLY: every
 // decomposition of the level has n - k <= RES_KT * KT, so only the resident
 // path is built.
-template <class E, int NT, bool RES_ONLY>
+// PRE: the top up step writes its output in the exchange form for the middle
+// (UpArgs::presplit).
+template <class E, int NT, bool RES_ONLY, bool PRE = false>
 __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
     constexpr int NW = NT / 64;
     __shared__ int srow[CROW_MAX];
@@ -993,9 +1035,13 @@ __global__ __launch_bounds__(NT) void up_res16(UpArgs A, long long nid) {
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     const int r = nt * 16 + lr;
-                    if (r < nr)
-                        out[(yo + row) * A.nrhs + r0 + r] = make_float2(cr[0][nt][v] + sv[v][nt].x,
-                                                                        ci[0][nt][v] + sv[v][nt].y);
+                    if (r < nr) {
+                        const float xr = cr[0][nt][v] + sv[v][nt].x, xi = ci[0][nt][v] + sv[v][nt].y;
+                        if constexpr (PRE)
+                            ((uint2*)out)[(yo + row) * A.nrhs + r0 + r] =
+                                split_one<E>(xr * A.presplit, xi * A.presplit);
+                        else out[(yo + row) * A.nrhs + r0 + r] = make_float2(xr, xi);
+                    }
                 }
             }
         }
@@ -1061,7 +1107,7 @@ __global__ __launch_bounds__(256) void src_rows_kernel(SrcRowsArgs A) {
 // TWO: two-tile B stages and at most 128 registers, so that two workgroups
 // share a CU (LDS 80 KB each at 512 threads) and one's table loads, first
 // gather and barriers overlap the other's products.
-template <class E, int NT, bool ANG, bool TWO = false>
+template <class E, int NT, bool ANG, bool TWO = false, bool PRE = false>
 __global__ __launch_bounds__(NT, TWO ? NT / 128 : 1) void middle_res16(MidArgs A, const long long* tile_off) {
     constexpr int NW = NT / 64;
     constexpr int RCT = TWO ? 2 : rct_for<NT>();
@@ -1105,8 +1151,8 @@ __global__ __launch_bounds__(NT, TWO ? NT / 128 : 1) void middle_res16(MidArgs A
         floatx4 cr[1][4], ci[1][4];
         zero_acc<1>(cr, ci);
         // (only the middle itself, with phase tiles, changes the vectors' scale)
-        gemm_res16<E, NT, MAD, ANG, false, TWO ? RCT : 0>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB,
-                                                         ANG ? A.bscale : 1.f, Sang, pipe, m0 == m_first);
+        gemm_res16<E, NT, MAD, ANG, false, TWO ? RCT : 0, PRE>(cr, ci, St, M, K, base, xin + r0, boff, nr, sB,
+                                                              ANG ? A.bscale : 1.f, Sang, pipe, m0 == m_first);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = base + 4 * lk + v;
@@ -1438,8 +1484,14 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
     if (which == LevelKernel::Up) {
         const UpArgs& a = *(const UpArgs*)args;
         MIDBF_CHECK(a.lev.src != nullptr, MIDBF_ERR_ARG, "the split up kernels need the level's source-row table");
-        if (a.nred_max <= RES_KT * KT) hipLaunchKernelGGL((up_res16<E, NT, true>), grid, dim3(NT), 0, s, a, count);
-        else hipLaunchKernelGGL((up_res16<E, NT, false>), grid, dim3(NT), 0, s, a, count);
+        const bool res = a.nred_max <= RES_KT * KT;
+        if (a.presplit > 0.f) {
+            if (res) hipLaunchKernelGGL((up_res16<E, NT, true, true>), grid, dim3(NT), 0, s, a, count);
+            else hipLaunchKernelGGL((up_res16<E, NT, false, true>), grid, dim3(NT), 0, s, a, count);
+        } else {
+            if (res) hipLaunchKernelGGL((up_res16<E, NT, true>), grid, dim3(NT), 0, s, a, count);
+            else hipLaunchKernelGGL((up_res16<E, NT, false>), grid, dim3(NT), 0, s, a, count);
+        }
     }
     else if (which == LevelKernel::Middle) {
         // one workgroup per chunk of NT / 64 row tiles of a block
@@ -1447,7 +1499,10 @@ void launch_res16(LevelKernel which, const void* args, long long count, int nrhs
         MIDBF_CHECK(a.ang || a.bscale == 1.f, MIDBF_ERR_ARG, "a scale change needs the middle's phase tiles");
         a.mchunks = std::max(1, (a.out_max + NT / 4 - 1) / (NT / 4));
         const dim3 mgrid((unsigned)(count * a.mchunks), grid.y);
-        if (a.ang) hipLaunchKernelGGL((middle_res16<E, NT, true, TWO>), mgrid, dim3(NT), 0, s, a, tile_off);
+        MIDBF_CHECK(!a.presplit || a.ang, MIDBF_ERR_ARG, "split vectors go to the phase-tile middle only");
+        if (a.ang && a.presplit)
+            hipLaunchKernelGGL((middle_res16<E, NT, true, TWO, true>), mgrid, dim3(NT), 0, s, a, tile_off);
+        else if (a.ang) hipLaunchKernelGGL((middle_res16<E, NT, true, TWO>), mgrid, dim3(NT), 0, s, a, tile_off);
         else hipLaunchKernelGGL((middle_res16<E, NT, false, TWO>), mgrid, dim3(NT), 0, s, a, tile_off);
     }
     else if (which == LevelKernel::Down && ((const DownArgs*)args)->kmax <= RES_KT * KT)

@@ -426,6 +426,31 @@ def test_fp16x3_two_workgroup_middle_odd_levels(n, nrhs, variant):
     assert rel_l2(gh, g64) < 5e-6, (n, nrhs, variant)
 
 
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("n,nrhs", [(64, 70), (128, 64), (256, 20)])
+def test_split_exchange_top_up_to_middle(precision, n, nrhs):
+    """The top up step hands the middle its output already split into hi / lo halves when both run
+    source-table kernels (variants 7-10); the halves come from the same conversions as the middle's
+    own split, so the apply is bitwise the one with FP32 pairs (MIDBF_SPLIT_EXCHANGE=0).  Mixed
+    variant sets where one side is outside 7-10 turn the exchange off by themselves."""
+    import os
+    F = _build(n, "fio_ellipse", precisions=1 | 4 | 8)
+    f = W.complex_gaussian(n * n, nrhs, 83, n)
+    fd = to_dev(f, torch.complex64)
+    g64 = from_dev(F.apply(to_dev(f)))
+    for vs in ([9, 8, 10], [10, 10, 10], [7, 6, 7], [9, 8, 5], [2, 8, 10]):
+        F.set_variants(vs, precision=precision)
+        print(f"[exchange] {precision} {n}^2 x {nrhs} variants {vs}", flush=True)
+        g = F.apply(fd, precision=precision)
+        os.environ["MIDBF_SPLIT_EXCHANGE"] = "0"
+        try:
+            g_pairs = F.apply(fd, precision=precision)
+        finally:
+            del os.environ["MIDBF_SPLIT_EXCHANGE"]
+        assert torch.equal(g, g_pairs), (precision, n, nrhs, vs)
+        assert rel_l2(from_dev(g), g64) < (5e-6 if precision == "fp16x3" else 1e-4), (precision, vs)
+
+
 @pytest.mark.parametrize("nrhs", [64, 70])
 def test_fp16x3_lattice_input_path(nrhs):
     """When the first up step keeps every leaf point (64^2: every leaf decomposition is full rank),
