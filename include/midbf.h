@@ -492,7 +492,11 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
  * applies, variants 7-10 of the up kind read per-level source-row tables
  * built with the plan; when the first up step keeps every leaf point, they
  * also replace that step by the (scaled) transpose of the input into the
- * apply's row-major copy.
+ * apply's row-major copy.  When the top up step and the middle both run
+ * variants 7-10, the up step writes its output already split into hi / lo
+ * halves for the middle (the same conversions, so the result is bitwise the
+ * same); the environment variable MIDBF_SPLIT_EXCHANGE=0, read when an apply
+ * is planned, keeps FP32 pairs instead.
  */
 midbf_status midbf_tune(midbf_handle h, int nrhs, midbf_precision prec, void* stream, int* variants);
 midbf_status midbf_set_variants(midbf_handle h, midbf_precision prec, const int* variants);
