@@ -481,7 +481,8 @@ midbf_status midbf_profile_read(midbf_handle h, midbf_kernel_time* out, int max_
  * midbf_tune -- autotuner of the many-right-hand-side (matrix-core) apply:
  * times every tile variant (rows per wave, K chunk, pipelining, workgroup
  * width) of the up, down and middle kernels on this factorization with nrhs
- * right-hand sides and keeps the fastest per kernel kind and MSCS step.
+ * right-hand sides and keeps the fastest per kernel kind and MSCS step
+ * (one warm-up apply per variant, then the faster of two timed applies).
  * Allocates and frees two N x nrhs buffers; synchronizes `stream`.  If
  * variants != NULL, writes the choice for the top step of up and down and
  * for the middle to variants[0..3).  midbf_set_variants installs one variant
